@@ -1,0 +1,422 @@
+/*
+ * amgs_ref.c -- CPU oracle for A-orthonormalising modified Gram-Schmidt.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
+ * benchmark's CPU-baseline leg load this library.  It shares no code, header
+ * or helper with the GPU library.
+ *
+ * Problem (Section 1, eq. (1)): given Z (m x n, m >= n) and a symmetric
+ * positive definite A (m x m), compute Z = QR with Q^T A Q = I_n and R upper
+ * triangular with a positive diagonal.
+ *
+ * The three variants of Section 2 are implemented step by step:
+ *   naive (Alg. 3 column / Alg. 4 row): r_ij = p_i^T z_j with p_i = A q_i,
+ *         two matrix-vector products (MV) per column, 2n MV in total;
+ *   HA    (Alg. 5 column / Alg. 7 row): p_j = x_j / r_jj (eq. (tec1)),
+ *         one MV per column, n MV in total;
+ *   HP    (Alg. 6 column / Alg. 8 row): X = A Z as one block product, then
+ *         x_j^{(j-1)} = x_j^{(0)} - sum_{i<j} r_ij p_i (eq. (tec2)).
+ *
+ * Arithmetic conventions (the paper fixes none of these):
+ *   - FP64 throughout in precision 0.  Compile with -ffp-contract=off so that
+ *     every a - r*b is a rounded multiply followed by a rounded subtract.
+ *   - dot products: rows are split into consecutive blocks of 1024; each block
+ *     is summed left to right, then the block sums are added left to right.
+ *     The result therefore does not depend on the number of OpenMP threads.
+ *   - CSR MV: each row sums a_kl * v_l in stored (ascending column) order.
+ *     Dense MV: y_k = sum_l A[l,k] v_l with l ascending (A is symmetric and
+ *     column-major, so this walks column k).
+ *   - division is a true division.
+ *   - a column whose squared A-norm z_j^T x_j is not positive and finite is a
+ *     breakdown: the routine stops and reports the 1-based column index.
+ *
+ * Precision 1 emulates the FP32-storage form: A, Z, Q, P, X hold binary32
+ * values; MV, the projections r_ij = p_i^T z_j (binary32 accumulation) and
+ * the updates z_j -= r_ij q_i, x_j -= r_ij p_i run in binary32; the squared
+ * A-norm is accumulated in binary64 from the binary32 values, the square root
+ * and the divisions q_j = z_j / r_jj, p_j = x_j / r_jj are binary64 and their
+ * results are rounded to binary32.  R is binary64.
+ *
+ * Optional reorthogonalisation (the paper names it in Section 2.1 without a
+ * definition): after the MGS projections of column j, a classical second
+ * pass s_i = p_i^T z_j for all i < j (binary64 accumulation), then
+ * z_j <- z_j - sum_i s_i q_i (binary64, rounded once to storage), and
+ * r_ij += s_i.  For HP the same s_i also correct x_j: x_j <- x_j -
+ * sum_i s_i p_i (binary64, rounded once), applied after the first-pass
+ * recurrence.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define REF_NAIVE 0
+#define REF_HA 1
+#define REF_HP 2
+#define REF_COL 0
+#define REF_ROW 1
+#define REF_FP64 0
+#define REF_FP32 1
+#define DOT_BLOCK 1024
+
+typedef struct {
+    int kind; /* 0 dense, 1 csr */
+    int64_t m;
+    const double *a; int64_t lda;                /* dense, column-major */
+    const int32_t *row_ptr, *col_idx; const double *vals; /* csr */
+} ref_op;
+
+/* Round to the storage precision. */
+static inline double st(double v, int prec) { return prec == REF_FP32 ? (double)(float)v : v; }
+
+/* ---------------------------------------------------------------- dots */
+/* r = a^T b accumulated in the storage precision (binary32 in precision 1). */
+static double dot_st(const double *a, const double *b, int64_t m, int prec)
+{
+    int64_t nb = (m + DOT_BLOCK - 1) / DOT_BLOCK;
+    double *part = (double *)malloc((size_t)(nb > 0 ? nb : 1) * sizeof(double));
+#pragma omp parallel for schedule(static)
+    for (int64_t blk = 0; blk < nb; ++blk) {
+        int64_t lo = blk * DOT_BLOCK, hi = lo + DOT_BLOCK < m ? lo + DOT_BLOCK : m;
+        if (prec == REF_FP32) {
+            float s = 0.0f;
+            for (int64_t k = lo; k < hi; ++k) {
+                float prod = (float)a[k] * (float)b[k];
+                s = s + prod;
+            }
+            part[blk] = s;
+        } else {
+            double s = 0.0;
+            for (int64_t k = lo; k < hi; ++k) {
+                double prod = a[k] * b[k];
+                s = s + prod;
+            }
+            part[blk] = s;
+        }
+    }
+    double r;
+    if (prec == REF_FP32) {
+        float s = 0.0f;
+        for (int64_t blk = 0; blk < nb; ++blk) s = s + (float)part[blk];
+        r = s;
+    } else {
+        double s = 0.0;
+        for (int64_t blk = 0; blk < nb; ++blk) s = s + part[blk];
+        r = s;
+    }
+    free(part);
+    return r;
+}
+
+/* a^T b accumulated in binary64 (used for the A-norm and the second pass). */
+static double dot_hi(const double *a, const double *b, int64_t m)
+{
+    return dot_st(a, b, m, REF_FP64);
+}
+
+/* ---------------------------------------------------------------- axpy */
+/* z <- z - r q  (eq. (AXPY)), in the storage precision. */
+static void axpy_st(double *z, double r, const double *q, int64_t m, int prec)
+{
+    if (prec == REF_FP32) {
+        float rf = (float)r;
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < m; ++k) {
+            float prod = rf * (float)q[k];
+            float zk = (float)z[k] - prod;
+            z[k] = zk;
+        }
+    } else {
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < m; ++k) {
+            double prod = r * q[k];
+            z[k] = z[k] - prod;
+        }
+    }
+}
+
+/* ---------------------------------------------------------------- MV */
+/* y <- A v in the storage precision. */
+static void mv_st(const ref_op *A, const double *v, double *y, int prec)
+{
+    int64_t m = A->m;
+    if (A->kind == 1) {
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < m; ++k) {
+            if (prec == REF_FP32) {
+                float s = 0.0f;
+                for (int32_t e = A->row_ptr[k]; e < A->row_ptr[k + 1]; ++e) {
+                    float prod = (float)A->vals[e] * (float)v[A->col_idx[e]];
+                    s = s + prod;
+                }
+                y[k] = s;
+            } else {
+                double s = 0.0;
+                for (int32_t e = A->row_ptr[k]; e < A->row_ptr[k + 1]; ++e) {
+                    double prod = A->vals[e] * v[A->col_idx[e]];
+                    s = s + prod;
+                }
+                y[k] = s;
+            }
+        }
+    } else {
+#pragma omp parallel for schedule(static)
+        for (int64_t k = 0; k < m; ++k) {
+            const double *col = A->a + k * A->lda;
+            if (prec == REF_FP32) {
+                float s = 0.0f;
+                for (int64_t l = 0; l < m; ++l) {
+                    float prod = (float)col[l] * (float)v[l];
+                    s = s + prod;
+                }
+                y[k] = s;
+            } else {
+                double s = 0.0;
+                for (int64_t l = 0; l < m; ++l) {
+                    double prod = col[l] * v[l];
+                    s = s + prod;
+                }
+                y[k] = s;
+            }
+        }
+    }
+}
+
+/* y <- v / r  (eq. (scaling)): binary64 division, rounded to storage. */
+static void scale(double *y, const double *v, double r, int64_t m, int prec)
+{
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < m; ++k) y[k] = st(v[k] / r, prec);
+}
+
+/* ------------------------------------------------- second (reorth) pass */
+/* s_i = p_i^T z for i < j (binary64), z <- z - sum_i s_i q_i, r_ij += s_i.
+ * For HP, also x <- x - sum_i s_i p_i. */
+static void reorth_pass(double *z, double *x_or_null, int64_t j, const double *Q, int64_t ldq,
+                        const double *P, int64_t ldp, double *Rcol, int64_t m, int prec)
+{
+    if (j == 0) return;
+    double *s = (double *)malloc((size_t)j * sizeof(double));
+    for (int64_t i = 0; i < j; ++i) s[i] = dot_hi(P + i * ldp, z, m);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < m; ++k) {
+        double zk = z[k];
+        for (int64_t i = 0; i < j; ++i) {
+            double prod = s[i] * Q[i * ldq + k];
+            zk = zk - prod;
+        }
+        z[k] = st(zk, prec);
+        if (x_or_null) {
+            double xk = x_or_null[k];
+            for (int64_t i = 0; i < j; ++i) {
+                double prod = s[i] * P[i * ldp + k];
+                xk = xk - prod;
+            }
+            x_or_null[k] = st(xk, prec);
+        }
+    }
+    for (int64_t i = 0; i < j; ++i) Rcol[i] = Rcol[i] + s[i];
+    free(s);
+}
+
+/* r_jj = sqrt(z^T x) with binary64 accumulation; returns 0 on breakdown. */
+static int anorm(const double *z, const double *x, int64_t m, double *rjj)
+{
+    double rr = dot_hi(z, x, m);
+    if (!(rr > 0.0) || !isfinite(rr)) return 0;
+    *rjj = sqrt(rr);
+    return 1;
+}
+
+/* ------------------------------------------------------------ driver */
+/* Column-oriented: Alg. 3 (naive), Alg. 5 (HA), Alg. 6 (HP). */
+static int qr_col(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq, double *R,
+                  int64_t ldr, double *P, int64_t ldp, double *X, int variant, int reorth,
+                  int prec, int64_t *mv_calls, int64_t *mv_cols)
+{
+    double *x = (double *)malloc((size_t)m * sizeof(double));
+    if (variant == REF_HP) {            /* Alg. 6 first line: X = A Z, one block MV */
+        for (int64_t j = 0; j < n; ++j) mv_st(A, Q + j * ldq, X + j * m, prec);
+        *mv_calls += 1; *mv_cols += n;
+    }
+    int info = 0;
+    for (int64_t j = 0; j < n && !info; ++j) {
+        double *z = Q + j * ldq;        /* holds z_j^{(i)}; overwritten by q_j */
+        double *Rc = R + j * ldr;
+        for (int64_t i = 0; i < j; ++i) {           /* projections */
+            Rc[i] = dot_st(P + i * ldp, z, m, prec); /* r_ij = p_i^T z_j^{(i-1)} */
+            axpy_st(z, Rc[i], Q + i * ldq, m, prec); /* z_j^{(i)} = z_j^{(i-1)} - r_ij q_i */
+        }
+        double *xr = NULL;
+        if (variant == REF_HP) {
+            /* x_j^{(j-1)} = x_j^{(0)} - sum_{i<j} r_ij p_i, i ascending */
+            memcpy(x, X + j * m, (size_t)m * sizeof(double));
+            for (int64_t i = 0; i < j; ++i) axpy_st(x, st(Rc[i], prec), P + i * ldp, m, prec);
+            xr = x;
+        }
+        if (reorth) reorth_pass(z, xr, j, Q, ldq, P, ldp, Rc, m, prec);
+        if (variant != REF_HP) {        /* boxed MV: x_j^{(j-1)} = A z_j^{(j-1)} */
+            mv_st(A, z, x, prec);
+            *mv_calls += 1; *mv_cols += 1;
+        }
+        double rjj;
+        if (!anorm(z, x, m, &rjj)) { info = (int)(j + 1); break; }
+        Rc[j] = rjj;
+        scale(z, z, rjj, m, prec);                  /* q_j = z_j^{(j-1)} / r_jj */
+        if (variant == REF_NAIVE) {                 /* boxed MV: p_j = A q_j */
+            mv_st(A, z, P + j * ldp, prec);
+            *mv_calls += 1; *mv_cols += 1;
+        } else {
+            scale(P + j * ldp, x, rjj, m, prec);    /* p_j = x_j^{(j-1)} / r_jj (eq. tec1) */
+        }
+    }
+    free(x);
+    return info;
+}
+
+/* Row-oriented: Alg. 4 (naive), Alg. 7 (HA), Alg. 8 (HP).  In HP(row) the
+ * x-update printed in the paper is read as: at step i, for every j > i,
+ * x_j^{(i)} = x_j^{(i-1)} - r_ij p_i (the row analogue of eq. (tec2)). */
+static int qr_row(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq, double *R,
+                  int64_t ldr, double *P, int64_t ldp, double *X, int variant, int reorth,
+                  int prec, int64_t *mv_calls, int64_t *mv_cols)
+{
+    double *x = (double *)malloc((size_t)m * sizeof(double));
+    if (variant == REF_HP) {
+        for (int64_t j = 0; j < n; ++j) mv_st(A, Q + j * ldq, X + j * m, prec);
+        *mv_calls += 1; *mv_cols += n;
+    }
+    int info = 0;
+    for (int64_t i = 0; i < n && !info; ++i) {
+        double *z = Q + i * ldq;
+        double *xr = NULL;
+        if (variant == REF_HP) xr = X + i * m;      /* already x_i^{(i-1)} */
+        if (reorth) reorth_pass(z, xr, i, Q, ldq, P, ldp, R + i * ldr, m, prec);
+        if (variant == REF_HP) {
+            memcpy(x, X + i * m, (size_t)m * sizeof(double));
+        } else {
+            mv_st(A, z, x, prec);                   /* x_i^{(i-1)} = A z_i^{(i-1)} */
+            *mv_calls += 1; *mv_cols += 1;
+        }
+        double rii;
+        if (!anorm(z, x, m, &rii)) { info = (int)(i + 1); break; }
+        R[i * ldr + i] = rii;
+        scale(z, z, rii, m, prec);                  /* q_i */
+        if (variant == REF_NAIVE) {
+            mv_st(A, z, P + i * ldp, prec);         /* p_i = A q_i */
+            *mv_calls += 1; *mv_cols += 1;
+        } else {
+            scale(P + i * ldp, x, rii, m, prec);    /* p_i = x_i^{(i-1)} / r_ii */
+        }
+        for (int64_t j = i + 1; j < n; ++j) {
+            double rij = dot_st(P + i * ldp, Q + j * ldq, m, prec);
+            R[j * ldr + i] = rij;
+            axpy_st(Q + j * ldq, rij, Q + i * ldq, m, prec);
+        }
+        if (variant == REF_HP)
+            for (int64_t j = i + 1; j < n; ++j)
+                axpy_st(X + j * m, st(R[j * ldr + i], prec), P + i * ldp, m, prec);
+    }
+    free(x);
+    return info;
+}
+
+static int run(const ref_op *A, int64_t n, const double *Z, int64_t ldz, double *Q, int64_t ldq,
+               double *R, int64_t ldr, double *P, int64_t ldp, int variant, int orientation,
+               int reorth, int prec, int64_t *stats)
+{
+    int64_t m = A->m;
+    if (m < 0 || n < 0 || n > m || ldz < m || ldq < m || ldr < n) return -1;
+    if (variant < 0 || variant > 2 || orientation < 0 || orientation > 1) return -1;
+    if (prec < 0 || prec > 1) return -1;
+    if (n == 0) { if (stats) stats[0] = stats[1] = 0; return 0; }
+    if (!Z || !Q || !R) return -1;
+    /* a0: working copy (Q holds z_j^{(i)}), R zeroed; inputs rounded to storage */
+    for (int64_t j = 0; j < n; ++j)
+        for (int64_t k = 0; k < m; ++k) Q[j * ldq + k] = st(Z[j * ldz + k], prec);
+    for (int64_t j = 0; j < n; ++j) memset(R + j * ldr, 0, (size_t)n * sizeof(double));
+    double *Pw = P;
+    int64_t ldpw = ldp;
+    if (!Pw) { Pw = (double *)calloc((size_t)m * n, sizeof(double)); ldpw = m; }
+    double *X = NULL;
+    if (variant == REF_HP) X = (double *)malloc((size_t)m * n * sizeof(double));
+    int64_t calls = 0, cols = 0;
+    int info = orientation == REF_COL
+        ? qr_col(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols)
+        : qr_row(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols);
+    if (stats) { stats[0] = calls; stats[1] = cols; }
+    free(X);
+    if (!P) free(Pw);
+    return info;
+}
+
+/* Round a matrix in place to storage precision (inputs of precision 1). */
+static double *rounded_copy(const double *v, int64_t len, int prec)
+{
+    double *c = (double *)malloc((size_t)(len > 0 ? len : 1) * sizeof(double));
+    for (int64_t k = 0; k < len; ++k) c[k] = st(v[k], prec);
+    return c;
+}
+
+/* ---------------------------------------------------------- exports */
+/* Dense symmetric A (column-major, lda >= m).  Returns 0 on success, j >= 1 if
+ * column j broke down (columns before j are valid), -1 on a bad argument.
+ * stats (nullable, 2 entries): number of MV calls (a block product counts
+ * once) and number of MV columns. */
+int amgs_ref_qr_dense(int64_t m, const double *a, int64_t lda, int64_t n, const double *Z,
+                      int64_t ldz, double *Q, int64_t ldq, double *R, int64_t ldr, double *P,
+                      int64_t ldp, int variant, int orientation, int reorth, int precision,
+                      int64_t *stats)
+{
+    if (!a || lda < m) return -1;
+    ref_op A = {0};
+    A.kind = 0; A.m = m; A.lda = lda;
+    double *ar = NULL;
+    if (precision == REF_FP32) { ar = rounded_copy(a, lda * m, precision); A.a = ar; }
+    else A.a = a;
+    int info = run(&A, n, Z, ldz, Q, ldq, R, ldr, P, ldp, variant, orientation, reorth,
+                   precision, stats);
+    free(ar);
+    return info;
+}
+
+/* CSR symmetric A (int32 indices, columns ascending within each row). */
+int amgs_ref_qr_csr(int64_t m, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                    const double *vals, int64_t n, const double *Z, int64_t ldz, double *Q,
+                    int64_t ldq, double *R, int64_t ldr, double *P, int64_t ldp, int variant,
+                    int orientation, int reorth, int precision, int64_t *stats)
+{
+    if (!row_ptr || (nnz > 0 && (!col_idx || !vals))) return -1;
+    if (row_ptr[0] != 0 || row_ptr[m] != nnz) return -1;
+    ref_op A = {0};
+    A.kind = 1; A.m = m; A.row_ptr = row_ptr; A.col_idx = col_idx;
+    double *vr = NULL;
+    if (precision == REF_FP32) { vr = rounded_copy(vals, nnz, precision); A.vals = vr; }
+    else A.vals = vals;
+    int info = run(&A, n, Z, ldz, Q, ldq, R, ldr, P, ldp, variant, orientation, reorth,
+                   precision, stats);
+    free(vr);
+    return info;
+}
+
+/* Plain matrix-vector product with the same conventions (for tests). */
+int amgs_ref_mv_csr(int64_t m, const int32_t *row_ptr, const int32_t *col_idx,
+                    const double *vals, const double *v, double *y, int precision)
+{
+    ref_op A = {0};
+    A.kind = 1; A.m = m; A.row_ptr = row_ptr; A.col_idx = col_idx; A.vals = vals;
+    mv_st(&A, v, y, precision);
+    return 0;
+}
+
+int amgs_ref_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,67 @@
+"""Plant plausible mistakes in a copy of the oracle and check that the pins
+catch every one of them (the mistakes live only in temporary copies)."""
+import os
+import shutil
+import tempfile
+
+import pytest
+
+import pins
+from conftest import ROOT, read_golden
+from oracle import ref
+
+SRC = os.path.join(ROOT, "oracle", "amgs_ref.c")
+
+# (name, original text, planted text)
+MUTANTS = [
+    ("projection uses q instead of p (standard inner product)",
+     "Rc[i] = dot_st(P + i * ldp, z, m, prec);", "Rc[i] = dot_st(Q + i * ldq, z, m, prec);"),
+    ("projection update sign flipped",
+     "z[k] = z[k] - prod;", "z[k] = z[k] + prod;"),
+    ("HP recurrence uses q instead of p",
+     "axpy_st(x, st(Rc[i], prec), P + i * ldp, m, prec);",
+     "axpy_st(x, st(Rc[i], prec), Q + i * ldq, m, prec);"),
+    ("HP recurrence term dropped (last i)",
+     "for (int64_t i = 0; i < j; ++i) axpy_st(x, st(Rc[i], prec)",
+     "for (int64_t i = 0; i + 1 < j; ++i) axpy_st(x, st(Rc[i], prec)"),
+    ("HA auxiliary vector from z instead of x",
+     "scale(P + j * ldp, x, rjj, m, prec);", "scale(P + j * ldp, z, rjj, m, prec);"),
+    ("A-norm without square root", "*rjj = sqrt(rr);", "*rjj = rr;"),
+    ("row form stores r_ij transposed",
+     "R[j * ldr + i] = rij;", "R[i * ldr + j] = rij;"),
+    ("row HP recurrence uses the wrong column of X",
+     "axpy_st(X + j * m, st(R[j * ldr + i], prec)", "axpy_st(X + i * m, st(R[j * ldr + i], prec)"),
+    ("second pass does not add s_i into R",
+     "Rcol[i] = Rcol[i] + s[i];", "Rcol[i] = Rcol[i];"),
+    ("A-norm accumulated in binary32 in the binary32 form",
+     "double rr = dot_hi(z, x, m);", "double rr = dot_st(z, x, m, REF_FP32);"),
+    ("binary32 projections accumulated in binary64",
+     "        if (prec == REF_FP32) {\n            float s = 0.0f;\n            for (int64_t k = lo;",
+     "        if (0) {\n            float s = 0.0f;\n            for (int64_t k = lo;"),
+    ("dense MV walks a row of the wrong matrix (transposed operand of a non-symmetric read)",
+     "const double *col = A->a + k * A->lda;", "const double *col = A->a + k;"),
+]
+
+
+@pytest.mark.parametrize("name,orig,planted", MUTANTS, ids=[m[0] for m in MUTANTS])
+def test_mutant_is_caught(name, orig, planted):
+    src = open(SRC).read()
+    assert src.count(orig) >= 1, f"mutation anchor not found: {orig!r}"
+    tmp = tempfile.mkdtemp(prefix="amgs_mut_")
+    try:
+        msrc = os.path.join(tmp, "mut.c")
+        with open(msrc, "w") as f:
+            f.write(src.replace(orig, planted, 1))
+        lib = ref.load(ref.build(src=msrc, out=os.path.join(tmp, "libmut.so")))
+        golden = read_golden("hand_example.txt")
+        caught = []
+        for pin in pins.ALL_PINS:
+            try:
+                fails = pin(lib, golden) if pin is pins.pin_hand_example else pin(lib)
+            except Exception as e:  # a crash of the mutant also counts as caught
+                fails = [repr(e)]
+            if fails:
+                caught.append(pin.__name__)
+        assert caught, f"no pin catches mutant: {name}"
+    finally:
+        shutil.rmtree(tmp, ignore_errors=True)
