@@ -1,0 +1,202 @@
+/*
+ * amgs.h -- C ABI of the MI355X library for A-orthonormalising modified
+ * Gram-Schmidt (Imakura & Yamamoto, "Efficient implementations of the
+ * modified Gram-Schmidt orthogonalization with a non-standard inner
+ * product").
+ *
+ * Problem (Section 1, eq. (1)): given Z (m x n, m >= n) and a symmetric
+ * positive definite A (m x m), compute
+ *         Z = Q R,    Q^T A Q = I_n,
+ * with R upper triangular and positive on the diagonal.  The A-inner product
+ * is (x, y)_A = x^T A y (Section 1, notation).
+ *
+ * Variants (Section 2):
+ *   AMGS_NAIVE  Alg. 3: r_ij = p_i^T z_j with p_i = A q_i; two
+ *               matrix-vector products (MV) per column, 2n MV in total.
+ *   AMGS_HA     Alg. 5: p_j = x_j / r_jj (eq. (tec1)); n MV in total.
+ *   AMGS_HP     Alg. 6: X = A Z as one block product, then
+ *               x_j = x_j^{(0)} - sum_{i<j} r_ij p_i (eq. (tec2)).
+ * Every variant returns the numbers of the column-oriented algorithm
+ * (Alg. 3/5/6); the library schedules the same per-column operations in
+ * right-looking order (Section 2.1 notes that both orders compute the same
+ * values).
+ *
+ * Precisions:
+ *   AMGS_FP64   everything in binary64.
+ *   AMGS_FP32   A, Z, Q, P (= AQ) and the HP block X are binary32; MV and the
+ *               projections r_ij = p_i^T z_j, z_j -= r_ij q_i, x_j -= r_ij p_i
+ *               run in binary32 with binary32 accumulation; the squared
+ *               A-norm z_j^T x_j is accumulated in binary64, and the square
+ *               root and the divisions q_j = z_j / r_jj, p_j = x_j / r_jj are
+ *               binary64 rounded once to binary32.  R is binary64.
+ *
+ * Optional second pass (opts->reorth = 1; the paper mentions
+ * reorthogonalisation in Section 2.1 without defining it): after the MGS
+ * projections of column j, s_i = p_i^T z_j for all i < j (binary64
+ * accumulation), z_j -= sum_i s_i q_i (binary64, rounded once), r_ij += s_i;
+ * for HP also x_j -= sum_i s_i p_i.
+ *
+ * Conventions shared by all entry points:
+ *   - Matrices are column-major with a leading dimension (ld >= rows).
+ *   - Every matrix/vector pointer passed to amgs_qr_* is DEVICE memory owned
+ *     by the caller; the library never allocates, frees or synchronises
+ *     inside amgs_qr_*: all work is enqueued on `stream` (a hipStream_t;
+ *     NULL = the null stream).  Scratch memory is the caller's `work`
+ *     buffer of at least amgs_workspace_bytes(...) bytes.
+ *   - Z may alias Q (in-place, ldz == ldq).  Otherwise Z is read only.
+ *   - R is n x n binary64 in both precisions; its strictly lower triangle is
+ *     set to zero.
+ *   - `info` is a device int32: 0 on success, j >= 1 if column j (1-based)
+ *     had a squared A-norm that was not positive and finite (Z rank
+ *     deficient, A not positive definite, or cancellation); columns before
+ *     j are valid, later ones are not.  It is written asynchronously.
+ *   - Synchronous errors: AMGS_ERR_ARG for invalid sizes, leading
+ *     dimensions, enum values or null pointers; AMGS_ERR_WORKSPACE when
+ *     work_bytes is too small; AMGS_ERR_HIP when a launch fails.
+ *   - n == 0 is a no-op returning AMGS_OK.
+ *   - A CSR matrix must be valid: row_ptr[0] = 0, non-decreasing,
+ *     row_ptr[m] = nnz, 0 <= col_idx < m.  amgs_csr_check() verifies this on
+ *     the device; the solver itself does not re-check indices.
+ *   - One handle may be used from one host thread at a time.
+ */
+#ifndef AMGS_H
+#define AMGS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum { AMGS_NAIVE = 0, AMGS_HA = 1, AMGS_HP = 2 } amgs_variant_t;
+typedef enum { AMGS_FP64 = 0, AMGS_FP32 = 1 } amgs_precision_t;
+typedef enum {
+    AMGS_OK = 0,
+    AMGS_ERR_ARG = -1,
+    AMGS_ERR_WORKSPACE = -2,
+    AMGS_ERR_HIP = -3,
+    AMGS_ERR_UNSUPPORTED = -4
+} amgs_status_t;
+
+typedef struct amgs_handle *amgs_handle_t;
+
+/* Per-call options; passing NULL means all zero. */
+typedef struct {
+    int32_t reorth;    /* 1: second (reorthogonalisation) pass per column */
+    int32_t reserved0;
+    int32_t reserved1;
+    int32_t reserved2;
+} amgs_opts_t;
+
+/* Counters of the most recent amgs_qr_* call on a handle. */
+typedef struct {
+    int64_t mv_calls;        /* MV launches: 2n naive, n HA, 1 block product HP */
+    int64_t mv_columns;      /* columns multiplied by A */
+    int64_t kernel_launches; /* all kernels enqueued */
+    int64_t sweep_launches;  /* projection-sweep kernels enqueued */
+    double  sweep_bytes;     /* algorithmic HBM bytes of all sweeps (see below) */
+    double  mv_bytes;        /* algorithmic HBM bytes of all MV / block products */
+} amgs_stats_t;
+
+/* Handle bound to a device (HIP ordinal).  Returns AMGS_ERR_ARG for a bad
+ * ordinal or NULL out-pointer.  The handle holds device properties, launch
+ * geometry and counters; destroying it frees nothing the caller owns. */
+amgs_status_t amgs_create(amgs_handle_t *h, int device);
+amgs_status_t amgs_destroy(amgs_handle_t h);
+
+/* Bytes of device workspace needed by amgs_qr_csr (is_dense = 0) or
+ * amgs_qr_dense (is_dense = 1) for these sizes; P_given = 1 if the caller
+ * passes its own P (= AQ) buffer.  Returns 0 for invalid arguments. */
+size_t amgs_workspace_bytes(amgs_handle_t h, int64_t m, int64_t n, int32_t is_dense,
+                            amgs_variant_t v, amgs_precision_t p, int32_t P_given,
+                            const amgs_opts_t *o);
+
+/* Z = QR, Q^T A Q = I for CSR A (Alg. 3 / 5 / 6, eq. (1)).
+ *   row_ptr[m+1], col_idx[nnz]: int32; vals[nnz]: binary64 (AMGS_FP64) or
+ *   binary32 (AMGS_FP32), matching `p`.  Z, Q, P: element type of `p`.
+ *   P (nullable, ld ldp): receives the auxiliary vectors p_j = A q_j
+ *   (Section 2.1); when NULL the workspace holds them. */
+amgs_status_t amgs_qr_csr(amgs_handle_t h, int64_t m, int64_t nnz, const int32_t *row_ptr,
+                          const int32_t *col_idx, const void *vals, int64_t n,
+                          const void *Z, int64_t ldz, void *Q, int64_t ldq, double *R,
+                          int64_t ldr, void *P, int64_t ldp, amgs_variant_t v,
+                          amgs_precision_t p, const amgs_opts_t *o, void *work,
+                          size_t work_bytes, int32_t *info, void *stream);
+
+/* Same for a dense symmetric A (column-major, lda >= m); the block product
+ * X = A Z of HP (Alg. 6, first line) runs on the matrix cores. */
+amgs_status_t amgs_qr_dense(amgs_handle_t h, int64_t m, const void *A, int64_t lda, int64_t n,
+                            const void *Z, int64_t ldz, void *Q, int64_t ldq, double *R,
+                            int64_t ldr, void *P, int64_t ldp, amgs_variant_t v,
+                            amgs_precision_t p, const amgs_opts_t *o, void *work,
+                            size_t work_bytes, int32_t *info, void *stream);
+
+/* Device-side CSR validation: writes 0 to *flag if the structure is valid,
+ * 1 otherwise (flag is device int32). */
+amgs_status_t amgs_csr_check(amgs_handle_t h, int64_t m, int64_t nnz, const int32_t *row_ptr,
+                             const int32_t *col_idx, int32_t *flag, void *stream);
+
+/* ---------------------------------------------------------------------
+ * Batched form: many independent problems (each its own CSR A_k, Z_k) in
+ * one persistent launch replayed from a HIP graph.  Each instance is the
+ * single-problem computation above (Alg. 5 or 6) on one workgroup.
+ * ------------------------------------------------------------------- */
+typedef struct {
+    int64_t m, n, nnz;          /* instance sizes (m >= n >= 1) */
+    const int32_t *row_ptr;     /* device, m+1 */
+    const int32_t *col_idx;     /* device, nnz */
+    const void *vals;           /* device, nnz, element type of the precision */
+    const void *Z; int64_t ldz; /* device, read only (may alias Q) */
+    void *Q; int64_t ldq;       /* device, output */
+    double *R; int64_t ldr;     /* device, output n x n */
+} amgs_batch_desc_t;
+
+typedef struct amgs_batch_plan *amgs_batch_plan_t;
+
+/* Build a plan for `batch` instances with sizes m_host[k], n_host[k] (host
+ * arrays): largest-first work order, per-size-class kernel tiles chosen by
+ * the autotuner (autotune = 1 times the candidates on the device with
+ * synthetic data of the same shapes; 0 uses the built-in table).  The plan
+ * owns its small device tables.  Returns AMGS_ERR_ARG on invalid sizes. */
+amgs_status_t amgs_batch_plan_create(amgs_handle_t h, int32_t batch, const int64_t *m_host,
+                                     const int64_t *n_host, amgs_variant_t v,
+                                     amgs_precision_t p, const amgs_opts_t *o,
+                                     int32_t autotune, amgs_batch_plan_t *plan);
+amgs_status_t amgs_batch_plan_destroy(amgs_batch_plan_t plan);
+/* Device workspace bytes the plan needs (P and X blocks of every instance). */
+size_t amgs_batch_workspace_bytes(amgs_batch_plan_t plan);
+
+/* Run every instance of the plan: desc is a DEVICE array of `batch`
+ * descriptors in the order the sizes were given; info is a DEVICE int32
+ * array of `batch` entries (per-instance breakdown index, 0 = success).
+ * The first call for a given (desc, work, info, stream) captures the
+ * launch into a HIP graph; later calls replay it. */
+amgs_status_t amgs_qr_batched(amgs_batch_plan_t plan, const amgs_batch_desc_t *desc,
+                              void *work, size_t work_bytes, int32_t *info, void *stream);
+
+/* Tile chosen for each size class (written to out[0..nclass-1] as packed
+ * integers; returns the number of classes). */
+int32_t amgs_batch_plan_tiles(amgs_batch_plan_t plan, int32_t *out, int32_t cap);
+
+/* ---------------------------------------------------------------------
+ * Introspection
+ * ------------------------------------------------------------------- */
+amgs_status_t amgs_get_stats(amgs_handle_t h, amgs_stats_t *out);
+const char *amgs_status_string(amgs_status_t s);
+
+/* Kernel timing with HIP events recorded on the call's stream around each
+ * launch of a kernel category (0 = projection sweep, 1 = MV / column
+ * kernels, 2 = block product X = AZ).  amgs_profile_enable(h, 1) starts
+ * recording for subsequent calls; amgs_profile_read() synchronises on the
+ * recorded events and returns the summed milliseconds and launch count of a
+ * category since the last reset. */
+amgs_status_t amgs_profile_enable(amgs_handle_t h, int32_t on);
+amgs_status_t amgs_profile_read(amgs_handle_t h, int32_t category, double *total_ms,
+                                int64_t *launches);
+amgs_status_t amgs_profile_reset(amgs_handle_t h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AMGS_H */

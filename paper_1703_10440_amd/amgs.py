@@ -1,0 +1,264 @@
+"""Thin ctypes binding of the HIP library ``libamgs.so`` (C ABI in
+``include/amgs.h``).
+
+Functions named ``amgs_*`` mirror the C entry points one to one (argument
+marshalling only).  ``qr_csr`` / ``qr_dense`` / ``BatchPlan`` are
+conveniences that allocate outputs and workspace with torch (device memory
+and streams only) and call those entry points; every arithmetic step runs in
+the library's kernels.  If the library is missing this module raises: there
+is no other implementation to fall back to.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libamgs.so")
+
+VARIANTS = {"naive": 0, "ha": 1, "hp": 2}
+PRECISIONS = {"fp64": 0, "fp32": 1}
+STATUS = {0: "ok", -1: "invalid argument", -2: "workspace too small", -3: "HIP error",
+          -4: "unsupported"}
+
+
+class AmgsError(RuntimeError):
+    pass
+
+
+class Opts(C.Structure):
+    _fields_ = [("reorth", C.c_int32), ("reserved0", C.c_int32), ("reserved1", C.c_int32),
+                ("reserved2", C.c_int32)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("mv_calls", C.c_int64), ("mv_columns", C.c_int64),
+                ("kernel_launches", C.c_int64), ("sweep_launches", C.c_int64),
+                ("sweep_bytes", C.c_double), ("mv_bytes", C.c_double)]
+
+
+class BatchDesc(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("nnz", C.c_int64),
+                ("row_ptr", C.c_void_p), ("col_idx", C.c_void_p), ("vals", C.c_void_p),
+                ("Z", C.c_void_p), ("ldz", C.c_int64), ("Q", C.c_void_p), ("ldq", C.c_int64),
+                ("R", C.c_void_p), ("ldr", C.c_int64)]
+
+
+_lib = None
+
+# (name, restype, argtypes) of every exported entry point
+_vp, _i64, _i32, _sz = C.c_void_p, C.c_int64, C.c_int32, C.c_size_t
+_SIGS = [
+    ("amgs_create", C.c_int, [C.POINTER(_vp), C.c_int]),
+    ("amgs_destroy", C.c_int, [_vp]),
+    ("amgs_workspace_bytes", _sz, [_vp, _i64, _i64, _i32, C.c_int, C.c_int, _i32,
+                                   C.POINTER(Opts)]),
+    ("amgs_qr_csr", C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
+                              _i64, _vp, _i64, C.c_int, C.c_int, C.POINTER(Opts), _vp, _sz, _vp,
+                              _vp]),
+    ("amgs_qr_dense", C.c_int, [_vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
+                                _i64, C.c_int, C.c_int, C.POINTER(Opts), _vp, _sz, _vp, _vp]),
+    ("amgs_csr_check", C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp]),
+    ("amgs_batch_plan_create", C.c_int, [_vp, _i32, C.POINTER(_i64), C.POINTER(_i64), C.c_int,
+                                         C.c_int, C.POINTER(Opts), _i32, C.POINTER(_vp)]),
+    ("amgs_batch_plan_destroy", C.c_int, [_vp]),
+    ("amgs_batch_workspace_bytes", _sz, [_vp]),
+    ("amgs_qr_batched", C.c_int, [_vp, _vp, _vp, _sz, _vp, _vp]),
+    ("amgs_batch_plan_tiles", _i32, [_vp, C.POINTER(_i32), _i32]),
+    ("amgs_get_stats", C.c_int, [_vp, C.POINTER(Stats)]),
+    ("amgs_status_string", C.c_char_p, [C.c_int]),
+    ("amgs_profile_enable", C.c_int, [_vp, _i32]),
+    ("amgs_profile_read", C.c_int, [_vp, _i32, C.POINTER(C.c_double), C.POINTER(_i64)]),
+    ("amgs_profile_reset", C.c_int, [_vp]),
+]
+EXPORTS = [s[0] for s in _SIGS]
+
+
+def load(path: Optional[str] = None):
+    """Load libamgs.so (built by ``__graft_entry__.build()``)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIB_PATH
+    if not os.path.exists(p):
+        raise AmgsError(f"HIP library not built: {p} is missing (run __graft_entry__.build())")
+    lib = C.CDLL(p)
+    for name, res, args in _SIGS:
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise AmgsError(f"{what}: {STATUS.get(status, status)}")
+
+
+# ----------------------------------------------------------- raw entry points
+def amgs_create(device: int = 0) -> int:
+    h = _vp()
+    _check(load().amgs_create(C.byref(h), device), "amgs_create")
+    return h.value
+
+
+def amgs_destroy(h: int) -> int:
+    return load().amgs_destroy(h)
+
+
+def amgs_workspace_bytes(h, m, n, is_dense, variant, precision, P_given, opts=None) -> int:
+    return int(load().amgs_workspace_bytes(h, m, n, is_dense, variant, precision, P_given,
+                                            C.byref(opts) if opts is not None else None))
+
+
+def amgs_qr_csr(*args) -> int:
+    return load().amgs_qr_csr(*args)
+
+
+def amgs_qr_dense(*args) -> int:
+    return load().amgs_qr_dense(*args)
+
+
+def amgs_csr_check(*args) -> int:
+    return load().amgs_csr_check(*args)
+
+
+def amgs_get_stats(h) -> Stats:
+    s = Stats()
+    _check(load().amgs_get_stats(h, C.byref(s)), "amgs_get_stats")
+    return s
+
+
+def amgs_status_string(s: int) -> str:
+    return load().amgs_status_string(s).decode()
+
+
+def amgs_profile_enable(h, on: int) -> int:
+    return load().amgs_profile_enable(h, on)
+
+
+def amgs_profile_read(h, category: int):
+    ms, n = C.c_double(), _i64()
+    _check(load().amgs_profile_read(h, category, C.byref(ms), C.byref(n)), "amgs_profile_read")
+    return ms.value, n.value
+
+
+def amgs_profile_reset(h) -> int:
+    return load().amgs_profile_reset(h)
+
+
+# --------------------------------------------------------------- conveniences
+_handles = {}
+
+
+def handle(device: int = 0) -> int:
+    if device not in _handles:
+        _handles[device] = amgs_create(device)
+    return _handles[device]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def colmajor(t, dtype=None):
+    """Return an (m, n) column-major (stride (1, m)) device copy/view of t."""
+    torch = _torch()
+    if dtype is not None and t.dtype != dtype:
+        t = t.to(dtype)
+    if t.dim() == 1:
+        t = t[:, None]
+    m, n = t.shape
+    if t.stride(0) == 1 and t.stride(1) >= max(m, 1):
+        return t
+    return t.t().contiguous().t()
+
+
+def empty_colmajor(m, n, dtype, device):
+    torch = _torch()
+    return torch.empty((n, m), dtype=dtype, device=device).t()
+
+
+@dataclass
+class QRResult:
+    Q: object       # (m, n) column-major device tensor
+    R: object       # (n, n) column-major float64 device tensor
+    P: object       # (m, n) column-major device tensor (= A Q), or None
+    info: object    # int32 device tensor with one entry
+    stats: Stats
+
+
+def _prep(Z, precision, device, Q, P, return_p):
+    torch = _torch()
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    Zc = colmajor(Z.to(device), dt)
+    m, n = Zc.shape
+    Qc = Q if Q is not None else empty_colmajor(m, n, dt, device)
+    R = empty_colmajor(n, n, torch.float64, device)
+    Pc = P if P is not None else (empty_colmajor(m, n, dt, device) if return_p else None)
+    info = torch.zeros(1, dtype=torch.int32, device=device)
+    return dt, Zc, Qc, R, Pc, info, m, n
+
+
+def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=False,
+           return_p=False, Q=None, P=None, work=None, stream=None, device=None) -> QRResult:
+    """A-orthonormalise the columns of Z (device tensors; A in CSR)."""
+    torch = _torch()
+    device = device or Z.device
+    dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p)
+    vals = vals.to(device=device, dtype=dt).contiguous()
+    row_ptr = row_ptr.to(device=device, dtype=torch.int32).contiguous()
+    col_idx = col_idx.to(device=device, dtype=torch.int32).contiguous()
+    h = handle(device.index or 0)
+    opts = Opts(int(bool(reorth)), 0, 0, 0)
+    v, p = VARIANTS[variant], PRECISIONS[precision]
+    wb = amgs_workspace_bytes(h, m, n, 0, v, p, int(Pc is not None), opts)
+    if work is None:
+        work = torch.empty(max(wb, 1), dtype=torch.uint8, device=device)
+    s = stream if stream is not None else torch.cuda.current_stream(device).cuda_stream
+    st = amgs_qr_csr(h, m, int(vals.numel()), row_ptr.data_ptr(), col_idx.data_ptr(),
+                     vals.data_ptr(), n, Zc.data_ptr(), max(Zc.stride(1), m), Qc.data_ptr(),
+                     max(Qc.stride(1), m), R.data_ptr(), max(n, 1),
+                     Pc.data_ptr() if Pc is not None else None,
+                     max(Pc.stride(1), m) if Pc is not None else 0, v, p, C.byref(opts),
+                     work.data_ptr(), work.numel(), info.data_ptr(), s)
+    _check(st, "amgs_qr_csr")
+    return QRResult(Qc, R, Pc, info, amgs_get_stats(h))
+
+
+def qr_dense(A, Z, variant="ha", precision="fp64", reorth=False, return_p=False, Q=None,
+             P=None, work=None, stream=None, device=None) -> QRResult:
+    """A-orthonormalise the columns of Z (device tensors; A dense symmetric)."""
+    torch = _torch()
+    device = device or Z.device
+    dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p)
+    Ac = colmajor(A.to(device), dt)
+    h = handle(device.index or 0)
+    opts = Opts(int(bool(reorth)), 0, 0, 0)
+    v, p = VARIANTS[variant], PRECISIONS[precision]
+    wb = amgs_workspace_bytes(h, m, n, 1, v, p, int(Pc is not None), opts)
+    if work is None:
+        work = torch.empty(max(wb, 1), dtype=torch.uint8, device=device)
+    s = stream if stream is not None else torch.cuda.current_stream(device).cuda_stream
+    st = amgs_qr_dense(h, m, Ac.data_ptr(), max(Ac.stride(1), m), n, Zc.data_ptr(),
+                       max(Zc.stride(1), m), Qc.data_ptr(), max(Qc.stride(1), m), R.data_ptr(),
+                       max(n, 1), Pc.data_ptr() if Pc is not None else None,
+                       max(Pc.stride(1), m) if Pc is not None else 0, v, p, C.byref(opts),
+                       work.data_ptr(), work.numel(), info.data_ptr(), s)
+    _check(st, "amgs_qr_dense")
+    return QRResult(Qc, R, Pc, info, amgs_get_stats(h))
+
+
+def csr_check(row_ptr, col_idx, m: int) -> bool:
+    torch = _torch()
+    flag = torch.ones(1, dtype=torch.int32, device=row_ptr.device)
+    h = handle(row_ptr.device.index or 0)
+    s = torch.cuda.current_stream(row_ptr.device).cuda_stream
+    _check(amgs_csr_check(h, m, int(col_idx.numel()), row_ptr.data_ptr(), col_idx.data_ptr(),
+                          flag.data_ptr(), s), "amgs_csr_check")
+    return int(flag.item()) == 0

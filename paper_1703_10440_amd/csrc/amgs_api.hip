@@ -1,0 +1,412 @@
+// amgs_api.hip -- host side of the C ABI declared in include/amgs.h:
+// argument checks, workspace layout, and the per-column launch schedule of
+// the single-problem solver.
+#include <hip/hip_runtime.h>
+
+#include <new>
+#include <vector>
+
+#include "../../include/amgs.h"
+#include "amgs_internal.h"
+#include "amgs_batched.h"
+
+struct amgs_handle {
+    int device;
+    int num_cu;
+    amgs_stats_t stats;
+    int profiling;
+    struct Rec {
+        int cat;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;        // recorded since the last read/reset
+    std::vector<hipEvent_t> pool; // idle events
+    double prof_ms[3];
+    int64_t prof_n[3];
+};
+
+namespace {
+
+using namespace amgs;
+
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(int dev)
+    {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) (void)hipSetDevice(dev);
+    }
+    ~DeviceGuard()
+    {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+hipEvent_t take_event(amgs_handle *h)
+{
+    if (!h->pool.empty()) {
+        hipEvent_t e = h->pool.back();
+        h->pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Records an event pair around one launch when profiling is on.
+struct ProfScope {
+    amgs_handle *h;
+    int cat;
+    hipStream_t s;
+    hipEvent_t a = nullptr, b = nullptr;
+    ProfScope(amgs_handle *h_, int cat_, hipStream_t s_) : h(h_), cat(cat_), s(s_)
+    {
+        if (!h->profiling) return;
+        a = take_event(h);
+        b = take_event(h);
+        if (a && b) (void)hipEventRecord(a, s);
+    }
+    ~ProfScope()
+    {
+        if (!h->profiling || !a || !b) return;
+        (void)hipEventRecord(b, s);
+        h->recs.push_back({cat, a, b});
+    }
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+    size_t part, s_part, rr_part, S, zt, xv, X, P, total;
+};
+
+Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_given, int reorth)
+{
+    Layout L{};
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        size_t o = off;
+        off += align256(bytes);
+        return o;
+    };
+    // MV kernels never use more than MAX_G_MV workgroups, whatever the CSR
+    // lane count, so the size does not depend on nnz
+    int64_t g_rr = g.g_rows > MAX_G_MV ? g.g_rows : MAX_G_MV;
+    L.part = take((size_t)n * g.g_rows * 8);
+    L.s_part = reorth ? take((size_t)n * g.g_rows * 8) : off;
+    L.rr_part = take((size_t)g_rr * 8);
+    L.S = reorth ? take((size_t)n * 8) : off;
+    L.zt = variant != VAR_HP ? take((size_t)m * w) : off;
+    L.xv = variant != VAR_HP ? take((size_t)m * w) : off;
+    L.X = variant == VAR_HP ? take((size_t)m * n * w) : off;
+    L.P = P_given ? off : take((size_t)m * n * w);
+    L.total = off;
+    return L;
+}
+
+bool valid_enums(amgs_variant_t v, amgs_precision_t p)
+{
+    return (v == AMGS_NAIVE || v == AMGS_HA || v == AMGS_HP) && (p == AMGS_FP64 || p == AMGS_FP32);
+}
+
+// Algorithmic HBM bytes of one sweep at step j (see the design notes): each
+// later column is read and written once (read only at j = 0), plus the
+// vectors q_{j-1}, z_j, x_j (or p_j) read and q_j, p_j written.
+double sweep_bytes(int64_t m, int64_t n, int64_t j, size_t w, int variant)
+{
+    const double ncols = (double)(n - j - 1);
+    const double per_col = (j > 0 ? 2.0 : 1.0) * (double)m * (double)w;
+    double vec = 2.0 + (j > 0 ? 1.0 : 0.0) + (variant == VAR_NAIVE ? 0.0 : 1.0) + 1.0;
+    return ncols * per_col + vec * (double)m * (double)w;
+}
+
+template <typename T>
+amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
+{
+    const size_t w = sizeof(T);
+    amgs_stats_t &st = h->stats;
+    st = amgs_stats_t{};
+    launch_init<T>(c, c.Z != c.Q);
+    st.kernel_launches++;
+    const double mvA = c.is_dense ? (double)c.m * (double)c.m * w
+                                  : (double)c.nnz * (w + 4) + 4.0 * (double)(c.m + 1);
+    if (variant == VAR_HP) {
+        ProfScope ps(h, 2, c.stream);
+        if (c.is_dense) launch_dense_gemm<T>(c);
+        else launch_csr_spmm<T>(c);
+        st.kernel_launches++;
+        st.mv_calls += 1;
+        st.mv_columns += c.n;
+        st.mv_bytes += mvA + 2.0 * (double)c.m * c.n * w;
+    }
+    for (int64_t j = 0; j < c.n; ++j) {
+        int64_t n_rr;
+        {
+            ProfScope ps(h, 1, c.stream);
+            if (variant == VAR_HP) {
+                if (reorth && j > 0) {
+                    launch_col_hp<T>(c, j, true);
+                    launch_reorth_fin(c, j);
+                    launch_reorth_b<T>(c, j, true);
+                    st.kernel_launches += 3;
+                } else {
+                    launch_col_hp<T>(c, j, false);
+                    st.kernel_launches += 1;
+                }
+                n_rr = c.geo.g_rows;
+            } else {
+                if (reorth && j > 0) {
+                    launch_reorth_a<T>(c, j);
+                    launch_reorth_fin(c, j);
+                    launch_reorth_b<T>(c, j, false);
+                    launch_mv<T>(c, j, SRC_VEC);
+                    st.kernel_launches += 4;
+                } else {
+                    launch_mv<T>(c, j, SRC_UPD);
+                    st.kernel_launches += 1;
+                }
+                st.mv_calls += 1;
+                st.mv_columns += 1;
+                st.mv_bytes += mvA + 2.0 * (double)c.m * w;
+                if (variant == VAR_NAIVE) {
+                    launch_mv<T>(c, j, SRC_DIV);
+                    st.kernel_launches += 1;
+                    st.mv_calls += 1;
+                    st.mv_columns += 1;
+                    st.mv_bytes += mvA + 2.0 * (double)c.m * w;
+                }
+                n_rr = c.n_rr_mv;
+            }
+        }
+        {
+            ProfScope ps(h, 0, c.stream);
+            launch_sweep<T>(c, j, variant, n_rr);
+        }
+        st.kernel_launches++;
+        st.sweep_launches++;
+        st.sweep_bytes += sweep_bytes(c.m, c.n, j, w, variant);
+    }
+    if (hipGetLastError() != hipSuccess) return AMGS_ERR_HIP;
+    return AMGS_OK;
+}
+
+amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision_t p,
+                        const amgs_opts_t *o, void *work, size_t work_bytes, int P_given)
+{
+    const int reorth = o ? (o->reorth != 0) : 0;
+    const size_t w = p == AMGS_FP64 ? 8 : 4;
+    c.geo = make_geo(c.m, c.nnz, c.is_dense);
+    Layout L = layout(c.m, c.n, c.geo, (int)v, w, P_given, reorth);
+    if (!work || work_bytes < L.total) return AMGS_ERR_WORKSPACE;
+    char *base = (char *)work;
+    c.sp.part = base + L.part;
+    c.sp.g = c.geo.g_rows;
+    c.s_part = (double *)(base + L.s_part);
+    c.rr_part = (double *)(base + L.rr_part);
+    c.S = (double *)(base + L.S);
+    c.zt = base + L.zt;
+    c.xv = base + L.xv;
+    c.X = v == AMGS_HP ? (void *)(base + L.X) : nullptr;
+    if (!P_given) {
+        c.P = base + L.P;
+        c.ldp = c.m;
+    }
+    c.n_rr_mv = c.is_dense ? c.geo.g_dense : c.geo.g_csr;
+    DeviceGuard dg(h->device);
+    return p == AMGS_FP64 ? run_single<double>(h, c, (int)v, reorth)
+                          : run_single<float>(h, c, (int)v, reorth);
+}
+
+bool common_args_ok(amgs_handle_t h, int64_t m, int64_t n, const void *Z, int64_t ldz,
+                    const void *Q, int64_t ldq, const double *R, int64_t ldr, const void *P,
+                    int64_t ldp, amgs_variant_t v, amgs_precision_t p, const int32_t *info)
+{
+    if (!h || m < 0 || n < 0 || n > m || !valid_enums(v, p)) return false;
+    if (n == 0) return true;
+    if (!Z || !Q || !R || !info) return false;
+    if (ldz < m || ldq < m || ldr < n) return false;
+    if (P && ldp < m) return false;
+    if (Z == Q && ldz != ldq) return false;
+    if (m > (int64_t)0x7fffffff) return false; // int32 row indices in CSR
+    return true;
+}
+
+} // namespace
+
+namespace amgs {
+Geo make_geo(int64_t m, int64_t nnz, int is_dense)
+{
+    Geo g{};
+    const int64_t cap = 256 * 1024;
+    g.U = m <= cap ? 1 : m <= 2 * cap ? 2 : m <= 4 * cap ? 4 : 8;
+    g.g_rows = (m + 256 * g.U - 1) / (256 * g.U);
+    if (g.g_rows < 1) g.g_rows = 1;
+    const double avg = m > 0 ? (double)nnz / (double)m : 0.0;
+    g.lanes = avg <= 12 ? 1 : avg <= 24 ? 2 : avg <= 48 ? 4 : avg <= 96 ? 8 : avg <= 192 ? 16
+            : avg <= 384 ? 32 : 64;
+    const int64_t rows_per_wg = 512 / g.lanes;
+    g.g_csr = (m + rows_per_wg - 1) / rows_per_wg;
+    if (g.g_csr > MAX_G_MV) g.g_csr = MAX_G_MV;
+    if (g.g_csr < 1) g.g_csr = 1;
+    g.g_dense = (m + DENSE_CB - 1) / DENSE_CB;
+    if (g.g_dense > MAX_G_MV) g.g_dense = MAX_G_MV;
+    if (g.g_dense < 1) g.g_dense = 1;
+    (void)is_dense;
+    return g;
+}
+} // namespace amgs
+
+extern "C" {
+
+amgs_status_t amgs_create(amgs_handle_t *out, int device)
+{
+    if (!out) return AMGS_ERR_ARG;
+    *out = nullptr;
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || device < 0 || device >= count) return AMGS_ERR_ARG;
+    amgs_handle *h = new (std::nothrow) amgs_handle();
+    if (!h) return AMGS_ERR_HIP;
+    h->device = device;
+    h->num_cu = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) h->num_cu = prop.multiProcessorCount;
+    h->stats = amgs_stats_t{};
+    h->profiling = 0;
+    for (int i = 0; i < 3; ++i) {
+        h->prof_ms[i] = 0.0;
+        h->prof_n[i] = 0;
+    }
+    *out = h;
+    return AMGS_OK;
+}
+
+amgs_status_t amgs_destroy(amgs_handle_t h)
+{
+    if (!h) return AMGS_ERR_ARG;
+    for (auto &r : h->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : h->pool) (void)hipEventDestroy(e);
+    delete h;
+    return AMGS_OK;
+}
+
+size_t amgs_workspace_bytes(amgs_handle_t h, int64_t m, int64_t n, int32_t is_dense,
+                            amgs_variant_t v, amgs_precision_t p, int32_t P_given,
+                            const amgs_opts_t *o)
+{
+    if (!h || m < 0 || n < 0 || n > m || !valid_enums(v, p)) return 0;
+    if (n == 0) return 0;
+    // nnz only selects the CSR lane count, which does not change any size
+    Geo g = make_geo(m, is_dense ? 0 : m, is_dense);
+    Layout L = layout(m, n, g, (int)v, p == AMGS_FP64 ? 8 : 4, P_given, o ? o->reorth != 0 : 0);
+    return L.total;
+}
+
+amgs_status_t amgs_qr_csr(amgs_handle_t h, int64_t m, int64_t nnz, const int32_t *row_ptr,
+                          const int32_t *col_idx, const void *vals, int64_t n, const void *Z,
+                          int64_t ldz, void *Q, int64_t ldq, double *R, int64_t ldr, void *P,
+                          int64_t ldp, amgs_variant_t v, amgs_precision_t p,
+                          const amgs_opts_t *o, void *work, size_t work_bytes, int32_t *info,
+                          void *stream)
+{
+    if (!common_args_ok(h, m, n, Z, ldz, Q, ldq, R, ldr, P, ldp, v, p, info)) return AMGS_ERR_ARG;
+    if (nnz < 0 || nnz > (int64_t)0x7fffffff) return AMGS_ERR_ARG;
+    if (n == 0) return AMGS_OK;
+    if (!row_ptr || (nnz > 0 && (!col_idx || !vals))) return AMGS_ERR_ARG;
+    Ctx c{};
+    c.m = m; c.n = n; c.is_dense = 0;
+    c.row_ptr = row_ptr; c.col_idx = col_idx; c.vals = vals; c.nnz = nnz;
+    c.Z = Z; c.ldz = ldz; c.Q = Q; c.ldq = ldq; c.R = R; c.ldr = ldr;
+    c.P = P; c.ldp = ldp; c.info = info; c.stream = (hipStream_t)stream;
+    return qr_common(h, c, v, p, o, work, work_bytes, P != nullptr);
+}
+
+amgs_status_t amgs_qr_dense(amgs_handle_t h, int64_t m, const void *A, int64_t lda, int64_t n,
+                            const void *Z, int64_t ldz, void *Q, int64_t ldq, double *R,
+                            int64_t ldr, void *P, int64_t ldp, amgs_variant_t v,
+                            amgs_precision_t p, const amgs_opts_t *o, void *work,
+                            size_t work_bytes, int32_t *info, void *stream)
+{
+    if (!common_args_ok(h, m, n, Z, ldz, Q, ldq, R, ldr, P, ldp, v, p, info)) return AMGS_ERR_ARG;
+    if (n == 0) return AMGS_OK;
+    if (!A || lda < m) return AMGS_ERR_ARG;
+    Ctx c{};
+    c.m = m; c.n = n; c.is_dense = 1; c.A = A; c.lda = lda; c.nnz = m * m;
+    c.Z = Z; c.ldz = ldz; c.Q = Q; c.ldq = ldq; c.R = R; c.ldr = ldr;
+    c.P = P; c.ldp = ldp; c.info = info; c.stream = (hipStream_t)stream;
+    return qr_common(h, c, v, p, o, work, work_bytes, P != nullptr);
+}
+
+amgs_status_t amgs_csr_check(amgs_handle_t h, int64_t m, int64_t nnz, const int32_t *row_ptr,
+                             const int32_t *col_idx, int32_t *flag, void *stream)
+{
+    if (!h || m < 0 || nnz < 0 || !row_ptr || !flag || (nnz > 0 && !col_idx)) return AMGS_ERR_ARG;
+    DeviceGuard dg(h->device);
+    launch_csr_check(m, nnz, row_ptr, col_idx, flag, (hipStream_t)stream);
+    return hipGetLastError() == hipSuccess ? AMGS_OK : AMGS_ERR_HIP;
+}
+
+amgs_status_t amgs_get_stats(amgs_handle_t h, amgs_stats_t *out)
+{
+    if (!h || !out) return AMGS_ERR_ARG;
+    *out = h->stats;
+    return AMGS_OK;
+}
+
+const char *amgs_status_string(amgs_status_t s)
+{
+    switch (s) {
+    case AMGS_OK: return "ok";
+    case AMGS_ERR_ARG: return "invalid argument";
+    case AMGS_ERR_WORKSPACE: return "workspace too small";
+    case AMGS_ERR_HIP: return "HIP launch or runtime error";
+    case AMGS_ERR_UNSUPPORTED: return "unsupported";
+    }
+    return "unknown status";
+}
+
+amgs_status_t amgs_profile_enable(amgs_handle_t h, int32_t on)
+{
+    if (!h) return AMGS_ERR_ARG;
+    h->profiling = on ? 1 : 0;
+    return AMGS_OK;
+}
+
+amgs_status_t amgs_profile_read(amgs_handle_t h, int32_t category, double *total_ms,
+                                int64_t *launches)
+{
+    if (!h || category < 0 || category > 2) return AMGS_ERR_ARG;
+    DeviceGuard dg(h->device);
+    for (auto &r : h->recs) {
+        if (hipEventSynchronize(r.b) != hipSuccess) return AMGS_ERR_HIP;
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return AMGS_ERR_HIP;
+        h->prof_ms[r.cat] += ms;
+        h->prof_n[r.cat] += 1;
+        h->pool.push_back(r.a);
+        h->pool.push_back(r.b);
+    }
+    h->recs.clear();
+    if (total_ms) *total_ms = h->prof_ms[category];
+    if (launches) *launches = h->prof_n[category];
+    return AMGS_OK;
+}
+
+amgs_status_t amgs_profile_reset(amgs_handle_t h)
+{
+    if (!h) return AMGS_ERR_ARG;
+    double ms;
+    int64_t n;
+    amgs_status_t s = amgs_profile_read(h, 0, &ms, &n);
+    for (int i = 0; i < 3; ++i) {
+        h->prof_ms[i] = 0.0;
+        h->prof_n[i] = 0;
+    }
+    return s;
+}
+
+} // extern "C"

@@ -1,0 +1,68 @@
+// amgs_device.h -- device helpers shared by the library's HIP kernels.
+//
+// Reductions are deterministic: every sum is taken in a fixed order that does
+// not depend on timing, so repeated runs return identical bits and every
+// workgroup that re-reduces the same partials obtains the same value.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace amgs {
+
+constexpr int WAVE = 64;
+
+// z - r*q with one rounding (the projection update z_j -= r_ij q_i,
+// eq. (AXPY)).  Every kernel applies the update through this function, so a
+// value recomputed on the fly equals the stored one bit for bit.
+__device__ __forceinline__ double upd(double z, double r, double q) { return __builtin_fma(-r, q, z); }
+__device__ __forceinline__ float upd(float z, float r, float q) { return __builtin_fmaf(-r, q, z); }
+
+// Scaling q = z / r_jj (eq. (scaling)) in binary64, rounded once to storage.
+template <typename T>
+__device__ __forceinline__ T scale_div(T z, double r) { return (T)((double)z / r); }
+
+// Butterfly sum over a wave; every lane ends with the same bits because each
+// stage adds the same two operands (in commuted order) on both partners.
+template <typename A>
+__device__ __forceinline__ A wave_sum(A v)
+{
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
+    return v;
+}
+
+// Canonical reduction of v[0..N): lane l adds v[l], v[l+64], ... in
+// ascending order, then the butterfly.  Any wave of any workgroup calling it
+// on the same data gets the same bits.
+template <typename A>
+__device__ __forceinline__ A wave_reduce_seq(const A *__restrict__ v, int64_t N)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    A s0 = 0, s1 = 0;
+    int64_t i = lane;
+    for (; i + WAVE < N; i += 2 * WAVE) {
+        s0 += v[i];
+        s1 += v[i + WAVE];
+    }
+    if (i < N) s0 += v[i];
+    return wave_sum(s0 + s1);
+}
+
+// Sum over a workgroup of NT threads: wave butterflies, then the NT/64 wave
+// results added in wave order by every thread.  `lds` holds NT/64 entries.
+template <typename A, int NT>
+__device__ __forceinline__ A block_sum(A v, A *lds)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x & (WAVE - 1)) == 0) lds[threadIdx.x / WAVE] = v;
+    __syncthreads();
+    A t = lds[0];
+#pragma unroll
+    for (int w = 1; w < NT / WAVE; ++w) t += lds[w];
+    __syncthreads();
+    return t;
+}
+
+__device__ __forceinline__ bool norm_ok(double rr) { return rr > 0.0 && rr <= 1.7976931348623157e308; }
+
+} // namespace amgs

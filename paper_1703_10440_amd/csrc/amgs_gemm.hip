@@ -1,0 +1,142 @@
+// amgs_gemm.hip -- the HP block product X = A Z for dense A on the matrix
+// cores (Alg. 6, first line: the n MV of the method issued as one
+// matrix-matrix product, which Section 2.3 expects to run much faster than
+// n sequential MV).
+//
+// A is symmetric and column-major, so X[k, c] = sum_l A[l, k] Z[l, c]: both
+// operands are contiguous along the contraction index l.  A workgroup of
+// four waves computes a 64 x 64 tile of X; each wave owns a 32 x 32 block as
+// 2 x 2 MFMA 16x16 tiles (v_mfma_f64_16x16x4f64 in binary64,
+// v_mfma_f32_16x16x4f32 in binary32).  K is consumed in slabs of 16 staged
+// through LDS (double-buffered), loaded with 16-byte vector reads.
+#include "amgs_device.h"
+#include "amgs_internal.h"
+
+namespace amgs {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+// Result rows: register v of lane l holds row 4*v + l/16 for the binary64
+// instruction and row 4*(l/16) + v for the binary32 one (column l%16 in
+// both), as measured on gfx950.
+template <> struct Mfma<double> {
+    typedef d4 acc_t;
+    static __device__ __forceinline__ acc_t op(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <> struct Mfma<float> {
+    typedef f4 acc_t;
+    static __device__ __forceinline__ acc_t op(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
+constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
+
+// Operand layout of the 16x16x4 instructions: lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; result rows follow Mfma<T>::row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_gemm_atb(int64_t m, int64_t n, const T *__restrict__ A,
+                                                  int64_t lda, const T *__restrict__ Z,
+                                                  int64_t ldz, T *__restrict__ X, int64_t ldx)
+{
+    typedef typename Mfma<T>::acc_t acc_t;
+    // LDS: [buffer][k][col], padded by one element per row against bank
+    // conflicts between the four k rows read by one instruction.
+    __shared__ T As[2][GB_K][GB_M + 1];
+    __shared__ T Bs[2][GB_K][GB_N + 1];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int64_t m0 = (int64_t)blockIdx.x * GB_M;   // rows of X (= columns of A)
+    const int64_t n0 = (int64_t)blockIdx.y * GB_N;   // columns of X (= columns of Z)
+    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+
+    // each thread stages 4 consecutive k values of one column, for A and Z
+    const int lc = tid >> 2;            // column within the tile, 0..63
+    const int lk = (tid & 3) * 4;       // first k of the thread's 4
+    const bool a_ok = m0 + lc < m, b_ok = n0 + lc < n;
+    const T *__restrict__ Acol = A + (a_ok ? (m0 + lc) : 0) * lda;
+    const T *__restrict__ Zcol = Z + (b_ok ? (n0 + lc) : 0) * ldz;
+
+    acc_t acc[2][2];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc[a][b][v] = 0;
+
+    T ra[4], rb[4];
+    auto gload = [&](int64_t k0) {
+        const bool full = k0 + GB_K <= m;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int64_t k = k0 + lk + t;
+            const bool kin = full || k < m;
+            ra[t] = (a_ok && kin) ? Acol[k] : (T)0;
+            rb[t] = (b_ok && kin) ? Zcol[k] : (T)0;
+        }
+    };
+    auto lstore = [&](int buf) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            As[buf][lk + t][lc] = ra[t];
+            Bs[buf][lk + t][lc] = rb[t];
+        }
+    };
+    const int64_t nk = (m + GB_K - 1) / GB_K;
+    gload(0);
+    lstore(0);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int buf = (int)(kt & 1);
+        if (kt + 1 < nk) gload((kt + 1) * GB_K);
+#pragma unroll
+        for (int ks = 0; ks < GB_K; ks += 4) {
+            const int kk = ks + (lane >> 4);
+            T av[2], bv[2];
+#pragma unroll
+            for (int a = 0; a < 2; ++a) av[a] = As[buf][kk][wm + a * 16 + (lane & 15)];
+#pragma unroll
+            for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kk][wn + b * 16 + (lane & 15)];
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::op(av[a], bv[b], acc[a][b]);
+        }
+        if (kt + 1 < nk) {
+            lstore(buf ^ 1);
+        }
+        __syncthreads();
+    }
+    // store each 16x16 tile
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int64_t row = m0 + wm + a * 16 + Mfma<T>::row(lane, v);
+                const int64_t col = n0 + wn + b * 16 + (lane & 15);
+                if (row < m && col < n) X[row + col * ldx] = acc[a][b][v];
+            }
+}
+
+template <typename T>
+void launch_dense_gemm(const Ctx &c)
+{
+    const dim3 grid((unsigned)((c.m + GB_M - 1) / GB_M), (unsigned)((c.n + GB_N - 1) / GB_N));
+    hipLaunchKernelGGL(k_gemm_atb<T>, grid, dim3(256), 0, c.stream, c.m, c.n, (const T *)c.A,
+                       c.lda, (const T *)c.Q, c.ldq, (T *)c.X, c.m);
+}
+
+template void launch_dense_gemm<double>(const Ctx &);
+template void launch_dense_gemm<float>(const Ctx &);
+
+} // namespace amgs

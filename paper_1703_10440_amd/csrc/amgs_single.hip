@@ -1,0 +1,766 @@
+// amgs_single.hip -- kernels of the single-problem A-orthonormalising MGS.
+//
+// Schedule.  Column j of the column-oriented algorithms (Alg. 3 naive,
+// Alg. 5 HA, Alg. 6 HP) needs, in order: the projections r_ij = p_i^T z_j,
+// z_j -= r_ij q_i for i < j; its vector x_j (one MV for naive/HA, the
+// recurrence of eq. (tec2) for HP); r_jj = sqrt(z_j^T x_j); q_j = z_j / r_jj
+// and p_j (x_j / r_jj by eq. (tec1), or A q_j for naive).  The library runs
+// the same per-column operations right-looking (the order of Alg. 4/7/8):
+// at step j one "sweep" kernel normalises column j and then passes once over
+// every later column c, applying the pending update by q_{j-1}
+// (z_c -= r_{j-1,c} q_{j-1}) and forming the partial dots p_j^T z_c.  A
+// "column" kernel in between applies the last update to column j+1 and
+// builds its x vector and its squared A-norm partials.  Two launches per
+// column (three for naive, whose second MV p_j = A q_j has its own kernel).
+//
+// Reductions never use atomics or grid-wide barriers: a kernel writes one
+// partial per workgroup, and the next kernel re-reduces those partials in a
+// fixed order (every workgroup that needs a scalar reduces it itself, with
+// identical bits).  The column kernel also publishes the finished r_{j-1,c}
+// of the previous sweep into R, spread over its workgroups.
+#include "amgs_device.h"
+#include "amgs_internal.h"
+
+namespace amgs {
+
+// ----------------------------------------------------------------- init
+// Q <- Z (unless aliased), R <- 0, info <- 0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_init(int64_t m, int64_t n, const T *__restrict__ Z,
+                                              int64_t ldz, T *__restrict__ Q, int64_t ldq,
+                                              double *__restrict__ R, int64_t ldr, int32_t *info,
+                                              int copy)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (copy)
+        for (int64_t e = t0; e < m * n; e += stride) {
+            int64_t j = e / m, k = e - j * m;
+            Q[k + j * ldq] = Z[k + j * ldz];
+        }
+    for (int64_t e = t0; e < n * n; e += stride) {
+        int64_t j = e / n, i = e - j * n;
+        R[i + j * ldr] = 0.0;
+    }
+    if (t0 == 0) *info = 0;
+}
+
+// ------------------------------------------------- publish finished r_{j-1,c}
+// Spread over all waves of the launching grid: wave w of the grid finalises
+// columns c = c0 + w, c0 + w + nwaves, ... from the previous sweep's partials.
+template <typename T>
+__device__ __forceinline__ void publish_row(const SweepPart &sp, int64_t jrow, int64_t c0,
+                                            int64_t n, double *__restrict__ R, int64_t ldr)
+{
+    const T *part = (const T *)sp.part;
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    for (int64_t c = c0 + w; c < n; c += nw) {
+        T s = wave_reduce_seq(part + c * sp.g, sp.g);
+        if ((threadIdx.x & (WAVE - 1)) == 0) R[jrow + c * ldr] = (double)s;
+    }
+}
+
+// ------------------------------------------------------- CSR MV (column kernel)
+// y = A s where s is, per SRC:
+//   SRC_UPD  s = z_j - r q_{j-1} computed on the fly (r = r_{j-1,j} re-reduced
+//            from the previous sweep); the own-row value is also stored in zt;
+//   SRC_VEC  s = src;
+//   SRC_DIV  s = src / r_jj rounded to storage (r_jj re-reduced from rr
+//            partials): the naive second MV p_j = A q_j.
+// With RR, also writes this workgroup's partial of s^T y (binary64).
+template <typename T, int L, int SRC, bool RR>
+__global__ __launch_bounds__(512) void k_csr_mv(CsrMvArgs a)
+{
+    __shared__ double lds[512 / WAVE];
+    if (*a.info) return;
+    const T *__restrict__ vals = (const T *)a.vals;
+    const T *__restrict__ src = (const T *)a.src;
+    const T *__restrict__ qprev = (const T *)a.qprev;
+    T *__restrict__ y = (T *)a.y;
+    T *__restrict__ zt = (T *)a.zt;
+
+    T r = 0;
+    double rjj = 1.0;
+    if (SRC == SRC_UPD && qprev) {
+        r = wave_reduce_seq((const T *)a.sp.part + a.j * a.sp.g, a.sp.g);
+        publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
+    }
+    if (SRC == SRC_DIV) {
+        double rr = wave_reduce_seq(a.rr_part, a.n_rr);
+        if (!norm_ok(rr)) return;
+        rjj = sqrt(rr);
+    }
+    auto load = [&](int64_t l) -> T {
+        T v = src[l];
+        if (SRC == SRC_UPD && qprev) v = upd(v, r, qprev[l]);
+        if (SRC == SRC_DIV) v = scale_div(v, rjj);
+        return v;
+    };
+    const int gpw = 512 / L;                   // rows per workgroup pass
+    const int g = threadIdx.x / L, lig = threadIdx.x % L;
+    double acc = 0.0;
+    for (int64_t row = (int64_t)blockIdx.x * gpw + g; row < a.m; row += (int64_t)gridDim.x * gpw) {
+        const int32_t e0 = a.row_ptr[row], e1 = a.row_ptr[row + 1];
+        T s = 0;
+        for (int32_t e = e0 + lig; e < e1; e += L) s += vals[e] * load(a.col_idx[e]);
+#pragma unroll
+        for (int off = L / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, L);
+        if (lig == 0) {
+            y[row] = s;
+            if (SRC == SRC_UPD || RR) {
+                T zs = load(row);
+                if (SRC == SRC_UPD) zt[row] = zs;
+                if (RR) acc += (double)zs * (double)s;
+            }
+        }
+    }
+    if (RR) {
+        double t = block_sum<double, 512>(acc, lds);
+        if (threadIdx.x == 0) a.rr_out[blockIdx.x] = t;
+    }
+}
+
+// ----------------------------------------------------- dense MV (column kernel)
+// Same contract as k_csr_mv for a dense symmetric column-major A: output
+// entry k is the dot of column k of A with s.  A workgroup owns CB outputs at
+// a time; its 256 threads stride down the columns (coalesced), each thread
+// keeps CB accumulators, then a fixed-order workgroup reduction.
+template <typename T, int CB, int SRC, bool RR>
+__global__ __launch_bounds__(256) void k_dense_mv(DenseMvArgs a)
+{
+    __shared__ T red[256 / WAVE][CB];
+    __shared__ double lds[256 / WAVE];
+    if (*a.info) return;
+    const T *__restrict__ A = (const T *)a.A;
+    const T *__restrict__ src = (const T *)a.src;
+    const T *__restrict__ qprev = (const T *)a.qprev;
+    T *__restrict__ y = (T *)a.y;
+    T *__restrict__ zt = (T *)a.zt;
+    T r = 0;
+    double rjj = 1.0;
+    if (SRC == SRC_UPD && qprev) {
+        r = wave_reduce_seq((const T *)a.sp.part + a.j * a.sp.g, a.sp.g);
+        publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
+    }
+    if (SRC == SRC_DIV) {
+        double rr = wave_reduce_seq(a.rr_part, a.n_rr);
+        if (!norm_ok(rr)) return;
+        rjj = sqrt(rr);
+    }
+    auto load = [&](int64_t l) -> T {
+        T v = src[l];
+        if (SRC == SRC_UPD && qprev) v = upd(v, r, qprev[l]);
+        if (SRC == SRC_DIV) v = scale_div(v, rjj);
+        return v;
+    };
+    const int tid = threadIdx.x, wave = tid / WAVE;
+    double acc_rr = 0.0;
+    for (int64_t k0 = (int64_t)blockIdx.x * CB; k0 < a.m; k0 += (int64_t)gridDim.x * CB) {
+        const int nc = (int)(a.m - k0 < CB ? a.m - k0 : CB);
+        T acc[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c) acc[c] = 0;
+        const T *__restrict__ Ak = A + k0 * a.lda;
+        if (nc == CB) {
+            for (int64_t l = tid; l < a.m; l += 256) {
+                const T s = load(l);
+#pragma unroll
+                for (int c = 0; c < CB; ++c) acc[c] += Ak[l + c * a.lda] * s;
+            }
+        } else {
+            for (int64_t l = tid; l < a.m; l += 256) {
+                const T s = load(l);
+#pragma unroll
+                for (int c = 0; c < CB; ++c)
+                    if (c < nc) acc[c] += Ak[l + c * a.lda] * s;
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CB; ++c) {
+            T v = wave_sum(acc[c]);
+            if ((tid & (WAVE - 1)) == 0) red[wave][c] = v;
+        }
+        __syncthreads();
+        if (tid < nc) {
+            T s = red[0][tid];
+#pragma unroll
+            for (int w = 1; w < 256 / WAVE; ++w) s += red[w][tid];
+            y[k0 + tid] = s;
+            if (SRC == SRC_UPD || RR) {
+                T zs = load(k0 + tid);
+                if (SRC == SRC_UPD) zt[k0 + tid] = zs;
+                if (RR) acc_rr += (double)zs * (double)s;
+            }
+        }
+        __syncthreads();
+    }
+    if (RR) {
+        double t = block_sum<double, 256>(acc_rr, lds);
+        if (tid == 0) a.rr_out[blockIdx.x] = t;
+    }
+}
+
+// ------------------------------------------------------ HP column kernel
+// Row-local: z_j -= r_{j-1,j} q_{j-1} in place, then the recurrence of
+// eq. (tec2), x_j = x_j^{(0)} - sum_{i<j} r_ij p_i with i ascending, in
+// place in X, and the partial of z_j^T x_j.  With REORTH_A it instead stops
+// after the recurrence and writes partials of s_i = p_i^T z_j (binary64)
+// for the second pass (no A-norm yet).
+template <typename T, int U, bool REORTH_A>
+__global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
+{
+    __shared__ double lds[256 / WAVE];
+    __shared__ double red[256 / WAVE][4];
+    if (*a.info) return;
+    const int64_t j = a.j;
+    T *__restrict__ Q = (T *)a.Q;
+    T *__restrict__ X = (T *)a.X;
+    const T *__restrict__ P = (const T *)a.P;
+    T r = 0;
+    if (j > 0) {
+        r = wave_reduce_seq((const T *)a.sp.part + j * a.sp.g, a.sp.g);
+        publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
+    }
+    const int tid = threadIdx.x;
+    const int64_t row0 = (int64_t)blockIdx.x * 256 * U;
+    T zr[U], xr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = row0 + u * 256 + tid;
+        zr[u] = 0;
+        xr[u] = 0;
+        if (k < a.m) {
+            T z = Q[k + j * a.ldq];
+            if (j > 0) {
+                z = upd(z, r, Q[k + (j - 1) * a.ldq]);
+                Q[k + j * a.ldq] = z;
+            }
+            zr[u] = z;
+        }
+    }
+    // x recurrence, i ascending; r_ij (i < j-1) were published by earlier
+    // column kernels, r_{j-1,j} is the value re-reduced above.
+    {
+        T x[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = row0 + u * 256 + tid;
+            x[u] = k < a.m ? X[k + j * a.ldx] : (T)0;
+        }
+        for (int64_t i = 0; i < j; ++i) {
+            const T ri = (i == j - 1) ? r : (T)a.R[i + j * a.ldr];
+            const T *__restrict__ Pi = P + i * a.ldp;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t k = row0 + u * 256 + tid;
+                if (k < a.m) x[u] = upd(x[u], ri, Pi[k]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = row0 + u * 256 + tid;
+            if (k < a.m) X[k + j * a.ldx] = x[u];
+            xr[u] = x[u];
+        }
+    }
+    if (!REORTH_A) {
+        double acc = 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc += (double)zr[u] * (double)xr[u];
+        double t = block_sum<double, 256>(acc, lds);
+        if (tid == 0) a.rr_out[blockIdx.x] = t;
+    } else {
+        // partials of s_i = p_i^T z_j, four i at a time
+        const int wave = tid / WAVE;
+        for (int64_t i0 = 0; i0 < j; i0 += 4) {
+            double s[4] = {0, 0, 0, 0};
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                if (i0 + t < j) {
+                    const T *__restrict__ Pi = P + (i0 + t) * a.ldp;
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int64_t k = row0 + u * 256 + tid;
+                        if (k < a.m) s[t] += (double)Pi[k] * (double)zr[u];
+                    }
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                double v = wave_sum(s[t]);
+                if ((tid & (WAVE - 1)) == 0) red[wave][t] = v;
+            }
+            __syncthreads();
+            if (tid < 4 && i0 + tid < j) {
+                double v = red[0][tid];
+#pragma unroll
+                for (int w = 1; w < 256 / WAVE; ++w) v += red[w][tid];
+                a.s_part[(i0 + tid) * gridDim.x + blockIdx.x] = v;
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// ------------------------------------- second pass, step A for naive / HA
+// zt = z_j - r_{j-1,j} q_{j-1} (row local) and partials of s_i = p_i^T zt.
+template <typename T, int U>
+__global__ __launch_bounds__(256) void k_reorth_a(RowArgs a)
+{
+    __shared__ double red[256 / WAVE][4];
+    if (*a.info) return;
+    const int64_t j = a.j;
+    const T *__restrict__ Q = (const T *)a.Q;
+    const T *__restrict__ P = (const T *)a.P;
+    T *__restrict__ zt = (T *)a.zt;
+    T r = 0;
+    if (j > 0) {
+        r = wave_reduce_seq((const T *)a.sp.part + j * a.sp.g, a.sp.g);
+        publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
+    }
+    const int tid = threadIdx.x, wave = tid / WAVE;
+    const int64_t row0 = (int64_t)blockIdx.x * 256 * U;
+    T zr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = row0 + u * 256 + tid;
+        zr[u] = 0;
+        if (k < a.m) {
+            T z = Q[k + j * a.ldq];
+            if (j > 0) z = upd(z, r, Q[k + (j - 1) * a.ldq]);
+            zt[k] = z;
+            zr[u] = z;
+        }
+    }
+    for (int64_t i0 = 0; i0 < j; i0 += 4) {
+        double s[4] = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (i0 + t < j) {
+                const T *__restrict__ Pi = P + (i0 + t) * a.ldp;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t k = row0 + u * 256 + tid;
+                    if (k < a.m) s[t] += (double)Pi[k] * (double)zr[u];
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            double v = wave_sum(s[t]);
+            if ((tid & (WAVE - 1)) == 0) red[wave][t] = v;
+        }
+        __syncthreads();
+        if (tid < 4 && i0 + tid < j) {
+            double v = red[0][tid];
+#pragma unroll
+            for (int w = 1; w < 256 / WAVE; ++w) v += red[w][tid];
+            a.s_part[(i0 + tid) * gridDim.x + blockIdx.x] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// ----------------------------------------------- second pass: finish s_i
+// Wave w of the grid handles coefficient i = w: S[i] = sum of its partials,
+// and r_ij += S[i].
+__global__ __launch_bounds__(256) void k_reorth_fin(const double *__restrict__ s_part,
+                                                    int64_t g, int64_t j, double *__restrict__ S,
+                                                    double *__restrict__ R, int64_t ldr,
+                                                    const int32_t *info)
+{
+    if (*info) return;
+    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    if (i >= j) return;
+    double s = wave_reduce_seq(s_part + i * g, g);
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        S[i] = s;
+        R[i + j * ldr] = R[i + j * ldr] + s;
+    }
+}
+
+// ------------------------------------- second pass, step B (all variants)
+// z_j <- z_j - sum_i S_i q_i and (HP) x_j <- x_j - sum_i S_i p_i, binary64
+// accumulation, rounded once; HP also forms the A-norm partials.
+template <typename T, int U, bool HP>
+__global__ __launch_bounds__(256) void k_reorth_b(RowArgs a)
+{
+    __shared__ double lds[256 / WAVE];
+    if (*a.info) return;
+    const int64_t j = a.j;
+    const T *__restrict__ Q = (const T *)a.Q;
+    const T *__restrict__ P = (const T *)a.P;
+    T *__restrict__ zv = HP ? (T *)a.Q + j * a.ldq : (T *)a.zt;
+    T *__restrict__ xv = HP ? (T *)a.X + j * a.ldx : nullptr;
+    const int tid = threadIdx.x;
+    const int64_t row0 = (int64_t)blockIdx.x * 256 * U;
+    double zd[U], xd[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = row0 + u * 256 + tid;
+        zd[u] = k < a.m ? (double)zv[k] : 0.0;
+        xd[u] = (HP && k < a.m) ? (double)xv[k] : 0.0;
+    }
+    for (int64_t i = 0; i < j; ++i) {
+        const double s = a.S[i];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = row0 + u * 256 + tid;
+            if (k < a.m) {
+                zd[u] -= s * (double)Q[k + i * a.ldq];
+                if (HP) xd[u] -= s * (double)P[k + i * a.ldp];
+            }
+        }
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = row0 + u * 256 + tid;
+        if (k < a.m) {
+            const T z = (T)zd[u];
+            zv[k] = z;
+            if (HP) {
+                const T x = (T)xd[u];
+                xv[k] = x;
+                acc += (double)z * (double)x;
+            }
+        }
+    }
+    if (HP) {
+        double t = block_sum<double, 256>(acc, lds);
+        if (tid == 0) a.rr_out[blockIdx.x] = t;
+    }
+}
+
+// ------------------------------------------------------------ sweep
+// Step j: r_jj from the A-norm partials (breakdown -> info = j+1); column j
+// normalised: q_j = z_j / r_jj, p_j = x_j / r_jj (HA, HP; eq. (tec1)) or
+// p_j = A q_j already formed (naive).  Then for every later column c owned
+// by this workgroup (CPW columns per grid row y):
+//     z_c <- z_c - r_{j-1,c} q_{j-1}     (update of step j-1)
+//     partial of r_{j,c} = p_j^T z_c     (dot of step j)
+// with z_c read and written once.
+template <typename T, int U, int CPW, int VAR>
+__global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
+{
+    __shared__ T red[256 / WAVE][CPW];
+    if (*a.info) return;
+    const int64_t j = a.j, m = a.m;
+    T *__restrict__ Q = (T *)a.Q;
+    T *__restrict__ P = (T *)a.P;
+    const double rr = wave_reduce_seq(a.rr_part, a.n_rr);
+    if (!norm_ok(rr)) {
+        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.info = (int32_t)(j + 1);
+        return;
+    }
+    const double rjj = sqrt(rr);
+    const int tid = threadIdx.x, wave = tid / WAVE;
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) a.R[j + j * a.ldr] = rjj;
+    const int64_t row0 = (int64_t)blockIdx.x * 256 * U;
+    const T *__restrict__ zsrc = VAR == VAR_HP ? Q + j * a.ldq : (const T *)a.zt;
+    const T *__restrict__ xsrc = VAR == VAR_HP ? (const T *)a.X + j * a.ldx : (const T *)a.xv;
+    const bool own = blockIdx.y == 0;
+    T p[U], qp[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = row0 + u * 256 + tid;
+        p[u] = 0;
+        qp[u] = 0;
+        if (k < m) {
+            T pv;
+            if (VAR == VAR_NAIVE) pv = P[k + j * a.ldp];
+            else pv = scale_div(xsrc[k], rjj);
+            if (own) {
+                // only the owning workgroup reads z_j: for HP it is
+                // overwritten in place by q_j
+                Q[k + j * a.ldq] = scale_div(zsrc[k], rjj);
+                if (VAR != VAR_NAIVE) P[k + j * a.ldp] = pv;
+            }
+            p[u] = pv;
+            if (j > 0) qp[u] = Q[k + (j - 1) * a.ldq];
+        }
+    }
+    const int64_t c0 = j + 1 + (int64_t)blockIdx.y * CPW;
+    const int64_t c1 = (c0 + CPW < a.n) ? c0 + CPW : a.n;
+    if (c0 >= c1) return;
+    const bool full_rows = row0 + 256 * U <= m;
+    for (int64_t cb = c0; cb < c1; cb += 4) {
+        T r[4], acc[4];
+        T zv[4][U];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            acc[t] = 0;
+            r[t] = (j > 0 && cb + t < c1) ? (T)a.R[(j - 1) + (cb + t) * a.ldr] : (T)0;
+        }
+        // issue all loads first
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const T *__restrict__ Zc = Q + (cb + t) * a.ldq;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t k = row0 + u * 256 + tid;
+                zv[t][u] = (cb + t < c1 && (full_rows || k < m)) ? Zc[k] : (T)0;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            T *__restrict__ Zc = Q + (cb + t) * a.ldq;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t k = row0 + u * 256 + tid;
+                if (cb + t < c1 && (full_rows || k < m)) {
+                    T z = zv[t][u];
+                    if (j > 0) {
+                        z = upd(z, r[t], qp[u]);
+                        Zc[k] = z;
+                    }
+                    acc[t] += p[u] * z;
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            T v = wave_sum(acc[t]);
+            if ((tid & (WAVE - 1)) == 0 && cb + t < c1) red[wave][cb - c0 + t] = v;
+        }
+    }
+    __syncthreads();
+    if (tid < c1 - c0) {
+        T s = red[0][tid];
+#pragma unroll
+        for (int w = 1; w < 256 / WAVE; ++w) s += red[w][tid];
+        ((T *)a.sp.part)[(c0 + tid) * a.sp.g + blockIdx.x] = s;
+    }
+}
+
+// ------------------------------------------------- HP block product, CSR
+// X = A Z for all n columns (Alg. 6, first line): A is read once per group
+// of 8 columns; thread per row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_csr_spmm(int64_t m, int64_t n, const int32_t *__restrict__ row_ptr,
+                                                  const int32_t *__restrict__ col_idx,
+                                                  const T *__restrict__ vals, const T *__restrict__ Z,
+                                                  int64_t ldz, T *__restrict__ X, int64_t ldx)
+{
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t c0 = (int64_t)blockIdx.y * 8;
+    if (row >= m) return;
+    const int32_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
+    T acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0;
+    const int nc = (int)(n - c0 < 8 ? n - c0 : 8);
+    for (int32_t e = e0; e < e1; ++e) {
+        const T v = vals[e];
+        const int64_t l = col_idx[e];
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+            if (c < nc) acc[c] += v * Z[l + (c0 + c) * ldz];
+    }
+#pragma unroll
+    for (int c = 0; c < 8; ++c)
+        if (c < nc) X[row + (c0 + c) * ldx] = acc[c];
+}
+
+// --------------------------------------------------------- CSR validation
+__global__ __launch_bounds__(256) void k_csr_check(int64_t m, int64_t nnz, const int32_t *__restrict__ row_ptr,
+                                                   const int32_t *__restrict__ col_idx,
+                                                   int32_t *flag)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    bool bad = false;
+    if (t0 == 0) bad = row_ptr[0] != 0 || row_ptr[m] != nnz;
+    for (int64_t k = t0; k < m; k += stride) bad |= row_ptr[k + 1] < row_ptr[k];
+    for (int64_t e = t0; e < nnz; e += stride) bad |= col_idx[e] < 0 || col_idx[e] >= m;
+    if (bad) *flag = 1;
+}
+
+__global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
+
+// ====================================================================
+// Host launchers
+// ====================================================================
+template <typename T>
+void launch_init(const Ctx &c, int copy)
+{
+    int64_t work = copy ? c.m * c.n : c.n * c.n;
+    int64_t blocks = (work + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_init<T>, dim3((unsigned)blocks), dim3(256), 0, c.stream, c.m, c.n,
+                       (const T *)c.Z, c.ldz, (T *)c.Q, c.ldq, c.R, c.ldr, c.info, copy);
+}
+
+template <typename T, int SRC, bool RR>
+static void launch_csr_mv_L(const Ctx &c, CsrMvArgs &a)
+{
+    const dim3 grid((unsigned)c.geo.g_csr), block(512);
+    switch (c.geo.lanes) {
+    case 1: hipLaunchKernelGGL((k_csr_mv<T, 1, SRC, RR>), grid, block, 0, c.stream, a); break;
+    case 2: hipLaunchKernelGGL((k_csr_mv<T, 2, SRC, RR>), grid, block, 0, c.stream, a); break;
+    case 4: hipLaunchKernelGGL((k_csr_mv<T, 4, SRC, RR>), grid, block, 0, c.stream, a); break;
+    case 8: hipLaunchKernelGGL((k_csr_mv<T, 8, SRC, RR>), grid, block, 0, c.stream, a); break;
+    case 16: hipLaunchKernelGGL((k_csr_mv<T, 16, SRC, RR>), grid, block, 0, c.stream, a); break;
+    case 32: hipLaunchKernelGGL((k_csr_mv<T, 32, SRC, RR>), grid, block, 0, c.stream, a); break;
+    default: hipLaunchKernelGGL((k_csr_mv<T, 64, SRC, RR>), grid, block, 0, c.stream, a); break;
+    }
+}
+
+// MV of the column kernel / naive second MV.  src_mode: SRC_UPD (column
+// kernel, builds zt and x), SRC_VEC (after the second pass), SRC_DIV (naive
+// p_j = A q_j).
+template <typename T>
+void launch_mv(const Ctx &c, int64_t j, int src_mode)
+{
+    const T *Q = (const T *)c.Q;
+    if (c.is_dense) {
+        DenseMvArgs a{};
+        a.m = c.m; a.n = c.n; a.j = j; a.A = c.A; a.lda = c.lda;
+        a.info = c.info; a.R = c.R; a.ldr = c.ldr; a.sp = c.sp;
+        a.rr_part = c.rr_part; a.n_rr = c.n_rr_mv; a.rr_out = c.rr_part;
+        if (src_mode == SRC_UPD) {
+            a.src = Q + j * c.ldq; a.qprev = j > 0 ? Q + (j - 1) * c.ldq : nullptr;
+            a.y = c.xv; a.zt = c.zt;
+            hipLaunchKernelGGL((k_dense_mv<T, DENSE_CB, SRC_UPD, true>), dim3((unsigned)c.geo.g_dense),
+                               dim3(256), 0, c.stream, a);
+        } else if (src_mode == SRC_VEC) {
+            a.src = c.zt; a.y = c.xv;
+            hipLaunchKernelGGL((k_dense_mv<T, DENSE_CB, SRC_VEC, true>), dim3((unsigned)c.geo.g_dense),
+                               dim3(256), 0, c.stream, a);
+        } else {
+            a.src = c.zt; a.y = (T *)c.P + j * c.ldp;
+            hipLaunchKernelGGL((k_dense_mv<T, DENSE_CB, SRC_DIV, false>), dim3((unsigned)c.geo.g_dense),
+                               dim3(256), 0, c.stream, a);
+        }
+    } else {
+        CsrMvArgs a{};
+        a.m = c.m; a.n = c.n; a.j = j; a.row_ptr = c.row_ptr; a.col_idx = c.col_idx; a.vals = c.vals;
+        a.info = c.info; a.R = c.R; a.ldr = c.ldr; a.sp = c.sp;
+        a.rr_part = c.rr_part; a.n_rr = c.n_rr_mv; a.rr_out = c.rr_part;
+        if (src_mode == SRC_UPD) {
+            a.src = Q + j * c.ldq; a.qprev = j > 0 ? Q + (j - 1) * c.ldq : nullptr;
+            a.y = c.xv; a.zt = c.zt;
+            launch_csr_mv_L<T, SRC_UPD, true>(c, a);
+        } else if (src_mode == SRC_VEC) {
+            a.src = c.zt; a.y = c.xv;
+            launch_csr_mv_L<T, SRC_VEC, true>(c, a);
+        } else {
+            a.src = c.zt; a.y = (T *)c.P + j * c.ldp;
+            launch_csr_mv_L<T, SRC_DIV, false>(c, a);
+        }
+    }
+}
+
+static RowArgs row_args(const Ctx &c, int64_t j)
+{
+    RowArgs a{};
+    a.m = c.m; a.n = c.n; a.j = j; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp;
+    a.X = c.X; a.ldx = c.m; a.zt = c.zt; a.R = c.R; a.ldr = c.ldr; a.info = c.info;
+    a.sp = c.sp; a.rr_out = c.rr_part; a.s_part = c.s_part; a.S = c.S;
+    return a;
+}
+
+#define AMGS_DISPATCH_U(U_, ...)                                                                  \
+    switch (U_) {                                                                                 \
+    case 1: { constexpr int UU = 1; __VA_ARGS__; } break;                                         \
+    case 2: { constexpr int UU = 2; __VA_ARGS__; } break;                                         \
+    case 4: { constexpr int UU = 4; __VA_ARGS__; } break;                                         \
+    default: { constexpr int UU = 8; __VA_ARGS__; } break;                                        \
+    }
+
+template <typename T>
+void launch_col_hp(const Ctx &c, int64_t j, bool reorth_a)
+{
+    RowArgs a = row_args(c, j);
+    const dim3 grid((unsigned)c.geo.g_rows), block(256);
+    if (reorth_a) {
+        AMGS_DISPATCH_U(c.geo.U, hipLaunchKernelGGL((k_col_hp<T, UU, true>), grid, block, 0, c.stream, a));
+    } else {
+        AMGS_DISPATCH_U(c.geo.U, hipLaunchKernelGGL((k_col_hp<T, UU, false>), grid, block, 0, c.stream, a));
+    }
+}
+
+template <typename T>
+void launch_reorth_a(const Ctx &c, int64_t j)
+{
+    RowArgs a = row_args(c, j);
+    const dim3 grid((unsigned)c.geo.g_rows), block(256);
+    AMGS_DISPATCH_U(c.geo.U, hipLaunchKernelGGL((k_reorth_a<T, UU>), grid, block, 0, c.stream, a));
+}
+
+void launch_reorth_fin(const Ctx &c, int64_t j)
+{
+    const int64_t blocks = (j + 3) / 4;
+    hipLaunchKernelGGL(k_reorth_fin, dim3((unsigned)blocks), dim3(256), 0, c.stream,
+                       (const double *)c.s_part, c.geo.g_rows, j, c.S, c.R, c.ldr, c.info);
+}
+
+template <typename T>
+void launch_reorth_b(const Ctx &c, int64_t j, bool hp)
+{
+    RowArgs a = row_args(c, j);
+    const dim3 grid((unsigned)c.geo.g_rows), block(256);
+    if (hp) {
+        AMGS_DISPATCH_U(c.geo.U, hipLaunchKernelGGL((k_reorth_b<T, UU, true>), grid, block, 0, c.stream, a));
+    } else {
+        AMGS_DISPATCH_U(c.geo.U, hipLaunchKernelGGL((k_reorth_b<T, UU, false>), grid, block, 0, c.stream, a));
+    }
+}
+
+template <typename T>
+void launch_sweep(const Ctx &c, int64_t j, int variant, int64_t n_rr)
+{
+    SweepArgs a{};
+    a.m = c.m; a.n = c.n; a.j = j; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp;
+    a.X = c.X; a.ldx = c.m; a.zt = c.zt; a.xv = c.xv; a.R = c.R; a.ldr = c.ldr;
+    a.info = c.info; a.sp = c.sp; a.rr_part = c.rr_part; a.n_rr = n_rr;
+    const int64_t ncols = c.n - j - 1;
+    const int64_t gy = ncols > 0 ? (ncols + SWEEP_CPW - 1) / SWEEP_CPW : 1;
+    const dim3 grid((unsigned)c.geo.g_rows, (unsigned)gy), block(256);
+#define AMGS_SWEEP_V(V_)                                                                          \
+    AMGS_DISPATCH_U(c.geo.U, hipLaunchKernelGGL((k_sweep<T, UU, SWEEP_CPW, V_>), grid, block, 0,  \
+                                                c.stream, a))
+    if (variant == VAR_NAIVE) { AMGS_SWEEP_V(VAR_NAIVE); }
+    else if (variant == VAR_HA) { AMGS_SWEEP_V(VAR_HA); }
+    else { AMGS_SWEEP_V(VAR_HP); }
+#undef AMGS_SWEEP_V
+}
+
+template <typename T>
+void launch_csr_spmm(const Ctx &c)
+{
+    const dim3 grid((unsigned)((c.m + 255) / 256), (unsigned)((c.n + 7) / 8)), block(256);
+    hipLaunchKernelGGL(k_csr_spmm<T>, grid, block, 0, c.stream, c.m, c.n, c.row_ptr, c.col_idx,
+                       (const T *)c.vals, (const T *)c.Q, c.ldq, (T *)c.X, c.m);
+}
+
+void launch_csr_check(int64_t m, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
+                      int32_t *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_set_i32, dim3(1), dim3(1), 0, s, flag, 0);
+    int64_t work = m > nnz ? m : nnz;
+    int64_t blocks = (work + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    if (blocks < 1) blocks = 1;
+    hipLaunchKernelGGL(k_csr_check, dim3((unsigned)blocks), dim3(256), 0, s, m, nnz, row_ptr,
+                       col_idx, flag);
+}
+
+template void launch_init<double>(const Ctx &, int);
+template void launch_init<float>(const Ctx &, int);
+template void launch_mv<double>(const Ctx &, int64_t, int);
+template void launch_mv<float>(const Ctx &, int64_t, int);
+template void launch_col_hp<double>(const Ctx &, int64_t, bool);
+template void launch_col_hp<float>(const Ctx &, int64_t, bool);
+template void launch_reorth_a<double>(const Ctx &, int64_t);
+template void launch_reorth_a<float>(const Ctx &, int64_t);
+template void launch_reorth_b<double>(const Ctx &, int64_t, bool);
+template void launch_reorth_b<float>(const Ctx &, int64_t, bool);
+template void launch_sweep<double>(const Ctx &, int64_t, int, int64_t);
+template void launch_sweep<float>(const Ctx &, int64_t, int, int64_t);
+template void launch_csr_spmm<double>(const Ctx &);
+template void launch_csr_spmm<float>(const Ctx &);
+
+} // namespace amgs
