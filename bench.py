@@ -137,6 +137,8 @@ def main():
     ap.add_argument("--workload", default="lap64_n64")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--variant", default="hp", choices=["naive", "ha", "hp"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -154,7 +156,7 @@ def main():
     data = to_device(prob, dev, torch)
     log(f"[bench] m={prob.m} n={prob.n}")
 
-    head_variant, head_prec = "hp", "fp64"
+    head_variant, head_prec = args.variant, args.precision
     run = Runner(prob, data, head_variant, head_prec, torch, amgs)
     t, out = time_steps(run, args.steps, args.warmup, torch)
     info = int(out.info.item())
@@ -195,7 +197,7 @@ def main():
     line = {"metric": METRIC, "value": round(prob.n / t, 2), "unit": "cols/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t * 1e3, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f64", "data": "synthetic", "config": cfg, "roofline": roof,
+            "dtype": "f64" if head_prec == "fp64" else "f32", "data": "synthetic", "config": cfg, "roofline": roof,
             "cpu_baseline": cpu, "variants": variants}
     print(json.dumps(line), flush=True)
 

@@ -262,3 +262,113 @@ def csr_check(row_ptr, col_idx, m: int) -> bool:
     _check(amgs_csr_check(h, m, int(col_idx.numel()), row_ptr.data_ptr(), col_idx.data_ptr(),
                           flag.data_ptr(), s), "amgs_csr_check")
     return int(flag.item()) == 0
+
+
+# ------------------------------------------------------------------ batched
+def amgs_batch_plan_create(h, batch, m_arr, n_arr, variant, precision, opts, autotune) -> int:
+    plan = _vp()
+    M = (_i64 * max(batch, 1))(*m_arr)
+    N = (_i64 * max(batch, 1))(*n_arr)
+    _check(load().amgs_batch_plan_create(h, batch, M, N, variant, precision,
+                                         C.byref(opts) if opts is not None else None,
+                                         autotune, C.byref(plan)), "amgs_batch_plan_create")
+    return plan.value
+
+
+def amgs_batch_plan_destroy(plan) -> int:
+    return load().amgs_batch_plan_destroy(plan)
+
+
+def amgs_batch_workspace_bytes(plan) -> int:
+    return int(load().amgs_batch_workspace_bytes(plan))
+
+
+def amgs_qr_batched(plan, desc_ptr, work_ptr, work_bytes, info_ptr, stream) -> int:
+    return load().amgs_qr_batched(plan, desc_ptr, work_ptr, work_bytes, info_ptr, stream)
+
+
+def amgs_batch_plan_tiles(plan):
+    out = (_i32 * 16)()
+    k = load().amgs_batch_plan_tiles(plan, out, 16)
+    return [out[i] for i in range(k)]
+
+
+class BatchPlan:
+    """A plan for one list of instance shapes (see amgs_batch_plan_create)."""
+
+    def __init__(self, ms, ns, variant="ha", precision="fp64", reorth=False, autotune=False,
+                 device=0):
+        self.h = handle(device)
+        self.batch = len(ms)
+        self.variant, self.precision = variant, precision
+        self.opts = Opts(int(bool(reorth)), 0, 0, 0)
+        self.plan = amgs_batch_plan_create(self.h, self.batch, list(ms), list(ns),
+                                           VARIANTS[variant], PRECISIONS[precision], self.opts,
+                                           int(bool(autotune)))
+
+    def workspace_bytes(self) -> int:
+        return amgs_batch_workspace_bytes(self.plan)
+
+    def tiles(self):
+        return amgs_batch_plan_tiles(self.plan)
+
+    def run(self, desc, work, info, stream=None):
+        torch = _torch()
+        s = stream if stream is not None else torch.cuda.current_stream(desc.device).cuda_stream
+        _check(amgs_qr_batched(self.plan, desc.data_ptr(), work.data_ptr() if work is not None
+                               else None, work.numel() if work is not None else 0,
+                               info.data_ptr(), s), "amgs_qr_batched")
+
+    def __del__(self):
+        try:
+            if getattr(self, "plan", None):
+                amgs_batch_plan_destroy(self.plan)
+        except Exception:
+            pass
+
+
+def pack_descriptors(items, device):
+    """items: list of dicts with device tensors row_ptr, col_idx, vals, Z, Q, R
+    (Z, Q column-major m x n; R column-major n x n float64).  Returns a device
+    uint8 tensor holding the amgs_batch_desc_t array."""
+    torch = _torch()
+    arr = (BatchDesc * max(len(items), 1))()
+    for k, it in enumerate(items):
+        Z, Q, R = it["Z"], it["Q"], it["R"]
+        m, n = Z.shape
+        arr[k] = BatchDesc(m, n, int(it["vals"].numel()), it["row_ptr"].data_ptr(),
+                           it["col_idx"].data_ptr(), it["vals"].data_ptr(), Z.data_ptr(),
+                           max(Z.stride(1), m), Q.data_ptr(), max(Q.stride(1), m), R.data_ptr(),
+                           max(R.stride(1), n))
+    raw = bytes(arr)[: C.sizeof(BatchDesc) * len(items)]
+    host = torch.frombuffer(bytearray(raw), dtype=torch.uint8)
+    return host.to(device)
+
+
+def qr_batched(instances, variant="ha", precision="fp64", reorth=False, autotune=False,
+               plan=None, stream=None):
+    """instances: list of (row_ptr, col_idx, vals, Z) device tensors (CSR A, Z
+    m x n).  Returns (Qs, Rs, info, plan)."""
+    torch = _torch()
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    dev = instances[0][3].device
+    items, Qs, Rs = [], [], []
+    for rp, ci, va, Z in instances:
+        Zc = colmajor(Z, dt)
+        m, n = Zc.shape
+        Q = empty_colmajor(m, n, dt, dev)
+        R = empty_colmajor(n, n, torch.float64, dev)
+        items.append(dict(row_ptr=rp.to(torch.int32).contiguous(),
+                          col_idx=ci.to(torch.int32).contiguous(),
+                          vals=va.to(dt).contiguous(), Z=Zc, Q=Q, R=R))
+        Qs.append(Q)
+        Rs.append(R)
+    if plan is None:
+        plan = BatchPlan([it["Z"].shape[0] for it in items], [it["Z"].shape[1] for it in items],
+                         variant, precision, reorth, autotune, dev.index or 0)
+    desc = pack_descriptors(items, dev)
+    work = torch.empty(max(plan.workspace_bytes(), 1), dtype=torch.uint8, device=dev)
+    info = torch.full((len(items),), -7, dtype=torch.int32, device=dev)
+    plan.run(desc, work, info, stream)
+    # keep the operands alive with the outputs
+    return Qs, Rs, info, plan, (items, desc, work)

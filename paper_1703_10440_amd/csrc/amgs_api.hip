@@ -9,21 +9,7 @@
 #include "../../include/amgs.h"
 #include "amgs_internal.h"
 #include "amgs_batched.h"
-
-struct amgs_handle {
-    int device;
-    int num_cu;
-    amgs_stats_t stats;
-    int profiling;
-    struct Rec {
-        int cat;
-        hipEvent_t a, b;
-    };
-    std::vector<Rec> recs;        // recorded since the last read/reset
-    std::vector<hipEvent_t> pool; // idle events
-    double prof_ms[3];
-    int64_t prof_n[3];
-};
+#include "amgs_handle.h"
 
 namespace {
 
@@ -185,6 +171,10 @@ amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
             launch_sweep<T>(c, j, variant, n_rr);
         }
         st.kernel_launches++;
+        if (variant == VAR_HP) {
+            ProfScope ps(h, 1, c.stream);
+            if (launch_hp_xblock<T>(c, j)) st.kernel_launches++;
+        }
         st.sweep_launches++;
         st.sweep_bytes += sweep_bytes(c.m, c.n, j, w, variant);
     }
@@ -239,7 +229,8 @@ namespace amgs {
 Geo make_geo(int64_t m, int64_t nnz, int is_dense)
 {
     Geo g{};
-    const int64_t cap = 256 * 1024;
+    // about 512 row chunks of 256*U rows (U <= 8)
+    const int64_t cap = 256 * 512;
     g.U = m <= cap ? 1 : m <= 2 * cap ? 2 : m <= 4 * cap ? 4 : 8;
     g.g_rows = (m + 256 * g.U - 1) / (256 * g.U);
     if (g.g_rows < 1) g.g_rows = 1;

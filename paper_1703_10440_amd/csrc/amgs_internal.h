@@ -8,8 +8,11 @@ namespace amgs {
 
 enum { VAR_NAIVE = 0, VAR_HA = 1, VAR_HP = 2 };
 enum { SRC_UPD = 0, SRC_VEC = 1, SRC_DIV = 2 };
-constexpr int SWEEP_CPW = 8;   // trailing columns per sweep workgroup
+constexpr int MAX_CPW = 256;   // trailing columns per sweep workgroup (max)
+constexpr int SWEEP_TARGET_WG = 1024; // sweep workgroups aimed for
+constexpr int HP_XB = 8;       // HP recurrence terms applied per blocked update
 constexpr int DENSE_CB = 16;   // outputs per dense-MV workgroup pass
+constexpr int SPMM_C = 8;      // columns per CSR block-product thread
 constexpr int MAX_G_MV = 512;  // partials of an MV column kernel
 
 // Partials of the projection sweep: part[c * g + w] holds workgroup w's part
@@ -90,6 +93,7 @@ struct SweepArgs {
     SweepPart sp;
     const double *rr_part;
     int64_t n_rr;
+    int64_t cpw;
 };
 
 // Everything one amgs_qr_* call needs on the host side.
@@ -133,6 +137,7 @@ template <typename T> void launch_reorth_a(const Ctx &c, int64_t j);
 void launch_reorth_fin(const Ctx &c, int64_t j);
 template <typename T> void launch_reorth_b(const Ctx &c, int64_t j, bool hp);
 template <typename T> void launch_sweep(const Ctx &c, int64_t j, int variant, int64_t n_rr);
+template <typename T> bool launch_hp_xblock(const Ctx &c, int64_t s);
 template <typename T> void launch_csr_spmm(const Ctx &c);
 template <typename T> void launch_dense_gemm(const Ctx &c);
 void launch_csr_check(int64_t m, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,

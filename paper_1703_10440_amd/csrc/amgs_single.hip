@@ -239,8 +239,9 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
             zr[u] = z;
         }
     }
-    // x recurrence, i ascending; r_ij (i < j-1) were published by earlier
-    // column kernels, r_{j-1,j} is the value re-reduced above.
+    // x recurrence, i ascending, terms i >= XB floor((j-1)/XB) (the earlier
+    // ones were applied by k_hp_xblock); r_ij (i < j-1) were published by
+    // earlier column kernels, r_{j-1,j} is the value re-reduced above.
     {
         T x[U];
 #pragma unroll
@@ -248,7 +249,8 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
             const int64_t k = row0 + u * 256 + tid;
             x[u] = k < a.m ? X[k + j * a.ldx] : (T)0;
         }
-        for (int64_t i = 0; i < j; ++i) {
+        const int64_t i0 = j > 0 ? HP_XB * ((j - 1) / HP_XB) : 0;
+        for (int64_t i = i0; i < j; ++i) {
             const T ri = (i == j - 1) ? r : (T)a.R[i + j * a.ldr];
             const T *__restrict__ Pi = P + i * a.ldp;
 #pragma unroll
@@ -437,52 +439,61 @@ __global__ __launch_bounds__(256) void k_reorth_b(RowArgs a)
 // Step j: r_jj from the A-norm partials (breakdown -> info = j+1); column j
 // normalised: q_j = z_j / r_jj, p_j = x_j / r_jj (HA, HP; eq. (tec1)) or
 // p_j = A q_j already formed (naive).  Then for every later column c owned
-// by this workgroup (CPW columns per grid row y):
+// by this workgroup (columns c0 .. c0+cpw-1 of grid row y):
 //     z_c <- z_c - r_{j-1,c} q_{j-1}     (update of step j-1)
 //     partial of r_{j,c} = p_j^T z_c     (dot of step j)
-// with z_c read and written once.
-template <typename T, int U, int CPW, int VAR>
+// with z_c read and written once.  One wave re-reduces the A-norm partials
+// and broadcasts r_jj through LDS.
+template <typename T, int U, int VAR>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 {
-    __shared__ T red[256 / WAVE][CPW];
+    __shared__ T red[256 / WAVE][MAX_CPW];
+    __shared__ double s_rr;
     if (*a.info) return;
     const int64_t j = a.j, m = a.m;
+    const int tid = threadIdx.x, wave = tid / WAVE;
     T *__restrict__ Q = (T *)a.Q;
     T *__restrict__ P = (T *)a.P;
-    const double rr = wave_reduce_seq(a.rr_part, a.n_rr);
-    if (!norm_ok(rr)) {
-        if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *a.info = (int32_t)(j + 1);
-        return;
-    }
-    const double rjj = sqrt(rr);
-    const int tid = threadIdx.x, wave = tid / WAVE;
-    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) a.R[j + j * a.ldr] = rjj;
     const int64_t row0 = (int64_t)blockIdx.x * 256 * U;
+    const bool own = blockIdx.y == 0;
     const T *__restrict__ zsrc = VAR == VAR_HP ? Q + j * a.ldq : (const T *)a.zt;
     const T *__restrict__ xsrc = VAR == VAR_HP ? (const T *)a.X + j * a.ldx : (const T *)a.xv;
-    const bool own = blockIdx.y == 0;
-    T p[U], qp[U];
+    // issue the vector loads before waiting for r_jj
+    T xs[U], zs[U], qp[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
-        p[u] = 0;
-        qp[u] = 0;
-        if (k < m) {
-            T pv;
-            if (VAR == VAR_NAIVE) pv = P[k + j * a.ldp];
-            else pv = scale_div(xsrc[k], rjj);
-            if (own) {
-                // only the owning workgroup reads z_j: for HP it is
-                // overwritten in place by q_j
-                Q[k + j * a.ldq] = scale_div(zsrc[k], rjj);
-                if (VAR != VAR_NAIVE) P[k + j * a.ldp] = pv;
-            }
-            p[u] = pv;
-            if (j > 0) qp[u] = Q[k + (j - 1) * a.ldq];
+        const bool in = k < m;
+        xs[u] = in ? (VAR == VAR_NAIVE ? P[k + j * a.ldp] : xsrc[k]) : (T)0;
+        zs[u] = (in && own) ? zsrc[k] : (T)0;
+        qp[u] = (in && j > 0) ? Q[k + (j - 1) * a.ldq] : (T)0;
+    }
+    if (wave == 0) {
+        const double rr = wave_reduce_seq(a.rr_part, a.n_rr);
+        if (tid == 0) s_rr = rr;
+    }
+    __syncthreads();
+    const double rr = s_rr;
+    if (!norm_ok(rr)) {
+        if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) *a.info = (int32_t)(j + 1);
+        return;
+    }
+    const double rjj = sqrt(rr);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) a.R[j + j * a.ldr] = rjj;
+    T p[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = row0 + u * 256 + tid;
+        p[u] = VAR == VAR_NAIVE ? xs[u] : scale_div(xs[u], rjj);
+        if (own && k < m) {
+            // only the owning workgroup reads z_j: for HP it is overwritten
+            // in place by q_j
+            Q[k + j * a.ldq] = scale_div(zs[u], rjj);
+            if (VAR != VAR_NAIVE) P[k + j * a.ldp] = p[u];
         }
     }
-    const int64_t c0 = j + 1 + (int64_t)blockIdx.y * CPW;
-    const int64_t c1 = (c0 + CPW < a.n) ? c0 + CPW : a.n;
+    const int64_t c0 = j + 1 + (int64_t)blockIdx.y * a.cpw;
+    const int64_t c1 = (c0 + a.cpw < a.n) ? c0 + a.cpw : a.n;
     if (c0 >= c1) return;
     const bool full_rows = row0 + 256 * U <= m;
     for (int64_t cb = c0; cb < c1; cb += 4) {
@@ -493,7 +504,6 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
             acc[t] = 0;
             r[t] = (j > 0 && cb + t < c1) ? (T)a.R[(j - 1) + (cb + t) * a.ldr] : (T)0;
         }
-        // issue all loads first
 #pragma unroll
         for (int t = 0; t < 4; ++t) {
             const T *__restrict__ Zc = Q + (cb + t) * a.ldq;
@@ -526,40 +536,100 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         }
     }
     __syncthreads();
-    if (tid < c1 - c0) {
-        T s = red[0][tid];
+    for (int64_t c = tid; c < c1 - c0; c += 256) {
+        T s = red[0][c];
 #pragma unroll
-        for (int w = 1; w < 256 / WAVE; ++w) s += red[w][tid];
-        ((T *)a.sp.part)[(c0 + tid) * a.sp.g + blockIdx.x] = s;
+        for (int w = 1; w < 256 / WAVE; ++w) s += red[w][c];
+        ((T *)a.sp.part)[(c0 + c) * a.sp.g + blockIdx.x] = s;
+    }
+}
+
+// ------------------------------------------- HP recurrence, blocked terms
+// At steps s = XB, 2 XB, ... the terms i = s-XB .. s-1 of eq. (tec2) are
+// applied to every later column: x_c <- x_c - r_ic p_i, i ascending.  The
+// column kernel of column j then only adds the terms i >= XB floor((j-1)/XB),
+// so every x_c receives its terms in ascending i, as in the sequential
+// recurrence, while each p_i is streamed once per block instead of once per
+// column.
+template <typename T>
+__global__ __launch_bounds__(256) void k_hp_xblock(int64_t m, int64_t n, int64_t s, int64_t cpw,
+                                                   const T *__restrict__ P, int64_t ldp,
+                                                   T *__restrict__ X, int64_t ldx,
+                                                   const double *__restrict__ R, int64_t ldr,
+                                                   const int32_t *info)
+{
+    if (*info) return;
+    const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t c0 = s + 1 + (int64_t)blockIdx.y * cpw;
+    const int64_t c1 = (c0 + cpw < n) ? c0 + cpw : n;
+    if (k >= m || c0 >= c1) return;
+    T pv[HP_XB];
+#pragma unroll
+    for (int i = 0; i < HP_XB; ++i) pv[i] = P[k + (s - HP_XB + i) * ldp];
+    int64_t c = c0;
+    for (; c + 4 <= c1; c += 4) {
+        T x[4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) x[t] = X[k + (c + t) * ldx];
+#pragma unroll
+        for (int i = 0; i < HP_XB; ++i)
+#pragma unroll
+            for (int t = 0; t < 4; ++t) x[t] = upd(x[t], (T)R[(s - HP_XB + i) + (c + t) * ldr], pv[i]);
+#pragma unroll
+        for (int t = 0; t < 4; ++t) X[k + (c + t) * ldx] = x[t];
+    }
+    for (; c < c1; ++c) {
+        T x = X[k + c * ldx];
+#pragma unroll
+        for (int i = 0; i < HP_XB; ++i) x = upd(x, (T)R[(s - HP_XB + i) + c * ldr], pv[i]);
+        X[k + c * ldx] = x;
     }
 }
 
 // ------------------------------------------------- HP block product, CSR
-// X = A Z for all n columns (Alg. 6, first line): A is read once per group
-// of 8 columns; thread per row.
+// X = A Z for all n columns (Alg. 6, first line).  Thread per row and grid
+// row y per group of SPMM_C columns; a row's entries are staged in registers
+// eight at a time so that all loads of Z for them are in flight together.
 template <typename T>
 __global__ __launch_bounds__(256) void k_csr_spmm(int64_t m, int64_t n, const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ col_idx,
                                                   const T *__restrict__ vals, const T *__restrict__ Z,
                                                   int64_t ldz, T *__restrict__ X, int64_t ldx)
 {
+    constexpr int C = SPMM_C;
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t c0 = (int64_t)blockIdx.y * 8;
+    const int64_t c0 = (int64_t)blockIdx.y * C;
     if (row >= m) return;
     const int32_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
-    T acc[8];
+    const int nc = (int)(n - c0 < C ? n - c0 : C);
+    const T *__restrict__ Zc = Z + c0 * ldz;
+    T acc[C];
 #pragma unroll
-    for (int c = 0; c < 8; ++c) acc[c] = 0;
-    const int nc = (int)(n - c0 < 8 ? n - c0 : 8);
-    for (int32_t e = e0; e < e1; ++e) {
-        const T v = vals[e];
-        const int64_t l = col_idx[e];
+    for (int c = 0; c < C; ++c) acc[c] = 0;
+    for (int32_t eb = e0; eb < e1; eb += 8) {
+        int64_t l[8];
+        T v[8];
 #pragma unroll
-        for (int c = 0; c < 8; ++c)
-            if (c < nc) acc[c] += v * Z[l + (c0 + c) * ldz];
+        for (int t = 0; t < 8; ++t) {
+            const bool in = eb + t < e1;
+            l[t] = in ? col_idx[eb + t] : 0;
+            v[t] = in ? vals[eb + t] : (T)0;
+        }
+        if (nc == C) {
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+#pragma unroll
+                for (int t = 0; t < 8; ++t) acc[c] += v[t] * Zc[l[t] + c * ldz];
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (c < nc)
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) acc[c] += v[t] * Zc[l[t] + c * ldz];
+        }
     }
 #pragma unroll
-    for (int c = 0; c < 8; ++c)
+    for (int c = 0; c < C; ++c)
         if (c < nc) X[row + (c0 + c) * ldx] = acc[c];
 }
 
@@ -709,6 +779,25 @@ void launch_reorth_b(const Ctx &c, int64_t j, bool hp)
     }
 }
 
+// Column groups of the sweep: enough workgroups to fill the chip even when
+// there are few row chunks; each group is a multiple of 4 columns.
+static void sweep_cols(const Ctx &c, int64_t ncols, int64_t &gy, int64_t &cpw)
+{
+    if (ncols <= 0) {
+        gy = 1;
+        cpw = 4;
+        return;
+    }
+    gy = (SWEEP_TARGET_WG + c.geo.g_rows - 1) / c.geo.g_rows;
+    const int64_t max_gy = (ncols + 3) / 4;
+    if (gy > max_gy) gy = max_gy;
+    if (gy < 1) gy = 1;
+    cpw = (ncols + gy - 1) / gy;
+    cpw = (cpw + 3) / 4 * 4;
+    if (cpw > MAX_CPW) cpw = MAX_CPW;
+    gy = (ncols + cpw - 1) / cpw;
+}
+
 template <typename T>
 void launch_sweep(const Ctx &c, int64_t j, int variant, int64_t n_rr)
 {
@@ -716,12 +805,12 @@ void launch_sweep(const Ctx &c, int64_t j, int variant, int64_t n_rr)
     a.m = c.m; a.n = c.n; a.j = j; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp;
     a.X = c.X; a.ldx = c.m; a.zt = c.zt; a.xv = c.xv; a.R = c.R; a.ldr = c.ldr;
     a.info = c.info; a.sp = c.sp; a.rr_part = c.rr_part; a.n_rr = n_rr;
-    const int64_t ncols = c.n - j - 1;
-    const int64_t gy = ncols > 0 ? (ncols + SWEEP_CPW - 1) / SWEEP_CPW : 1;
+    int64_t gy, cpw;
+    sweep_cols(c, c.n - j - 1, gy, cpw);
+    a.cpw = cpw;
     const dim3 grid((unsigned)c.geo.g_rows, (unsigned)gy), block(256);
 #define AMGS_SWEEP_V(V_)                                                                          \
-    AMGS_DISPATCH_U(c.geo.U, hipLaunchKernelGGL((k_sweep<T, UU, SWEEP_CPW, V_>), grid, block, 0,  \
-                                                c.stream, a))
+    AMGS_DISPATCH_U(c.geo.U, hipLaunchKernelGGL((k_sweep<T, UU, V_>), grid, block, 0, c.stream, a))
     if (variant == VAR_NAIVE) { AMGS_SWEEP_V(VAR_NAIVE); }
     else if (variant == VAR_HA) { AMGS_SWEEP_V(VAR_HA); }
     else { AMGS_SWEEP_V(VAR_HP); }
@@ -729,9 +818,27 @@ void launch_sweep(const Ctx &c, int64_t j, int variant, int64_t n_rr)
 }
 
 template <typename T>
+bool launch_hp_xblock(const Ctx &c, int64_t s)
+{
+    if (s < HP_XB || s % HP_XB != 0 || s + 1 >= c.n) return false;
+    const int64_t ncols = c.n - s - 1;
+    const int64_t gx = (c.m + 255) / 256;
+    int64_t gy = (SWEEP_TARGET_WG + gx - 1) / gx;
+    const int64_t max_gy = (ncols + 3) / 4;
+    if (gy > max_gy) gy = max_gy;
+    if (gy < 1) gy = 1;
+    int64_t cpw = (ncols + gy - 1) / gy;
+    gy = (ncols + cpw - 1) / cpw;
+    hipLaunchKernelGGL(k_hp_xblock<T>, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, c.stream,
+                       c.m, c.n, s, cpw, (const T *)c.P, c.ldp, (T *)c.X, c.m, c.R, c.ldr, c.info);
+    return true;
+}
+
+template <typename T>
 void launch_csr_spmm(const Ctx &c)
 {
-    const dim3 grid((unsigned)((c.m + 255) / 256), (unsigned)((c.n + 7) / 8)), block(256);
+    const dim3 grid((unsigned)((c.m + 255) / 256), (unsigned)((c.n + SPMM_C - 1) / SPMM_C)),
+        block(256);
     hipLaunchKernelGGL(k_csr_spmm<T>, grid, block, 0, c.stream, c.m, c.n, c.row_ptr, c.col_idx,
                        (const T *)c.vals, (const T *)c.Q, c.ldq, (T *)c.X, c.m);
 }
@@ -760,6 +867,8 @@ template void launch_reorth_b<double>(const Ctx &, int64_t, bool);
 template void launch_reorth_b<float>(const Ctx &, int64_t, bool);
 template void launch_sweep<double>(const Ctx &, int64_t, int, int64_t);
 template void launch_sweep<float>(const Ctx &, int64_t, int, int64_t);
+template bool launch_hp_xblock<double>(const Ctx &, int64_t);
+template bool launch_hp_xblock<float>(const Ctx &, int64_t);
 template void launch_csr_spmm<double>(const Ctx &);
 template void launch_csr_spmm<float>(const Ctx &);
 
