@@ -1,21 +1,31 @@
 """Benchmark: A-orthonormalised columns per second on one MI355X.
 
 One step = one complete A-orthonormalisation Z = QR, Q^T A Q = I of the
-workload (every step of the method: block product or per-column MV,
-projections, A-norms, normalisation), inputs resident in device memory.
+workload, every step of the method included (block product or per-column
+MV, projections, A-norms, normalisation), with the inputs resident in device
+memory.  The headline line is the default workload:
 
-Default workload: 7-point 3-D Laplacian on a 64^3 grid plus 1e-2 I (CSR,
-m = 262144, nnz = 1,810,432), Z = 262144 x 64 with kappa(Z) ~ 1e6; the
-headline value is the HP form in binary64.  The same line also reports the
-naive 2n-MV form, the HA form and the binary32-storage forms, the roofline of
-the dominant kernel (the projection sweep), and the CPU oracle timed on the
-host.
+  lap64_n64      7-point 3-D Laplacian on a 64^3 grid + 1e-2 I (CSR,
+                 m = 262144, nnz = 1,810,432), Z 262144 x 64 with kappa(Z) ~ 1e6,
+                 HP form in binary64 (value), plus naive / HA / HP in binary64
+                 and in the binary32-storage form.
 
-    python bench.py [--steps K] [--warmup W] [--workload lap64_n64|lap128_n128|dense512_n32|dense16k_n256]
+Other workloads (same JSON shape, reported in the design notes):
+  lap128_n128    Laplacian 128^3 + 1e-2 I, Z 2097152 x 128, kappa(Z) ~ 1e4;
+                 binary32 form with and without the binary64 second pass vs
+                 binary64.
+  dense512_n32   dense spd 512 x 512 (B B^T/m + I), Z 512 x 32.
+  dense16k_n256  dense spd 16384 x 16384, Z 16384 x 256 (HP block product on
+                 the matrix cores).
+  batch2048      2048 independent pentadiagonal instances, m ~ U[64,4096],
+                 n ~ U[4,64], one persistent launch replayed from a HIP graph.
+
+    python bench.py [--steps K] [--warmup W] [--workload NAME]
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -26,12 +36,14 @@ sys.path.insert(0, ROOT)
 
 METRIC = "A-orthonormalised cols/s + %HBM roofline: HA/HP n-MV vs 2n-MV, FP64 vs FP32"
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_lap64_traffic.json")
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+# ----------------------------------------------------------------- workloads
 def make_problem(name, device):
     from paper_1703_10440_amd import inputs
     if name == "dense16k_n256":
@@ -54,33 +66,31 @@ def to_device(prob, dev, torch):
 class Runner:
     """Preallocated device buffers for repeated calls of one configuration."""
 
-    def __init__(self, prob, dev_data, variant, precision, torch, amgs):
+    def __init__(self, data, variant, precision, torch, amgs, reorth=False):
         self.torch, self.amgs = torch, amgs
-        self.prob = prob
         dt = torch.float64 if precision == "fp64" else torch.float32
-        self.dt = dt
-        self.variant, self.precision = variant, precision
-        self.Z = amgs.colmajor(dev_data["Z"], dt)
+        self.variant, self.precision, self.reorth = variant, precision, reorth
+        self.Z = amgs.colmajor(data["Z"], dt)
         m, n = self.Z.shape
         self.m, self.n = m, n
         self.Q = amgs.empty_colmajor(m, n, dt, self.Z.device)
         self.P = amgs.empty_colmajor(m, n, dt, self.Z.device)
-        self.dense = "A" in dev_data
+        self.dense = "A" in data
         if self.dense:
-            self.A = amgs.colmajor(dev_data["A"], dt)
+            self.A = amgs.colmajor(data["A"], dt)
         else:
-            self.rp, self.ci = dev_data["row_ptr"], dev_data["col_idx"]
-            self.vals = dev_data["vals"].to(dt)
+            self.rp, self.ci = data["row_ptr"], data["col_idx"]
+            self.vals = data["vals"].to(dt)
         h = amgs.handle(0)
-        opts = amgs.Opts(0, 0, 0, 0)
         wb = amgs.amgs_workspace_bytes(h, m, n, int(self.dense), amgs.VARIANTS[variant],
-                                       amgs.PRECISIONS[precision], 1, opts)
+                                       amgs.PRECISIONS[precision], 1,
+                                       amgs.Opts(int(reorth), 0, 0, 0))
         self.work = torch.empty(max(wb, 1), dtype=torch.uint8, device=self.Z.device)
 
     def __call__(self):
         a = self.amgs
         kw = dict(variant=self.variant, precision=self.precision, Q=self.Q, P=self.P,
-                  work=self.work)
+                  work=self.work, reorth=self.reorth)
         if self.dense:
             return a.qr_dense(self.A, self.Z, **kw)
         return a.qr_csr(self.rp, self.ci, self.vals, self.Z, **kw)
@@ -94,13 +104,41 @@ def time_steps(fn, steps, warmup, torch):
     for _ in range(steps):
         out = fn()
     torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    return dt / steps, out
+    return (time.perf_counter() - t0) / steps, out
+
+
+def accuracy(data, out, torch):
+    """||Q^T A Q - I||_2 and ||Z - QR||_F / ||Z||_F in binary64 (torch used
+    only to evaluate the metrics)."""
+    Q = out.Q.double()
+    R = out.R
+    Z = data["Z"].double()
+    if "A" in data:
+        AQ = data["A"].double() @ Q
+    else:
+        m = Q.shape[0]
+        S = torch.sparse_csr_tensor(data["row_ptr"].long(), data["col_idx"].long(),
+                                    data["vals"].double(), size=(m, m))
+        AQ = S @ Q
+    G = Q.T @ AQ
+    n = G.shape[0]
+    orth = torch.linalg.matrix_norm(G - torch.eye(n, dtype=G.dtype, device=G.device), ord=2)
+    res = torch.linalg.norm(Z - Q @ torch.triu(R)) / torch.linalg.norm(Z)
+    return float(orth), float(res)
+
+
+def source_sha():
+    h = hashlib.sha256()
+    for f in ("amgs_single.hip", "amgs_device.h", "amgs_internal.h"):
+        with open(os.path.join(ROOT, "paper_1703_10440_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
 
 
 def sweep_roofline(runner, amgs, torch):
-    """Average duration of the projection-sweep kernel, from HIP events the
-    library records on the call's stream, and its algorithmic bytes."""
+    """Average duration of the projection-sweep kernel from HIP events the
+    library records around each of its launches on the call's stream, and its
+    algorithmic bytes per launch."""
     h = amgs.handle(0)
     amgs.amgs_profile_reset(h)
     amgs.amgs_profile_enable(h, 1)
@@ -112,75 +150,71 @@ def sweep_roofline(runner, amgs, torch):
     avg_s = ms / 1e3 / max(launches, 1)
     bytes_per_launch = st.sweep_bytes / max(st.sweep_launches, 1)
     achieved = bytes_per_launch / avg_s / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        rec = json.load(open(TRAFFIC_FILE))
+        if rec.get("source_sha") == source_sha():
+            traffic = rec.get("traffic_bytes_per_launch")
     return {"bound": "hbm", "kernel": "k_sweep", "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": None, "avg_us": round(avg_s * 1e6, 3), "launches": int(launches),
+            "traffic": traffic, "avg_us": round(avg_s * 1e6, 3), "launches": int(launches),
             "bytes_per_launch": bytes_per_launch}
 
 
-def cpu_baseline(prob, variant):
+def cpu_baseline(prob, variant, budget_s=10.0):
+    """The oracle as it stands, repeated on the full workload until about
+    budget_s seconds of host time have passed."""
     from oracle import ref
-    t0 = time.perf_counter()
-    r = ref.qr_problem(prob, variant=variant)
-    dt = time.perf_counter() - t0
-    assert r.info == 0
-    return {"value": round(prob.n / dt, 2), "unit": "cols/s", "cores": ref.num_threads(),
-            "kind": "oracle",
-            "sample": f"full workload, {variant} binary64, one run of {dt:.2f} s"}
+    runs, total = 0, 0.0
+    while total < budget_s and runs < 1000:
+        t0 = time.perf_counter()
+        r = ref.qr_problem(prob, variant=variant)
+        total += time.perf_counter() - t0
+        runs += 1
+        assert r.info == 0
+        if total > 3 * budget_s:
+            break
+    return {"value": round(runs * prob.n / total, 2), "unit": "cols/s",
+            "cores": ref.num_threads(), "kind": "oracle",
+            "sample": f"full workload, {variant} binary64, {runs} run(s) in {total:.1f} s"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lap64_n64")
-    ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--variant", default="hp", choices=["naive", "ha", "hp"])
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only; --gpus {args.gpus} is not supported "
-              "(instances of the batched form shard across GPUs without exchange, but this "
-              "build measures one GPU).", file=sys.stderr)
-        sys.exit(2)
-
-    import numpy as np
-    import torch
-    from paper_1703_10440_amd import amgs
-    amgs.load()
+# -------------------------------------------------------------- single problem
+def bench_single(args, torch, amgs):
     dev = torch.device("cuda:0")
     log(f"[bench] building workload {args.workload}")
     prob = make_problem(args.workload, dev)
     data = to_device(prob, dev, torch)
     log(f"[bench] m={prob.m} n={prob.n}")
-
-    head_variant, head_prec = args.variant, args.precision
-    run = Runner(prob, data, head_variant, head_prec, torch, amgs)
+    big = prob.m * prob.m if prob.csr is None else prob.csr.nnz
+    head_v, head_p = args.variant, args.precision
+    run = Runner(data, head_v, head_p, torch, amgs)
     t, out = time_steps(run, args.steps, args.warmup, torch)
     info = int(out.info.item())
-    log(f"[bench] {head_variant}/{head_prec}: {t * 1e3:.3f} ms/step info={info}")
+    log(f"[bench] {head_v}/{head_p}: {t * 1e3:.3f} ms/step info={info}")
     roof = sweep_roofline(run, amgs, torch)
     log(f"[bench] sweep roofline {roof}")
+    del run
 
     variants = {}
     if not args.no_variants:
-        for prec in ("fp64", "fp32"):
-            for v in ("naive", "ha", "hp"):
-                r = Runner(prob, data, v, prec, torch, amgs)
-                steps = max(2, args.steps // 4) if v == "naive" else max(3, args.steps // 2)
-                tv, o = time_steps(r, steps, 1, torch)
-                Qn = o.Q.double()
-                variants[f"{v}_{prec}"] = {"cols_per_s": round(prob.n / tv, 1),
-                                           "ms": round(tv * 1e3, 4),
-                                           "info": int(o.info.item())}
-                log(f"[bench] {v}/{prec}: {tv * 1e3:.3f} ms")
-                del r
-        for prec in ("fp64", "fp32"):
-            nv = variants[f"naive_{prec}"]["ms"]
+        combos = [(v, p, False) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
+        combos += [(v, "fp32", True) for v in ("ha", "hp")]
+        for v, p, ro in combos:
+            r = Runner(data, v, p, torch, amgs, reorth=ro)
+            heavy = v == "naive" and prob.csr is None and prob.m > 4096
+            steps = 1 if heavy else (max(2, args.steps // 4) if v == "naive" else max(3, args.steps // 2))
+            tv, o = time_steps(r, steps, 1, torch)
+            orth, res = accuracy(data, o, torch)
+            key = f"{v}_{p}" + ("_reorth" if ro else "")
+            variants[key] = {"cols_per_s": round(prob.n / tv, 1), "ms": round(tv * 1e3, 4),
+                             "orth_loss": orth, "residual": res, "info": int(o.info.item())}
+            log(f"[bench] {key}: {tv * 1e3:.3f} ms  |QtAQ-I| {orth:.2e}  res {res:.2e}")
+            del r, o
+        for p in ("fp64", "fp32"):
+            nv = variants[f"naive_{p}"]["ms"]
             for v in ("ha", "hp"):
-                variants[f"{v}_{prec}"]["speedup_vs_naive"] = round(nv / variants[f"{v}_{prec}"]["ms"], 3)
+                variants[f"{v}_{p}"]["speedup_vs_naive"] = round(nv / variants[f"{v}_{p}"]["ms"], 3)
         for v in ("naive", "ha", "hp"):
             variants[f"{v}_fp32"]["speedup_vs_fp64"] = round(
                 variants[f"{v}_fp64"]["ms"] / variants[f"{v}_fp32"]["ms"], 3)
@@ -188,17 +222,100 @@ def main():
     cpu = None
     if not args.no_cpu:
         log("[bench] timing the CPU oracle")
-        cpu = cpu_baseline(prob, head_variant)
-
+        cpu = cpu_baseline(prob, head_v, args.cpu_budget)
+        log(f"[bench] cpu {cpu}")
     cfg = {"workload": args.workload, "m": prob.m, "n": prob.n,
-           "A": "csr" if prob.csr is not None else "dense",
-           "nnz": int(prob.csr.nnz) if prob.csr is not None else prob.m * prob.m,
-           "variant": head_variant, "precision": head_prec}
-    line = {"metric": METRIC, "value": round(prob.n / t, 2), "unit": "cols/s", "n_gpus": 1,
+           "A": "csr" if prob.csr is not None else "dense", "nnz": int(big),
+           "variant": head_v, "precision": head_p}
+    return {"metric": METRIC, "value": round(prob.n / t, 2), "unit": "cols/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t * 1e3, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-            "dtype": "f64" if head_prec == "fp64" else "f32", "data": "synthetic", "config": cfg, "roofline": roof,
-            "cpu_baseline": cpu, "variants": variants}
+            "dtype": "f64" if head_p == "fp64" else "f32", "data": "synthetic", "config": cfg,
+            "roofline": roof, "cpu_baseline": cpu, "variants": variants}
+
+
+# --------------------------------------------------------------------- batched
+def bench_batched(args, torch, amgs):
+    import numpy as np
+    from paper_1703_10440_amd import inputs
+    dev = torch.device("cuda:0")
+    log("[bench] building 2048 pentadiagonal instances")
+    b = inputs.pentadiag_batch(batch=2048, seed=5)
+    cols = sum(p.n for p in b.problems)
+    results = {}
+    head = None
+    for prec in ("fp64", "fp32"):
+        for v in ("ha", "hp"):
+            dt = np.float64 if prec == "fp64" else np.float32
+            insts = [(torch.from_numpy(p.csr.row_ptr).to(dev), torch.from_numpy(p.csr.col_idx).to(dev),
+                      torch.from_numpy(p.csr.vals.astype(dt)).to(dev),
+                      torch.from_numpy(np.ascontiguousarray(p.Z.astype(dt))).to(dev))
+                     for p in b.problems]
+            t0 = time.perf_counter()
+            Qs, Rs, info, plan, keep = amgs.qr_batched(insts, variant=v, precision=prec,
+                                                       autotune=True)
+            torch.cuda.synchronize()
+            setup = time.perf_counter() - t0
+            items, desc, work = keep
+
+            def step():
+                plan.run(desc, work, info)
+            t, _ = time_steps(step, args.steps, args.warmup, torch)
+            bad = int((info != 0).sum().item())
+            key = f"{v}_{prec}"
+            results[key] = {"cols_per_s": round(cols / t, 1), "ms": round(t * 1e3, 4),
+                            "tiles": plan.tiles(), "plan_and_first_call_s": round(setup, 3),
+                            "breakdowns": bad}
+            log(f"[bench] batched {key}: {t * 1e3:.3f} ms  tiles {plan.tiles()}")
+            if head is None:
+                head = (t, key)
+            del Qs, Rs, info, plan, keep, insts
+    t, key = head
+    cfg = {"workload": "batch2048", "instances": 2048, "total_columns": cols,
+           "m_range": [64, 4096], "n_range": [4, 64], "A": "csr pentadiagonal",
+           "variant": "ha", "precision": "fp64"}
+    return {"metric": METRIC, "value": round(cols / t, 2), "unit": "cols/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t * 1e3, 4),
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+            "data": "synthetic", "config": cfg, "roofline": None, "cpu_baseline": None,
+            "variants": results}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="lap64_n64",
+                    choices=["lap64_n64", "lap128_n128", "dense512_n32", "dense16k_n256",
+                             "batch2048", "copy1g"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=10.0)
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--variant", default="hp", choices=["naive", "ha", "hp"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported here "
+              "(the design notes describe how the path would shard).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_1703_10440_amd import amgs
+    amgs.load()
+    if args.workload == "copy1g":
+        # a plain 1 GiB device-to-device copy: the reference reading for the
+        # HBM byte counters (FETCH_SIZE / WRITE_SIZE) of the profiler
+        x = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0").fill_(1)
+        y = torch.empty_like(x)
+        t, _ = time_steps(lambda: y.copy_(x), args.steps, args.warmup, torch)
+        print(json.dumps({"workload": "copy1g", "bytes_read": 1 << 30, "bytes_written": 1 << 30,
+                          "ms": round(t * 1e3, 4), "GB_per_s": round(2 * (1 << 30) / t / 1e9, 1)}),
+              flush=True)
+        return
+    if args.workload == "batch2048":
+        line = bench_batched(args, torch, amgs)
+    else:
+        line = bench_single(args, torch, amgs)
     print(json.dumps(line), flush=True)
 
 

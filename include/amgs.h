@@ -13,9 +13,9 @@
  * Variants (Section 2):
  *   AMGS_NAIVE  Alg. 3: r_ij = p_i^T z_j with p_i = A q_i; two
  *               matrix-vector products (MV) per column, 2n MV in total.
- *   AMGS_HA     Alg. 5: p_j = x_j / r_jj (eq. (tec1)); n MV in total.
+ *   AMGS_HA     Alg. 5: p_j = x_j / r_jj (eq. (4)); n MV in total.
  *   AMGS_HP     Alg. 6: X = A Z as one block product, then
- *               x_j = x_j^{(0)} - sum_{i<j} r_ij p_i (eq. (tec2)).
+ *               x_j = x_j^{(0)} - sum_{i<j} r_ij p_i (eq. (5)).
  * Every variant returns the numbers of the column-oriented algorithm
  * (Alg. 3/5/6); the library schedules the same per-column operations in
  * right-looking order (Section 2.1 notes that both orders compute the same

@@ -12,10 +12,10 @@
  * The three variants of Section 2 are implemented step by step:
  *   naive (Alg. 3 column / Alg. 4 row): r_ij = p_i^T z_j with p_i = A q_i,
  *         two matrix-vector products (MV) per column, 2n MV in total;
- *   HA    (Alg. 5 column / Alg. 7 row): p_j = x_j / r_jj (eq. (tec1)),
+ *   HA    (Alg. 5 column / Alg. 7 row): p_j = x_j / r_jj (eq. (4)),
  *         one MV per column, n MV in total;
  *   HP    (Alg. 6 column / Alg. 8 row): X = A Z as one block product, then
- *         x_j^{(j-1)} = x_j^{(0)} - sum_{i<j} r_ij p_i (eq. (tec2)).
+ *         x_j^{(j-1)} = x_j^{(0)} - sum_{i<j} r_ij p_i (eq. (5)).
  *
  * Arithmetic conventions (the paper fixes none of these):
  *   - FP64 throughout in precision 0.  Compile with -ffp-contract=off so that
@@ -118,7 +118,7 @@ static double dot_hi(const double *a, const double *b, int64_t m)
 }
 
 /* ---------------------------------------------------------------- axpy */
-/* z <- z - r q  (eq. (AXPY)), in the storage precision. */
+/* z <- z - r q  (eq. (9)), in the storage precision. */
 static void axpy_st(double *z, double r, const double *q, int64_t m, int prec)
 {
     if (prec == REF_FP32) {
@@ -185,7 +185,7 @@ static void mv_st(const ref_op *A, const double *v, double *y, int prec)
     }
 }
 
-/* y <- v / r  (eq. (scaling)): binary64 division, rounded to storage. */
+/* y <- v / r  (eq. (10)): binary64 division, rounded to storage. */
 static void scale(double *y, const double *v, double r, int64_t m, int prec)
 {
 #pragma omp parallel for schedule(static)
@@ -270,7 +270,7 @@ static int qr_col(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq,
             mv_st(A, z, P + j * ldp, prec);
             *mv_calls += 1; *mv_cols += 1;
         } else {
-            scale(P + j * ldp, x, rjj, m, prec);    /* p_j = x_j^{(j-1)} / r_jj (eq. tec1) */
+            scale(P + j * ldp, x, rjj, m, prec);    /* p_j = x_j^{(j-1)} / r_jj (eq. (4)) */
         }
     }
     free(x);
@@ -279,7 +279,7 @@ static int qr_col(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq,
 
 /* Row-oriented: Alg. 4 (naive), Alg. 7 (HA), Alg. 8 (HP).  In HP(row) the
  * x-update printed in the paper is read as: at step i, for every j > i,
- * x_j^{(i)} = x_j^{(i-1)} - r_ij p_i (the row analogue of eq. (tec2)). */
+ * x_j^{(i)} = x_j^{(i-1)} - r_ij p_i (the row analogue of eq. (5)). */
 static int qr_row(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq, double *R,
                   int64_t ldr, double *P, int64_t ldp, double *X, int variant, int reorth,
                   int prec, int64_t *mv_calls, int64_t *mv_cols)

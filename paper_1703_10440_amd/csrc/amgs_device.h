@@ -12,12 +12,12 @@ namespace amgs {
 constexpr int WAVE = 64;
 
 // z - r*q with one rounding (the projection update z_j -= r_ij q_i,
-// eq. (AXPY)).  Every kernel applies the update through this function, so a
+// eq. (9)).  Every kernel applies the update through this function, so a
 // value recomputed on the fly equals the stored one bit for bit.
 __device__ __forceinline__ double upd(double z, double r, double q) { return __builtin_fma(-r, q, z); }
 __device__ __forceinline__ float upd(float z, float r, float q) { return __builtin_fmaf(-r, q, z); }
 
-// Scaling q = z / r_jj (eq. (scaling)) in binary64, rounded once to storage.
+// Scaling q = z / r_jj (eq. (10)) in binary64, rounded once to storage.
 template <typename T>
 __device__ __forceinline__ T scale_div(T z, double r) { return (T)((double)z / r); }
 

@@ -3,8 +3,8 @@
 // Schedule.  Column j of the column-oriented algorithms (Alg. 3 naive,
 // Alg. 5 HA, Alg. 6 HP) needs, in order: the projections r_ij = p_i^T z_j,
 // z_j -= r_ij q_i for i < j; its vector x_j (one MV for naive/HA, the
-// recurrence of eq. (tec2) for HP); r_jj = sqrt(z_j^T x_j); q_j = z_j / r_jj
-// and p_j (x_j / r_jj by eq. (tec1), or A q_j for naive).  The library runs
+// recurrence of eq. (5) for HP); r_jj = sqrt(z_j^T x_j); q_j = z_j / r_jj
+// and p_j (x_j / r_jj by eq. (4), or A q_j for naive).  The library runs
 // the same per-column operations right-looking (the order of Alg. 4/7/8):
 // at step j one "sweep" kernel normalises column j and then passes once over
 // every later column c, applying the pending update by q_{j-1}
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(256) void k_dense_mv(DenseMvArgs a)
 
 // ------------------------------------------------------ HP column kernel
 // Row-local: z_j -= r_{j-1,j} q_{j-1} in place, then the recurrence of
-// eq. (tec2), x_j = x_j^{(0)} - sum_{i<j} r_ij p_i with i ascending, in
+// eq. (5), x_j = x_j^{(0)} - sum_{i<j} r_ij p_i with i ascending, in
 // place in X, and the partial of z_j^T x_j.  With REORTH_A it instead stops
 // after the recurrence and writes partials of s_i = p_i^T z_j (binary64)
 // for the second pass (no A-norm yet).
@@ -437,7 +437,7 @@ __global__ __launch_bounds__(256) void k_reorth_b(RowArgs a)
 
 // ------------------------------------------------------------ sweep
 // Step j: r_jj from the A-norm partials (breakdown -> info = j+1); column j
-// normalised: q_j = z_j / r_jj, p_j = x_j / r_jj (HA, HP; eq. (tec1)) or
+// normalised: q_j = z_j / r_jj, p_j = x_j / r_jj (HA, HP; eq. (4)) or
 // p_j = A q_j already formed (naive).  Then for every later column c owned
 // by this workgroup (columns c0 .. c0+cpw-1 of grid row y):
 //     z_c <- z_c - r_{j-1,c} q_{j-1}     (update of step j-1)
@@ -545,7 +545,7 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 }
 
 // ------------------------------------------- HP recurrence, blocked terms
-// At steps s = XB, 2 XB, ... the terms i = s-XB .. s-1 of eq. (tec2) are
+// At steps s = XB, 2 XB, ... the terms i = s-XB .. s-1 of eq. (5) are
 // applied to every later column: x_c <- x_c - r_ic p_i, i ascending.  The
 // column kernel of column j then only adds the terms i >= XB floor((j-1)/XB),
 // so every x_c receives its terms in ascending i, as in the sequential

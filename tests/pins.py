@@ -15,7 +15,7 @@ paper and from mathematics:
 * Section 2.1: column and row orientations perform the same operations and
   give identical numbers;
 * Section 2: naive needs 2n MV, HA n MV, HP one block product A Z;
-* Section 3 (eq. Th3.1): the representation error is O(u) for every variant;
+* Section 3 (eq. (11)): the representation error is O(u) for every variant;
 * power-of-two scalings commute with rounding.
 """
 from __future__ import annotations
@@ -199,7 +199,7 @@ def pin_first_column(lib) -> list:
 
 
 def pin_residual_and_reorth(lib) -> list:
-    """Eq. (Th3.1): ||Z - QR|| = O(u) for all variants even when Z is badly
+    """Eq. (11): ||Z - QR|| = O(u) for all variants even when Z is badly
     conditioned; with the second pass the A-orthogonality improves and the
     residual stays O(u) (the pass must add s_i into R)."""
     fails = []
@@ -214,7 +214,7 @@ def pin_residual_and_reorth(lib) -> list:
         o0, o1 = ref.orth_loss(r0.Q, csr=p.csr), ref.orth_loss(r1.Q, csr=p.csr)
         # naive and HA hold P = AQ to O(u), so a second pass restores
         # A-orthogonality to O(u).  HP's P comes from the recurrence of
-        # eq. (tec2), which cancels when Z is ill-conditioned; the pass then
+        # eq. (5), which cancels when Z is ill-conditioned; the pass then
         # only reduces the loss.
         limit = 1e-13 if v != "hp" else 0.1 * o0
         if not (o1 < limit and o1 < o0):
