@@ -136,9 +136,10 @@ def source_sha():
 
 
 def sweep_roofline(runner, amgs, torch):
-    """Average duration of the projection-sweep kernel from HIP events the
-    library records around each of its launches on the call's stream, and its
-    algorithmic bytes per launch."""
+    """Average duration of the projection-sweep kernel, from HIP events that
+    the library binds to each sweep dispatch on the call's stream
+    (hipExtLaunchKernel start/stop events), and its algorithmic bytes per
+    launch."""
     h = amgs.handle(0)
     amgs.amgs_profile_reset(h)
     amgs.amgs_profile_enable(h, 1)
@@ -188,7 +189,7 @@ def bench_single(args, torch, amgs):
     log(f"[bench] m={prob.m} n={prob.n}")
     big = prob.m * prob.m if prob.csr is None else prob.csr.nnz
     head_v, head_p = args.variant, args.precision
-    run = Runner(data, head_v, head_p, torch, amgs)
+    run = Runner(data, head_v, head_p, torch, amgs, reorth=args.reorth)
     t, out = time_steps(run, args.steps, args.warmup, torch)
     info = int(out.info.item())
     log(f"[bench] {head_v}/{head_p}: {t * 1e3:.3f} ms/step info={info}")
@@ -226,7 +227,7 @@ def bench_single(args, torch, amgs):
         log(f"[bench] cpu {cpu}")
     cfg = {"workload": args.workload, "m": prob.m, "n": prob.n,
            "A": "csr" if prob.csr is not None else "dense", "nnz": int(big),
-           "variant": head_v, "precision": head_p}
+           "variant": head_v, "precision": head_p, "reorth": bool(args.reorth)}
     return {"metric": METRIC, "value": round(prob.n / t, 2), "unit": "cols/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t * 1e3, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -294,6 +295,7 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--variant", default="hp", choices=["naive", "ha", "hp"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--reorth", action="store_true", help="second pass in the headline run")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported here "

@@ -81,7 +81,8 @@ def load(path: Optional[str] = None):
     global _lib
     if _lib is not None and path is None:
         return _lib
-    p = path or LIB_PATH
+    # AMGS_LIB_PATH selects another build of the same library (tuning runs)
+    p = path or os.environ.get("AMGS_LIB_PATH") or LIB_PATH
     if not os.path.exists(p):
         raise AmgsError(f"HIP library not built: {p} is missing (run __graft_entry__.build())")
     lib = C.CDLL(p)

@@ -79,9 +79,9 @@ Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_g
     };
     // MV kernels never use more than MAX_G_MV workgroups, whatever the CSR
     // lane count, so the size does not depend on nnz
-    int64_t g_rr = g.g_rows > MAX_G_MV ? g.g_rows : MAX_G_MV;
+    int64_t g_rr = g.g_rows2 > MAX_G_MV ? g.g_rows2 : MAX_G_MV;
     L.part = take((size_t)n * g.g_rows * 8);
-    L.s_part = reorth ? take((size_t)n * g.g_rows * 8) : off;
+    L.s_part = reorth ? take((size_t)n * g.g_rows2 * 8) : off;
     L.rr_part = take((size_t)g_rr * 8);
     L.S = reorth ? take((size_t)n * 8) : off;
     L.zt = variant != VAR_HP ? take((size_t)m * w) : off;
@@ -141,7 +141,7 @@ amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
                     launch_col_hp<T>(c, j, false);
                     st.kernel_launches += 1;
                 }
-                n_rr = c.geo.g_rows;
+                n_rr = c.geo.g_rows2;
             } else {
                 if (reorth && j > 0) {
                     launch_reorth_a<T>(c, j);
@@ -166,8 +166,15 @@ amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
                 n_rr = c.n_rr_mv;
             }
         }
-        {
-            ProfScope ps(h, 0, c.stream);
+        if (h->profiling) {
+            // events bound to the sweep's own dispatch: exact kernel time
+            hipEvent_t e0 = take_event(h), e1 = take_event(h);
+            c.ev_start = e0;
+            c.ev_stop = e1;
+            launch_sweep<T>(c, j, variant, n_rr);
+            c.ev_start = c.ev_stop = nullptr;
+            if (e0 && e1) h->recs.push_back({0, e0, e1});
+        } else {
             launch_sweep<T>(c, j, variant, n_rr);
         }
         st.kernel_launches++;
@@ -229,15 +236,21 @@ namespace amgs {
 Geo make_geo(int64_t m, int64_t nnz, int is_dense)
 {
     Geo g{};
-    // about 512 row chunks of 256*U rows (U <= 8)
-    const int64_t cap = 256 * 512;
+    // about 256 row chunks of 256*U rows (U <= 8): more rows per thread
+    // keep more loads in flight in the streaming kernels
+    const int64_t cap = 256 * 256;
     g.U = m <= cap ? 1 : m <= 2 * cap ? 2 : m <= 4 * cap ? 4 : 8;
     g.g_rows = (m + 256 * g.U - 1) / (256 * g.U);
     if (g.g_rows < 1) g.g_rows = 1;
+    // the column and second-pass kernels hold several vectors per row in
+    // registers, so they keep at most 4 rows per thread
+    g.U2 = g.U < 4 ? g.U : 4;
+    g.g_rows2 = (m + 256 * g.U2 - 1) / (256 * g.U2);
+    if (g.g_rows2 < 1) g.g_rows2 = 1;
     const double avg = m > 0 ? (double)nnz / (double)m : 0.0;
-    g.lanes = avg <= 12 ? 1 : avg <= 24 ? 2 : avg <= 48 ? 4 : avg <= 96 ? 8 : avg <= 192 ? 16
-            : avg <= 384 ? 32 : 64;
-    const int64_t rows_per_wg = 512 / g.lanes;
+    g.lanes = avg <= 7.5 ? 0 : avg <= 12 ? 1 : avg <= 24 ? 2 : avg <= 48 ? 4 : avg <= 96 ? 8
+            : avg <= 192 ? 16 : avg <= 384 ? 32 : 64;
+    const int64_t rows_per_wg = g.lanes == 0 ? 512 : 512 / g.lanes;
     g.g_csr = (m + rows_per_wg - 1) / rows_per_wg;
     if (g.g_csr > MAX_G_MV) g.g_csr = MAX_G_MV;
     if (g.g_csr < 1) g.g_csr = 1;

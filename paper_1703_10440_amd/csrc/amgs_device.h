@@ -21,14 +21,52 @@ __device__ __forceinline__ float upd(float z, float r, float q) { return __built
 template <typename T>
 __device__ __forceinline__ T scale_div(T z, double r) { return (T)((double)z / r); }
 
-// Butterfly sum over a wave; every lane ends with the same bits because each
-// stage adds the same two operands (in commuted order) on both partners.
+// Data-parallel-primitive (DPP) move of a 32-bit lane value; lanes whose
+// source is outside the pattern, or whose row is masked off, receive 0.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ float dpp_mov(float v)
+{
+    return __builtin_bit_cast(float, dpp32<CTRL, ROWS>(__builtin_bit_cast(uint32_t, v)));
+}
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_mov(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = dpp32<CTRL, ROWS>((uint32_t)b), hi = dpp32<CTRL, ROWS>((uint32_t)(b >> 32));
+    return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+__device__ __forceinline__ float lane63(float v)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ double lane63(double v)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint64_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+    const uint64_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), 63);
+    return __builtin_bit_cast(double, (hi << 32) | lo);
+}
+
+// Sum over a wave with DPP moves: pairs and quads (quad_perm), the four
+// quads of each 16-lane row (row_ror 4, 8), then rows 0..3 folded into lane
+// 63 (row_bcast 15 and 31), whose value is broadcast to every lane.  The
+// order is fixed, so the bits are the same on every run and in every wave
+// given the same per-lane inputs.
 template <typename A>
 __device__ __forceinline__ A wave_sum(A v)
 {
-#pragma unroll
-    for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, WAVE);
-    return v;
+    v += dpp_mov<0xb1, 0xf>(v);   // quad_perm [1,0,3,2]
+    v += dpp_mov<0x4e, 0xf>(v);   // quad_perm [2,3,0,1]
+    v += dpp_mov<0x124, 0xf>(v);  // row_ror 4
+    v += dpp_mov<0x128, 0xf>(v);  // row_ror 8
+    v += dpp_mov<0x142, 0xa>(v);  // row_bcast 15 into rows 1 and 3
+    v += dpp_mov<0x143, 0xc>(v);  // row_bcast 31 into rows 2 and 3
+    return lane63(v);
 }
 
 // Canonical reduction of v[0..N): lane l adds v[l], v[l+64], ... in
@@ -46,6 +84,19 @@ __device__ __forceinline__ A wave_reduce_seq(const A *__restrict__ v, int64_t N)
     }
     if (i < N) s0 += v[i];
     return wave_sum(s0 + s1);
+}
+
+// wave_reduce_seq computed once per workgroup (by wave 0) and broadcast
+// through one LDS slot; every thread must call it.
+template <typename A>
+__device__ __forceinline__ A block_reduce_bcast(const A *__restrict__ v, int64_t N, A *slot)
+{
+    if (threadIdx.x < WAVE) {
+        const A s = wave_reduce_seq(v, N);
+        if (threadIdx.x == 0) *slot = s;
+    }
+    __syncthreads();
+    return *slot;
 }
 
 // Sum over a workgroup of NT threads: wave butterflies, then the NT/64 wave

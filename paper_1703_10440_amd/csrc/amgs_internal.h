@@ -10,10 +10,13 @@ enum { VAR_NAIVE = 0, VAR_HA = 1, VAR_HP = 2 };
 enum { SRC_UPD = 0, SRC_VEC = 1, SRC_DIV = 2 };
 constexpr int MAX_CPW = 256;   // trailing columns per sweep workgroup (max)
 constexpr int SWEEP_TARGET_WG = 1024; // sweep workgroups aimed for
+constexpr int SWEEP_CB = 4;    // later columns streamed together by one sweep thread
+constexpr double SWEEP_NT_BYTES = 192.0 * (1 << 20); // trailing block streamed non-temporally above this
 constexpr int HP_XB = 8;       // HP recurrence terms applied per blocked update
 constexpr int DENSE_CB = 16;   // outputs per dense-MV workgroup pass
 constexpr int SPMM_C = 8;      // columns per CSR block-product thread
 constexpr int MAX_G_MV = 512;  // partials of an MV column kernel
+constexpr int STREAM_CAP = 4096; // CSR entries staged per 512-row tile
 
 // Partials of the projection sweep: part[c * g + w] holds workgroup w's part
 // of r_{j,c} (element type of the storage precision).
@@ -23,9 +26,11 @@ struct SweepPart {
 };
 
 struct Geo {
-    int U;          // rows per thread in row-partitioned kernels (1,2,4,8)
-    int64_t g_rows; // row chunks of 256*U rows
-    int lanes;      // lanes per CSR row in the MV kernel
+    int U;          // rows per thread of the sweep (1,2,4,8)
+    int64_t g_rows; // sweep row chunks of 256*U rows
+    int U2;         // rows per thread of the column / second-pass kernels (<= 4)
+    int64_t g_rows2;// their row chunks of 256*U2 rows
+    int lanes;      // lanes per CSR row in the MV kernel (0: 512-row tiles staged in LDS)
     int64_t g_csr;  // workgroups of the CSR MV kernel
     int64_t g_dense;// workgroups of the dense MV kernel
 };
@@ -126,6 +131,9 @@ struct Ctx {
     int32_t *info;
     Geo geo;
     hipStream_t stream;
+    // when set, the sweep is launched with these events bound to its own
+    // dispatch (exact kernel start and end, no extra stream markers)
+    hipEvent_t ev_start, ev_stop;
 };
 
 Geo make_geo(int64_t m, int64_t nnz, int is_dense);

@@ -18,6 +18,8 @@
 // fixed order (every workgroup that needs a scalar reduces it itself, with
 // identical bits).  The column kernel also publishes the finished r_{j-1,c}
 // of the previous sweep into R, spread over its workgroups.
+#include <hip/hip_ext.h>
+
 #include "amgs_device.h"
 #include "amgs_internal.h"
 
@@ -73,6 +75,8 @@ template <typename T, int L, int SRC, bool RR>
 __global__ __launch_bounds__(512) void k_csr_mv(CsrMvArgs a)
 {
     __shared__ double lds[512 / WAVE];
+    __shared__ T s_r;
+    __shared__ double s_rr;
     if (*a.info) return;
     const T *__restrict__ vals = (const T *)a.vals;
     const T *__restrict__ src = (const T *)a.src;
@@ -83,11 +87,11 @@ __global__ __launch_bounds__(512) void k_csr_mv(CsrMvArgs a)
     T r = 0;
     double rjj = 1.0;
     if (SRC == SRC_UPD && qprev) {
-        r = wave_reduce_seq((const T *)a.sp.part + a.j * a.sp.g, a.sp.g);
         publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
+        r = block_reduce_bcast((const T *)a.sp.part + a.j * a.sp.g, a.sp.g, &s_r);
     }
     if (SRC == SRC_DIV) {
-        double rr = wave_reduce_seq(a.rr_part, a.n_rr);
+        double rr = block_reduce_bcast(a.rr_part, a.n_rr, &s_rr);
         if (!norm_ok(rr)) return;
         rjj = sqrt(rr);
     }
@@ -121,6 +125,79 @@ __global__ __launch_bounds__(512) void k_csr_mv(CsrMvArgs a)
     }
 }
 
+// CSR MV for short rows ("CSR stream"): a workgroup takes 512 consecutive
+// rows, stages their entries (at most STREAM_CAP) in LDS with coalesced
+// loads, then each thread sums its own row from LDS in stored order.  Same
+// contract as k_csr_mv; a tile with more entries than fit is summed straight
+// from memory.
+template <typename T, int SRC, bool RR>
+__global__ __launch_bounds__(512) void k_csr_mv_stream(CsrMvArgs a)
+{
+    __shared__ int32_t s_col[STREAM_CAP];
+    __shared__ T s_val[STREAM_CAP];
+    __shared__ double lds[512 / WAVE];
+    __shared__ T s_r;
+    __shared__ double s_rr;
+    if (*a.info) return;
+    const T *__restrict__ vals = (const T *)a.vals;
+    const T *__restrict__ src = (const T *)a.src;
+    const T *__restrict__ qprev = (const T *)a.qprev;
+    T *__restrict__ y = (T *)a.y;
+    T *__restrict__ zt = (T *)a.zt;
+    T r = 0;
+    double rjj = 1.0;
+    if (SRC == SRC_UPD && qprev) {
+        publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
+        r = block_reduce_bcast((const T *)a.sp.part + a.j * a.sp.g, a.sp.g, &s_r);
+    }
+    if (SRC == SRC_DIV) {
+        double rr = block_reduce_bcast(a.rr_part, a.n_rr, &s_rr);
+        if (!norm_ok(rr)) return;
+        rjj = sqrt(rr);
+    }
+    auto load = [&](int64_t l) -> T {
+        T v = src[l];
+        if (SRC == SRC_UPD && qprev) v = upd(v, r, qprev[l]);
+        if (SRC == SRC_DIV) v = scale_div(v, rjj);
+        return v;
+    };
+    const int tid = threadIdx.x;
+    double acc = 0.0;
+    for (int64_t row0 = (int64_t)blockIdx.x * 512; row0 < a.m; row0 += (int64_t)gridDim.x * 512) {
+        const int64_t row = row0 + tid;
+        const int64_t rend = row0 + 512 < a.m ? row0 + 512 : a.m;
+        const int32_t t0 = a.row_ptr[row0], t1 = a.row_ptr[rend];
+        const bool staged = t1 - t0 <= STREAM_CAP;
+        if (staged) {
+            for (int32_t e = t0 + tid; e < t1; e += 512) {
+                s_col[e - t0] = a.col_idx[e];
+                s_val[e - t0] = vals[e];
+            }
+        }
+        __syncthreads();
+        if (row < a.m) {
+            const int32_t e0 = a.row_ptr[row], e1 = a.row_ptr[row + 1];
+            T s = 0;
+            if (staged) {
+                for (int32_t e = e0; e < e1; ++e) s += s_val[e - t0] * load(s_col[e - t0]);
+            } else {
+                for (int32_t e = e0; e < e1; ++e) s += vals[e] * load(a.col_idx[e]);
+            }
+            y[row] = s;
+            if (SRC == SRC_UPD || RR) {
+                T zs = load(row);
+                if (SRC == SRC_UPD) zt[row] = zs;
+                if (RR) acc += (double)zs * (double)s;
+            }
+        }
+        __syncthreads();
+    }
+    if (RR) {
+        double t = block_sum<double, 512>(acc, lds);
+        if (tid == 0) a.rr_out[blockIdx.x] = t;
+    }
+}
+
 // ----------------------------------------------------- dense MV (column kernel)
 // Same contract as k_csr_mv for a dense symmetric column-major A: output
 // entry k is the dot of column k of A with s.  A workgroup owns CB outputs at
@@ -131,6 +208,8 @@ __global__ __launch_bounds__(256) void k_dense_mv(DenseMvArgs a)
 {
     __shared__ T red[256 / WAVE][CB];
     __shared__ double lds[256 / WAVE];
+    __shared__ T s_r;
+    __shared__ double s_rr;
     if (*a.info) return;
     const T *__restrict__ A = (const T *)a.A;
     const T *__restrict__ src = (const T *)a.src;
@@ -140,11 +219,11 @@ __global__ __launch_bounds__(256) void k_dense_mv(DenseMvArgs a)
     T r = 0;
     double rjj = 1.0;
     if (SRC == SRC_UPD && qprev) {
-        r = wave_reduce_seq((const T *)a.sp.part + a.j * a.sp.g, a.sp.g);
         publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
+        r = block_reduce_bcast((const T *)a.sp.part + a.j * a.sp.g, a.sp.g, &s_r);
     }
     if (SRC == SRC_DIV) {
-        double rr = wave_reduce_seq(a.rr_part, a.n_rr);
+        double rr = block_reduce_bcast(a.rr_part, a.n_rr, &s_rr);
         if (!norm_ok(rr)) return;
         rjj = sqrt(rr);
     }
@@ -201,6 +280,51 @@ __global__ __launch_bounds__(256) void k_dense_mv(DenseMvArgs a)
     }
 }
 
+// Partials of the second-pass coefficients s_i = p_i^T z_j, i < j, for the
+// rows this workgroup owns (binary64 accumulation): eight p_i are streamed
+// together, each wave reduces its part, and the four wave sums are combined
+// in wave order once per 64 coefficients.
+template <typename T, int U>
+__device__ __forceinline__ void reorth_partials(const T *__restrict__ P, int64_t ldp, int64_t j,
+                                                const T (&zr)[U], int64_t row0, int64_t m,
+                                                double *__restrict__ s_part, double (*red)[64])
+{
+    const int tid = threadIdx.x, wave = tid / WAVE;
+    for (int64_t ib0 = 0; ib0 < j; ib0 += 64) {
+        const int64_t nb = (j - ib0 < 64) ? j - ib0 : 64;
+        for (int64_t ib = ib0; ib < ib0 + nb; ib += 8) {
+            double sacc[8];
+            T pv[8][U];
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t k = row0 + u * 256 + tid;
+                    pv[t][u] = (ib + t < ib0 + nb && k < m) ? P[k + (ib + t) * ldp] : (T)0;
+                }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                sacc[t] = 0.0;
+#pragma unroll
+                for (int u = 0; u < U; ++u) sacc[t] += (double)pv[t][u] * (double)zr[u];
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const double v = wave_sum(sacc[t]);
+                if ((tid & (WAVE - 1)) == 0 && ib + t < ib0 + nb) red[wave][ib - ib0 + t] = v;
+            }
+        }
+        __syncthreads();
+        if (tid < nb) {
+            double v = red[0][tid];
+#pragma unroll
+            for (int w = 1; w < 256 / WAVE; ++w) v += red[w][tid];
+            s_part[(ib0 + tid) * gridDim.x + blockIdx.x] = v;
+        }
+        __syncthreads();
+    }
+}
+
 // ------------------------------------------------------ HP column kernel
 // Row-local: z_j -= r_{j-1,j} q_{j-1} in place, then the recurrence of
 // eq. (5), x_j = x_j^{(0)} - sum_{i<j} r_ij p_i with i ascending, in
@@ -211,52 +335,53 @@ template <typename T, int U, bool REORTH_A>
 __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
 {
     __shared__ double lds[256 / WAVE];
-    __shared__ double red[256 / WAVE][4];
+    __shared__ double red[256 / WAVE][64];
+    __shared__ T s_r;
     if (*a.info) return;
     const int64_t j = a.j;
     T *__restrict__ Q = (T *)a.Q;
     T *__restrict__ X = (T *)a.X;
     const T *__restrict__ P = (const T *)a.P;
-    T r = 0;
-    if (j > 0) {
-        r = wave_reduce_seq((const T *)a.sp.part + j * a.sp.g, a.sp.g);
-        publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
-    }
     const int tid = threadIdx.x;
     const int64_t row0 = (int64_t)blockIdx.x * 256 * U;
-    T zr[U], xr[U];
+    // issue the row loads before waiting for r_{j-1,j}
+    T zr[U], qp[U], x[U], pv[HP_XB][U];
+    const int64_t i0 = j > 0 ? HP_XB * ((j - 1) / HP_XB) : 0;
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
-        zr[u] = 0;
-        xr[u] = 0;
-        if (k < a.m) {
-            T z = Q[k + j * a.ldq];
-            if (j > 0) {
-                z = upd(z, r, Q[k + (j - 1) * a.ldq]);
-                Q[k + j * a.ldq] = z;
-            }
-            zr[u] = z;
+        const bool in = k < a.m;
+        zr[u] = in ? Q[k + j * a.ldq] : (T)0;
+        qp[u] = (in && j > 0) ? Q[k + (j - 1) * a.ldq] : (T)0;
+        x[u] = in ? X[k + j * a.ldx] : (T)0;
+#pragma unroll
+        for (int t = 0; t < HP_XB; ++t) pv[t][u] = (in && i0 + t < j) ? P[k + (i0 + t) * a.ldp] : (T)0;
+    }
+    T r = 0;
+    if (j > 0) {
+        publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
+        r = block_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
+    }
+    T xr[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = row0 + u * 256 + tid;
+        if (k < a.m && j > 0) {
+            zr[u] = upd(zr[u], r, qp[u]);
+            Q[k + j * a.ldq] = zr[u];
         }
     }
     // x recurrence, i ascending, terms i >= XB floor((j-1)/XB) (the earlier
     // ones were applied by k_hp_xblock); r_ij (i < j-1) were published by
     // earlier column kernels, r_{j-1,j} is the value re-reduced above.
     {
-        T x[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t k = row0 + u * 256 + tid;
-            x[u] = k < a.m ? X[k + j * a.ldx] : (T)0;
-        }
-        const int64_t i0 = j > 0 ? HP_XB * ((j - 1) / HP_XB) : 0;
-        for (int64_t i = i0; i < j; ++i) {
-            const T ri = (i == j - 1) ? r : (T)a.R[i + j * a.ldr];
-            const T *__restrict__ Pi = P + i * a.ldp;
+        for (int t = 0; t < HP_XB; ++t) {
+            const int64_t i = i0 + t;
+            if (i < j) {
+                const T ri = (i == j - 1) ? r : (T)a.R[i + j * a.ldr];
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t k = row0 + u * 256 + tid;
-                if (k < a.m) x[u] = upd(x[u], ri, Pi[k]);
+                for (int u = 0; u < U; ++u) x[u] = upd(x[u], ri, pv[t][u]);
             }
         }
 #pragma unroll
@@ -273,35 +398,7 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
         double t = block_sum<double, 256>(acc, lds);
         if (tid == 0) a.rr_out[blockIdx.x] = t;
     } else {
-        // partials of s_i = p_i^T z_j, four i at a time
-        const int wave = tid / WAVE;
-        for (int64_t i0 = 0; i0 < j; i0 += 4) {
-            double s[4] = {0, 0, 0, 0};
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                if (i0 + t < j) {
-                    const T *__restrict__ Pi = P + (i0 + t) * a.ldp;
-#pragma unroll
-                    for (int u = 0; u < U; ++u) {
-                        const int64_t k = row0 + u * 256 + tid;
-                        if (k < a.m) s[t] += (double)Pi[k] * (double)zr[u];
-                    }
-                }
-            }
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                double v = wave_sum(s[t]);
-                if ((tid & (WAVE - 1)) == 0) red[wave][t] = v;
-            }
-            __syncthreads();
-            if (tid < 4 && i0 + tid < j) {
-                double v = red[0][tid];
-#pragma unroll
-                for (int w = 1; w < 256 / WAVE; ++w) v += red[w][tid];
-                a.s_part[(i0 + tid) * gridDim.x + blockIdx.x] = v;
-            }
-            __syncthreads();
-        }
+        reorth_partials<T, U>(P, a.ldp, j, zr, row0, a.m, a.s_part, red);
     }
 }
 
@@ -310,58 +407,36 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
 template <typename T, int U>
 __global__ __launch_bounds__(256) void k_reorth_a(RowArgs a)
 {
-    __shared__ double red[256 / WAVE][4];
+    __shared__ double red[256 / WAVE][64];
+    __shared__ T s_r;
     if (*a.info) return;
     const int64_t j = a.j;
     const T *__restrict__ Q = (const T *)a.Q;
     const T *__restrict__ P = (const T *)a.P;
     T *__restrict__ zt = (T *)a.zt;
-    T r = 0;
-    if (j > 0) {
-        r = wave_reduce_seq((const T *)a.sp.part + j * a.sp.g, a.sp.g);
-        publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
-    }
-    const int tid = threadIdx.x, wave = tid / WAVE;
+    const int tid = threadIdx.x;
     const int64_t row0 = (int64_t)blockIdx.x * 256 * U;
-    T zr[U];
+    T zr[U], qp[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
-        zr[u] = 0;
+        zr[u] = k < a.m ? Q[k + j * a.ldq] : (T)0;
+        qp[u] = (k < a.m && j > 0) ? Q[k + (j - 1) * a.ldq] : (T)0;
+    }
+    T r = 0;
+    if (j > 0) {
+        publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
+        r = block_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = row0 + u * 256 + tid;
         if (k < a.m) {
-            T z = Q[k + j * a.ldq];
-            if (j > 0) z = upd(z, r, Q[k + (j - 1) * a.ldq]);
-            zt[k] = z;
-            zr[u] = z;
+            if (j > 0) zr[u] = upd(zr[u], r, qp[u]);
+            zt[k] = zr[u];
         }
     }
-    for (int64_t i0 = 0; i0 < j; i0 += 4) {
-        double s[4] = {0, 0, 0, 0};
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            if (i0 + t < j) {
-                const T *__restrict__ Pi = P + (i0 + t) * a.ldp;
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t k = row0 + u * 256 + tid;
-                    if (k < a.m) s[t] += (double)Pi[k] * (double)zr[u];
-                }
-            }
-        }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            double v = wave_sum(s[t]);
-            if ((tid & (WAVE - 1)) == 0) red[wave][t] = v;
-        }
-        __syncthreads();
-        if (tid < 4 && i0 + tid < j) {
-            double v = red[0][tid];
-#pragma unroll
-            for (int w = 1; w < 256 / WAVE; ++w) v += red[w][tid];
-            a.s_part[(i0 + tid) * gridDim.x + blockIdx.x] = v;
-        }
-        __syncthreads();
-    }
+    reorth_partials<T, U>(P, a.ldp, j, zr, row0, a.m, a.s_part, red);
 }
 
 // ----------------------------------------------- second pass: finish s_i
@@ -404,14 +479,26 @@ __global__ __launch_bounds__(256) void k_reorth_b(RowArgs a)
         zd[u] = k < a.m ? (double)zv[k] : 0.0;
         xd[u] = (HP && k < a.m) ? (double)xv[k] : 0.0;
     }
-    for (int64_t i = 0; i < j; ++i) {
-        const double s = a.S[i];
+    for (int64_t ib = 0; ib < j; ib += 4) {
+        T qv[4][U], pv[HP ? 4 : 1][U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t k = row0 + u * 256 + tid;
-            if (k < a.m) {
-                zd[u] -= s * (double)Q[k + i * a.ldq];
-                if (HP) xd[u] -= s * (double)P[k + i * a.ldp];
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t k = row0 + u * 256 + tid;
+                const bool in = ib + t < j && k < a.m;
+                qv[t][u] = in ? Q[k + (ib + t) * a.ldq] : (T)0;
+                if (HP) pv[HP ? t : 0][u] = in ? P[k + (ib + t) * a.ldp] : (T)0;
+            }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (ib + t < j) {
+                const double s = a.S[ib + t];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    zd[u] -= s * (double)qv[t][u];
+                    if (HP) xd[u] -= s * (double)pv[HP ? t : 0][u];
+                }
             }
         }
     }
@@ -444,7 +531,22 @@ __global__ __launch_bounds__(256) void k_reorth_b(RowArgs a)
 //     partial of r_{j,c} = p_j^T z_c     (dot of step j)
 // with z_c read and written once.  One wave re-reduces the A-norm partials
 // and broadcasts r_jj through LDS.
-template <typename T, int U, int VAR>
+// Loads and stores of the later columns; NT selects the non-temporal
+// (streaming) cache policy.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_stream(const T *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_stream(T *p, T v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
+template <typename T, int U, int VAR, bool NTS>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 {
     __shared__ T red[256 / WAVE][MAX_CPW];
@@ -467,6 +569,21 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
         xs[u] = in ? (VAR == VAR_NAIVE ? P[k + j * a.ldp] : xsrc[k]) : (T)0;
         zs[u] = (in && own) ? zsrc[k] : (T)0;
         qp[u] = (in && j > 0) ? Q[k + (j - 1) * a.ldq] : (T)0;
+    }
+    const int64_t c0 = j + 1 + (int64_t)blockIdx.y * a.cpw;
+    const int64_t c1 = (c0 + a.cpw < a.n) ? c0 + a.cpw : a.n;
+    const bool full_rows = row0 + 256 * U <= m;
+    // start streaming the first group of later columns before waiting for
+    // the A-norm reduction
+    T zv[SWEEP_CB][U];
+#pragma unroll
+    for (int t = 0; t < SWEEP_CB; ++t) {
+        const T *__restrict__ Zc = Q + (c0 + t) * a.ldq;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = row0 + u * 256 + tid;
+            zv[t][u] = (c0 + t < c1 && (full_rows || k < m)) ? ld_stream<NTS>(Zc + k) : (T)0;
+        }
     }
     if (wave == 0) {
         const double rr = wave_reduce_seq(a.rr_part, a.n_rr);
@@ -492,29 +609,27 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
             if (VAR != VAR_NAIVE) P[k + j * a.ldp] = p[u];
         }
     }
-    const int64_t c0 = j + 1 + (int64_t)blockIdx.y * a.cpw;
-    const int64_t c1 = (c0 + a.cpw < a.n) ? c0 + a.cpw : a.n;
     if (c0 >= c1) return;
-    const bool full_rows = row0 + 256 * U <= m;
-    for (int64_t cb = c0; cb < c1; cb += 4) {
-        T r[4], acc[4];
-        T zv[4][U];
+    for (int64_t cb = c0; cb < c1; cb += SWEEP_CB) {
+        T r[SWEEP_CB], acc[SWEEP_CB];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < SWEEP_CB; ++t) {
             acc[t] = 0;
             r[t] = (j > 0 && cb + t < c1) ? (T)a.R[(j - 1) + (cb + t) * a.ldr] : (T)0;
         }
+        if (cb > c0) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const T *__restrict__ Zc = Q + (cb + t) * a.ldq;
+            for (int t = 0; t < SWEEP_CB; ++t) {
+                const T *__restrict__ Zc = Q + (cb + t) * a.ldq;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t k = row0 + u * 256 + tid;
-                zv[t][u] = (cb + t < c1 && (full_rows || k < m)) ? Zc[k] : (T)0;
+                for (int u = 0; u < U; ++u) {
+                    const int64_t k = row0 + u * 256 + tid;
+                    zv[t][u] = (cb + t < c1 && (full_rows || k < m)) ? ld_stream<NTS>(Zc + k) : (T)0;
+                }
             }
         }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < SWEEP_CB; ++t) {
             T *__restrict__ Zc = Q + (cb + t) * a.ldq;
 #pragma unroll
             for (int u = 0; u < U; ++u) {
@@ -523,14 +638,14 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
                     T z = zv[t][u];
                     if (j > 0) {
                         z = upd(z, r[t], qp[u]);
-                        Zc[k] = z;
+                        st_stream<NTS>(Zc + k, z);
                     }
                     acc[t] += p[u] * z;
                 }
             }
         }
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < SWEEP_CB; ++t) {
             T v = wave_sum(acc[t]);
             if ((tid & (WAVE - 1)) == 0 && cb + t < c1) red[wave][cb - c0 + t] = v;
         }
@@ -668,6 +783,7 @@ static void launch_csr_mv_L(const Ctx &c, CsrMvArgs &a)
 {
     const dim3 grid((unsigned)c.geo.g_csr), block(512);
     switch (c.geo.lanes) {
+    case 0: hipLaunchKernelGGL((k_csr_mv_stream<T, SRC, RR>), grid, block, 0, c.stream, a); break;
     case 1: hipLaunchKernelGGL((k_csr_mv<T, 1, SRC, RR>), grid, block, 0, c.stream, a); break;
     case 2: hipLaunchKernelGGL((k_csr_mv<T, 2, SRC, RR>), grid, block, 0, c.stream, a); break;
     case 4: hipLaunchKernelGGL((k_csr_mv<T, 4, SRC, RR>), grid, block, 0, c.stream, a); break;
@@ -740,15 +856,22 @@ static RowArgs row_args(const Ctx &c, int64_t j)
     default: { constexpr int UU = 8; __VA_ARGS__; } break;                                        \
     }
 
+#define AMGS_DISPATCH_U2(U_, ...)                                                                 \
+    switch (U_) {                                                                                 \
+    case 1: { constexpr int UU = 1; __VA_ARGS__; } break;                                         \
+    case 2: { constexpr int UU = 2; __VA_ARGS__; } break;                                         \
+    default: { constexpr int UU = 4; __VA_ARGS__; } break;                                        \
+    }
+
 template <typename T>
 void launch_col_hp(const Ctx &c, int64_t j, bool reorth_a)
 {
     RowArgs a = row_args(c, j);
-    const dim3 grid((unsigned)c.geo.g_rows), block(256);
+    const dim3 grid((unsigned)c.geo.g_rows2), block(256);
     if (reorth_a) {
-        AMGS_DISPATCH_U(c.geo.U, hipLaunchKernelGGL((k_col_hp<T, UU, true>), grid, block, 0, c.stream, a));
+        AMGS_DISPATCH_U2(c.geo.U2, hipLaunchKernelGGL((k_col_hp<T, UU, true>), grid, block, 0, c.stream, a));
     } else {
-        AMGS_DISPATCH_U(c.geo.U, hipLaunchKernelGGL((k_col_hp<T, UU, false>), grid, block, 0, c.stream, a));
+        AMGS_DISPATCH_U2(c.geo.U2, hipLaunchKernelGGL((k_col_hp<T, UU, false>), grid, block, 0, c.stream, a));
     }
 }
 
@@ -756,26 +879,26 @@ template <typename T>
 void launch_reorth_a(const Ctx &c, int64_t j)
 {
     RowArgs a = row_args(c, j);
-    const dim3 grid((unsigned)c.geo.g_rows), block(256);
-    AMGS_DISPATCH_U(c.geo.U, hipLaunchKernelGGL((k_reorth_a<T, UU>), grid, block, 0, c.stream, a));
+    const dim3 grid((unsigned)c.geo.g_rows2), block(256);
+    AMGS_DISPATCH_U2(c.geo.U2, hipLaunchKernelGGL((k_reorth_a<T, UU>), grid, block, 0, c.stream, a));
 }
 
 void launch_reorth_fin(const Ctx &c, int64_t j)
 {
     const int64_t blocks = (j + 3) / 4;
     hipLaunchKernelGGL(k_reorth_fin, dim3((unsigned)blocks), dim3(256), 0, c.stream,
-                       (const double *)c.s_part, c.geo.g_rows, j, c.S, c.R, c.ldr, c.info);
+                       (const double *)c.s_part, c.geo.g_rows2, j, c.S, c.R, c.ldr, c.info);
 }
 
 template <typename T>
 void launch_reorth_b(const Ctx &c, int64_t j, bool hp)
 {
     RowArgs a = row_args(c, j);
-    const dim3 grid((unsigned)c.geo.g_rows), block(256);
+    const dim3 grid((unsigned)c.geo.g_rows2), block(256);
     if (hp) {
-        AMGS_DISPATCH_U(c.geo.U, hipLaunchKernelGGL((k_reorth_b<T, UU, true>), grid, block, 0, c.stream, a));
+        AMGS_DISPATCH_U2(c.geo.U2, hipLaunchKernelGGL((k_reorth_b<T, UU, true>), grid, block, 0, c.stream, a));
     } else {
-        AMGS_DISPATCH_U(c.geo.U, hipLaunchKernelGGL((k_reorth_b<T, UU, false>), grid, block, 0, c.stream, a));
+        AMGS_DISPATCH_U2(c.geo.U2, hipLaunchKernelGGL((k_reorth_b<T, UU, false>), grid, block, 0, c.stream, a));
     }
 }
 
@@ -785,15 +908,15 @@ static void sweep_cols(const Ctx &c, int64_t ncols, int64_t &gy, int64_t &cpw)
 {
     if (ncols <= 0) {
         gy = 1;
-        cpw = 4;
+        cpw = SWEEP_CB;
         return;
     }
     gy = (SWEEP_TARGET_WG + c.geo.g_rows - 1) / c.geo.g_rows;
-    const int64_t max_gy = (ncols + 3) / 4;
+    const int64_t max_gy = (ncols + SWEEP_CB - 1) / SWEEP_CB;
     if (gy > max_gy) gy = max_gy;
     if (gy < 1) gy = 1;
     cpw = (ncols + gy - 1) / gy;
-    cpw = (cpw + 3) / 4 * 4;
+    cpw = (cpw + SWEEP_CB - 1) / SWEEP_CB * SWEEP_CB;
     if (cpw > MAX_CPW) cpw = MAX_CPW;
     gy = (ncols + cpw - 1) / cpw;
 }
@@ -809,11 +932,23 @@ void launch_sweep(const Ctx &c, int64_t j, int variant, int64_t n_rr)
     sweep_cols(c, c.n - j - 1, gy, cpw);
     a.cpw = cpw;
     const dim3 grid((unsigned)c.geo.g_rows, (unsigned)gy), block(256);
-#define AMGS_SWEEP_V(V_)                                                                          \
-    AMGS_DISPATCH_U(c.geo.U, hipLaunchKernelGGL((k_sweep<T, UU, V_>), grid, block, 0, c.stream, a))
-    if (variant == VAR_NAIVE) { AMGS_SWEEP_V(VAR_NAIVE); }
-    else if (variant == VAR_HA) { AMGS_SWEEP_V(VAR_HA); }
-    else { AMGS_SWEEP_V(VAR_HP); }
+    // later columns that no longer fit the last-level cache are streamed with
+    // non-temporal loads and stores; smaller trailing blocks stay cached for
+    // the next step
+    const bool nts = (double)(c.n - j - 1) * (double)c.m * sizeof(T) > SWEEP_NT_BYTES;
+#define AMGS_SWEEP_V(V_, NT_)                                                                     \
+    AMGS_DISPATCH_U(c.geo.U, if (c.ev_start) hipExtLaunchKernelGGL((k_sweep<T, UU, V_, NT_>),     \
+        grid, block, 0, c.stream, c.ev_start, c.ev_stop, 0, a);                                   \
+        else hipLaunchKernelGGL((k_sweep<T, UU, V_, NT_>), grid, block, 0, c.stream, a))
+    if (nts) {
+        if (variant == VAR_NAIVE) { AMGS_SWEEP_V(VAR_NAIVE, true); }
+        else if (variant == VAR_HA) { AMGS_SWEEP_V(VAR_HA, true); }
+        else { AMGS_SWEEP_V(VAR_HP, true); }
+    } else {
+        if (variant == VAR_NAIVE) { AMGS_SWEEP_V(VAR_NAIVE, false); }
+        else if (variant == VAR_HA) { AMGS_SWEEP_V(VAR_HA, false); }
+        else { AMGS_SWEEP_V(VAR_HP, false); }
+    }
 #undef AMGS_SWEEP_V
 }
 
