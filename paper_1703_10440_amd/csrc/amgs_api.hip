@@ -79,12 +79,12 @@ Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_g
     };
     // MV kernels never use more than MAX_G_MV workgroups, whatever the CSR
     // lane count, so the size does not depend on nnz
-    int64_t g_rr = g.g_rows2 > MAX_G_MV ? g.g_rows2 : MAX_G_MV;
+    int64_t g_rr = g.g_rows1 > MAX_G_MV ? g.g_rows1 : MAX_G_MV;
     L.part = take((size_t)n * g.g_rows * 8);
     L.s_part = reorth ? take((size_t)n * g.g_rows2 * 8) : off;
     L.rr_part = take((size_t)g_rr * 8);
     L.S = reorth ? take((size_t)n * 8) : off;
-    L.zt = variant != VAR_HP ? take((size_t)m * w) : off;
+    L.zt = (variant != VAR_HP || reorth) ? take((size_t)m * w) : off;
     L.xv = variant != VAR_HP ? take((size_t)m * w) : off;
     L.X = variant == VAR_HP ? take((size_t)m * n * w) : off;
     L.P = P_given ? off : take((size_t)m * n * w);
@@ -137,11 +137,12 @@ amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
                     launch_reorth_fin(c, j);
                     launch_reorth_b<T>(c, j, true);
                     st.kernel_launches += 3;
+                    n_rr = c.geo.g_rows1;   // A-norm partials of k_reorth_b
                 } else {
                     launch_col_hp<T>(c, j, false);
                     st.kernel_launches += 1;
+                    n_rr = c.geo.g_rows2;
                 }
-                n_rr = c.geo.g_rows2;
             } else {
                 if (reorth && j > 0) {
                     launch_reorth_a<T>(c, j);
@@ -247,6 +248,8 @@ Geo make_geo(int64_t m, int64_t nnz, int is_dense)
     g.U2 = g.U < 4 ? g.U : 4;
     g.g_rows2 = (m + 256 * g.U2 - 1) / (256 * g.U2);
     if (g.g_rows2 < 1) g.g_rows2 = 1;
+    g.g_rows1 = (m + 255) / 256;
+    if (g.g_rows1 < 1) g.g_rows1 = 1;
     const double avg = m > 0 ? (double)nnz / (double)m : 0.0;
     g.lanes = avg <= 7.5 ? 0 : avg <= 12 ? 1 : avg <= 24 ? 2 : avg <= 48 ? 4 : avg <= 96 ? 8
             : avg <= 192 ? 16 : avg <= 384 ? 32 : 64;

@@ -13,6 +13,7 @@ constexpr int SWEEP_TARGET_WG = 1024; // sweep workgroups aimed for
 constexpr int SWEEP_CB = 4;    // later columns streamed together by one sweep thread
 constexpr double SWEEP_NT_BYTES = 192.0 * (1 << 20); // trailing block streamed non-temporally above this
 constexpr int HP_XB = 8;       // HP recurrence terms applied per blocked update
+constexpr int RE_GROUP = 8;    // second-pass coefficients per workgroup row
 constexpr int DENSE_CB = 16;   // outputs per dense-MV workgroup pass
 constexpr int SPMM_C = 8;      // columns per CSR block-product thread
 constexpr int MAX_G_MV = 512;  // partials of an MV column kernel
@@ -30,6 +31,7 @@ struct Geo {
     int64_t g_rows; // sweep row chunks of 256*U rows
     int U2;         // rows per thread of the column / second-pass kernels (<= 4)
     int64_t g_rows2;// their row chunks of 256*U2 rows
+    int64_t g_rows1;// 256-row chunks (one row per thread)
     int lanes;      // lanes per CSR row in the MV kernel (0: 512-row tiles staged in LDS)
     int64_t g_csr;  // workgroups of the CSR MV kernel
     int64_t g_dense;// workgroups of the dense MV kernel

@@ -287,11 +287,13 @@ __global__ __launch_bounds__(256) void k_dense_mv(DenseMvArgs a)
 template <typename T, int U>
 __device__ __forceinline__ void reorth_partials(const T *__restrict__ P, int64_t ldp, int64_t j,
                                                 const T (&zr)[U], int64_t row0, int64_t m,
-                                                double *__restrict__ s_part, double (*red)[64])
+                                                double *__restrict__ s_part, double (*red)[64],
+                                                int64_t i_lo, int64_t i_hi)
 {
     const int tid = threadIdx.x, wave = tid / WAVE;
-    for (int64_t ib0 = 0; ib0 < j; ib0 += 64) {
-        const int64_t nb = (j - ib0 < 64) ? j - ib0 : 64;
+    if (i_hi > j) i_hi = j;
+    for (int64_t ib0 = i_lo; ib0 < i_hi; ib0 += 64) {
+        const int64_t nb = (i_hi - ib0 < 64) ? i_hi - ib0 : 64;
         for (int64_t ib = ib0; ib < ib0 + nb; ib += 8) {
             double sacc[8];
             T pv[8][U];
@@ -351,25 +353,29 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
         const bool in = k < a.m;
+        const bool xin = in && blockIdx.y == 0;   // only grid row 0 needs x_j
         zr[u] = in ? Q[k + j * a.ldq] : (T)0;
         qp[u] = (in && j > 0) ? Q[k + (j - 1) * a.ldq] : (T)0;
-        x[u] = in ? X[k + j * a.ldx] : (T)0;
+        x[u] = xin ? X[k + j * a.ldx] : (T)0;
 #pragma unroll
-        for (int t = 0; t < HP_XB; ++t) pv[t][u] = (in && i0 + t < j) ? P[k + (i0 + t) * a.ldp] : (T)0;
+        for (int t = 0; t < HP_XB; ++t) pv[t][u] = (xin && i0 + t < j) ? P[k + (i0 + t) * a.ldp] : (T)0;
     }
+    // with REORTH_A the grid has one row per group of second-pass
+    // coefficients; grid row 0 alone writes z_j (to zt, so that the other
+    // grid rows still read the old z_j from Q), x_j, and publishes R
+    const bool own = blockIdx.y == 0;
+    T *__restrict__ zdst = REORTH_A ? (T *)a.zt : Q + j * a.ldq;
     T r = 0;
     if (j > 0) {
-        publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
+        if (own) publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
         r = block_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
     }
     T xr[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
-        if (k < a.m && j > 0) {
-            zr[u] = upd(zr[u], r, qp[u]);
-            Q[k + j * a.ldq] = zr[u];
-        }
+        if (k < a.m && j > 0) zr[u] = upd(zr[u], r, qp[u]);
+        if (k < a.m && own && (j > 0 || REORTH_A)) zdst[k] = zr[u];
     }
     // x recurrence, i ascending, terms i >= XB floor((j-1)/XB) (the earlier
     // ones were applied by k_hp_xblock); r_ij (i < j-1) were published by
@@ -387,7 +393,7 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t k = row0 + u * 256 + tid;
-            if (k < a.m) X[k + j * a.ldx] = x[u];
+            if (k < a.m && own) X[k + j * a.ldx] = x[u];
             xr[u] = x[u];
         }
     }
@@ -398,7 +404,8 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
         double t = block_sum<double, 256>(acc, lds);
         if (tid == 0) a.rr_out[blockIdx.x] = t;
     } else {
-        reorth_partials<T, U>(P, a.ldp, j, zr, row0, a.m, a.s_part, red);
+        const int64_t i_lo = (int64_t)blockIdx.y * RE_GROUP;
+        reorth_partials<T, U>(P, a.ldp, j, zr, row0, a.m, a.s_part, red, i_lo, i_lo + RE_GROUP);
     }
 }
 
@@ -425,7 +432,7 @@ __global__ __launch_bounds__(256) void k_reorth_a(RowArgs a)
     }
     T r = 0;
     if (j > 0) {
-        publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
+        if (blockIdx.y == 0) publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
         r = block_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
     }
 #pragma unroll
@@ -433,10 +440,12 @@ __global__ __launch_bounds__(256) void k_reorth_a(RowArgs a)
         const int64_t k = row0 + u * 256 + tid;
         if (k < a.m) {
             if (j > 0) zr[u] = upd(zr[u], r, qp[u]);
-            zt[k] = zr[u];
+            if (blockIdx.y == 0) zt[k] = zr[u];
         }
     }
-    reorth_partials<T, U>(P, a.ldp, j, zr, row0, a.m, a.s_part, red);
+    // this grid row's group of coefficients
+    const int64_t i_lo = (int64_t)blockIdx.y * RE_GROUP;
+    reorth_partials<T, U>(P, a.ldp, j, zr, row0, a.m, a.s_part, red, i_lo, i_lo + RE_GROUP);
 }
 
 // ----------------------------------------------- second pass: finish s_i
@@ -468,7 +477,10 @@ __global__ __launch_bounds__(256) void k_reorth_b(RowArgs a)
     const int64_t j = a.j;
     const T *__restrict__ Q = (const T *)a.Q;
     const T *__restrict__ P = (const T *)a.P;
-    T *__restrict__ zv = HP ? (T *)a.Q + j * a.ldq : (T *)a.zt;
+    // z_j after the first pass is in zt (all variants); the corrected
+    // column goes back to zt (naive, HA: their MV reads it) or to Q (HP)
+    const T *__restrict__ zv = (const T *)a.zt;
+    T *__restrict__ zout = HP ? (T *)a.Q + j * a.ldq : (T *)a.zt;
     T *__restrict__ xv = HP ? (T *)a.X + j * a.ldx : nullptr;
     const int tid = threadIdx.x;
     const int64_t row0 = (int64_t)blockIdx.x * 256 * U;
@@ -508,7 +520,7 @@ __global__ __launch_bounds__(256) void k_reorth_b(RowArgs a)
         const int64_t k = row0 + u * 256 + tid;
         if (k < a.m) {
             const T z = (T)zd[u];
-            zv[k] = z;
+            zout[k] = z;
             if (HP) {
                 const T x = (T)xd[u];
                 xv[k] = x;
@@ -869,7 +881,8 @@ void launch_col_hp(const Ctx &c, int64_t j, bool reorth_a)
     RowArgs a = row_args(c, j);
     const dim3 grid((unsigned)c.geo.g_rows2), block(256);
     if (reorth_a) {
-        AMGS_DISPATCH_U2(c.geo.U2, hipLaunchKernelGGL((k_col_hp<T, UU, true>), grid, block, 0, c.stream, a));
+        const dim3 grid2((unsigned)c.geo.g_rows2, (unsigned)((j + RE_GROUP - 1) / RE_GROUP));
+        AMGS_DISPATCH_U2(c.geo.U2, hipLaunchKernelGGL((k_col_hp<T, UU, true>), grid2, block, 0, c.stream, a));
     } else {
         AMGS_DISPATCH_U2(c.geo.U2, hipLaunchKernelGGL((k_col_hp<T, UU, false>), grid, block, 0, c.stream, a));
     }
@@ -879,7 +892,7 @@ template <typename T>
 void launch_reorth_a(const Ctx &c, int64_t j)
 {
     RowArgs a = row_args(c, j);
-    const dim3 grid((unsigned)c.geo.g_rows2), block(256);
+    const dim3 grid((unsigned)c.geo.g_rows2, (unsigned)((j + RE_GROUP - 1) / RE_GROUP)), block(256);
     AMGS_DISPATCH_U2(c.geo.U2, hipLaunchKernelGGL((k_reorth_a<T, UU>), grid, block, 0, c.stream, a));
 }
 
@@ -890,16 +903,15 @@ void launch_reorth_fin(const Ctx &c, int64_t j)
                        (const double *)c.s_part, c.geo.g_rows2, j, c.S, c.R, c.ldr, c.info);
 }
 
+// One row per thread: the pass reads j earlier columns per row, so the
+// kernel needs many resident waves rather than several rows per thread.
 template <typename T>
 void launch_reorth_b(const Ctx &c, int64_t j, bool hp)
 {
     RowArgs a = row_args(c, j);
-    const dim3 grid((unsigned)c.geo.g_rows2), block(256);
-    if (hp) {
-        AMGS_DISPATCH_U2(c.geo.U2, hipLaunchKernelGGL((k_reorth_b<T, UU, true>), grid, block, 0, c.stream, a));
-    } else {
-        AMGS_DISPATCH_U2(c.geo.U2, hipLaunchKernelGGL((k_reorth_b<T, UU, false>), grid, block, 0, c.stream, a));
-    }
+    const dim3 grid((unsigned)c.geo.g_rows1), block(256);
+    if (hp) hipLaunchKernelGGL((k_reorth_b<T, 1, true>), grid, block, 0, c.stream, a);
+    else hipLaunchKernelGGL((k_reorth_b<T, 1, false>), grid, block, 0, c.stream, a);
 }
 
 // Column groups of the sweep: enough workgroups to fill the chip even when

@@ -216,3 +216,36 @@ def test_argument_errors():
     st = amgs.amgs_qr_dense(h, 10, Z.data_ptr(), 10, 0, Z.data_ptr(), 10, Z.data_ptr(), 10,
                             Z.data_ptr(), 1, None, 0, 1, 0, None, None, 0, info.data_ptr(), None)
     assert st == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_second_pass_many_workgroups(variant, precision):
+    """The second pass on a problem large enough that its kernels run
+    hundreds of workgroups per grid row and several grid rows of
+    coefficient groups (m = 64000, n = 40): parity with the oracle and
+    bit-identical repeated runs (a read/write race between workgroups would
+    show in either)."""
+    p = inputs.laplacian_graded_problem(N=40, n=40, decades=2.0, seed=14)
+    if precision == "fp32":
+        p = inputs.Problem(p.name, np.asfortranarray(p.Z.astype(np.float32).astype(np.float64)),
+                           csr=inputs.CSR(p.m, p.csr.row_ptr, p.csr.col_idx,
+                                          p.csr.vals.astype(np.float32).astype(np.float64)))
+    want = ref.qr_problem(p, variant=variant, reorth=True, precision=precision)
+    Q, R, P, info, _ = gpu_run(p, variant, precision=precision, reorth=True)
+    Q2, R2, _, _, _ = gpu_run(p, variant, precision=precision, reorth=True)
+    assert info == 0
+    assert np.array_equal(R, R2) and np.array_equal(Q, Q2)
+    o_g, o_o = orth(p, Q), orth(p, want.Q)
+    if precision == "fp64":
+        e = _rel(R, want.R)
+        print(f"  R {e:.2e} orth {o_g:.2e} (oracle {o_o:.2e})")
+        assert e <= 1e-10
+        assert o_g <= max(1e-13, 10 * o_o)
+    else:
+        kappa = np.linalg.cond(ref.qr_problem(p, variant=variant).R)
+        tol = 64 * U32 * kappa * np.sqrt(p.n)
+        e = _rel(R, want.R)
+        print(f"  R vs fp32 oracle {e:.2e} tol {tol:.2e} orth {o_g:.2e} (oracle {o_o:.2e})")
+        assert e <= tol
+        assert o_g <= max(10 * o_o, 1e-6)
