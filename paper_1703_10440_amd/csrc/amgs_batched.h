@@ -13,6 +13,8 @@ constexpr int BT_MAX_M = BT_NT * BT_RPT;
 constexpr int BT_MAX_N = 256;       // largest n of an instance
 constexpr int BT_RED = 8;           // values per workgroup reduction
 constexpr int BT_NCLASS = 8;        // size classes: 4 ranges of m x (n <= 16, n > 16)
+constexpr int BT_TILE_HA = 8;       // widest column block (registers): naive / HA
+constexpr int BT_TILE_HP = 4;       // HP keeps z and x blocks
 
 // One entry of the device work list, in largest-first order.
 struct BatchItem {

@@ -33,28 +33,35 @@ __device__ __forceinline__ void bt_zero(A *v, int n)
 }
 
 // Sum NV per-thread values across the workgroup (only the first nv <= NV
-// are used); the result for value v lands in out[v] (LDS), readable by
-// every thread after the closing barrier.  Fixed order: wave butterflies,
-// then the waves in order.
+// are used) with a single barrier: each wave's DPP sum goes to LDS slot
+// buffer `buf` (callers alternate 0/1 between consecutive reductions, so a
+// slot is never rewritten while another thread may still read it), then
+// every thread adds the wave sums in wave order.  out[v] receives the sum of
+// value v in every thread (registers, no second barrier).
 template <typename A, int NV>
-__device__ __forceinline__ void bt_reduce(const A (&vals)[NV], int nv, A (*red)[BT_RED], A *out)
+__device__ __forceinline__ void bt_reduce(const A (&vals)[NV], int nv, A (*red)[BT_NT / WAVE][BT_RED],
+                                          int &buf, A (&out)[NV])
 {
     const int lane = threadIdx.x & (WAVE - 1), wave = threadIdx.x / WAVE;
 #pragma unroll
     for (int v = 0; v < NV; ++v) {
         if (v < nv) {
             A s = wave_sum(vals[v]);
-            if (lane == 0) red[wave][v] = s;
+            if (lane == 0) red[buf][wave][v] = s;
         }
     }
     __syncthreads();
-    if (threadIdx.x < nv) {
-        A s = red[0][threadIdx.x];
 #pragma unroll
-        for (int w = 1; w < BT_NT / WAVE; ++w) s += red[w][threadIdx.x];
-        out[threadIdx.x] = s;
+    for (int v = 0; v < NV; ++v) {
+        A s = 0;
+        if (v < nv) {
+            s = red[buf][0][v];
+#pragma unroll
+            for (int w = 1; w < BT_NT / WAVE; ++w) s += red[buf][w][v];
+        }
+        out[v] = s;
     }
-    __syncthreads();
+    buf ^= 1;
 }
 
 template <typename T, int VAR, int BMAX>
@@ -65,12 +72,11 @@ __global__ __launch_bounds__(BT_NT) void k_batched(const amgs_batch_desc_t *__re
                                                    uint32_t *__restrict__ counter, int reorth)
 {
     __shared__ T vec[BT_MAX_M];                 // one column for the in-workgroup MV
-    __shared__ T redT[BT_NT / WAVE][BT_RED];
-    __shared__ double redD[BT_NT / WAVE][BT_RED];
-    __shared__ T outT[BT_RED];
-    __shared__ double outD[BT_RED];
+    __shared__ T redT[2][BT_NT / WAVE][BT_RED];
+    __shared__ double redD[2][BT_NT / WAVE][BT_RED];
     __shared__ int32_t s_idx;
     const int tid = threadIdx.x;
+    int bufT = 0, bufD = 0;
 
     for (;;) {
         if (tid == 0) s_idx = (int32_t)atomicAdd(counter, 1u);
@@ -120,14 +126,24 @@ __global__ __launch_bounds__(BT_NT) void k_batched(const amgs_batch_desc_t *__re
                     zb[b][u] = in ? Z[r + (j0 + b) * ldz] : (T)0;
                     if (VAR == VAR_HP) xb[b][u] = in ? X[r + (j0 + b) * m] : (T)0;
                 }
-            // earlier columns, i ascending: one reduction of bw dots per i
+            // earlier columns, i ascending: one reduction of bw dots per i;
+            // the loads of p_{i+1}, q_{i+1} are issued before the reduction
+            T pn[BT_RPT], qn[BT_RPT];
+#pragma unroll
+            for (int u = 0; u < BT_RPT; ++u) {
+                const int64_t r = tid + u * BT_NT;
+                pn[u] = (j0 > 0 && r < m) ? P[r] : (T)0;
+                qn[u] = (j0 > 0 && r < m) ? Q[r] : (T)0;
+            }
             for (int64_t i = 0; i < j0; ++i) {
-                T pr[BT_RPT], qr[BT_RPT], dots[BMAX];
+                T pr[BT_RPT], qr[BT_RPT], dots[BMAX], rvals[BMAX];
 #pragma unroll
                 for (int u = 0; u < BT_RPT; ++u) {
+                    pr[u] = pn[u];
+                    qr[u] = qn[u];
                     const int64_t r = tid + u * BT_NT;
-                    pr[u] = r < m ? P[r + i * m] : (T)0;
-                    qr[u] = r < m ? Q[r + i * ldq] : (T)0;
+                    pn[u] = (i + 1 < j0 && r < m) ? P[r + (i + 1) * m] : (T)0;
+                    qn[u] = (i + 1 < j0 && r < m) ? Q[r + (i + 1) * ldq] : (T)0;
                 }
 #pragma unroll
                 for (int b = 0; b < BMAX; ++b) {
@@ -136,11 +152,11 @@ __global__ __launch_bounds__(BT_NT) void k_batched(const amgs_batch_desc_t *__re
                     for (int u = 0; u < BT_RPT; ++u) s += pr[u] * zb[b][u];
                     dots[b] = s;
                 }
-                bt_reduce<T, BMAX>(dots, bw, redT, outT);
+                bt_reduce<T, BMAX>(dots, bw, redT, bufT, rvals);
 #pragma unroll
                 for (int b = 0; b < BMAX; ++b) {
                     if (b < bw) {
-                        const T rib = outT[b];
+                        const T rib = rvals[b];
 #pragma unroll
                         for (int u = 0; u < BT_RPT; ++u) {
                             zb[b][u] = upd(zb[b][u], rib, qr[u]);
@@ -179,11 +195,12 @@ __global__ __launch_bounds__(BT_NT) void k_batched(const amgs_batch_desc_t *__re
                             }
                             sp[t] = sacc;
                         }
-                        bt_reduce<double, BT_RED>(sp, ni, redD, outD);
+                        double sv[BT_RED];
+                        bt_reduce<double, BT_RED>(sp, ni, redD, bufD, sv);
 #pragma unroll
                         for (int t = 0; t < BT_RED; ++t) {
                             if (t < ni) {
-                                const double sc = outD[t];
+                                const double sc = sv[t];
 #pragma unroll
                                 for (int u = 0; u < BT_RPT; ++u) {
                                     const int64_t r = tid + u * BT_NT;
@@ -228,8 +245,9 @@ __global__ __launch_bounds__(BT_NT) void k_batched(const amgs_batch_desc_t *__re
                 nrm[0] = 0.0;
 #pragma unroll
                 for (int u = 0; u < BT_RPT; ++u) nrm[0] += (double)zb[b][u] * (double)xr[u];
-                bt_reduce<double, 1>(nrm, 1, redD, outD);
-                const double rr = outD[0];
+                double rrv[1];
+                bt_reduce<double, 1>(nrm, 1, redD, bufD, rrv);
+                const double rr = rrv[0];
                 if (!norm_ok(rr)) {
                     if (tid == 0) info[it.k] = (int32_t)(j + 1);
                     broke = true;
@@ -282,11 +300,12 @@ __global__ __launch_bounds__(BT_NT) void k_batched(const amgs_batch_desc_t *__re
                         }
                         dots[c] = s;
                     }
-                    bt_reduce<T, BMAX>(dots, bw, redT, outT);
+                    T rv[BMAX];
+                    bt_reduce<T, BMAX>(dots, bw, redT, bufT, rv);
 #pragma unroll
                     for (int c = 0; c < BMAX; ++c) {
                         if (c > b && c < bw) {
-                            const T rjc = outT[c];
+                            const T rjc = rv[c];
 #pragma unroll
                             for (int u = 0; u < BT_RPT; ++u) {
                                 zb[c][u] = upd(zb[c][u], rjc, qv[u]);
@@ -316,17 +335,22 @@ static void launch_t(int grid, const amgs_batch_desc_t *desc, const BatchItem *i
 }
 
 // Widest tile compiled for a variant: HP keeps two register blocks (z and
-// x), so it stops at 2 columns to stay clear of register spills.
-static int max_tile(int variant) { return variant == VAR_HP ? 2 : 4; }
+// x), so its limit is lower, to stay clear of register spills.
+static int max_tile(int variant) { return variant == VAR_HP ? BT_TILE_HP : BT_TILE_HA; }
+
+template <int VAR> constexpr int tile_cap() { return VAR == VAR_HP ? BT_TILE_HP : BT_TILE_HA; }
+template <int B, int CAP> constexpr int tile_clip() { return B < CAP ? B : CAP; }
 
 template <typename T, int VAR>
 static void launch_v(int bmax, int grid, const amgs_batch_desc_t *desc, const BatchItem *items,
                      int32_t count, void *work, int32_t *info, uint32_t *counter, int reorth,
                      hipStream_t s)
 {
+    constexpr int CAP = tile_cap<VAR>();
     if (bmax <= 1) launch_t<T, VAR, 1>(grid, desc, items, count, work, info, counter, reorth, s);
-    else if (bmax <= 2 || VAR == VAR_HP) launch_t<T, VAR, 2>(grid, desc, items, count, work, info, counter, reorth, s);
-    else launch_t<T, VAR, (VAR == VAR_HP ? 2 : 4)>(grid, desc, items, count, work, info, counter, reorth, s);
+    else if (bmax <= 2) launch_t<T, VAR, tile_clip<2, CAP>()>(grid, desc, items, count, work, info, counter, reorth, s);
+    else if (bmax <= 4) launch_t<T, VAR, tile_clip<4, CAP>()>(grid, desc, items, count, work, info, counter, reorth, s);
+    else launch_t<T, VAR, tile_clip<8, CAP>()>(grid, desc, items, count, work, info, counter, reorth, s);
 }
 
 void launch_batched(int precision, int variant, int bmax, int reorth, int grid,
@@ -357,8 +381,10 @@ static int occ_t()
 template <typename T, int VAR>
 static int occ_v(int bmax)
 {
+    constexpr int CAP = tile_cap<VAR>();
     return bmax <= 1 ? occ_t<T, VAR, 1>()
-         : (bmax <= 2 || VAR == VAR_HP) ? occ_t<T, VAR, 2>() : occ_t<T, VAR, (VAR == VAR_HP ? 2 : 4)>();
+         : bmax <= 2 ? occ_t<T, VAR, tile_clip<2, CAP>()>()
+         : bmax <= 4 ? occ_t<T, VAR, tile_clip<4, CAP>()>() : occ_t<T, VAR, tile_clip<8, CAP>()>();
 }
 
 int batched_resident_wgs(int device, int precision, int variant, int bmax)
@@ -578,7 +604,8 @@ float time_tile(amgs_batch_plan *pl, TuneSet &ts, int B, hipStream_t s, hipEvent
     return best;
 }
 
-// Autotuner: for every size class present, time B in {1, 2, 4} on up to 64
+// Autotuner: for every size class present, time B in {1, 2, 4, 8} (up to the
+// variant's register limit) on up to 64
 // synthetic instances with the class's largest shapes and keep the fastest.
 template <typename T>
 void autotune(amgs_batch_plan *pl)
@@ -601,7 +628,7 @@ void autotune(amgs_batch_plan *pl)
         if (!make_tune_set<T>(ts, ks, pl)) continue;
         int bestB = pl->class_B[cls];
         float bestT = -1.f;
-        for (int B : {1, 2, 4}) {
+        for (int B : {1, 2, 4, 8}) {
             if (B > max_tile(pl->variant)) continue;
             const float t = time_tile(pl, ts, B, s, e0, e1);
             if (t > 0.f && (bestT < 0.f || t < bestT)) {
