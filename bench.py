@@ -282,6 +282,53 @@ def bench_batched(args, torch, amgs):
             "variants": results}
 
 
+# ------------------------------------------------------- accuracy experiment
+def bench_exp2(args, torch, amgs):
+    """Experiments II/III (Section 4) on the GPU binary64 path: m = 100,
+    n = 20, kappa(A), kappa(Z) on the 28-point grid 10^0.5 .. 10^14, cases 1
+    and 2.  Reports the loss of A-orthogonality of each variant against
+    delta_1 = u kappa(A) kappa(A^{1/2} Z) and delta_2 = u (kappa(A) +
+    kappa(A^{1/2} Z)); kappa(A^{1/2} Z) is taken as kappa(R)."""
+    import numpy as np
+    from paper_1703_10440_amd import inputs
+    u = 2.0 ** -53
+    dev = torch.device("cuda:0")
+    grid = [10.0 ** (0.5 * k) for k in range(1, 29)]
+    out = {}
+    t0 = time.perf_counter()
+    for case in (1, 2):
+        rec = {v: [] for v in ("naive", "ha", "hp")}
+        for ia, ka in enumerate(grid):
+            for iz, kz in enumerate(grid):
+                p = inputs.exp2_problem(100, 20, ka, kz, case, seed=10000 * case + 100 * ia + iz)
+                A = torch.from_numpy(np.ascontiguousarray(p.dense)).to(dev)
+                Zt = torch.from_numpy(np.ascontiguousarray(p.Z)).to(dev)
+                for v in rec:
+                    o = amgs.qr_dense(A, Zt, variant=v)
+                    Q, R = o.Q, o.R
+                    G = Q.T @ (A @ Q)
+                    loss = float(torch.linalg.matrix_norm(G - torch.eye(20, dtype=G.dtype, device=dev), ord=2))
+                    kAZ = float(torch.linalg.cond(R))
+                    rec[v].append((ka, kAZ, loss, int(o.info.item())))
+        summ = {}
+        for v, rows in rec.items():
+            ok = [r for r in rows if r[3] == 0]
+            d1 = np.array([u * r[0] * r[1] for r in ok])
+            d2 = np.array([u * (r[0] + r[1]) for r in ok])
+            lo = np.array([r[2] for r in ok])
+            summ[v] = {"problems": len(rows), "breakdowns": len(rows) - len(ok),
+                       "median_loss_over_delta1": float(np.median(lo / d1)),
+                       "max_loss_over_delta1": float(np.max(lo / d1)),
+                       "median_loss_over_delta2": float(np.median(lo / d2))}
+        n = len(rec["ha"])
+        better = sum(1 for a, b in zip(rec["ha"], rec["naive"]) if a[2] < b[2])
+        summ["ha_more_accurate_than_naive"] = f"{better}/{n}"
+        out[f"case{case}"] = summ
+        log(f"[bench] exp2 case {case}: {summ}")
+    return {"workload": "exp2", "grid": "28 x 28 kappa(A), kappa(Z) in 10^0.5..10^14",
+            "m": 100, "n": 20, "seconds": round(time.perf_counter() - t0, 1), "results": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -289,7 +336,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lap64_n64",
                     choices=["lap64_n64", "lap128_n128", "dense512_n32", "dense16k_n256",
-                             "batch2048", "copy1g"])
+                             "batch2048", "copy1g", "exp2"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-variants", action="store_true")
@@ -313,6 +360,9 @@ def main():
         print(json.dumps({"workload": "copy1g", "bytes_read": 1 << 30, "bytes_written": 1 << 30,
                           "ms": round(t * 1e3, 4), "GB_per_s": round(2 * (1 << 30) / t / 1e9, 1)}),
               flush=True)
+        return
+    if args.workload == "exp2":
+        print(json.dumps(bench_exp2(args, torch, amgs)), flush=True)
         return
     if args.workload == "batch2048":
         line = bench_batched(args, torch, amgs)
