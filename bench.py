@@ -162,6 +162,31 @@ def sweep_roofline(runner, amgs, torch):
             "bytes_per_launch": bytes_per_launch}
 
 
+def mv_roofline(data, precision, amgs, torch):
+    """The per-column MV of the HA form (Alg. 5; CSR SpMV or dense MV with
+    the pending projection applied on the fly): average duration from HIP
+    events bound to each MV dispatch, and its algorithmic bytes (A once, the
+    two source vectors, the two written vectors)."""
+    h = amgs.handle(0)
+    r = Runner(data, "ha", precision, torch, amgs)
+    r()
+    torch.cuda.synchronize()
+    amgs.amgs_profile_reset(h)
+    amgs.amgs_profile_enable(h, 1)
+    out = r()
+    torch.cuda.synchronize()
+    amgs.amgs_profile_enable(h, 0)
+    ms, launches = amgs.amgs_profile_read(h, 1)
+    st = out.stats
+    avg_s = ms / 1e3 / max(launches, 1)
+    bpl = st.mv_bytes / max(st.mv_calls, 1)
+    ach = bpl / avg_s / 1e9
+    return {"bound": "hbm", "kernel": "k_csr_mv_stream / k_dense_mv (HA column MV)",
+            "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(ach / HBM_PEAK_GBS, 4), "avg_us": round(avg_s * 1e6, 3),
+            "launches": int(launches), "bytes_per_launch": bpl}
+
+
 def cpu_baseline(prob, variant, budget_s=10.0):
     """The oracle as it stands, repeated on the full workload until about
     budget_s seconds of host time have passed."""
@@ -196,6 +221,8 @@ def bench_single(args, torch, amgs):
     roof = sweep_roofline(run, amgs, torch)
     log(f"[bench] sweep roofline {roof}")
     del run
+    mvroof = mv_roofline(data, head_p, amgs, torch)
+    log(f"[bench] mv roofline {mvroof}")
 
     variants = {}
     if not args.no_variants:
@@ -232,7 +259,7 @@ def bench_single(args, torch, amgs):
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t * 1e3, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64" if head_p == "fp64" else "f32", "data": "synthetic", "config": cfg,
-            "roofline": roof, "cpu_baseline": cpu, "variants": variants}
+            "roofline": roof, "mv_roofline": mvroof, "cpu_baseline": cpu, "variants": variants}
 
 
 # --------------------------------------------------------------------- batched

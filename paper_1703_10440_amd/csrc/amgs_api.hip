@@ -49,14 +49,14 @@ struct ProfScope {
     hipEvent_t a = nullptr, b = nullptr;
     ProfScope(amgs_handle *h_, int cat_, hipStream_t s_) : h(h_), cat(cat_), s(s_)
     {
-        if (!h->profiling) return;
+        if (!h->profiling || cat < 0) return;
         a = take_event(h);
         b = take_event(h);
         if (a && b) (void)hipEventRecord(a, s);
     }
     ~ProfScope()
     {
-        if (!h->profiling || !a || !b) return;
+        if (!h->profiling || cat < 0 || !a || !b) return;
         (void)hipEventRecord(b, s);
         h->recs.push_back({cat, a, b});
     }
@@ -130,7 +130,7 @@ amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
     for (int64_t j = 0; j < c.n; ++j) {
         int64_t n_rr;
         {
-            ProfScope ps(h, 1, c.stream);
+            ProfScope ps(h, variant == VAR_HP ? 1 : -1, c.stream);
             if (variant == VAR_HP) {
                 if (reorth && j > 0) {
                     launch_col_hp<T>(c, j, true);
@@ -144,19 +144,36 @@ amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
                     n_rr = c.geo.g_rows2;
                 }
             } else {
+                // with profiling on, the column MV (category 1) is timed with
+                // events bound to its dispatch
+                hipEvent_t m0 = nullptr, m1 = nullptr;
+                if (h->profiling) {
+                    m0 = take_event(h);
+                    m1 = take_event(h);
+                }
                 if (reorth && j > 0) {
                     launch_reorth_a<T>(c, j);
                     launch_reorth_fin(c, j);
                     launch_reorth_b<T>(c, j, false);
+                    c.ev_start = m0;
+                    c.ev_stop = m1;
                     launch_mv<T>(c, j, SRC_VEC);
                     st.kernel_launches += 4;
                 } else {
+                    c.ev_start = m0;
+                    c.ev_stop = m1;
                     launch_mv<T>(c, j, SRC_UPD);
                     st.kernel_launches += 1;
                 }
+                c.ev_start = c.ev_stop = nullptr;
+                if (m0 && m1) h->recs.push_back({1, m0, m1});
                 st.mv_calls += 1;
                 st.mv_columns += 1;
-                st.mv_bytes += mvA + 2.0 * (double)c.m * w;
+                // A once; z_j and q_{j-1} read (z_j only at j = 0, or the
+                // corrected column after the second pass), x_j and z_j written
+                // (x_j only after the second pass)
+                const double vecs = (reorth && j > 0) ? 2.0 : (j > 0 ? 4.0 : 3.0);
+                st.mv_bytes += mvA + vecs * (double)c.m * w;
                 if (variant == VAR_NAIVE) {
                     launch_mv<T>(c, j, SRC_DIV);
                     st.kernel_launches += 1;

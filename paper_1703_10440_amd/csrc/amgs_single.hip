@@ -107,7 +107,23 @@ __global__ __launch_bounds__(512) void k_csr_mv(CsrMvArgs a)
     for (int64_t row = (int64_t)blockIdx.x * gpw + g; row < a.m; row += (int64_t)gridDim.x * gpw) {
         const int32_t e0 = a.row_ptr[row], e1 = a.row_ptr[row + 1];
         T s = 0;
-        for (int32_t e = e0 + lig; e < e1; e += L) s += vals[e] * load(a.col_idx[e]);
+        // each lane takes every L-th entry, eight at a time with all gathers
+        // in flight; entries past the row's end are skipped
+        for (int32_t eb = e0 + lig; eb < e1; eb += 8 * L) {
+            int64_t col[8];
+            T av[8], xv[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const bool in = eb + t * L < e1;
+                col[t] = in ? a.col_idx[eb + t * L] : row;
+                av[t] = in ? vals[eb + t * L] : (T)0;
+            }
+#pragma unroll
+            for (int t = 0; t < 8; ++t) xv[t] = load(col[t]);
+#pragma unroll
+            for (int t = 0; t < 8; ++t)
+                if (eb + t * L < e1) s += av[t] * xv[t];
+        }
 #pragma unroll
         for (int off = L / 2; off >= 1; off >>= 1) s += __shfl_xor(s, off, L);
         if (lig == 0) {
@@ -178,10 +194,23 @@ __global__ __launch_bounds__(512) void k_csr_mv_stream(CsrMvArgs a)
         if (row < a.m) {
             const int32_t e0 = a.row_ptr[row], e1 = a.row_ptr[row + 1];
             T s = 0;
-            if (staged) {
-                for (int32_t e = e0; e < e1; ++e) s += s_val[e - t0] * load(s_col[e - t0]);
-            } else {
-                for (int32_t e = e0; e < e1; ++e) s += vals[e] * load(a.col_idx[e]);
+            // eight entries at a time: indices and values first, then every
+            // gather in flight, then the sum in stored order (entries past
+            // the row's end are skipped, not multiplied by zero)
+            for (int32_t eb = e0; eb < e1; eb += 8) {
+                int64_t col[8];
+                T av[8], xv[8];
+#pragma unroll
+                for (int t = 0; t < 8; ++t) {
+                    const bool in = eb + t < e1;
+                    col[t] = in ? (staged ? s_col[eb + t - t0] : a.col_idx[eb + t]) : row;
+                    av[t] = in ? (staged ? s_val[eb + t - t0] : vals[eb + t]) : (T)0;
+                }
+#pragma unroll
+                for (int t = 0; t < 8; ++t) xv[t] = load(col[t]);
+#pragma unroll
+                for (int t = 0; t < 8; ++t)
+                    if (eb + t < e1) s += av[t] * xv[t];
             }
             y[row] = s;
             if (SRC == SRC_UPD || RR) {
@@ -742,17 +771,20 @@ __global__ __launch_bounds__(256) void k_csr_spmm(int64_t m, int64_t n, const in
             l[t] = in ? col_idx[eb + t] : 0;
             v[t] = in ? vals[eb + t] : (T)0;
         }
+        // entries past the row's end are skipped, not multiplied by zero
         if (nc == C) {
 #pragma unroll
             for (int c = 0; c < C; ++c)
 #pragma unroll
-                for (int t = 0; t < 8; ++t) acc[c] += v[t] * Zc[l[t] + c * ldz];
+                for (int t = 0; t < 8; ++t)
+                    if (eb + t < e1) acc[c] += v[t] * Zc[l[t] + c * ldz];
         } else {
 #pragma unroll
             for (int c = 0; c < C; ++c)
                 if (c < nc)
 #pragma unroll
-                    for (int t = 0; t < 8; ++t) acc[c] += v[t] * Zc[l[t] + c * ldz];
+                    for (int t = 0; t < 8; ++t)
+                        if (eb + t < e1) acc[c] += v[t] * Zc[l[t] + c * ldz];
         }
     }
 #pragma unroll
@@ -790,19 +822,28 @@ void launch_init(const Ctx &c, int copy)
                        (const T *)c.Z, c.ldz, (T *)c.Q, c.ldq, c.R, c.ldr, c.info, copy);
 }
 
+// Launch on the context's stream; with profiling events set, the events are
+// bound to the kernel's own dispatch.
+template <typename K, typename A>
+static void launch_k(const Ctx &c, K kernel, dim3 grid, dim3 block, const A &args)
+{
+    if (c.ev_start) hipExtLaunchKernelGGL(kernel, grid, block, 0, c.stream, c.ev_start, c.ev_stop, 0, args);
+    else hipLaunchKernelGGL(kernel, grid, block, 0, c.stream, args);
+}
+
 template <typename T, int SRC, bool RR>
 static void launch_csr_mv_L(const Ctx &c, CsrMvArgs &a)
 {
     const dim3 grid((unsigned)c.geo.g_csr), block(512);
     switch (c.geo.lanes) {
-    case 0: hipLaunchKernelGGL((k_csr_mv_stream<T, SRC, RR>), grid, block, 0, c.stream, a); break;
-    case 1: hipLaunchKernelGGL((k_csr_mv<T, 1, SRC, RR>), grid, block, 0, c.stream, a); break;
-    case 2: hipLaunchKernelGGL((k_csr_mv<T, 2, SRC, RR>), grid, block, 0, c.stream, a); break;
-    case 4: hipLaunchKernelGGL((k_csr_mv<T, 4, SRC, RR>), grid, block, 0, c.stream, a); break;
-    case 8: hipLaunchKernelGGL((k_csr_mv<T, 8, SRC, RR>), grid, block, 0, c.stream, a); break;
-    case 16: hipLaunchKernelGGL((k_csr_mv<T, 16, SRC, RR>), grid, block, 0, c.stream, a); break;
-    case 32: hipLaunchKernelGGL((k_csr_mv<T, 32, SRC, RR>), grid, block, 0, c.stream, a); break;
-    default: hipLaunchKernelGGL((k_csr_mv<T, 64, SRC, RR>), grid, block, 0, c.stream, a); break;
+    case 0: launch_k(c, k_csr_mv_stream<T, SRC, RR>, grid, block, a); break;
+    case 1: launch_k(c, k_csr_mv<T, 1, SRC, RR>, grid, block, a); break;
+    case 2: launch_k(c, k_csr_mv<T, 2, SRC, RR>, grid, block, a); break;
+    case 4: launch_k(c, k_csr_mv<T, 4, SRC, RR>, grid, block, a); break;
+    case 8: launch_k(c, k_csr_mv<T, 8, SRC, RR>, grid, block, a); break;
+    case 16: launch_k(c, k_csr_mv<T, 16, SRC, RR>, grid, block, a); break;
+    case 32: launch_k(c, k_csr_mv<T, 32, SRC, RR>, grid, block, a); break;
+    default: launch_k(c, k_csr_mv<T, 64, SRC, RR>, grid, block, a); break;
     }
 }
 
@@ -821,16 +862,13 @@ void launch_mv(const Ctx &c, int64_t j, int src_mode)
         if (src_mode == SRC_UPD) {
             a.src = Q + j * c.ldq; a.qprev = j > 0 ? Q + (j - 1) * c.ldq : nullptr;
             a.y = c.xv; a.zt = c.zt;
-            hipLaunchKernelGGL((k_dense_mv<T, DENSE_CB, SRC_UPD, true>), dim3((unsigned)c.geo.g_dense),
-                               dim3(256), 0, c.stream, a);
+            launch_k(c, k_dense_mv<T, DENSE_CB, SRC_UPD, true>, dim3((unsigned)c.geo.g_dense), dim3(256), a);
         } else if (src_mode == SRC_VEC) {
             a.src = c.zt; a.y = c.xv;
-            hipLaunchKernelGGL((k_dense_mv<T, DENSE_CB, SRC_VEC, true>), dim3((unsigned)c.geo.g_dense),
-                               dim3(256), 0, c.stream, a);
+            launch_k(c, k_dense_mv<T, DENSE_CB, SRC_VEC, true>, dim3((unsigned)c.geo.g_dense), dim3(256), a);
         } else {
             a.src = c.zt; a.y = (T *)c.P + j * c.ldp;
-            hipLaunchKernelGGL((k_dense_mv<T, DENSE_CB, SRC_DIV, false>), dim3((unsigned)c.geo.g_dense),
-                               dim3(256), 0, c.stream, a);
+            launch_k(c, k_dense_mv<T, DENSE_CB, SRC_DIV, false>, dim3((unsigned)c.geo.g_dense), dim3(256), a);
         }
     } else {
         CsrMvArgs a{};
