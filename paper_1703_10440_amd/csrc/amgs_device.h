@@ -69,21 +69,23 @@ __device__ __forceinline__ A wave_sum(A v)
     return lane63(v);
 }
 
-// Canonical reduction of v[0..N): lane l adds v[l], v[l+64], ... in
-// ascending order, then the butterfly.  Any wave of any workgroup calling it
-// on the same data gets the same bits.
+// Canonical reduction of v[0..N): lane l adds v[l], v[l+64], v[l+128], ...
+// in ascending order into one accumulator, then the butterfly.  The loads
+// are issued eight at a time, so N <= 512 costs one memory round trip.  Any
+// wave of any workgroup calling it on the same data gets the same bits.
 template <typename A>
 __device__ __forceinline__ A wave_reduce_seq(const A *__restrict__ v, int64_t N)
 {
     const int lane = threadIdx.x & (WAVE - 1);
-    A s0 = 0, s1 = 0;
-    int64_t i = lane;
-    for (; i + WAVE < N; i += 2 * WAVE) {
-        s0 += v[i];
-        s1 += v[i + WAVE];
+    A s = 0;
+    for (int64_t i = lane; i < N; i += 8 * WAVE) {
+        A t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t[k] = i + k * WAVE < N ? v[i + k * WAVE] : (A)0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) s += t[k];
     }
-    if (i < N) s0 += v[i];
-    return wave_sum(s0 + s1);
+    return wave_sum(s);
 }
 
 // wave_reduce_seq computed once per workgroup (by wave 0) and broadcast

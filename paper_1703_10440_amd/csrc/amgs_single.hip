@@ -86,10 +86,7 @@ __global__ __launch_bounds__(512) void k_csr_mv(CsrMvArgs a)
 
     T r = 0;
     double rjj = 1.0;
-    if (SRC == SRC_UPD && qprev) {
-        publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
-        r = block_reduce_bcast((const T *)a.sp.part + a.j * a.sp.g, a.sp.g, &s_r);
-    }
+    if (SRC == SRC_UPD && qprev) r = block_reduce_bcast((const T *)a.sp.part + a.j * a.sp.g, a.sp.g, &s_r);
     if (SRC == SRC_DIV) {
         double rr = block_reduce_bcast(a.rr_part, a.n_rr, &s_rr);
         if (!norm_ok(rr)) return;
@@ -139,6 +136,8 @@ __global__ __launch_bounds__(512) void k_csr_mv(CsrMvArgs a)
         double t = block_sum<double, 512>(acc, lds);
         if (threadIdx.x == 0) a.rr_out[blockIdx.x] = t;
     }
+    // R[j-1, c] for c >= j (read by later kernels only) is published last
+    if (SRC == SRC_UPD && qprev) publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
 }
 
 // CSR MV for short rows ("CSR stream"): a workgroup takes 512 consecutive
@@ -149,6 +148,7 @@ __global__ __launch_bounds__(512) void k_csr_mv(CsrMvArgs a)
 template <typename T, int SRC, bool RR>
 __global__ __launch_bounds__(512) void k_csr_mv_stream(CsrMvArgs a)
 {
+    constexpr int PER = STREAM_CAP / 512;
     __shared__ int32_t s_col[STREAM_CAP];
     __shared__ T s_val[STREAM_CAP];
     __shared__ double lds[512 / WAVE];
@@ -160,39 +160,78 @@ __global__ __launch_bounds__(512) void k_csr_mv_stream(CsrMvArgs a)
     const T *__restrict__ qprev = (const T *)a.qprev;
     T *__restrict__ y = (T *)a.y;
     T *__restrict__ zt = (T *)a.zt;
+    const bool with_upd = SRC == SRC_UPD && qprev;
+    const int tid = threadIdx.x;
     T r = 0;
     double rjj = 1.0;
-    if (SRC == SRC_UPD && qprev) {
-        publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
-        r = block_reduce_bcast((const T *)a.sp.part + a.j * a.sp.g, a.sp.g, &s_r);
-    }
-    if (SRC == SRC_DIV) {
-        double rr = block_reduce_bcast(a.rr_part, a.n_rr, &s_rr);
-        if (!norm_ok(rr)) return;
-        rjj = sqrt(rr);
-    }
-    auto load = [&](int64_t l) -> T {
-        T v = src[l];
-        if (SRC == SRC_UPD && qprev) v = upd(v, r, qprev[l]);
-        if (SRC == SRC_DIV) v = scale_div(v, rjj);
-        return v;
-    };
-    const int tid = threadIdx.x;
     double acc = 0.0;
+    bool first = true;
     for (int64_t row0 = (int64_t)blockIdx.x * 512; row0 < a.m; row0 += (int64_t)gridDim.x * 512) {
         const int64_t row = row0 + tid;
         const int64_t rend = row0 + 512 < a.m ? row0 + 512 : a.m;
+        // everything that does not depend on the coefficient is requested
+        // first: the tile's bounds, this thread's row bounds and own entry,
+        // and the tile's column indices and values
         const int32_t t0 = a.row_ptr[row0], t1 = a.row_ptr[rend];
+        int32_t e0 = 0, e1 = 0;
+        T own_s = 0, own_q = 0;
+        if (row < a.m) {
+            e0 = a.row_ptr[row];
+            e1 = a.row_ptr[row + 1];
+            if (SRC == SRC_UPD || RR) {
+                own_s = src[row];
+                if (with_upd) own_q = qprev[row];
+            }
+        }
         const bool staged = t1 - t0 <= STREAM_CAP;
+        int32_t cl[PER];
+        T vl[PER];
         if (staged) {
-            for (int32_t e = t0 + tid; e < t1; e += 512) {
-                s_col[e - t0] = a.col_idx[e];
-                s_val[e - t0] = vals[e];
+#pragma unroll
+            for (int t = 0; t < PER; ++t) {
+                const int32_t e = t0 + tid + t * 512;
+                cl[t] = e < t1 ? a.col_idx[e] : 0;
+                vl[t] = e < t1 ? vals[e] : (T)0;
+            }
+        }
+        // the coefficient r_{j-1,j} (or r_jj for the naive second MV) is
+        // re-reduced by wave 0 while those loads are in flight
+        if (first && (with_upd || SRC == SRC_DIV) && tid < WAVE) {
+            if (with_upd) {
+                const T v = wave_reduce_seq((const T *)a.sp.part + a.j * a.sp.g, a.sp.g);
+                if (tid == 0) s_r = v;
+            } else {
+                const double v = wave_reduce_seq(a.rr_part, a.n_rr);
+                if (tid == 0) s_rr = v;
+            }
+        }
+        if (staged) {
+#pragma unroll
+            for (int t = 0; t < PER; ++t) {
+                const int32_t e = t0 + tid + t * 512;
+                if (e < t1) {
+                    s_col[e - t0] = cl[t];
+                    s_val[e - t0] = vl[t];
+                }
             }
         }
         __syncthreads();
+        if (first) {
+            first = false;
+            if (with_upd) r = s_r;
+            if (SRC == SRC_DIV) {
+                const double rr = s_rr;
+                if (!norm_ok(rr)) return; // uniform over the workgroup
+                rjj = sqrt(rr);
+            }
+        }
+        auto load = [&](int64_t l) -> T {
+            T v = src[l];
+            if (with_upd) v = upd(v, r, qprev[l]);
+            if (SRC == SRC_DIV) v = scale_div(v, rjj);
+            return v;
+        };
         if (row < a.m) {
-            const int32_t e0 = a.row_ptr[row], e1 = a.row_ptr[row + 1];
             T s = 0;
             // eight entries at a time: indices and values first, then every
             // gather in flight, then the sum in stored order (entries past
@@ -214,7 +253,9 @@ __global__ __launch_bounds__(512) void k_csr_mv_stream(CsrMvArgs a)
             }
             y[row] = s;
             if (SRC == SRC_UPD || RR) {
-                T zs = load(row);
+                T zs = own_s;
+                if (with_upd) zs = upd(zs, r, own_q);
+                if (SRC == SRC_DIV) zs = scale_div(zs, rjj);
                 if (SRC == SRC_UPD) zt[row] = zs;
                 if (RR) acc += (double)zs * (double)s;
             }
@@ -225,6 +266,9 @@ __global__ __launch_bounds__(512) void k_csr_mv_stream(CsrMvArgs a)
         double t = block_sum<double, 512>(acc, lds);
         if (tid == 0) a.rr_out[blockIdx.x] = t;
     }
+    // R[j-1, c] for c >= j, read by the next sweep, is published last so
+    // that it does not delay this kernel's own loads
+    if (with_upd) publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
 }
 
 // ----------------------------------------------------- dense MV (column kernel)
@@ -247,10 +291,7 @@ __global__ __launch_bounds__(256) void k_dense_mv(DenseMvArgs a)
     T *__restrict__ zt = (T *)a.zt;
     T r = 0;
     double rjj = 1.0;
-    if (SRC == SRC_UPD && qprev) {
-        publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
-        r = block_reduce_bcast((const T *)a.sp.part + a.j * a.sp.g, a.sp.g, &s_r);
-    }
+    if (SRC == SRC_UPD && qprev) r = block_reduce_bcast((const T *)a.sp.part + a.j * a.sp.g, a.sp.g, &s_r);
     if (SRC == SRC_DIV) {
         double rr = block_reduce_bcast(a.rr_part, a.n_rr, &s_rr);
         if (!norm_ok(rr)) return;
@@ -270,18 +311,27 @@ __global__ __launch_bounds__(256) void k_dense_mv(DenseMvArgs a)
 #pragma unroll
         for (int c = 0; c < CB; ++c) acc[c] = 0;
         const T *__restrict__ Ak = A + k0 * a.lda;
+        // all CB column entries and the vector entry are requested before
+        // the first multiply-add, so every load of a trip is in flight
+        // together
         if (nc == CB) {
             for (int64_t l = tid; l < a.m; l += 256) {
+                T av[CB];
+#pragma unroll
+                for (int c = 0; c < CB; ++c) av[c] = Ak[l + c * a.lda];
                 const T s = load(l);
 #pragma unroll
-                for (int c = 0; c < CB; ++c) acc[c] += Ak[l + c * a.lda] * s;
+                for (int c = 0; c < CB; ++c) acc[c] += av[c] * s;
             }
         } else {
             for (int64_t l = tid; l < a.m; l += 256) {
+                T av[CB];
+#pragma unroll
+                for (int c = 0; c < CB; ++c) av[c] = c < nc ? Ak[l + c * a.lda] : (T)0;
                 const T s = load(l);
 #pragma unroll
                 for (int c = 0; c < CB; ++c)
-                    if (c < nc) acc[c] += Ak[l + c * a.lda] * s;
+                    if (c < nc) acc[c] += av[c] * s;
             }
         }
 #pragma unroll
@@ -307,6 +357,8 @@ __global__ __launch_bounds__(256) void k_dense_mv(DenseMvArgs a)
         double t = block_sum<double, 256>(acc_rr, lds);
         if (tid == 0) a.rr_out[blockIdx.x] = t;
     }
+    // R[j-1, c] for c >= j (read by later kernels only) is published last
+    if (SRC == SRC_UPD && qprev) publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
 }
 
 // Partials of the second-pass coefficients s_i = p_i^T z_j, i < j, for the
@@ -395,10 +447,7 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
     const bool own = blockIdx.y == 0;
     T *__restrict__ zdst = REORTH_A ? (T *)a.zt : Q + j * a.ldq;
     T r = 0;
-    if (j > 0) {
-        if (own) publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
-        r = block_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
-    }
+    if (j > 0) r = block_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
     T xr[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -436,6 +485,8 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
         const int64_t i_lo = (int64_t)blockIdx.y * RE_GROUP;
         reorth_partials<T, U>(P, a.ldp, j, zr, row0, a.m, a.s_part, red, i_lo, i_lo + RE_GROUP);
     }
+    // R[j-1, c] for c >= j (read by later kernels only) is published last
+    if (j > 0 && own) publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
 }
 
 // ------------------------------------- second pass, step A for naive / HA
@@ -460,10 +511,7 @@ __global__ __launch_bounds__(256) void k_reorth_a(RowArgs a)
         qp[u] = (k < a.m && j > 0) ? Q[k + (j - 1) * a.ldq] : (T)0;
     }
     T r = 0;
-    if (j > 0) {
-        if (blockIdx.y == 0) publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
-        r = block_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
-    }
+    if (j > 0) r = block_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
@@ -475,6 +523,8 @@ __global__ __launch_bounds__(256) void k_reorth_a(RowArgs a)
     // this grid row's group of coefficients
     const int64_t i_lo = (int64_t)blockIdx.y * RE_GROUP;
     reorth_partials<T, U>(P, a.ldp, j, zr, row0, a.m, a.s_part, red, i_lo, i_lo + RE_GROUP);
+    // R[j-1, c] for c >= j (read by later kernels only) is published last
+    if (j > 0 && blockIdx.y == 0) publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
 }
 
 // ----------------------------------------------- second pass: finish s_i
