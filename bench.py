@@ -66,10 +66,10 @@ def to_device(prob, dev, torch):
 class Runner:
     """Preallocated device buffers for repeated calls of one configuration."""
 
-    def __init__(self, data, variant, precision, torch, amgs, reorth=False):
+    def __init__(self, data, variant, precision, torch, amgs, reorth=False, panel=0):
         self.torch, self.amgs = torch, amgs
         dt = torch.float64 if precision == "fp64" else torch.float32
-        self.variant, self.precision, self.reorth = variant, precision, reorth
+        self.variant, self.precision, self.reorth, self.panel = variant, precision, reorth, panel
         self.Z = amgs.colmajor(data["Z"], dt)
         m, n = self.Z.shape
         self.m, self.n = m, n
@@ -84,13 +84,13 @@ class Runner:
         h = amgs.handle(0)
         wb = amgs.amgs_workspace_bytes(h, m, n, int(self.dense), amgs.VARIANTS[variant],
                                        amgs.PRECISIONS[precision], 1,
-                                       amgs.Opts(int(reorth), 0, 0, 0))
+                                       amgs.Opts(int(reorth), int(panel), 0, 0))
         self.work = torch.empty(max(wb, 1), dtype=torch.uint8, device=self.Z.device)
 
     def __call__(self):
         a = self.amgs
         kw = dict(variant=self.variant, precision=self.precision, Q=self.Q, P=self.P,
-                  work=self.work, reorth=self.reorth)
+                  work=self.work, reorth=self.reorth, panel=self.panel)
         if self.dense:
             return a.qr_dense(self.A, self.Z, **kw)
         return a.qr_csr(self.rp, self.ci, self.vals, self.Z, **kw)
@@ -214,7 +214,7 @@ def bench_single(args, torch, amgs):
     log(f"[bench] m={prob.m} n={prob.n}")
     big = prob.m * prob.m if prob.csr is None else prob.csr.nnz
     head_v, head_p = args.variant, args.precision
-    run = Runner(data, head_v, head_p, torch, amgs, reorth=args.reorth)
+    run = Runner(data, head_v, head_p, torch, amgs, reorth=args.reorth, panel=args.panel)
     t, out = time_steps(run, args.steps, args.warmup, torch)
     info = int(out.info.item())
     log(f"[bench] {head_v}/{head_p}: {t * 1e3:.3f} ms/step info={info}")
@@ -226,15 +226,16 @@ def bench_single(args, torch, amgs):
 
     variants = {}
     if not args.no_variants:
-        combos = [(v, p, False) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
-        combos += [(v, "fp32", True) for v in ("ha", "hp")]
-        for v, p, ro in combos:
-            r = Runner(data, v, p, torch, amgs, reorth=ro)
+        combos = [(v, p, False, 0) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
+        combos += [(v, "fp32", True, 0) for v in ("ha", "hp")]
+        combos += [(v, p, False, 4) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
+        for v, p, ro, pan in combos:
+            r = Runner(data, v, p, torch, amgs, reorth=ro, panel=pan)
             heavy = v == "naive" and prob.csr is None and prob.m > 4096
             steps = 1 if heavy else (max(2, args.steps // 4) if v == "naive" else max(3, args.steps // 2))
             tv, o = time_steps(r, steps, 1, torch)
             orth, res = accuracy(data, o, torch)
-            key = f"{v}_{p}" + ("_reorth" if ro else "")
+            key = f"{v}_{p}" + ("_reorth" if ro else "") + (f"_panel{pan}" if pan else "")
             variants[key] = {"cols_per_s": round(prob.n / tv, 1), "ms": round(tv * 1e3, 4),
                              "orth_loss": orth, "residual": res, "info": int(o.info.item())}
             log(f"[bench] {key}: {tv * 1e3:.3f} ms  |QtAQ-I| {orth:.2e}  res {res:.2e}")
@@ -254,7 +255,8 @@ def bench_single(args, torch, amgs):
         log(f"[bench] cpu {cpu}")
     cfg = {"workload": args.workload, "m": prob.m, "n": prob.n,
            "A": "csr" if prob.csr is not None else "dense", "nnz": int(big),
-           "variant": head_v, "precision": head_p, "reorth": bool(args.reorth)}
+           "variant": head_v, "precision": head_p, "reorth": bool(args.reorth),
+           "schedule": f"panel{args.panel}" if args.panel else "column"}
     return {"metric": METRIC, "value": round(prob.n / t, 2), "unit": "cols/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t * 1e3, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
@@ -370,6 +372,8 @@ def main():
     ap.add_argument("--variant", default="hp", choices=["naive", "ha", "hp"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--reorth", action="store_true", help="second pass in the headline run")
+    ap.add_argument("--panel", type=int, default=0, choices=[0, 4],
+                    help="schedule of the headline run: 0 column order, 4 panels of four")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported here "

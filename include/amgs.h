@@ -81,10 +81,26 @@ typedef enum {
 
 typedef struct amgs_handle *amgs_handle_t;
 
-/* Per-call options; passing NULL means all zero. */
+/* Per-call options; passing NULL means all zero.
+ *   reorth  1: second (reorthogonalisation) pass per column (see above).
+ *   panel   0: the column algorithm's own order of operations (default).
+ *           4: panel schedule.  Columns are taken in panels of four; inside
+ *           a panel every step is the column algorithm's.  The effect of a
+ *           finished panel I on a later column c is applied as one block:
+ *           with W = P_I^T z_c (z_c before panel I) and
+ *           L = strict_lower(P_I^T Q_I), the coefficients r_{I,c} solve
+ *           (I + L) r_{I,c} = W by forward substitution, which in exact
+ *           arithmetic are the modified Gram-Schmidt coefficients
+ *           r_ic = p_i^T z_c^{(i-1)}; then z_c -= Q_I r_{I,c} (and for HP
+ *           x_c -= P_I r_{I,c}, the terms of eq. (5) in ascending i).  Each
+ *           later column is then read and written once per panel instead of
+ *           once per column.  Rounding differs from the column order;
+ *           A-orthogonality stays at the level of the column algorithm.
+ *           Not combined with reorth (AMGS_ERR_UNSUPPORTED); other values
+ *           are AMGS_ERR_ARG. */
 typedef struct {
-    int32_t reorth;    /* 1: second (reorthogonalisation) pass per column */
-    int32_t reserved0;
+    int32_t reorth;
+    int32_t panel;
     int32_t reserved1;
     int32_t reserved2;
 } amgs_opts_t;

@@ -37,6 +37,16 @@
  * and the divisions q_j = z_j / r_jj, p_j = x_j / r_jj are binary64 and their
  * results are rounded to binary32.  R is binary64.
  *
+ * Orientation 2 is the panel schedule of the GPU library (not in the paper;
+ * a regrouping of the column algorithm's projections): columns are taken in
+ * panels of PANEL_B; inside a panel the column algorithm runs on the panel's
+ * columns only; after a panel [s, e) is finished, every later column c gets
+ * the panel's effect as one block: W_i = p_i^T z_c (the same z_c for all i),
+ * L_ik = p_i^T q_k (k < i, both inside the panel), r_ic = W_i -
+ * sum_{k<i} L_ik r_kc (forward substitution, binary64), then z_c -= r_ic q_i
+ * for i ascending (HP: also x_c -= r_ic p_i).  In exact arithmetic this is
+ * the column algorithm, since z_c^{(i-1)} = z_c - sum_{k<i} r_kc q_k.
+ *
  * Optional reorthogonalisation (the paper names it in Section 2.1 without a
  * definition): after the MGS projections of column j, a classical second
  * pass s_i = p_i^T z_j for all i < j (binary64 accumulation), then
@@ -58,6 +68,8 @@
 #define REF_HP 2
 #define REF_COL 0
 #define REF_ROW 1
+#define REF_PANEL 2
+#define PANEL_B 4
 #define REF_FP64 0
 #define REF_FP32 1
 #define DOT_BLOCK 1024
@@ -324,13 +336,81 @@ static int qr_row(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq,
     return info;
 }
 
+/* Panel schedule (orientation 2): see the header comment. */
+static int qr_panel(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq, double *R,
+                    int64_t ldr, double *P, int64_t ldp, double *X, int variant, int prec,
+                    int64_t *mv_calls, int64_t *mv_cols)
+{
+    double *x = (double *)malloc((size_t)m * sizeof(double));
+    if (variant == REF_HP) {
+        for (int64_t j = 0; j < n; ++j) mv_st(A, Q + j * ldq, X + j * m, prec);
+        *mv_calls += 1; *mv_cols += n;
+    }
+    int info = 0;
+    for (int64_t s = 0; s < n && !info; s += PANEL_B) {
+        const int64_t e = s + PANEL_B < n ? s + PANEL_B : n;
+        /* the column algorithm on the panel's own columns */
+        for (int64_t j = s; j < e; ++j) {
+            double *z = Q + j * ldq;
+            double *Rc = R + j * ldr;
+            for (int64_t i = s; i < j; ++i) {
+                Rc[i] = dot_st(P + i * ldp, z, m, prec);
+                axpy_st(z, Rc[i], Q + i * ldq, m, prec);
+            }
+            if (variant == REF_HP) {
+                /* X[:, j] already holds the terms of the earlier panels */
+                memcpy(x, X + j * m, (size_t)m * sizeof(double));
+                for (int64_t i = s; i < j; ++i) axpy_st(x, st(Rc[i], prec), P + i * ldp, m, prec);
+            } else {
+                mv_st(A, z, x, prec);
+                *mv_calls += 1; *mv_cols += 1;
+            }
+            double rjj;
+            if (!anorm(z, x, m, &rjj)) { info = (int)(j + 1); break; }
+            Rc[j] = rjj;
+            scale(z, z, rjj, m, prec);
+            if (variant == REF_NAIVE) {
+                mv_st(A, z, P + j * ldp, prec);
+                *mv_calls += 1; *mv_cols += 1;
+            } else {
+                scale(P + j * ldp, x, rjj, m, prec);
+            }
+        }
+        if (info || e >= n) break;
+        /* the finished panel's effect on every later column, as one block */
+        const int b = (int)(e - s);
+        double L[PANEL_B][PANEL_B];
+        for (int i = 0; i < b; ++i)
+            for (int k = 0; k < i; ++k)
+                L[i][k] = dot_st(P + (s + i) * ldp, Q + (s + k) * ldq, m, prec);
+        for (int64_t c = e; c < n; ++c) {
+            double *z = Q + c * ldq;
+            double W[PANEL_B], r[PANEL_B];
+            for (int i = 0; i < b; ++i) W[i] = dot_st(P + (s + i) * ldp, z, m, prec);
+            for (int i = 0; i < b; ++i) {
+                double t = W[i];
+                for (int k = 0; k < i; ++k) t = t - L[i][k] * r[k];
+                r[i] = t;
+                R[c * ldr + s + i] = t;
+            }
+            for (int i = 0; i < b; ++i) axpy_st(z, st(r[i], prec), Q + (s + i) * ldq, m, prec);
+            if (variant == REF_HP)
+                for (int i = 0; i < b; ++i)
+                    axpy_st(X + c * m, st(r[i], prec), P + (s + i) * ldp, m, prec);
+        }
+    }
+    free(x);
+    return info;
+}
+
 static int run(const ref_op *A, int64_t n, const double *Z, int64_t ldz, double *Q, int64_t ldq,
                double *R, int64_t ldr, double *P, int64_t ldp, int variant, int orientation,
                int reorth, int prec, int64_t *stats)
 {
     int64_t m = A->m;
     if (m < 0 || n < 0 || n > m || ldz < m || ldq < m || ldr < n) return -1;
-    if (variant < 0 || variant > 2 || orientation < 0 || orientation > 1) return -1;
+    if (variant < 0 || variant > 2 || orientation < 0 || orientation > 2) return -1;
+    if (orientation == REF_PANEL && reorth) return -1;
     if (prec < 0 || prec > 1) return -1;
     if (n == 0) { if (stats) stats[0] = stats[1] = 0; return 0; }
     if (!Z || !Q || !R) return -1;
@@ -346,7 +426,9 @@ static int run(const ref_op *A, int64_t n, const double *Z, int64_t ldz, double 
     int64_t calls = 0, cols = 0;
     int info = orientation == REF_COL
         ? qr_col(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols)
-        : qr_row(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols);
+        : orientation == REF_ROW
+        ? qr_row(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols)
+        : qr_panel(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, prec, &calls, &cols);
     if (stats) { stats[0] = calls; stats[1] = cols; }
     free(X);
     if (!P) free(Pw);

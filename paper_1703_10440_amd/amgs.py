@@ -29,7 +29,7 @@ class AmgsError(RuntimeError):
 
 
 class Opts(C.Structure):
-    _fields_ = [("reorth", C.c_int32), ("reserved0", C.c_int32), ("reserved1", C.c_int32),
+    _fields_ = [("reorth", C.c_int32), ("panel", C.c_int32), ("reserved1", C.c_int32),
                 ("reserved2", C.c_int32)]
 
 
@@ -207,8 +207,10 @@ def _prep(Z, precision, device, Q, P, return_p):
 
 
 def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=False,
-           return_p=False, Q=None, P=None, work=None, stream=None, device=None) -> QRResult:
-    """A-orthonormalise the columns of Z (device tensors; A in CSR)."""
+           return_p=False, Q=None, P=None, work=None, stream=None, device=None,
+           panel=0) -> QRResult:
+    """A-orthonormalise the columns of Z (device tensors; A in CSR).
+    panel: 0 for the column schedule, 4 for the panel schedule."""
     torch = _torch()
     device = device or Z.device
     dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p)
@@ -216,7 +218,7 @@ def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=Fal
     row_ptr = row_ptr.to(device=device, dtype=torch.int32).contiguous()
     col_idx = col_idx.to(device=device, dtype=torch.int32).contiguous()
     h = handle(device.index or 0)
-    opts = Opts(int(bool(reorth)), 0, 0, 0)
+    opts = Opts(int(bool(reorth)), int(panel), 0, 0)
     v, p = VARIANTS[variant], PRECISIONS[precision]
     wb = amgs_workspace_bytes(h, m, n, 0, v, p, int(Pc is not None), opts)
     if work is None:
@@ -233,14 +235,15 @@ def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=Fal
 
 
 def qr_dense(A, Z, variant="ha", precision="fp64", reorth=False, return_p=False, Q=None,
-             P=None, work=None, stream=None, device=None) -> QRResult:
-    """A-orthonormalise the columns of Z (device tensors; A dense symmetric)."""
+             P=None, work=None, stream=None, device=None, panel=0) -> QRResult:
+    """A-orthonormalise the columns of Z (device tensors; A dense symmetric).
+    panel: 0 for the column schedule, 4 for the panel schedule."""
     torch = _torch()
     device = device or Z.device
     dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p)
     Ac = colmajor(A.to(device), dt)
     h = handle(device.index or 0)
-    opts = Opts(int(bool(reorth)), 0, 0, 0)
+    opts = Opts(int(bool(reorth)), int(panel), 0, 0)
     v, p = VARIANTS[variant], PRECISIONS[precision]
     wb = amgs_workspace_bytes(h, m, n, 1, v, p, int(Pc is not None), opts)
     if work is None:

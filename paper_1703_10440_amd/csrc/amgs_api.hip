@@ -65,10 +65,19 @@ struct ProfScope {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t part, s_part, rr_part, S, zt, xv, X, P, total;
+    size_t part, s_part, rr_part, S, zt, xv, X, P, wpart, lpart, total;
 };
 
-Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_given, int reorth)
+// Row chunks of the panel-schedule sweeps (256 threads of panel_rows rows).
+int64_t panel_chunks(int64_t m, size_t w)
+{
+    const int64_t rows = 256 * (int64_t)panel_rows_for(w == 8);
+    const int64_t g = (m + rows - 1) / rows;
+    return g < 1 ? 1 : g;
+}
+
+Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_given, int reorth,
+              int panel)
 {
     Layout L{};
     size_t off = 0;
@@ -80,7 +89,8 @@ Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_g
     // MV kernels never use more than MAX_G_MV workgroups, whatever the CSR
     // lane count, so the size does not depend on nnz
     int64_t g_rr = g.g_rows1 > MAX_G_MV ? g.g_rows1 : MAX_G_MV;
-    L.part = take((size_t)n * g.g_rows * 8);
+    const int64_t g_p = panel ? panel_chunks(m, w) : 0;
+    L.part = take((size_t)n * (panel ? g_p : g.g_rows) * 8);
     L.s_part = reorth ? take((size_t)n * g.g_rows2 * 8) : off;
     L.rr_part = take((size_t)g_rr * 8);
     L.S = reorth ? take((size_t)n * 8) : off;
@@ -88,6 +98,8 @@ Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_g
     L.xv = variant != VAR_HP ? take((size_t)m * w) : off;
     L.X = variant == VAR_HP ? take((size_t)m * n * w) : off;
     L.P = P_given ? off : take((size_t)m * n * w);
+    L.wpart = panel ? take((size_t)n * PANEL_B * g_p * 8) : off;
+    L.lpart = panel ? take((size_t)PANEL_B * PANEL_B * g_p * 8) : off;
     L.total = off;
     return L;
 }
@@ -109,8 +121,12 @@ double sweep_bytes(int64_t m, int64_t n, int64_t j, size_t w, int variant)
 }
 
 template <typename T>
+amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant);
+
+template <typename T>
 amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
 {
+    if (c.panel) return run_panel<T>(h, c, variant);
     const size_t w = sizeof(T);
     amgs_stats_t &st = h->stats;
     st = amgs_stats_t{};
@@ -207,17 +223,155 @@ amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
     return AMGS_OK;
 }
 
+// Algorithmic HBM bytes of one panel-schedule sweep: each later column is
+// read, and written back when a pending update applies (for HP with its x
+// column); plus z_j and x_j read, q_j and p_j written (naive: p_j read), the
+// pending q_k (HP: and p_k) and the dot vectors p_d, d < j, read.
+double psweep_bytes(int64_t m, size_t w, int64_t ncols, int64_t kw, int64_t bd, int variant)
+{
+    const double col = (double)m * (double)w;
+    double per_col = kw > 0 ? 2.0 : 1.0;
+    if (variant == VAR_HP && kw > 0) per_col += 2.0;
+    double vec = (variant == VAR_NAIVE ? 3.0 : 4.0) + (double)kw * (variant == VAR_HP ? 2.0 : 1.0)
+               + (double)(bd - 1);
+    return (double)ncols * per_col * col + vec * col;
+}
+
+// Panel schedule (opts->panel): the column algorithm inside each panel of
+// PANEL_B columns; after a panel's last column one sweep applies the
+// previous panel to every later column and forms the dots with this panel's
+// p vectors, and k_pfin turns them into the coefficients r_{I,c}.
+template <typename T>
+amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant)
+{
+    const size_t w = sizeof(T);
+    amgs_stats_t &st = h->stats;
+    st = amgs_stats_t{};
+    launch_init<T>(c, c.Z != c.Q);
+    st.kernel_launches++;
+    const double mvA = c.is_dense ? (double)c.m * (double)c.m * w
+                                  : (double)c.nnz * (w + 4) + 4.0 * (double)(c.m + 1);
+    if (variant == VAR_HP) {
+        ProfScope ps(h, 2, c.stream);
+        if (c.is_dense) launch_dense_gemm<T>(c);
+        else launch_csr_spmm<T>(c);
+        st.kernel_launches++;
+        st.mv_calls += 1;
+        st.mv_columns += c.n;
+        st.mv_bytes += mvA + 2.0 * (double)c.m * c.n * w;
+    }
+    const int64_t B = PANEL_B;
+    for (int64_t s = 0; s < c.n; s += B) {
+        const int64_t e = s + B < c.n ? s + B : c.n;
+        const int64_t prev = s - B;   // start of the previous panel (s > 0)
+        for (int64_t j = s; j < e; ++j) {
+            const bool first_blk = j == s && s > 0;
+            int64_t n_rr = 0;
+            // column kernels publish r_{j-1,c} only inside the panel
+            c.n_pub = e;
+            {
+                ProfScope ps(h, variant == VAR_HP ? 1 : -1, c.stream);
+                if (first_blk) {
+                    launch_pcol_blk<T>(c, variant, j, prev, s);
+                    st.kernel_launches++;
+                    n_rr = pcol_blk_partials(c);
+                } else if (variant == VAR_HP) {
+                    // the sweeps have applied every recurrence term but j-1
+                    c.x_from = j > 0 ? j - 1 : 0;
+                    launch_col_hp<T>(c, j, false);
+                    c.x_from = -1;
+                    st.kernel_launches++;
+                    n_rr = c.geo.g_rows2;
+                }
+                if (variant != VAR_HP) {
+                    hipEvent_t m0 = nullptr, m1 = nullptr;
+                    if (h->profiling) {
+                        m0 = take_event(h);
+                        m1 = take_event(h);
+                    }
+                    c.ev_start = m0;
+                    c.ev_stop = m1;
+                    launch_mv<T>(c, j, first_blk ? SRC_VEC : SRC_UPD);
+                    c.ev_start = c.ev_stop = nullptr;
+                    if (m0 && m1) h->recs.push_back({1, m0, m1});
+                    st.kernel_launches++;
+                    st.mv_calls += 1;
+                    st.mv_columns += 1;
+                    st.mv_bytes += mvA + (first_blk ? 2.0 : (j > 0 ? 4.0 : 3.0)) * (double)c.m * w;
+                    if (variant == VAR_NAIVE) {
+                        launch_mv<T>(c, j, SRC_DIV);
+                        st.kernel_launches++;
+                        st.mv_calls += 1;
+                        st.mv_columns += 1;
+                        st.mv_bytes += mvA + 2.0 * (double)c.m * w;
+                    }
+                    n_rr = c.n_rr_mv;
+                }
+            }
+            c.n_pub = c.n;
+            // a step inside the panel (also the last column of the last
+            // panel), or the sweep after the panel's last column
+            const bool panel_end = j == e - 1 && e < c.n;
+            int64_t k0, k1, d0, c0, c1;
+            if (!panel_end) {
+                k0 = j == s ? (s > 0 ? prev : s) : j - 1;
+                k1 = j == s ? s : j;
+                d0 = j;
+                c0 = j + 1;
+                c1 = e;
+            } else {
+                k0 = s > 0 ? prev : s;
+                k1 = s;
+                d0 = s;
+                c0 = e;
+                c1 = c.n;
+            }
+            if (h->profiling) {
+                hipEvent_t e0 = take_event(h), e1 = take_event(h);
+                c.ev_start = e0;
+                c.ev_stop = e1;
+                launch_psweep<T>(c, variant, j, k0, k1, d0, s, c0, c1, n_rr);
+                c.ev_start = c.ev_stop = nullptr;
+                if (e0 && e1) h->recs.push_back({0, e0, e1});
+            } else {
+                launch_psweep<T>(c, variant, j, k0, k1, d0, s, c0, c1, n_rr);
+            }
+            st.kernel_launches++;
+            st.sweep_launches++;
+            st.sweep_bytes += psweep_bytes(c.m, w, c1 > c0 ? c1 - c0 : 0, k1 - k0, j - d0 + 1, variant);
+            if (panel_end) {
+                launch_pfin<T>(c, s, e);
+                st.kernel_launches++;
+            }
+        }
+    }
+    if (hipGetLastError() != hipSuccess) return AMGS_ERR_HIP;
+    return AMGS_OK;
+}
+
 amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision_t p,
                         const amgs_opts_t *o, void *work, size_t work_bytes, int P_given)
 {
     const int reorth = o ? (o->reorth != 0) : 0;
+    const int panel = o ? o->panel : 0;
+    if (panel != 0 && panel != PANEL_B) return AMGS_ERR_ARG;
+    if (panel && reorth) return AMGS_ERR_UNSUPPORTED;
     const size_t w = p == AMGS_FP64 ? 8 : 4;
     c.geo = make_geo(c.m, c.nnz, c.is_dense);
-    Layout L = layout(c.m, c.n, c.geo, (int)v, w, P_given, reorth);
+    Layout L = layout(c.m, c.n, c.geo, (int)v, w, P_given, reorth, panel);
     if (!work || work_bytes < L.total) return AMGS_ERR_WORKSPACE;
     char *base = (char *)work;
     c.sp.part = base + L.part;
     c.sp.g = c.geo.g_rows;
+    c.panel = panel;
+    c.x_from = -1;
+    c.n_pub = c.n;
+    if (panel) {
+        c.g_p = panel_chunks(c.m, w);
+        c.sp.g = c.g_p;
+        c.wpart = base + L.wpart;
+        c.lpart = base + L.lpart;
+    }
     c.s_part = (double *)(base + L.s_part);
     c.rr_part = (double *)(base + L.rr_part);
     c.S = (double *)(base + L.S);
@@ -326,7 +480,10 @@ size_t amgs_workspace_bytes(amgs_handle_t h, int64_t m, int64_t n, int32_t is_de
     if (n == 0) return 0;
     // nnz only selects the CSR lane count, which does not change any size
     Geo g = make_geo(m, is_dense ? 0 : m, is_dense);
-    Layout L = layout(m, n, g, (int)v, p == AMGS_FP64 ? 8 : 4, P_given, o ? o->reorth != 0 : 0);
+    const int panel = o ? o->panel : 0;
+    if (panel != 0 && panel != PANEL_B) return 0;
+    Layout L = layout(m, n, g, (int)v, p == AMGS_FP64 ? 8 : 4, P_given, o ? o->reorth != 0 : 0,
+                      panel);
     return L.total;
 }
 

@@ -116,6 +116,21 @@ __device__ __forceinline__ A block_sum(A v, A *lds)
     return t;
 }
 
+// Loads and stores of streamed columns; NT selects the non-temporal
+// (streaming) cache policy.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_stream(const T *p)
+{
+    if constexpr (NT) return __builtin_nontemporal_load(p);
+    else return *p;
+}
+template <bool NT, typename T>
+__device__ __forceinline__ void st_stream(T *p, T v)
+{
+    if constexpr (NT) __builtin_nontemporal_store(v, p);
+    else *p = v;
+}
+
 __device__ __forceinline__ bool norm_ok(double rr) { return rr > 0.0 && rr <= 1.7976931348623157e308; }
 
 } // namespace amgs

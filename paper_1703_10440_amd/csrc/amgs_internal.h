@@ -18,6 +18,9 @@ constexpr int DENSE_CB = 16;   // outputs per dense-MV workgroup pass
 constexpr int SPMM_C = 8;      // columns per CSR block-product thread
 constexpr int MAX_G_MV = 512;  // partials of an MV column kernel
 constexpr int STREAM_CAP = 4096; // CSR entries staged per 512-row tile
+constexpr int PANEL_B = 4;     // columns per panel of the panel schedule
+constexpr int PS_CB = 2;       // later columns streamed together by a panel-sweep thread
+constexpr int PS_MAXC = 64;    // later columns per panel-sweep workgroup (max)
 
 // Partials of the projection sweep: part[c * g + w] holds workgroup w's part
 // of r_{j,c} (element type of the storage precision).
@@ -83,6 +86,7 @@ struct RowArgs {
     double *rr_out;
     double *s_part;
     const double *S;
+    int64_t x_from;   // HP column kernel: first recurrence term (-1: column schedule)
 };
 
 struct SweepArgs {
@@ -101,6 +105,33 @@ struct SweepArgs {
     const double *rr_part;
     int64_t n_rr;
     int64_t cpw;
+};
+
+// One step of the panel schedule (see k_psweep): normalise column j, apply
+// the pending columns [k0, k1) (coefficients already in R) to the later
+// columns [c0, c1), and form their dots with p_d, d in [d0, j].
+struct PSweepArgs {
+    int64_t m, n, j;
+    void *Q;
+    int64_t ldq;
+    void *P;
+    int64_t ldp;
+    void *X;
+    int64_t ldx;
+    const void *zt, *xv;
+    double *R;
+    int64_t ldr;
+    int32_t *info;
+    const double *rr_part;
+    int64_t n_rr;
+    int64_t k0, k1;   // pending update columns
+    int64_t d0;       // first dot column (j - d0 + 1 dots)
+    int64_t l0;       // panel start: partials of p_j^T q_k, k in [l0, j)
+    int64_t c0, c1, cpw;
+    void *part;       // dot partials: part[(c * pstride + d - d0) * g + w]
+    int64_t pstride;
+    int64_t g;
+    void *lpart;      // lpart[((j - l0) * PANEL_B + k - l0) * g + w]
 };
 
 // Everything one amgs_qr_* call needs on the host side.
@@ -132,6 +163,14 @@ struct Ctx {
     double *S;
     int32_t *info;
     Geo geo;
+    // panel schedule (panel = 0: column schedule)
+    int panel;
+    int Up;           // rows per thread of the panel sweeps
+    int64_t g_p;      // their row chunks
+    void *wpart;      // panel-sweep dot partials [n][PANEL_B][g_p]
+    void *lpart;      // partials of strict_lower(P_I^T Q_I) [PANEL_B][PANEL_B][g_p]
+    int64_t x_from;   // HP column kernel: first recurrence term it applies (-1: column schedule)
+    int64_t n_pub;    // column kernels publish r_{j-1,c} for c < n_pub
     hipStream_t stream;
     // when set, the sweep is launched with these events bound to its own
     // dispatch (exact kernel start and end, no extra stream markers)
@@ -150,6 +189,12 @@ template <typename T> void launch_sweep(const Ctx &c, int64_t j, int variant, in
 template <typename T> bool launch_hp_xblock(const Ctx &c, int64_t s);
 template <typename T> void launch_csr_spmm(const Ctx &c);
 template <typename T> void launch_dense_gemm(const Ctx &c);
+template <typename T> void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
+                                         int64_t d0, int64_t l0, int64_t c0, int64_t c1, int64_t n_rr);
+template <typename T> void launch_pfin(const Ctx &c, int64_t s, int64_t e);
+template <typename T> void launch_pcol_blk(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1);
+int64_t pcol_blk_partials(const Ctx &c);
+int panel_rows_for(int fp64);
 void launch_csr_check(int64_t m, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                       int32_t *flag, hipStream_t s);
 

@@ -1,0 +1,399 @@
+// amgs_panel.hip -- kernels of the panel schedule (opts->panel).
+//
+// Columns are taken in panels of PANEL_B.  Inside a panel every step is the
+// column algorithm's (Algs. 3/5/6): the column kernel, then a sweep that
+// normalises column j (eqs. (4), (10)), applies the pending update to the
+// later columns of the panel and forms their dots with p_j (eq. (9)).
+// After the last column of panel I a single sweep over every later column c
+// applies panel I-1 as one block (its coefficients r_{I-1,c} are final in R)
+// and forms W_c = P_I^T z_c; k_pfin then solves (I + L) r_{I,c} = W_c with
+// L = strict_lower(P_I^T Q_I).  Since z_c^{(i-1)} = z_c - sum_{k<i} r_kc q_k,
+// r_ic = p_i^T z_c^{(i-1)} = W_ic - sum_{k<i} (p_i^T q_k) r_kc: the same
+// coefficients as the column algorithm in exact arithmetic, obtained with one
+// pass over the later columns per panel instead of one per column.
+//
+// For HP the x columns follow the z columns: wherever z_c -= r_ic q_i is
+// applied, x_c -= r_ic p_i is applied with the same coefficient, so every x_c
+// receives the terms of eq. (5) once each in ascending i.
+#include <hip/hip_ext.h>
+
+#include "amgs_device.h"
+#include "amgs_internal.h"
+
+namespace amgs {
+
+// Rows per thread of the panel kernels: each thread holds, per row, the
+// pending q_k (and p_k for HP) and the dot vectors p_d in registers.
+template <typename T>
+constexpr int panel_rows() { return sizeof(T) == 8 ? 2 : 4; }
+
+// One step of the panel schedule.  DB = 1: a step inside a panel (dots with
+// p_j only, partials in the column-schedule layout part[c * g + w]).
+// DB = PANEL_B: the sweep after the last column j of a panel (dots with
+// p_d, d in [d0, j], partials part[(c * PANEL_B + d - d0) * g + w]).
+// Every launch also writes the partials of p_j^T q_k, k in [l0, j) (one row
+// of strict_lower(P_I^T Q_I)), from the workgroups of grid row 0.
+template <typename T, int U, int VAR, bool NTS, int DB>
+__global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
+{
+    constexpr int KB = PANEL_B;
+    constexpr bool HPX = VAR == VAR_HP;
+    constexpr int DL = DB > 1 ? DB - 1 : 1;
+    __shared__ T red[256 / WAVE][PS_MAXC * DB];
+    __shared__ T lred[256 / WAVE][KB];
+    __shared__ double s_rr;
+    if (*a.info) return;
+    const int64_t j = a.j, m = a.m;
+    const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
+    T *__restrict__ Q = (T *)a.Q;
+    T *__restrict__ P = (T *)a.P;
+    T *__restrict__ X = (T *)a.X;
+    const int64_t row0 = (int64_t)blockIdx.x * 256 * U;
+    const bool own = blockIdx.y == 0;
+    const int kw = (int)(a.k1 - a.k0);
+    const int bd = (int)(j - a.d0 + 1);
+    const T *__restrict__ zsrc = VAR == VAR_HP ? Q + j * a.ldq : (const T *)a.zt;
+    const T *__restrict__ xsrc = VAR == VAR_HP ? (const T *)X + j * a.ldx : (const T *)a.xv;
+    // every vector load is issued before waiting for r_jj
+    T xs[U], zs[U], qk[KB][U], pk[HPX ? KB : 1][U], pd[DL][U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = row0 + u * 256 + tid;
+        const bool in = k < m;
+        xs[u] = in ? (VAR == VAR_NAIVE ? P[k + j * a.ldp] : xsrc[k]) : (T)0;
+        zs[u] = (in && own) ? zsrc[k] : (T)0;
+#pragma unroll
+        for (int t = 0; t < KB; ++t) {
+            qk[t][u] = (in && t < kw) ? Q[k + (a.k0 + t) * a.ldq] : (T)0;
+            if (HPX) pk[t][u] = (in && t < kw) ? P[k + (a.k0 + t) * a.ldp] : (T)0;
+        }
+#pragma unroll
+        for (int t = 0; t < DL; ++t) pd[t][u] = (in && t < bd - 1) ? P[k + (a.d0 + t) * a.ldp] : (T)0;
+    }
+    if (wave == 0) {
+        const double rr = wave_reduce_seq(a.rr_part, a.n_rr);
+        if (tid == 0) s_rr = rr;
+    }
+    __syncthreads();
+    const double rr = s_rr;
+    if (!norm_ok(rr)) {
+        if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) *a.info = (int32_t)(j + 1);
+        return;
+    }
+    const double rjj = sqrt(rr);
+    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) a.R[j + j * a.ldr] = rjj;
+    T pj[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = row0 + u * 256 + tid;
+        pj[u] = VAR == VAR_NAIVE ? xs[u] : scale_div(xs[u], rjj);
+        if (own && k < m) {
+            Q[k + j * a.ldq] = scale_div(zs[u], rjj);
+            if (VAR != VAR_NAIVE) P[k + j * a.ldp] = pj[u];
+        }
+    }
+    const int64_t c0 = a.c0 + (int64_t)blockIdx.y * a.cpw;
+    const int64_t c1 = (c0 + a.cpw < a.c1) ? c0 + a.cpw : a.c1;
+    const bool full_rows = row0 + 256 * U <= m;
+    for (int64_t cb = c0; cb < c1; cb += PS_CB) {
+        T zv[PS_CB][U], xv[HPX ? PS_CB : 1][U];
+#pragma unroll
+        for (int t = 0; t < PS_CB; ++t) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t k = row0 + u * 256 + tid;
+                const bool in = cb + t < c1 && (full_rows || k < m);
+                zv[t][u] = in ? ld_stream<NTS>(Q + (cb + t) * a.ldq + k) : (T)0;
+                if (HPX) xv[t][u] = (in && kw > 0) ? ld_stream<NTS>(X + (cb + t) * a.ldx + k) : (T)0;
+            }
+        }
+        T acc[PS_CB][DB];
+#pragma unroll
+        for (int t = 0; t < PS_CB; ++t) {
+            const bool cin = cb + t < c1;
+            T rc[KB];
+#pragma unroll
+            for (int i = 0; i < KB; ++i)
+                rc[i] = (cin && i < kw) ? (T)a.R[(a.k0 + i) + (cb + t) * a.ldr] : (T)0;
+#pragma unroll
+            for (int d = 0; d < DB; ++d) acc[t][d] = 0;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t k = row0 + u * 256 + tid;
+                if (!(cin && (full_rows || k < m))) continue;
+                T z = zv[t][u];
+                if (kw > 0) {
+                    // pending terms in ascending column order
+#pragma unroll
+                    for (int i = 0; i < KB; ++i)
+                        if (i < kw) z = upd(z, rc[i], qk[i][u]);
+                    st_stream<NTS>(Q + (cb + t) * a.ldq + k, z);
+                    if (HPX) {
+                        T x = xv[t][u];
+#pragma unroll
+                        for (int i = 0; i < KB; ++i)
+                            if (i < kw) x = upd(x, rc[i], pk[i][u]);
+                        st_stream<NTS>(X + (cb + t) * a.ldx + k, x);
+                    }
+                }
+#pragma unroll
+                for (int d = 0; d < DB; ++d) {
+                    if (d == bd - 1) acc[t][d] += pj[u] * z;
+                    else if (d < DL && d < bd - 1) acc[t][d] += pd[d < DL ? d : 0][u] * z;
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < PS_CB; ++t)
+#pragma unroll
+            for (int d = 0; d < DB; ++d) {
+                const T v = wave_sum(acc[t][d]);
+                if (lane == 0 && cb + t < c1 && d < bd) red[wave][(cb - c0 + t) * DB + d] = v;
+            }
+    }
+    __syncthreads();
+    const int ncols = c0 < c1 ? (int)(c1 - c0) : 0;
+    for (int idx = tid; idx < ncols * bd; idx += 256) {
+        const int cl = idx / bd, d = idx - cl * bd;
+        T s = red[0][cl * DB + d];
+#pragma unroll
+        for (int w = 1; w < 256 / WAVE; ++w) s += red[w][cl * DB + d];
+        ((T *)a.part)[((c0 + cl) * a.pstride + d) * a.g + blockIdx.x] = s;
+    }
+    // row j of strict_lower(P_I^T Q_I): p_j^T q_k for k in [l0, j)
+    const int nl = (int)(j - a.l0);
+    if (own && nl > 0) {
+#pragma unroll
+        for (int i = 0; i < KB - 1; ++i) {
+            if (i < nl) {
+                T s = 0;
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int64_t k = row0 + u * 256 + tid;
+                    if (k < m) s += pj[u] * Q[k + (a.l0 + i) * a.ldq];
+                }
+                s = wave_sum(s);
+                if (lane == 0) lred[wave][i] = s;
+            }
+        }
+        __syncthreads();
+        if (tid < nl) {
+            T s = lred[0][tid];
+#pragma unroll
+            for (int w = 1; w < 256 / WAVE; ++w) s += lred[w][tid];
+            ((T *)a.lpart)[(nl * PANEL_B + tid) * a.g + blockIdx.x] = s;
+        }
+    }
+}
+
+// r_{I,c} for every later column c = e + blockIdx.x: the dots W_c and the
+// entries of L are re-reduced from their partials (fixed order, so every
+// workgroup obtains the same L), then (I + L) r = W is solved by forward
+// substitution in binary64 and r is written to R[s.., c].
+template <typename T>
+__global__ __launch_bounds__(256) void k_pfin(int64_t s, int64_t e, const T *__restrict__ wpart,
+                                              const T *__restrict__ lpart, int64_t g,
+                                              double *__restrict__ R, int64_t ldr,
+                                              const int32_t *info)
+{
+    constexpr int B = PANEL_B;
+    __shared__ T vals[B + B * B];
+    if (*info) return;
+    const int64_t c = e + blockIdx.x;
+    const int b = (int)(e - s);
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const int nitems = b + b * (b - 1) / 2;
+    for (int it = wave; it < nitems; it += 256 / WAVE) {
+        const T *src;
+        int slot;
+        if (it < b) {
+            src = wpart + (c * B + it) * g;
+            slot = it;
+        } else {
+            int q = it - b, i = 1;
+            while (q >= i) {
+                q -= i;
+                ++i;
+            }
+            src = lpart + ((int64_t)i * B + q) * g;
+            slot = B + i * B + q;
+        }
+        const T v = wave_reduce_seq(src, g);
+        if (lane == 0) vals[slot] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            if (i < b) {
+                double t = (double)vals[i];
+#pragma unroll
+                for (int k = 0; k < B; ++k)
+                    if (k < i) t = __builtin_fma(-(double)vals[B + i * B + k], r[k], t);
+                r[i] = t;
+                R[(s + i) + c * ldr] = t;
+            }
+        }
+    }
+}
+
+// First column j of a panel: z_j -= sum_k r_kj q_k over the previous panel
+// [k0, k1) (coefficients final in R, ascending k); for HP also
+// x_j -= sum_k r_kj p_k, both in place, and the partial of z_j^T x_j.  For
+// naive / HA the corrected z_j goes to zt, from where the column MV reads it.
+template <typename T, int U, int VAR>
+__global__ __launch_bounds__(256) void k_pcol_blk(RowArgs a, int64_t k0, int64_t k1)
+{
+    constexpr int KB = PANEL_B;
+    constexpr bool HP = VAR == VAR_HP;
+    __shared__ double lds[256 / WAVE];
+    if (*a.info) return;
+    const int64_t j = a.j;
+    T *__restrict__ Q = (T *)a.Q;
+    const T *__restrict__ P = (const T *)a.P;
+    T *__restrict__ X = (T *)a.X;
+    T *__restrict__ zt = (T *)a.zt;
+    const int kw = (int)(k1 - k0);
+    const int tid = threadIdx.x;
+    const int64_t row0 = (int64_t)blockIdx.x * 256 * U;
+    T r[KB];
+#pragma unroll
+    for (int i = 0; i < KB; ++i) r[i] = i < kw ? (T)a.R[(k0 + i) + j * a.ldr] : (T)0;
+    T z[U], x[U], qv[KB][U], pv[HP ? KB : 1][U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = row0 + u * 256 + tid;
+        const bool in = k < a.m;
+        z[u] = in ? Q[k + j * a.ldq] : (T)0;
+        x[u] = (HP && in) ? X[k + j * a.ldx] : (T)0;
+#pragma unroll
+        for (int i = 0; i < KB; ++i) {
+            qv[i][u] = (in && i < kw) ? Q[k + (k0 + i) * a.ldq] : (T)0;
+            if (HP) pv[i][u] = (in && i < kw) ? P[k + (k0 + i) * a.ldp] : (T)0;
+        }
+    }
+    double acc = 0.0;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = row0 + u * 256 + tid;
+        if (k >= a.m) continue;
+#pragma unroll
+        for (int i = 0; i < KB; ++i) {
+            if (i < kw) {
+                z[u] = upd(z[u], r[i], qv[i][u]);
+                if (HP) x[u] = upd(x[u], r[i], pv[i][u]);
+            }
+        }
+        if (HP) {
+            Q[k + j * a.ldq] = z[u];
+            X[k + j * a.ldx] = x[u];
+            acc += (double)z[u] * (double)x[u];
+        } else {
+            zt[k] = z[u];
+        }
+    }
+    if (HP) {
+        const double t = block_sum<double, 256>(acc, lds);
+        if (tid == 0) a.rr_out[blockIdx.x] = t;
+    }
+}
+
+// ------------------------------------------------------------- launchers
+template <typename T>
+void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1, int64_t d0,
+                   int64_t l0, int64_t c0, int64_t c1, int64_t n_rr)
+{
+    constexpr int U = panel_rows<T>();
+    PSweepArgs a{};
+    a.m = c.m; a.n = c.n; a.j = j; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp;
+    a.X = c.X; a.ldx = c.m; a.zt = c.zt; a.xv = c.xv; a.R = c.R; a.ldr = c.ldr;
+    a.info = c.info; a.rr_part = c.rr_part; a.n_rr = n_rr;
+    a.k0 = k0; a.k1 = k1; a.d0 = d0; a.l0 = l0; a.c0 = c0; a.c1 = c1 > c0 ? c1 : c0;
+    const bool block_dots = d0 < j;
+    a.part = block_dots ? c.wpart : c.sp.part;
+    a.pstride = block_dots ? PANEL_B : 1;
+    a.g = c.g_p;
+    a.lpart = c.lpart;
+    const int64_t ncols = a.c1 - a.c0;
+    int64_t gy = 1, cpw = PS_CB;
+    if (ncols > 0) {
+        gy = (SWEEP_TARGET_WG + c.g_p - 1) / c.g_p;
+        const int64_t max_gy = (ncols + PS_CB - 1) / PS_CB;
+        if (gy > max_gy) gy = max_gy;
+        if (gy < 1) gy = 1;
+        cpw = (ncols + gy - 1) / gy;
+        cpw = (cpw + PS_CB - 1) / PS_CB * PS_CB;
+        if (cpw > PS_MAXC) cpw = PS_MAXC;
+        gy = (ncols + cpw - 1) / cpw;
+    }
+    a.cpw = cpw;
+    const dim3 grid((unsigned)c.g_p, (unsigned)gy), block(256);
+    const bool nts = (double)ncols * (double)c.m * sizeof(T) > SWEEP_NT_BYTES;
+#define AMGS_PS_LAUNCH(V_, NT_, DB_)                                                              \
+    do {                                                                                          \
+        if (c.ev_start)                                                                           \
+            hipExtLaunchKernelGGL((k_psweep<T, U, V_, NT_, DB_>), grid, block, 0, c.stream,       \
+                                  c.ev_start, c.ev_stop, 0, a);                                   \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_psweep<T, U, V_, NT_, DB_>), grid, block, 0, c.stream, a);      \
+    } while (0)
+#define AMGS_PS_DB(V_, NT_)                                                                       \
+    do {                                                                                          \
+        if (block_dots) AMGS_PS_LAUNCH(V_, NT_, PANEL_B);                                         \
+        else AMGS_PS_LAUNCH(V_, NT_, 1);                                                          \
+    } while (0)
+#define AMGS_PS_NT(V_)                                                                            \
+    do {                                                                                          \
+        if (nts) AMGS_PS_DB(V_, true);                                                            \
+        else AMGS_PS_DB(V_, false);                                                               \
+    } while (0)
+    if (variant == VAR_NAIVE) AMGS_PS_NT(VAR_NAIVE);
+    else if (variant == VAR_HA) AMGS_PS_NT(VAR_HA);
+    else AMGS_PS_NT(VAR_HP);
+#undef AMGS_PS_NT
+#undef AMGS_PS_DB
+#undef AMGS_PS_LAUNCH
+}
+
+template <typename T>
+void launch_pfin(const Ctx &c, int64_t s, int64_t e)
+{
+    if (e >= c.n) return;
+    hipLaunchKernelGGL(k_pfin<T>, dim3((unsigned)(c.n - e)), dim3(256), 0, c.stream, s, e,
+                       (const T *)c.wpart, (const T *)c.lpart, c.g_p, c.R, c.ldr, c.info);
+}
+
+int64_t pcol_blk_partials(const Ctx &c) { return c.geo.g_rows2; }
+
+template <typename T>
+void launch_pcol_blk(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1)
+{
+    RowArgs a{};
+    a.m = c.m; a.n = c.n; a.j = j; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp;
+    a.X = c.X; a.ldx = c.m; a.zt = c.zt; a.R = c.R; a.ldr = c.ldr; a.info = c.info;
+    a.sp = c.sp; a.rr_out = c.rr_part; a.x_from = -1;
+    const dim3 grid((unsigned)c.geo.g_rows2), block(256);
+#define AMGS_PCB(V_)                                                                              \
+    switch (c.geo.U2) {                                                                           \
+    case 1: hipLaunchKernelGGL((k_pcol_blk<T, 1, V_>), grid, block, 0, c.stream, a, k0, k1); break; \
+    case 2: hipLaunchKernelGGL((k_pcol_blk<T, 2, V_>), grid, block, 0, c.stream, a, k0, k1); break; \
+    default: hipLaunchKernelGGL((k_pcol_blk<T, 4, V_>), grid, block, 0, c.stream, a, k0, k1); break; \
+    }
+    if (variant == VAR_HP) { AMGS_PCB(VAR_HP); }
+    else { AMGS_PCB(VAR_HA); }
+#undef AMGS_PCB
+}
+
+template void launch_psweep<double>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t, int64_t,
+                                    int64_t, int64_t, int64_t);
+template void launch_psweep<float>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t, int64_t,
+                                   int64_t, int64_t, int64_t);
+template void launch_pfin<double>(const Ctx &, int64_t, int64_t);
+template void launch_pfin<float>(const Ctx &, int64_t, int64_t);
+template void launch_pcol_blk<double>(const Ctx &, int, int64_t, int64_t, int64_t);
+template void launch_pcol_blk<float>(const Ctx &, int, int64_t, int64_t, int64_t);
+
+int panel_rows_for(int fp64) { return fp64 ? panel_rows<double>() : panel_rows<float>(); }
+
+} // namespace amgs

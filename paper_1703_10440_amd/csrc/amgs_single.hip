@@ -429,7 +429,10 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
     const int64_t row0 = (int64_t)blockIdx.x * 256 * U;
     // issue the row loads before waiting for r_{j-1,j}
     T zr[U], qp[U], x[U], pv[HP_XB][U];
-    const int64_t i0 = j > 0 ? HP_XB * ((j - 1) / HP_XB) : 0;
+    // first recurrence term applied here: in the column schedule the terms
+    // below XB floor((j-1)/XB) were applied by k_hp_xblock; in the panel
+    // schedule the sweeps have applied all terms but the last
+    const int64_t i0 = a.x_from >= 0 ? a.x_from : (j > 0 ? HP_XB * ((j - 1) / HP_XB) : 0);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
@@ -622,20 +625,6 @@ __global__ __launch_bounds__(256) void k_reorth_b(RowArgs a)
 //     partial of r_{j,c} = p_j^T z_c     (dot of step j)
 // with z_c read and written once.  One wave re-reduces the A-norm partials
 // and broadcasts r_jj through LDS.
-// Loads and stores of the later columns; NT selects the non-temporal
-// (streaming) cache policy.
-template <bool NT, typename T>
-__device__ __forceinline__ T ld_stream(const T *p)
-{
-    if constexpr (NT) return __builtin_nontemporal_load(p);
-    else return *p;
-}
-template <bool NT, typename T>
-__device__ __forceinline__ void st_stream(T *p, T v)
-{
-    if constexpr (NT) __builtin_nontemporal_store(v, p);
-    else *p = v;
-}
 
 template <typename T, int U, int VAR, bool NTS>
 __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
@@ -906,7 +895,7 @@ void launch_mv(const Ctx &c, int64_t j, int src_mode)
     const T *Q = (const T *)c.Q;
     if (c.is_dense) {
         DenseMvArgs a{};
-        a.m = c.m; a.n = c.n; a.j = j; a.A = c.A; a.lda = c.lda;
+        a.m = c.m; a.n = c.n_pub; a.j = j; a.A = c.A; a.lda = c.lda;
         a.info = c.info; a.R = c.R; a.ldr = c.ldr; a.sp = c.sp;
         a.rr_part = c.rr_part; a.n_rr = c.n_rr_mv; a.rr_out = c.rr_part;
         if (src_mode == SRC_UPD) {
@@ -922,7 +911,7 @@ void launch_mv(const Ctx &c, int64_t j, int src_mode)
         }
     } else {
         CsrMvArgs a{};
-        a.m = c.m; a.n = c.n; a.j = j; a.row_ptr = c.row_ptr; a.col_idx = c.col_idx; a.vals = c.vals;
+        a.m = c.m; a.n = c.n_pub; a.j = j; a.row_ptr = c.row_ptr; a.col_idx = c.col_idx; a.vals = c.vals;
         a.info = c.info; a.R = c.R; a.ldr = c.ldr; a.sp = c.sp;
         a.rr_part = c.rr_part; a.n_rr = c.n_rr_mv; a.rr_out = c.rr_part;
         if (src_mode == SRC_UPD) {
@@ -942,7 +931,7 @@ void launch_mv(const Ctx &c, int64_t j, int src_mode)
 static RowArgs row_args(const Ctx &c, int64_t j)
 {
     RowArgs a{};
-    a.m = c.m; a.n = c.n; a.j = j; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp;
+    a.m = c.m; a.n = c.n_pub; a.j = j; a.x_from = c.x_from; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp;
     a.X = c.X; a.ldx = c.m; a.zt = c.zt; a.R = c.R; a.ldr = c.ldr; a.info = c.info;
     a.sp = c.sp; a.rr_out = c.rr_part; a.s_part = c.s_part; a.S = c.S;
     return a;

@@ -46,9 +46,9 @@ def pin_hand_example(lib, golden) -> list:
     A, Z = golden["A"], golden["Z"]
     csr = inputs.csr_from_dense(A)
     for v in VARIANTS:
-        for o in ORIENTS:
+        for o in ORIENTS + ("panel",):
             for prec in ("fp64", "fp32"):
-                for re_ in (False, True):
+                for re_ in ((False, True) if o != "panel" else (False,)):
                     for kind in ("dense", "csr"):
                         kw = dict(dense=A) if kind == "dense" else dict(csr=csr)
                         r = ref.qr(Z, variant=v, orientation=o, reorth=re_, precision=prec,
@@ -336,6 +336,65 @@ def pin_breakdown(lib) -> list:
     return fails
 
 
+def pin_panel(lib) -> list:
+    """Panel schedule (orientation "panel", panels of 4 columns): the
+    regrouped projections give, in exact arithmetic, the column algorithm's
+    coefficients, so the same facts hold -- R = chol(Z^T A Z), Q = Z R^{-1},
+    P = AQ on well-conditioned problems with several panels and a ragged last
+    panel; Householder QR for A = I with the three variants equal bit for
+    bit; the hand example exactly; one panel (n <= 4) is the column
+    algorithm bit for bit; MV counts 2n / n / one block; and on an
+    experiment-II problem (case 2, kappa(A) = kappa(Z) = 1e8) the loss of
+    A-orthogonality stays within a small factor of the column algorithm's
+    and below 10 delta_1 (a block step without the triangular correction
+    loses orders of magnitude there)."""
+    fails = []
+    for seed in (11, 12):
+        for p in (inputs.random_dense_problem(60, 9, seed), inputs.random_csr_problem(300, 14, 9, seed)):
+            Ad = p.dense if p.dense is not None else p.csr.to_dense()
+            Rc = _chol_R(p.Z, Ad)
+            for v in VARIANTS:
+                r = ref.qr(p.Z, dense=p.dense, csr=p.csr, variant=v, orientation="panel", lib=lib)
+                e, eq, ep = (_rel(np.triu(r.R), Rc), _rel(r.Q, np.linalg.solve(Rc.T, p.Z.T).T),
+                             _rel(r.P, Ad @ r.Q))
+                if r.info != 0 or not (e <= 1e-13 and eq <= 1e-12 and ep <= 1e-12):
+                    fails.append(f"panel chol {p.name} {v}: R {e} Q {eq} P {ep} info {r.info}")
+                want_calls = {"naive": 2 * p.n, "ha": p.n, "hp": 1}[v]
+                if r.mv_calls != want_calls:
+                    fails.append(f"panel MV count {p.name} {v}: {r.mv_calls} != {want_calls}")
+    g = inputs.rng(22)
+    m, n = 150, 11
+    Z = np.asfortranarray(g.standard_normal((m, n)))
+    eye = inputs.CSR(m, np.arange(m + 1, dtype=np.int32), np.arange(m, dtype=np.int32), np.ones(m))
+    Qh, Rh = np.linalg.qr(Z)
+    D = np.sign(np.diag(Rh))
+    Qh, Rh = Qh * D[None, :], Rh * D[:, None]
+    outs = {v: ref.qr(Z, csr=eye, variant=v, orientation="panel", lib=lib) for v in VARIANTS}
+    for v, r in outs.items():
+        if _rel(np.triu(r.R), Rh) > 1e-14 or _rel(r.Q, Qh) > 1e-13:
+            fails.append(f"panel identity {v}: R {_rel(np.triu(r.R), Rh)} Q {_rel(r.Q, Qh)}")
+        if not (np.array_equal(r.R, outs["naive"].R) and np.array_equal(r.Q, outs["naive"].Q)):
+            fails.append(f"panel identity: {v} differs bitwise from naive")
+    p = inputs.random_dense_problem(40, 4, 5)
+    for v in VARIANTS:
+        a = ref.qr(p.Z, dense=p.dense, variant=v, lib=lib)
+        b = ref.qr(p.Z, dense=p.dense, variant=v, orientation="panel", lib=lib)
+        if not (np.array_equal(a.R, b.R) and np.array_equal(a.Q, b.Q)):
+            fails.append(f"panel single panel {v}: differs from the column algorithm")
+    u = 2.0 ** -53
+    p = inputs.exp2_problem(100, 20, 1e8, 1e8, 2, 7)
+    w, V = np.linalg.eigh(p.dense)
+    d1 = u * float(w[-1] / w[0]) * _kappa((V * np.sqrt(w)[None, :]) @ V.T @ p.Z)
+    for v in ("naive", "ha"):
+        lc = ref.orth_loss(ref.qr_problem(p, variant=v, lib=lib).Q, dense=p.dense)
+        r = ref.qr_problem(p, variant=v, orientation="panel", lib=lib)
+        lp = ref.orth_loss(r.Q, dense=p.dense)
+        if r.info != 0 or not (lp <= 30 * lc and lp <= 10 * d1):
+            fails.append(f"panel exp2 {v}: loss {lp} (column {lc}, 10 delta1 {10 * d1})")
+    return fails
+
+
 ALL_PINS = [pin_hand_example, pin_cholesky, pin_identity_householder, pin_cholesky_factor,
             pin_col_row_bitwise, pin_mv_counts, pin_scaling, pin_first_column,
-            pin_residual_and_reorth, pin_exp2_accuracy, pin_fp32_accumulation, pin_fp32_vs_fp64, pin_breakdown]
+            pin_residual_and_reorth, pin_exp2_accuracy, pin_fp32_accumulation, pin_fp32_vs_fp64, pin_breakdown,
+            pin_panel]

@@ -1,0 +1,190 @@
+"""Panel schedule (opts.panel = 4) of the GPU path against the oracle's panel
+orientation, which performs the same regrouped operations step by step and
+is itself pinned to the closed forms (tests/pins.py, pin_panel).
+
+Tolerances are those of the column schedule (tests/test_gpu_parity.py):
+R, Q, P within 1e-10 (relative, Frobenius) for kappa(Z) <= 1e3; for
+kappa(Z) > 1e3 the residual and ||Q^T A Q - I||_2 within 10x the oracle's;
+the binary32 form within 64 u_32 kappa(A^{1/2} Z) sqrt(n) of the oracle's
+binary32 emulation.
+"""
+import numpy as np
+import pytest
+
+from oracle import ref
+from paper_1703_10440_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():  # pragma: no cover - CPU container
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from paper_1703_10440_amd import amgs  # noqa: E402
+
+DEV = torch.device("cuda:0")
+VARIANTS = ("naive", "ha", "hp")
+U32 = 2.0 ** -24
+PANEL = 4
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb else 1.0))
+
+
+def gpu_run(prob, variant, precision="fp64", panel=PANEL):
+    Zt = torch.from_numpy(np.ascontiguousarray(prob.Z)).to(DEV)
+    print(f"[gpu] panel={panel} {prob.name} m={prob.m} n={prob.n} {variant} {precision}",
+          flush=True)
+    if prob.csr is not None:
+        out = amgs.qr_csr(torch.from_numpy(prob.csr.row_ptr).to(DEV),
+                          torch.from_numpy(prob.csr.col_idx).to(DEV),
+                          torch.from_numpy(prob.csr.vals).to(DEV), Zt, variant=variant,
+                          precision=precision, return_p=True, panel=panel)
+    else:
+        out = amgs.qr_dense(torch.from_numpy(np.ascontiguousarray(prob.dense)).to(DEV), Zt,
+                            variant=variant, precision=precision, return_p=True, panel=panel)
+    torch.cuda.synchronize()
+    return (out.Q.double().cpu().numpy(), out.R.cpu().numpy(), out.P.double().cpu().numpy(),
+            int(out.info.item()), out.stats)
+
+
+def oracle(prob, variant, precision="fp64"):
+    return ref.qr_problem(prob, variant=variant, orientation="panel", precision=precision)
+
+
+def orth(prob, Q):
+    return ref.orth_loss(Q, dense=prob.dense, csr=prob.csr)
+
+
+def small_problems():
+    return [
+        inputs.laplacian_graded_problem(N=12, n=13, decades=2.0, seed=7),   # m=1728, 4 panels
+        inputs.random_csr_problem(3001, 17, 40, seed=8),                    # 4 lanes/row
+        inputs.random_csr_problem(2003, 9, 220, seed=9),                    # 32 lanes/row
+        inputs.dense_gram_problem(512, 32, seed=1),                         # dense, 8 panels
+        inputs.random_dense_problem(333, 21, seed=10),                      # ragged
+    ]
+
+
+SMALL = small_problems()
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("pi", range(len(SMALL)), ids=[p.name for p in SMALL])
+def test_panel_fp64_parity(pi, variant):
+    p = SMALL[pi]
+    want = oracle(p, variant)
+    Q, R, P, info, st = gpu_run(p, variant)
+    assert info == 0 and want.info == 0
+    eR, eQ, eP = _rel(R, want.R), _rel(Q, want.Q), _rel(P, want.P)
+    print(f"  R {eR:.2e} Q {eQ:.2e} P {eP:.2e} |Q^TAQ-I| {orth(p, Q):.2e}")
+    assert eR <= 1e-10 and eQ <= 1e-10 and eP <= 1e-10
+    assert np.all(np.tril(R, -1) == 0) and np.all(np.diag(R) > 0)
+    assert st.mv_calls == {"naive": 2 * p.n, "ha": p.n, "hp": 1}[variant]
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_panel_graded_ill_conditioned(variant):
+    """kappa(Z) ~ 1e6, 6 panels: residual and orthogonality at the oracle's level."""
+    p = inputs.laplacian_graded_problem(N=16, n=24, decades=6.0, seed=11)
+    want = oracle(p, variant)
+    Q, R, P, info, _ = gpu_run(p, variant)
+    assert info == 0
+    res_g, res_o = ref.residual(p.Z, Q, R), ref.residual(p.Z, want.Q, want.R)
+    o_g, o_o = orth(p, Q), orth(p, want.Q)
+    print(f"  residual {res_g:.2e} (oracle {res_o:.2e}) orth {o_g:.2e} (oracle {o_o:.2e})")
+    assert res_g <= max(1e-12, 10 * res_o)
+    assert o_g <= max(1e-13, 10 * o_o)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("pi", [0, 1, 3], ids=[SMALL[i].name for i in (0, 1, 3)])
+def test_panel_fp32_form(pi, variant):
+    p = SMALL[pi]
+    Z32 = np.asfortranarray(p.Z.astype(np.float32).astype(np.float64))
+    if p.csr is not None:
+        p32 = inputs.Problem(p.name, Z32, csr=inputs.CSR(
+            p.m, p.csr.row_ptr, p.csr.col_idx, p.csr.vals.astype(np.float32).astype(np.float64)))
+    else:
+        p32 = inputs.Problem(p.name, Z32, dense=np.asfortranarray(
+            p.dense.astype(np.float32).astype(np.float64)))
+    want32 = oracle(p32, variant, "fp32")
+    kappa = np.linalg.cond(oracle(p32, variant).R)
+    Q, R, P, info, _ = gpu_run(p32, variant, precision="fp32")
+    assert info == 0
+    tol = 64 * U32 * kappa * np.sqrt(p.n)
+    e32 = _rel(R, want32.R)
+    o_g, o_o = orth(p32, Q), orth(p32, want32.Q)
+    print(f"  R vs fp32 oracle {e32:.2e} tol {tol:.2e} orth {o_g:.2e} (oracle {o_o:.2e})")
+    assert e32 <= tol
+    assert o_g <= max(10 * o_o, 1e-6)
+
+
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_panel_many_workgroups_deterministic(variant):
+    """m = 64000, n = 40: the sweeps after each panel run hundreds of row
+    chunks and several column groups; parity and bit-identical repeats."""
+    p = inputs.laplacian_graded_problem(N=40, n=40, decades=2.0, seed=14)
+    want = oracle(p, variant)
+    Q, R, P, info, _ = gpu_run(p, variant)
+    Q2, R2, _, _, _ = gpu_run(p, variant)
+    assert info == 0
+    assert np.array_equal(R, R2) and np.array_equal(Q, Q2)
+    e = _rel(R, want.R)
+    print(f"  R {e:.2e} orth {orth(p, Q):.2e} (oracle {orth(p, want.Q):.2e})")
+    assert e <= 1e-10 and _rel(Q, want.Q) <= 1e-10
+
+
+def test_panel_edges():
+    """Panel boundaries: n = 1, 4 (one full panel), 5 (a one-column last
+    panel), 8; square and tiny m; dense and CSR."""
+    g = inputs.rng(15)
+    for m, n in ((700, 1), (300, 4), (300, 5), (200, 8), (40, 40), (5, 3)):
+        A = inputs.gram_spd(g, m)
+        Z = np.asfortranarray(g.standard_normal((m, n)))
+        for prob in (inputs.Problem(f"edge{m}x{n}", Z, dense=A),
+                     inputs.Problem(f"edgecsr{m}x{n}", Z, csr=inputs.csr_from_dense(A))):
+            for v in VARIANTS:
+                want = oracle(prob, v)
+                Q, R, P, info, _ = gpu_run(prob, v)
+                assert info == 0
+                assert _rel(R, want.R) <= 1e-10, (prob.name, v, _rel(R, want.R))
+                assert _rel(Q, want.Q) <= 1e-10, (prob.name, v, _rel(Q, want.Q))
+
+
+def test_panel_breakdown_reports_column():
+    """A zero column in the second panel (column 6) and a NaN in the third
+    (column 10) stop at the right index; earlier columns stay valid."""
+    g = inputs.rng(16)
+    m, n = 300, 12
+    A = inputs.gram_spd(g, m)
+    Z = np.asfortranarray(g.standard_normal((m, n)))
+    Zc = Z.copy(order="F")
+    Zc[:, 5] = 0.0
+    Zn = Z.copy(order="F")
+    Zn[7, 9] = np.nan
+    for v in VARIANTS:
+        _, R, _, info, _ = gpu_run(inputs.Problem("zero", Zc, dense=A), v)
+        want = oracle(inputs.Problem("zero", Zc, dense=A), v)
+        assert info == 6 and want.info == 6
+        assert _rel(R[:5, :5], want.R[:5, :5]) <= 1e-10
+        _, _, _, info, _ = gpu_run(inputs.Problem("nan", Zn, csr=inputs.csr_from_dense(A)), v)
+        assert info == 10
+
+
+def test_panel_argument_errors():
+    h = amgs.handle(0)
+    import ctypes as C
+    info = torch.zeros(1, dtype=torch.int32, device=DEV)
+    Z = torch.zeros(10, 4, dtype=torch.float64, device=DEV)
+    work = torch.empty(1 << 20, dtype=torch.uint8, device=DEV)
+    for panel, reorth, want in ((3, 0, -1), (8, 0, -1), (4, 1, -4)):
+        opts = amgs.Opts(reorth, panel, 0, 0)
+        st = amgs.amgs_qr_dense(h, 10, Z.data_ptr(), 10, 4, Z.data_ptr(), 10, Z.data_ptr(), 10,
+                                Z.data_ptr(), 4, None, 0, 1, 0, C.byref(opts), work.data_ptr(),
+                                work.numel(), info.data_ptr(), None)
+        assert st == want, (panel, reorth, st)
+    assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(0, 3, 0, 0)) == 0
+    assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(0, 4, 0, 0)) > 0

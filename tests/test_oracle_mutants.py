@@ -40,6 +40,15 @@ MUTANTS = [
      "        if (0) {\n            float s = 0.0f;\n            for (int64_t k = lo;"),
     ("dense MV walks a row of the wrong matrix (transposed operand of a non-symmetric read)",
      "const double *col = A->a + k * A->lda;", "const double *col = A->a + k;"),
+    ("panel block step without the triangular correction",
+     "for (int k = 0; k < i; ++k) t = t - L[i][k] * r[k];",
+     "for (int k = 0; k < i; ++k) t = t - 0.0 * r[k];"),
+    ("panel block step updates x with q instead of p",
+     "axpy_st(X + c * m, st(r[i], prec), P + (s + i) * ldp, m, prec);",
+     "axpy_st(X + c * m, st(r[i], prec), Q + (s + i) * ldq, m, prec);"),
+    ("panel block step skips the last panel column",
+     "for (int i = 0; i < b; ++i) axpy_st(z, st(r[i], prec), Q + (s + i) * ldq, m, prec);",
+     "for (int i = 0; i + 1 < b; ++i) axpy_st(z, st(r[i], prec), Q + (s + i) * ldq, m, prec);"),
 ]
 
 
