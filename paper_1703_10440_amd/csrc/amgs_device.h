@@ -69,6 +69,31 @@ __device__ __forceinline__ A wave_sum(A v)
     return lane63(v);
 }
 
+// Sums of four per-lane values over a whole wave, transposed: on return
+// lane l holds the wave's total of value (l & 3).  Half of the values are
+// exchanged with lane l^1, then half of the rest with lane l^2 (quad_perm),
+// the row is closed with rotations by 4 and 8, and the four rows of the wave
+// are added with lane exchanges l^16 and l^32.  Each lane does the work of
+// about one reduction instead of four; the order is fixed, so the bits do
+// not depend on timing.
+template <typename A>
+__device__ __forceinline__ A wave_sum4(A v0, A v1, A v2, A v3)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const bool b0 = lane & 1, b1 = lane & 2;
+    const A s0 = b0 ? v0 : v1, s1 = b0 ? v2 : v3;
+    const A k0 = b0 ? v1 : v0, k1 = b0 ? v3 : v2;
+    const A t0 = k0 + dpp_mov<0xb1, 0xf>(s0);   // value b0 of the pair
+    const A t1 = k1 + dpp_mov<0xb1, 0xf>(s1);   // value b0 + 2 of the pair
+    const A s2 = b1 ? t0 : t1, k2 = b1 ? t1 : t0;
+    A r = k2 + dpp_mov<0x4e, 0xf>(s2);          // value (l & 3) of the quad
+    r += dpp_mov<0x124, 0xf>(r);                // row_ror 4
+    r += dpp_mov<0x128, 0xf>(r);                // row_ror 8
+    r += __shfl_xor(r, 16);
+    r += __shfl_xor(r, 32);
+    return r;
+}
+
 // Canonical reduction of v[0..N): lane l adds v[l], v[l+64], v[l+128], ...
 // in ascending order into one accumulator, then the butterfly.  The loads
 // are issued eight at a time, so N <= 512 costs one memory round trip.  Any

@@ -39,6 +39,7 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
     constexpr int KB = PANEL_B;
     constexpr bool HPX = VAR == VAR_HP;
     constexpr int DL = DB > 1 ? DB - 1 : 1;
+    static_assert(DB == 1 || DB == 4, "block dots are reduced four at a time");
     __shared__ T red[256 / WAVE][PS_MAXC * DB];
     __shared__ T lred[256 / WAVE][KB];
     __shared__ double s_rr;
@@ -70,6 +71,34 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
 #pragma unroll
         for (int t = 0; t < DL; ++t) pd[t][u] = (in && t < bd - 1) ? P[k + (a.d0 + t) * a.ldp] : (T)0;
     }
+    // q_k for the row of strict_lower(P_I^T Q_I), k in [l0, j)
+    const int nl = (int)(j - a.l0);
+    T ql[KB - 1][U];
+#pragma unroll
+    for (int i = 0; i < KB - 1; ++i)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = row0 + u * 256 + tid;
+            ql[i][u] = (own && i < nl && k < m) ? Q[k + (a.l0 + i) * a.ldq] : (T)0;
+        }
+    const int64_t c0 = a.c0 + (int64_t)blockIdx.y * a.cpw;
+    const int64_t c1 = (c0 + a.cpw < a.c1) ? c0 + a.cpw : a.c1;
+    const bool full_rows = row0 + 256 * U <= m;
+    // the first group of later columns is requested before waiting for r_jj
+    T zv[PS_CB][U], xv[HPX ? PS_CB : 1][U];
+    auto load_group = [&](int64_t cb) {
+#pragma unroll
+        for (int t = 0; t < PS_CB; ++t) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int64_t k = row0 + u * 256 + tid;
+                const bool in = cb + t < c1 && (full_rows || k < m);
+                zv[t][u] = in ? ld_stream<NTS>(Q + (cb + t) * a.ldq + k) : (T)0;
+                if (HPX) xv[t][u] = (in && kw > 0) ? ld_stream<NTS>(X + (cb + t) * a.ldx + k) : (T)0;
+            }
+        }
+    };
+    load_group(c0);
     if (wave == 0) {
         const double rr = wave_reduce_seq(a.rr_part, a.n_rr);
         if (tid == 0) s_rr = rr;
@@ -92,21 +121,8 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
             if (VAR != VAR_NAIVE) P[k + j * a.ldp] = pj[u];
         }
     }
-    const int64_t c0 = a.c0 + (int64_t)blockIdx.y * a.cpw;
-    const int64_t c1 = (c0 + a.cpw < a.c1) ? c0 + a.cpw : a.c1;
-    const bool full_rows = row0 + 256 * U <= m;
     for (int64_t cb = c0; cb < c1; cb += PS_CB) {
-        T zv[PS_CB][U], xv[HPX ? PS_CB : 1][U];
-#pragma unroll
-        for (int t = 0; t < PS_CB; ++t) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int64_t k = row0 + u * 256 + tid;
-                const bool in = cb + t < c1 && (full_rows || k < m);
-                zv[t][u] = in ? ld_stream<NTS>(Q + (cb + t) * a.ldq + k) : (T)0;
-                if (HPX) xv[t][u] = (in && kw > 0) ? ld_stream<NTS>(X + (cb + t) * a.ldx + k) : (T)0;
-            }
-        }
+        if (cb > c0) load_group(cb);
         T acc[PS_CB][DB];
 #pragma unroll
         for (int t = 0; t < PS_CB; ++t) {
@@ -143,13 +159,21 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
                 }
             }
         }
+        if constexpr (DB == 4) {
 #pragma unroll
-        for (int t = 0; t < PS_CB; ++t)
-#pragma unroll
-            for (int d = 0; d < DB; ++d) {
-                const T v = wave_sum(acc[t][d]);
-                if (lane == 0 && cb + t < c1 && d < bd) red[wave][(cb - c0 + t) * DB + d] = v;
+            for (int t = 0; t < PS_CB; ++t) {
+                const T v = wave_sum4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]);
+                if (lane < 4 && cb + t < c1 && lane < bd) red[wave][(cb - c0 + t) * DB + lane] = v;
             }
+        } else {
+#pragma unroll
+            for (int t = 0; t < PS_CB; ++t)
+#pragma unroll
+                for (int d = 0; d < DB; ++d) {
+                    const T v = wave_sum(acc[t][d]);
+                    if (lane == 0 && cb + t < c1 && d < bd) red[wave][(cb - c0 + t) * DB + d] = v;
+                }
+        }
     }
     __syncthreads();
     const int ncols = c0 < c1 ? (int)(c1 - c0) : 0;
@@ -161,17 +185,13 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
         ((T *)a.part)[((c0 + cl) * a.pstride + d) * a.g + blockIdx.x] = s;
     }
     // row j of strict_lower(P_I^T Q_I): p_j^T q_k for k in [l0, j)
-    const int nl = (int)(j - a.l0);
     if (own && nl > 0) {
 #pragma unroll
         for (int i = 0; i < KB - 1; ++i) {
             if (i < nl) {
                 T s = 0;
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t k = row0 + u * 256 + tid;
-                    if (k < m) s += pj[u] * Q[k + (a.l0 + i) * a.ldq];
-                }
+                for (int u = 0; u < U; ++u) s += pj[u] * ql[i][u];
                 s = wave_sum(s);
                 if (lane == 0) lred[wave][i] = s;
             }
