@@ -4,11 +4,10 @@
 // n sequential MV).
 //
 // A is symmetric and column-major, so X[k, c] = sum_l A[l, k] Z[l, c]: both
-// operands are contiguous along the contraction index l.  A workgroup of
-// four waves computes a 64 x 64 tile of X; each wave owns a 32 x 32 block as
-// 2 x 2 MFMA 16x16 tiles (v_mfma_f64_16x16x4f64 in binary64,
-// v_mfma_f32_16x16x4f32 in binary32).  K is consumed in slabs of 16 staged
-// through LDS (double-buffered), loaded with 16-byte vector reads.
+// operands are contiguous along the contraction index l.  MFMA 16x16 tiles
+// (v_mfma_f64_16x16x4f64 in binary64, v_mfma_f32_16x16x4f32 in binary32);
+// K is consumed in slabs of 16 staged through LDS (double-buffered), each
+// thread loading a run of consecutive k values of one column.
 #include "amgs_device.h"
 #include "amgs_internal.h"
 
@@ -38,57 +37,66 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
 };
 
-constexpr int GB_M = 64, GB_N = 64, GB_K = 16;
+constexpr int GB_K = 16;
 
 // Operand layout of the 16x16x4 instructions: lane l supplies A[l%16][l/16]
-// and B[l/16][l%16]; result rows follow Mfma<T>::row.
-template <typename T>
+// and B[l/16][l%16]; result rows follow Mfma<T>::row.  A workgroup of four
+// waves (2 x 2) computes a TM x TN tile of X; each wave owns a
+// (TM/2) x (TN/2) block of (TM/32) x (TN/32) MFMA tiles.  Larger tiles read
+// A fewer times (once per TN columns of X) and feed more MFMAs per LDS read.
+template <typename T, int TM, int TN>
 __global__ __launch_bounds__(256) void k_gemm_atb(int64_t m, int64_t n, const T *__restrict__ A,
                                                   int64_t lda, const T *__restrict__ Z,
                                                   int64_t ldz, T *__restrict__ X, int64_t ldx)
 {
     typedef typename Mfma<T>::acc_t acc_t;
+    constexpr int FM = TM / 32, FN = TN / 32;
+    // staging: each thread loads a run of consecutive k values of one column
+    constexpr int A_PER = TM * GB_K / 256, B_PER = TN * GB_K / 256;
+    constexpr int A_TPC = GB_K / A_PER, B_TPC = GB_K / B_PER;
+    static_assert(A_PER >= 1 && B_PER >= 1 && GB_K % A_PER == 0 && GB_K % B_PER == 0, "tile");
     // LDS: [buffer][k][col], padded by one element per row against bank
     // conflicts between the four k rows read by one instruction.
-    __shared__ T As[2][GB_K][GB_M + 1];
-    __shared__ T Bs[2][GB_K][GB_N + 1];
+    __shared__ T As[2][GB_K][TM + 1];
+    __shared__ T Bs[2][GB_K][TN + 1];
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int64_t m0 = (int64_t)blockIdx.x * GB_M;   // rows of X (= columns of A)
-    const int64_t n0 = (int64_t)blockIdx.y * GB_N;   // columns of X (= columns of Z)
-    const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
+    const int64_t m0 = (int64_t)blockIdx.x * TM;   // rows of X (= columns of A)
+    const int64_t n0 = (int64_t)blockIdx.y * TN;   // columns of X (= columns of Z)
+    const int wm = (wave & 1) * (TM / 2), wn = (wave >> 1) * (TN / 2);
 
-    // each thread stages 4 consecutive k values of one column, for A and Z
-    const int lc = tid >> 2;            // column within the tile, 0..63
-    const int lk = (tid & 3) * 4;       // first k of the thread's 4
-    const bool a_ok = m0 + lc < m, b_ok = n0 + lc < n;
-    const T *__restrict__ Acol = A + (a_ok ? (m0 + lc) : 0) * lda;
-    const T *__restrict__ Zcol = Z + (b_ok ? (n0 + lc) : 0) * ldz;
+    const int ac = tid / A_TPC, ak = (tid % A_TPC) * A_PER;
+    const int bc = tid / B_TPC, bk = (tid % B_TPC) * B_PER;
+    const bool a_ok = m0 + ac < m, b_ok = n0 + bc < n;
+    const T *__restrict__ Acol = A + (a_ok ? (m0 + ac) : 0) * lda;
+    const T *__restrict__ Zcol = Z + (b_ok ? (n0 + bc) : 0) * ldz;
 
-    acc_t acc[2][2];
+    acc_t acc[FM][FN];
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < FN; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[a][b][v] = 0;
 
-    T ra[4], rb[4];
+    T ra[A_PER], rb[B_PER];
     auto gload = [&](int64_t k0) {
         const bool full = k0 + GB_K <= m;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int64_t k = k0 + lk + t;
-            const bool kin = full || k < m;
-            ra[t] = (a_ok && kin) ? Acol[k] : (T)0;
-            rb[t] = (b_ok && kin) ? Zcol[k] : (T)0;
+        for (int t = 0; t < A_PER; ++t) {
+            const int64_t k = k0 + ak + t;
+            ra[t] = (a_ok && (full || k < m)) ? Acol[k] : (T)0;
+        }
+#pragma unroll
+        for (int t = 0; t < B_PER; ++t) {
+            const int64_t k = k0 + bk + t;
+            rb[t] = (b_ok && (full || k < m)) ? Zcol[k] : (T)0;
         }
     };
     auto lstore = [&](int buf) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            As[buf][lk + t][lc] = ra[t];
-            Bs[buf][lk + t][lc] = rb[t];
-        }
+        for (int t = 0; t < A_PER; ++t) As[buf][ak + t][ac] = ra[t];
+#pragma unroll
+        for (int t = 0; t < B_PER; ++t) Bs[buf][bk + t][bc] = rb[t];
     };
     const int64_t nk = (m + GB_K - 1) / GB_K;
     gload(0);
@@ -100,26 +108,24 @@ __global__ __launch_bounds__(256) void k_gemm_atb(int64_t m, int64_t n, const T 
 #pragma unroll
         for (int ks = 0; ks < GB_K; ks += 4) {
             const int kk = ks + (lane >> 4);
-            T av[2], bv[2];
+            T av[FM], bv[FN];
 #pragma unroll
-            for (int a = 0; a < 2; ++a) av[a] = As[buf][kk][wm + a * 16 + (lane & 15)];
+            for (int a = 0; a < FM; ++a) av[a] = As[buf][kk][wm + a * 16 + (lane & 15)];
 #pragma unroll
-            for (int b = 0; b < 2; ++b) bv[b] = Bs[buf][kk][wn + b * 16 + (lane & 15)];
+            for (int b = 0; b < FN; ++b) bv[b] = Bs[buf][kk][wn + b * 16 + (lane & 15)];
 #pragma unroll
-            for (int a = 0; a < 2; ++a)
+            for (int a = 0; a < FM; ++a)
 #pragma unroll
-                for (int b = 0; b < 2; ++b) acc[a][b] = Mfma<T>::op(av[a], bv[b], acc[a][b]);
+                for (int b = 0; b < FN; ++b) acc[a][b] = Mfma<T>::op(av[a], bv[b], acc[a][b]);
         }
-        if (kt + 1 < nk) {
-            lstore(buf ^ 1);
-        }
+        if (kt + 1 < nk) lstore(buf ^ 1);
         __syncthreads();
     }
     // store each 16x16 tile
 #pragma unroll
-    for (int a = 0; a < 2; ++a)
+    for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+        for (int b = 0; b < FN; ++b)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int64_t row = m0 + wm + a * 16 + Mfma<T>::row(lane, v);
@@ -128,12 +134,23 @@ __global__ __launch_bounds__(256) void k_gemm_atb(int64_t m, int64_t n, const T 
             }
 }
 
+// Large products: 128 x 64 tiles in binary64 and 128 x 128 in binary32 (the
+// faster of the two on MI355X for the 16384 x 16384 x 256 product), when the
+// grid still has a workgroup per compute unit; otherwise 64 x 64.
 template <typename T>
 void launch_dense_gemm(const Ctx &c)
 {
-    const dim3 grid((unsigned)((c.m + GB_M - 1) / GB_M), (unsigned)((c.n + GB_N - 1) / GB_N));
-    hipLaunchKernelGGL(k_gemm_atb<T>, grid, dim3(256), 0, c.stream, c.m, c.n, (const T *)c.A,
-                       c.lda, (const T *)c.Q, c.ldq, (T *)c.X, c.m);
+    constexpr int TN = sizeof(T) == 8 ? 64 : 128;
+    const int64_t big = ((c.m + 127) / 128) * ((c.n + TN - 1) / TN);
+    if (big >= 256) {
+        const dim3 grid((unsigned)((c.m + 127) / 128), (unsigned)((c.n + TN - 1) / TN));
+        hipLaunchKernelGGL((k_gemm_atb<T, 128, TN>), grid, dim3(256), 0, c.stream, c.m, c.n,
+                           (const T *)c.A, c.lda, (const T *)c.Q, c.ldq, (T *)c.X, c.m);
+    } else {
+        const dim3 grid((unsigned)((c.m + 63) / 64), (unsigned)((c.n + 63) / 64));
+        hipLaunchKernelGGL((k_gemm_atb<T, 64, 64>), grid, dim3(256), 0, c.stream, c.m, c.n,
+                           (const T *)c.A, c.lda, (const T *)c.Q, c.ldq, (T *)c.X, c.m);
+    }
 }
 
 template void launch_dense_gemm<double>(const Ctx &);
