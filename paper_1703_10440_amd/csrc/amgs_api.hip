@@ -424,7 +424,7 @@ Geo make_geo(int64_t m, int64_t nnz, int is_dense)
     const double avg = m > 0 ? (double)nnz / (double)m : 0.0;
     g.lanes = avg <= 7.5 ? 0 : avg <= 12 ? 1 : avg <= 24 ? 2 : avg <= 48 ? 4 : avg <= 96 ? 8
             : avg <= 192 ? 16 : avg <= 384 ? 32 : 64;
-    const int64_t rows_per_wg = g.lanes == 0 ? 512 : 512 / g.lanes;
+    const int64_t rows_per_wg = g.lanes == 0 ? MV_TILE : 512 / g.lanes;
     g.g_csr = (m + rows_per_wg - 1) / rows_per_wg;
     if (g.g_csr > MAX_G_MV) g.g_csr = MAX_G_MV;
     if (g.g_csr < 1) g.g_csr = 1;

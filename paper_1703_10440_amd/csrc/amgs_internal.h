@@ -17,7 +17,8 @@ constexpr int RE_GROUP = 8;    // second-pass coefficients per workgroup row
 constexpr int DENSE_CB = 16;   // outputs per dense-MV workgroup pass
 constexpr int SPMM_C = 8;      // columns per CSR block-product thread
 constexpr int MAX_G_MV = 512;  // partials of an MV column kernel
-constexpr int STREAM_CAP = 4096; // CSR entries staged per 512-row tile
+constexpr int MV_TILE = 512;   // rows (= threads) per CSR-stream MV workgroup
+constexpr int STREAM_CAP = 8 * MV_TILE; // CSR entries staged per tile
 constexpr int PANEL_B = 4;     // columns per panel of the panel schedule
 constexpr int PS_CB = 2;       // later columns streamed together by a panel-sweep thread
 constexpr int PS_MAXC = 64;    // later columns per panel-sweep workgroup (max)

@@ -140,18 +140,18 @@ __global__ __launch_bounds__(512) void k_csr_mv(CsrMvArgs a)
     if (SRC == SRC_UPD && qprev) publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
 }
 
-// CSR MV for short rows ("CSR stream"): a workgroup takes 512 consecutive
+// CSR MV for short rows ("CSR stream"): a workgroup takes MV_TILE consecutive
 // rows, stages their entries (at most STREAM_CAP) in LDS with coalesced
 // loads, then each thread sums its own row from LDS in stored order.  Same
 // contract as k_csr_mv; a tile with more entries than fit is summed straight
 // from memory.
 template <typename T, int SRC, bool RR>
-__global__ __launch_bounds__(512) void k_csr_mv_stream(CsrMvArgs a)
+__global__ __launch_bounds__(MV_TILE) void k_csr_mv_stream(CsrMvArgs a)
 {
-    constexpr int PER = STREAM_CAP / 512;
+    constexpr int PER = STREAM_CAP / MV_TILE;
     __shared__ int32_t s_col[STREAM_CAP];
     __shared__ T s_val[STREAM_CAP];
-    __shared__ double lds[512 / WAVE];
+    __shared__ double lds[MV_TILE / WAVE];
     __shared__ T s_r;
     __shared__ double s_rr;
     if (*a.info) return;
@@ -166,9 +166,9 @@ __global__ __launch_bounds__(512) void k_csr_mv_stream(CsrMvArgs a)
     double rjj = 1.0;
     double acc = 0.0;
     bool first = true;
-    for (int64_t row0 = (int64_t)blockIdx.x * 512; row0 < a.m; row0 += (int64_t)gridDim.x * 512) {
+    for (int64_t row0 = (int64_t)blockIdx.x * MV_TILE; row0 < a.m; row0 += (int64_t)gridDim.x * MV_TILE) {
         const int64_t row = row0 + tid;
-        const int64_t rend = row0 + 512 < a.m ? row0 + 512 : a.m;
+        const int64_t rend = row0 + MV_TILE < a.m ? row0 + MV_TILE : a.m;
         // everything that does not depend on the coefficient is requested
         // first: the tile's bounds, this thread's row bounds and own entry,
         // and the tile's column indices and values
@@ -189,7 +189,7 @@ __global__ __launch_bounds__(512) void k_csr_mv_stream(CsrMvArgs a)
         if (staged) {
 #pragma unroll
             for (int t = 0; t < PER; ++t) {
-                const int32_t e = t0 + tid + t * 512;
+                const int32_t e = t0 + tid + t * MV_TILE;
                 cl[t] = e < t1 ? a.col_idx[e] : 0;
                 vl[t] = e < t1 ? vals[e] : (T)0;
             }
@@ -208,7 +208,7 @@ __global__ __launch_bounds__(512) void k_csr_mv_stream(CsrMvArgs a)
         if (staged) {
 #pragma unroll
             for (int t = 0; t < PER; ++t) {
-                const int32_t e = t0 + tid + t * 512;
+                const int32_t e = t0 + tid + t * MV_TILE;
                 if (e < t1) {
                     s_col[e - t0] = cl[t];
                     s_val[e - t0] = vl[t];
@@ -263,7 +263,7 @@ __global__ __launch_bounds__(512) void k_csr_mv_stream(CsrMvArgs a)
         __syncthreads();
     }
     if (RR) {
-        double t = block_sum<double, 512>(acc, lds);
+        double t = block_sum<double, MV_TILE>(acc, lds);
         if (tid == 0) a.rr_out[blockIdx.x] = t;
     }
     // R[j-1, c] for c >= j, read by the next sweep, is published last so
@@ -875,7 +875,7 @@ static void launch_csr_mv_L(const Ctx &c, CsrMvArgs &a)
 {
     const dim3 grid((unsigned)c.geo.g_csr), block(512);
     switch (c.geo.lanes) {
-    case 0: launch_k(c, k_csr_mv_stream<T, SRC, RR>, grid, block, a); break;
+    case 0: launch_k(c, k_csr_mv_stream<T, SRC, RR>, grid, dim3(MV_TILE), a); break;
     case 1: launch_k(c, k_csr_mv<T, 1, SRC, RR>, grid, block, a); break;
     case 2: launch_k(c, k_csr_mv<T, 2, SRC, RR>, grid, block, a); break;
     case 4: launch_k(c, k_csr_mv<T, 4, SRC, RR>, grid, block, a); break;
