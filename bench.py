@@ -66,10 +66,11 @@ def to_device(prob, dev, torch):
 class Runner:
     """Preallocated device buffers for repeated calls of one configuration."""
 
-    def __init__(self, data, variant, precision, torch, amgs, reorth=False, panel=0):
+    def __init__(self, data, variant, precision, torch, amgs, reorth=False, panel=0, cgs=False):
         self.torch, self.amgs = torch, amgs
         dt = torch.float64 if precision == "fp64" else torch.float32
         self.variant, self.precision, self.reorth, self.panel = variant, precision, reorth, panel
+        self.cgs = cgs
         self.Z = amgs.colmajor(data["Z"], dt)
         m, n = self.Z.shape
         self.m, self.n = m, n
@@ -84,13 +85,13 @@ class Runner:
         h = amgs.handle(0)
         wb = amgs.amgs_workspace_bytes(h, m, n, int(self.dense), amgs.VARIANTS[variant],
                                        amgs.PRECISIONS[precision], 1,
-                                       amgs.Opts(int(reorth), int(panel), 0, 0))
+                                       amgs.Opts(int(reorth), int(panel), int(cgs), 0))
         self.work = torch.empty(max(wb, 1), dtype=torch.uint8, device=self.Z.device)
 
     def __call__(self):
         a = self.amgs
         kw = dict(variant=self.variant, precision=self.precision, Q=self.Q, P=self.P,
-                  work=self.work, reorth=self.reorth, panel=self.panel)
+                  work=self.work, reorth=self.reorth, panel=self.panel, cgs=self.cgs)
         if self.dense:
             return a.qr_dense(self.A, self.Z, **kw)
         return a.qr_csr(self.rp, self.ci, self.vals, self.Z, **kw)
@@ -226,16 +227,18 @@ def bench_single(args, torch, amgs):
 
     variants = {}
     if not args.no_variants:
-        combos = [(v, p, False, 0) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
-        combos += [(v, "fp32", True, 0) for v in ("ha", "hp")]
-        combos += [(v, p, False, 4) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
-        for v, p, ro, pan in combos:
-            r = Runner(data, v, p, torch, amgs, reorth=ro, panel=pan)
+        combos = [(v, p, False, 0, False) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
+        combos += [(v, "fp32", True, 0, False) for v in ("ha", "hp")]
+        combos += [(v, p, False, 4, False) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
+        combos += [(v, "fp64", ro, 0, True) for ro in (False, True) for v in ("naive", "ha", "hp")]
+        for v, p, ro, pan, cgs in combos:
+            r = Runner(data, v, p, torch, amgs, reorth=ro, panel=pan, cgs=cgs)
             heavy = v == "naive" and prob.csr is None and prob.m > 4096
             steps = 1 if heavy else (max(2, args.steps // 4) if v == "naive" else max(3, args.steps // 2))
             tv, o = time_steps(r, steps, 1, torch)
             orth, res = accuracy(data, o, torch)
-            key = f"{v}_{p}" + ("_reorth" if ro else "") + (f"_panel{pan}" if pan else "")
+            key = (("cgs_" if cgs else "") + f"{v}_{p}" + ("_reorth" if ro else "")
+                   + (f"_panel{pan}" if pan else ""))
             variants[key] = {"cols_per_s": round(prob.n / tv, 1), "ms": round(tv * 1e3, 4),
                              "orth_loss": orth, "residual": res, "info": int(o.info.item())}
             log(f"[bench] {key}: {tv * 1e3:.3f} ms  |QtAQ-I| {orth:.2e}  res {res:.2e}")

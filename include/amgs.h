@@ -96,12 +96,23 @@ typedef struct amgs_handle *amgs_handle_t;
  *           later column is then read and written once per panel instead of
  *           once per column.  Rounding differs from the column order;
  *           A-orthogonality stays at the level of the column algorithm.
- *           Not combined with reorth (AMGS_ERR_UNSUPPORTED); other values
- *           are AMGS_ERR_ARG. */
+ *           Not combined with reorth or cgs (AMGS_ERR_UNSUPPORTED); other
+ *           values are AMGS_ERR_ARG.
+ *   cgs     0: modified Gram-Schmidt (Algs. 3/5/6, default).
+ *           1: classical Gram-Schmidt with the same variants (Section 2, the
+ *           n-MV idea applied to CGS: CGS-naive, CGS-HA, CGS-HP, column
+ *           form): all coefficients of column j come from the unmodified
+ *           column, r_ij = p_i^T z_j^{(0)} for i < j, then
+ *           z_j^{(j-1)} = z_j^{(0)} - sum_{i<j} r_ij q_i (HP also
+ *           x_j = x_j^{(0)} - sum_{i<j} r_ij p_i), with binary64 accumulation
+ *           of the coefficients and of each corrected entry, rounded once to
+ *           storage.  With reorth = 1 the classical step is applied twice
+ *           (the second pass above), i.e. CGS2.  Other values are
+ *           AMGS_ERR_ARG. */
 typedef struct {
     int32_t reorth;
     int32_t panel;
-    int32_t reserved1;
+    int32_t cgs;
     int32_t reserved2;
 } amgs_opts_t;
 

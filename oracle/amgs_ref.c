@@ -47,6 +47,16 @@
  * for i ascending (HP: also x_c -= r_ic p_i).  In exact arithmetic this is
  * the column algorithm, since z_c^{(i-1)} = z_c - sum_{k<i} r_kc q_k.
  *
+ * Orientation 3 is classical Gram-Schmidt with the same three variants
+ * (Section 2: the n-MV idea applied to CGS; Section 3, analysis of CGS):
+ * column j takes all its coefficients from the unmodified column,
+ * r_ij = p_i^T z_j^{(0)} for i < j, then z_j^{(j-1)} = z_j^{(0)} -
+ * sum_{i<j} r_ij q_i, and for HP x_j^{(j-1)} = x_j^{(0)} - sum_{i<j} r_ij p_i;
+ * naive and HA then form x_j = A z_j^{(j-1)}.  This classical step uses the
+ * arithmetic of the second pass below (binary64 accumulation of the
+ * coefficients and of each corrected entry, one rounding to storage), and
+ * with reorth it is applied twice (CGS2).
+ *
  * Optional reorthogonalisation (the paper names it in Section 2.1 without a
  * definition): after the MGS projections of column j, a classical second
  * pass s_i = p_i^T z_j for all i < j (binary64 accumulation), then
@@ -69,6 +79,7 @@
 #define REF_COL 0
 #define REF_ROW 1
 #define REF_PANEL 2
+#define REF_CGS 3
 #define PANEL_B 4
 #define REF_FP64 0
 #define REF_FP32 1
@@ -403,13 +414,54 @@ static int qr_panel(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ld
     return info;
 }
 
+/* Classical Gram-Schmidt, column form (orientation 3). */
+static int qr_cgs(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq, double *R,
+                  int64_t ldr, double *P, int64_t ldp, double *X, int variant, int reorth,
+                  int prec, int64_t *mv_calls, int64_t *mv_cols)
+{
+    double *x = (double *)malloc((size_t)m * sizeof(double));
+    if (variant == REF_HP) {
+        for (int64_t j = 0; j < n; ++j) mv_st(A, Q + j * ldq, X + j * m, prec);
+        *mv_calls += 1; *mv_cols += n;
+    }
+    int info = 0;
+    for (int64_t j = 0; j < n && !info; ++j) {
+        double *z = Q + j * ldq;        /* z_j^{(0)}, corrected in place */
+        double *Rc = R + j * ldr;
+        double *xr = NULL;
+        if (variant == REF_HP) {
+            memcpy(x, X + j * m, (size_t)m * sizeof(double));
+            xr = x;
+        }
+        /* r_ij = p_i^T z_j^{(0)} for every i < j, then one correction */
+        reorth_pass(z, xr, j, Q, ldq, P, ldp, Rc, m, prec);
+        if (reorth) reorth_pass(z, xr, j, Q, ldq, P, ldp, Rc, m, prec);
+        if (variant != REF_HP) {
+            mv_st(A, z, x, prec);
+            *mv_calls += 1; *mv_cols += 1;
+        }
+        double rjj;
+        if (!anorm(z, x, m, &rjj)) { info = (int)(j + 1); break; }
+        Rc[j] = rjj;
+        scale(z, z, rjj, m, prec);
+        if (variant == REF_NAIVE) {
+            mv_st(A, z, P + j * ldp, prec);
+            *mv_calls += 1; *mv_cols += 1;
+        } else {
+            scale(P + j * ldp, x, rjj, m, prec);
+        }
+    }
+    free(x);
+    return info;
+}
+
 static int run(const ref_op *A, int64_t n, const double *Z, int64_t ldz, double *Q, int64_t ldq,
                double *R, int64_t ldr, double *P, int64_t ldp, int variant, int orientation,
                int reorth, int prec, int64_t *stats)
 {
     int64_t m = A->m;
     if (m < 0 || n < 0 || n > m || ldz < m || ldq < m || ldr < n) return -1;
-    if (variant < 0 || variant > 2 || orientation < 0 || orientation > 2) return -1;
+    if (variant < 0 || variant > 2 || orientation < 0 || orientation > 3) return -1;
     if (orientation == REF_PANEL && reorth) return -1;
     if (prec < 0 || prec > 1) return -1;
     if (n == 0) { if (stats) stats[0] = stats[1] = 0; return 0; }
@@ -428,7 +480,9 @@ static int run(const ref_op *A, int64_t n, const double *Z, int64_t ldz, double 
         ? qr_col(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols)
         : orientation == REF_ROW
         ? qr_row(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols)
-        : qr_panel(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, prec, &calls, &cols);
+        : orientation == REF_PANEL
+        ? qr_panel(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, prec, &calls, &cols)
+        : qr_cgs(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols);
     if (stats) { stats[0] = calls; stats[1] = cols; }
     free(X);
     if (!P) free(Pw);

@@ -29,7 +29,7 @@ class AmgsError(RuntimeError):
 
 
 class Opts(C.Structure):
-    _fields_ = [("reorth", C.c_int32), ("panel", C.c_int32), ("reserved1", C.c_int32),
+    _fields_ = [("reorth", C.c_int32), ("panel", C.c_int32), ("cgs", C.c_int32),
                 ("reserved2", C.c_int32)]
 
 
@@ -208,9 +208,10 @@ def _prep(Z, precision, device, Q, P, return_p):
 
 def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=False,
            return_p=False, Q=None, P=None, work=None, stream=None, device=None,
-           panel=0) -> QRResult:
+           panel=0, cgs=False) -> QRResult:
     """A-orthonormalise the columns of Z (device tensors; A in CSR).
-    panel: 0 for the column schedule, 4 for the panel schedule."""
+    panel: 0 for the column schedule, 4 for the panel schedule; cgs: classical
+    instead of modified Gram-Schmidt."""
     torch = _torch()
     device = device or Z.device
     dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p)
@@ -218,7 +219,7 @@ def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=Fal
     row_ptr = row_ptr.to(device=device, dtype=torch.int32).contiguous()
     col_idx = col_idx.to(device=device, dtype=torch.int32).contiguous()
     h = handle(device.index or 0)
-    opts = Opts(int(bool(reorth)), int(panel), 0, 0)
+    opts = Opts(int(bool(reorth)), int(panel), int(bool(cgs)), 0)
     v, p = VARIANTS[variant], PRECISIONS[precision]
     wb = amgs_workspace_bytes(h, m, n, 0, v, p, int(Pc is not None), opts)
     if work is None:
@@ -235,15 +236,16 @@ def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=Fal
 
 
 def qr_dense(A, Z, variant="ha", precision="fp64", reorth=False, return_p=False, Q=None,
-             P=None, work=None, stream=None, device=None, panel=0) -> QRResult:
+             P=None, work=None, stream=None, device=None, panel=0, cgs=False) -> QRResult:
     """A-orthonormalise the columns of Z (device tensors; A dense symmetric).
-    panel: 0 for the column schedule, 4 for the panel schedule."""
+    panel: 0 for the column schedule, 4 for the panel schedule; cgs: classical
+    instead of modified Gram-Schmidt."""
     torch = _torch()
     device = device or Z.device
     dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p)
     Ac = colmajor(A.to(device), dt)
     h = handle(device.index or 0)
-    opts = Opts(int(bool(reorth)), int(panel), 0, 0)
+    opts = Opts(int(bool(reorth)), int(panel), int(bool(cgs)), 0)
     v, p = VARIANTS[variant], PRECISIONS[precision]
     wb = amgs_workspace_bytes(h, m, n, 1, v, p, int(Pc is not None), opts)
     if work is None:

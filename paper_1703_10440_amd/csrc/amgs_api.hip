@@ -124,9 +124,13 @@ template <typename T>
 amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant);
 
 template <typename T>
+amgs_status_t run_cgs(amgs_handle *h, Ctx &c, int variant, int reorth);
+
+template <typename T>
 amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
 {
     if (c.panel) return run_panel<T>(h, c, variant);
+    if (c.cgs) return run_cgs<T>(h, c, variant, reorth);
     const size_t w = sizeof(T);
     amgs_stats_t &st = h->stats;
     st = amgs_stats_t{};
@@ -349,25 +353,102 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant)
     return AMGS_OK;
 }
 
+// Classical Gram-Schmidt (opts->cgs): per column j, the coefficients
+// r_ij = p_i^T z_j^{(0)} of all i < j from the unmodified column (one pass
+// over P_{<j}), z_j -= sum_i r_ij q_i (HP: x_j -= sum_i r_ij p_i), optionally
+// a second such pass, then the column MV (naive / HA) and the normalisation.
+template <typename T>
+amgs_status_t run_cgs(amgs_handle *h, Ctx &c, int variant, int reorth)
+{
+    const size_t w = sizeof(T);
+    amgs_stats_t &st = h->stats;
+    st = amgs_stats_t{};
+    launch_init<T>(c, c.Z != c.Q);
+    st.kernel_launches++;
+    const double mvA = c.is_dense ? (double)c.m * (double)c.m * w
+                                  : (double)c.nnz * (w + 4) + 4.0 * (double)(c.m + 1);
+    if (variant == VAR_HP) {
+        ProfScope ps(h, 2, c.stream);
+        if (c.is_dense) launch_dense_gemm<T>(c);
+        else launch_csr_spmm<T>(c);
+        st.kernel_launches++;
+        st.mv_calls += 1;
+        st.mv_columns += c.n;
+        st.mv_bytes += mvA + 2.0 * (double)c.m * c.n * w;
+    }
+    const int passes = reorth ? 2 : 1;
+    for (int64_t j = 0; j < c.n; ++j) {
+        int64_t n_rr;
+        if (j > 0) {
+            // classical passes: zt = z_j, then zt (HA) or Q[:, j] (HP) corrected
+            for (int pass = 0; pass < passes; ++pass) {
+                c.z_in_zt = (pass > 0 && variant != VAR_HP) ? 1 : 0;
+                launch_reorth_a<T>(c, j);
+                c.z_in_zt = 0;
+                launch_reorth_fin(c, j);
+                launch_reorth_b<T>(c, j, variant == VAR_HP);
+                st.kernel_launches += 3;
+            }
+        }
+        if (variant == VAR_HP) {
+            if (j == 0) {
+                c.x_from = 0;
+                launch_col_hp<T>(c, 0, false);
+                c.x_from = -1;
+                st.kernel_launches++;
+                n_rr = c.geo.g_rows2;
+            } else {
+                n_rr = c.geo.g_rows1;   // A-norm partials of k_reorth_b
+            }
+        } else {
+            // j = 0: the MV copies z_0 to zt; later columns read zt
+            launch_mv<T>(c, j, j > 0 ? SRC_VEC : SRC_UPD);
+            st.kernel_launches++;
+            st.mv_calls += 1;
+            st.mv_columns += 1;
+            st.mv_bytes += mvA + (j > 0 ? 2.0 : 3.0) * (double)c.m * w;
+            if (variant == VAR_NAIVE) {
+                launch_mv<T>(c, j, SRC_DIV);
+                st.kernel_launches++;
+                st.mv_calls += 1;
+                st.mv_columns += 1;
+                st.mv_bytes += mvA + 2.0 * (double)c.m * w;
+            }
+            n_rr = c.n_rr_mv;
+        }
+        // normalise column j only (no later columns, no dots)
+        launch_psweep<T>(c, variant, j, j, j, j, j, j + 1, j + 1, n_rr);
+        st.kernel_launches++;
+        st.sweep_launches++;
+    }
+    if (hipGetLastError() != hipSuccess) return AMGS_ERR_HIP;
+    return AMGS_OK;
+}
+
 amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision_t p,
                         const amgs_opts_t *o, void *work, size_t work_bytes, int P_given)
 {
     const int reorth = o ? (o->reorth != 0) : 0;
     const int panel = o ? o->panel : 0;
+    const int cgs = o ? o->cgs : 0;
     if (panel != 0 && panel != PANEL_B) return AMGS_ERR_ARG;
-    if (panel && reorth) return AMGS_ERR_UNSUPPORTED;
+    if (cgs != 0 && cgs != 1) return AMGS_ERR_ARG;
+    if (panel && (reorth || cgs)) return AMGS_ERR_UNSUPPORTED;
     const size_t w = p == AMGS_FP64 ? 8 : 4;
     c.geo = make_geo(c.m, c.nnz, c.is_dense);
-    Layout L = layout(c.m, c.n, c.geo, (int)v, w, P_given, reorth, panel);
+    Layout L = layout(c.m, c.n, c.geo, (int)v, w, P_given, reorth || cgs, panel);
     if (!work || work_bytes < L.total) return AMGS_ERR_WORKSPACE;
     char *base = (char *)work;
     c.sp.part = base + L.part;
     c.sp.g = c.geo.g_rows;
     c.panel = panel;
+    c.cgs = cgs;
+    c.z_in_zt = 0;
     c.x_from = -1;
     c.n_pub = c.n;
+    // the panel-sweep kernel also normalises the columns of the classical form
+    c.g_p = panel_chunks(c.m, w);
     if (panel) {
-        c.g_p = panel_chunks(c.m, w);
         c.sp.g = c.g_p;
         c.wpart = base + L.wpart;
         c.lpart = base + L.lpart;
@@ -481,9 +562,11 @@ size_t amgs_workspace_bytes(amgs_handle_t h, int64_t m, int64_t n, int32_t is_de
     // nnz only selects the CSR lane count, which does not change any size
     Geo g = make_geo(m, is_dense ? 0 : m, is_dense);
     const int panel = o ? o->panel : 0;
+    const int cgs = o ? o->cgs : 0;
     if (panel != 0 && panel != PANEL_B) return 0;
-    Layout L = layout(m, n, g, (int)v, p == AMGS_FP64 ? 8 : 4, P_given, o ? o->reorth != 0 : 0,
-                      panel);
+    if (cgs != 0 && cgs != 1) return 0;
+    Layout L = layout(m, n, g, (int)v, p == AMGS_FP64 ? 8 : 4, P_given,
+                      (o ? o->reorth != 0 : 0) || cgs, panel);
     return L.total;
 }
 

@@ -88,6 +88,8 @@ struct RowArgs {
     double *s_part;
     const double *S;
     int64_t x_from;   // HP column kernel: first recurrence term (-1: column schedule)
+    int32_t pend;     // k_reorth_a: apply the pending update r_{j-1,j} q_{j-1} and publish R
+    int32_t z_in_zt;  // k_reorth_a: z_j is read from zt instead of Q
 };
 
 struct SweepArgs {
@@ -172,6 +174,8 @@ struct Ctx {
     void *lpart;      // partials of strict_lower(P_I^T Q_I) [PANEL_B][PANEL_B][g_p]
     int64_t x_from;   // HP column kernel: first recurrence term it applies (-1: column schedule)
     int64_t n_pub;    // column kernels publish r_{j-1,c} for c < n_pub
+    int cgs;          // classical Gram-Schmidt (no pending MGS update in k_reorth_a)
+    int z_in_zt;      // k_reorth_a reads z_j from zt
     hipStream_t stream;
     // when set, the sweep is launched with these events bound to its own
     // dispatch (exact kernel start and end, no extra stream markers)

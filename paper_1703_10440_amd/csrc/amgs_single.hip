@@ -494,6 +494,8 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
 
 // ------------------------------------- second pass, step A for naive / HA
 // zt = z_j - r_{j-1,j} q_{j-1} (row local) and partials of s_i = p_i^T zt.
+// Also the first step of a classical Gram-Schmidt column (pend = 0): the
+// partials of r_ij = p_i^T z_j^{(0)}, i < j, with z_j unmodified.
 template <typename T, int U>
 __global__ __launch_bounds__(256) void k_reorth_a(RowArgs a)
 {
@@ -506,28 +508,33 @@ __global__ __launch_bounds__(256) void k_reorth_a(RowArgs a)
     T *__restrict__ zt = (T *)a.zt;
     const int tid = threadIdx.x;
     const int64_t row0 = (int64_t)blockIdx.x * 256 * U;
+    // z_j from Q (or, for a second classical pass of naive / HA, from zt);
+    // with pend, the pending update r_{j-1,j} q_{j-1} of the column
+    // schedule is applied first (classical Gram-Schmidt has none)
+    const bool pend = a.pend && j > 0;
+    const T *__restrict__ zsrc = a.z_in_zt ? (const T *)zt : Q + j * a.ldq;
     T zr[U], qp[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
-        zr[u] = k < a.m ? Q[k + j * a.ldq] : (T)0;
-        qp[u] = (k < a.m && j > 0) ? Q[k + (j - 1) * a.ldq] : (T)0;
+        zr[u] = k < a.m ? zsrc[k] : (T)0;
+        qp[u] = (k < a.m && pend) ? Q[k + (j - 1) * a.ldq] : (T)0;
     }
     T r = 0;
-    if (j > 0) r = block_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
+    if (pend) r = block_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
         if (k < a.m) {
-            if (j > 0) zr[u] = upd(zr[u], r, qp[u]);
-            if (blockIdx.y == 0) zt[k] = zr[u];
+            if (pend) zr[u] = upd(zr[u], r, qp[u]);
+            if (blockIdx.y == 0 && !a.z_in_zt) zt[k] = zr[u];
         }
     }
     // this grid row's group of coefficients
     const int64_t i_lo = (int64_t)blockIdx.y * RE_GROUP;
     reorth_partials<T, U>(P, a.ldp, j, zr, row0, a.m, a.s_part, red, i_lo, i_lo + RE_GROUP);
     // R[j-1, c] for c >= j (read by later kernels only) is published last
-    if (j > 0 && blockIdx.y == 0) publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
+    if (pend && blockIdx.y == 0) publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
 }
 
 // ----------------------------------------------- second pass: finish s_i
@@ -931,7 +938,9 @@ void launch_mv(const Ctx &c, int64_t j, int src_mode)
 static RowArgs row_args(const Ctx &c, int64_t j)
 {
     RowArgs a{};
-    a.m = c.m; a.n = c.n_pub; a.j = j; a.x_from = c.x_from; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp;
+    a.m = c.m; a.n = c.n_pub; a.j = j; a.x_from = c.x_from;
+    a.pend = c.cgs ? 0 : 1;
+    a.z_in_zt = c.z_in_zt; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp;
     a.X = c.X; a.ldx = c.m; a.zt = c.zt; a.R = c.R; a.ldr = c.ldr; a.info = c.info;
     a.sp = c.sp; a.rr_out = c.rr_part; a.s_part = c.s_part; a.S = c.S;
     return a;

@@ -46,7 +46,7 @@ def pin_hand_example(lib, golden) -> list:
     A, Z = golden["A"], golden["Z"]
     csr = inputs.csr_from_dense(A)
     for v in VARIANTS:
-        for o in ORIENTS + ("panel",):
+        for o in ORIENTS + ("panel", "cgs"):
             for prec in ("fp64", "fp32"):
                 for re_ in ((False, True) if o != "panel" else (False,)):
                     for kind in ("dense", "csr"):
@@ -394,7 +394,71 @@ def pin_panel(lib) -> list:
     return fails
 
 
+def pin_cgs(lib) -> list:
+    """Classical Gram-Schmidt (orientation "cgs"): the closed forms on
+    well-conditioned problems (with and without the second pass), Householder
+    for A = I with the three variants equal bit for bit, MV counts; Section 3
+    (analysis of CGS): CGS-HA loses about as much A-orthogonality as
+    CGS-naive; Section 4 (experiment II): the loss of CGS grows with the
+    square of kappa(A^{1/2} Z) while MGS grows linearly, so at
+    kappa(A^{1/2} Z) ~ 6e5 CGS is far less accurate than MGS (and within
+    10 u kappa(A) kappa(A^{1/2} Z)^2); a second classical pass (CGS2)
+    restores A-orthogonality to rounding level for naive and HA."""
+    fails = []
+    for seed in (11, 12):
+        for p in (inputs.random_dense_problem(60, 9, seed), inputs.random_csr_problem(300, 12, 9, seed)):
+            Ad = p.dense if p.dense is not None else p.csr.to_dense()
+            Rc = _chol_R(p.Z, Ad)
+            for v in VARIANTS:
+                for re_ in (False, True):
+                    r = ref.qr(p.Z, dense=p.dense, csr=p.csr, variant=v, orientation="cgs",
+                               reorth=re_, lib=lib)
+                    e, eq, ep = (_rel(np.triu(r.R), Rc), _rel(r.Q, np.linalg.solve(Rc.T, p.Z.T).T),
+                                 _rel(r.P, Ad @ r.Q))
+                    if r.info != 0 or not (e <= 1e-13 and eq <= 1e-12 and ep <= 1e-12):
+                        fails.append(f"cgs chol {p.name} {v}/reorth={re_}: R {e} Q {eq} P {ep}")
+                    want_calls = {"naive": 2 * p.n, "ha": p.n, "hp": 1}[v]
+                    if r.mv_calls != want_calls:
+                        fails.append(f"cgs MV count {p.name} {v}: {r.mv_calls}")
+    g = inputs.rng(23)
+    m, n = 150, 9
+    Z = np.asfortranarray(g.standard_normal((m, n)))
+    eye = inputs.CSR(m, np.arange(m + 1, dtype=np.int32), np.arange(m, dtype=np.int32), np.ones(m))
+    Qh, Rh = np.linalg.qr(Z)
+    D = np.sign(np.diag(Rh))
+    Qh, Rh = Qh * D[None, :], Rh * D[:, None]
+    outs = {v: ref.qr(Z, csr=eye, variant=v, orientation="cgs", lib=lib) for v in VARIANTS}
+    for v, r in outs.items():
+        if _rel(np.triu(r.R), Rh) > 1e-13 or _rel(r.Q, Qh) > 1e-12:
+            fails.append(f"cgs identity {v}: R {_rel(np.triu(r.R), Rh)} Q {_rel(r.Q, Qh)}")
+        if not (np.array_equal(r.R, outs["naive"].R) and np.array_equal(r.Q, outs["naive"].Q)):
+            fails.append(f"cgs identity: {v} differs bitwise from naive")
+    u = 2.0 ** -53
+    for ka, kz in ((1e2, 1e6), (1e4, 1e4)):
+        p = inputs.exp2_problem(100, 20, ka, kz, 1, 7)
+        w, V = np.linalg.eigh(p.dense)
+        kA = float(w[-1] / w[0])
+        kAZ = _kappa((V * np.sqrt(w)[None, :]) @ V.T @ p.Z)
+        loss = {}
+        for v in ("naive", "ha"):
+            r = ref.qr_problem(p, variant=v, orientation="cgs", lib=lib)
+            loss[v] = ref.orth_loss(r.Q, dense=p.dense)
+            if r.info != 0 or not loss[v] <= 10 * u * kA * kAZ ** 2:
+                fails.append(f"cgs exp2 {ka:g},{kz:g} {v}: loss {loss[v]} above the quadratic bound")
+            r2 = ref.qr_problem(p, variant=v, orientation="cgs", reorth=True, lib=lib)
+            l2 = ref.orth_loss(r2.Q, dense=p.dense)
+            if not l2 <= 1e-13:
+                fails.append(f"cgs2 exp2 {ka:g},{kz:g} {v}: loss {l2}")
+        if not (0.1 <= loss["ha"] / loss["naive"] <= 10):
+            fails.append(f"cgs exp2 {ka:g},{kz:g}: HA {loss['ha']} vs naive {loss['naive']}")
+        if kz >= 1e6:
+            lm = ref.orth_loss(ref.qr_problem(p, variant="ha", lib=lib).Q, dense=p.dense)
+            if not loss["ha"] >= 1e3 * lm:
+                fails.append(f"cgs exp2 {ka:g},{kz:g}: CGS {loss['ha']} not far above MGS {lm}")
+    return fails
+
+
 ALL_PINS = [pin_hand_example, pin_cholesky, pin_identity_householder, pin_cholesky_factor,
             pin_col_row_bitwise, pin_mv_counts, pin_scaling, pin_first_column,
             pin_residual_and_reorth, pin_exp2_accuracy, pin_fp32_accumulation, pin_fp32_vs_fp64, pin_breakdown,
-            pin_panel]
+            pin_panel, pin_cgs]

@@ -46,6 +46,9 @@ MUTANTS = [
     ("panel block step updates x with q instead of p",
      "axpy_st(X + c * m, st(r[i], prec), P + (s + i) * ldp, m, prec);",
      "axpy_st(X + c * m, st(r[i], prec), Q + (s + i) * ldq, m, prec);"),
+    ("classical Gram-Schmidt leaves the HP x column uncorrected",
+     "        /* r_ij = p_i^T z_j^{(0)} for every i < j, then one correction */\n        reorth_pass(z, xr, j,",
+     "        /* r_ij = p_i^T z_j^{(0)} for every i < j, then one correction */\n        reorth_pass(z, NULL, j,"),
     ("panel block step skips the last panel column",
      "for (int i = 0; i < b; ++i) axpy_st(z, st(r[i], prec), Q + (s + i) * ldq, m, prec);",
      "for (int i = 0; i + 1 < b; ++i) axpy_st(z, st(r[i], prec), Q + (s + i) * ldq, m, prec);"),
