@@ -108,12 +108,22 @@ typedef struct amgs_handle *amgs_handle_t;
  *           of the coefficients and of each corrected entry, rounded once to
  *           storage.  With reorth = 1 the classical step is applied twice
  *           (the second pass above), i.e. CGS2.  Other values are
- *           AMGS_ERR_ARG. */
+ *           AMGS_ERR_ARG.
+ *   first   successive orthogonalisation (Section 2.1 notes that the column
+ *           form suits it): columns 0..first-1 are already A-orthonormal and
+ *           final -- Q[:, <first] holds q_1..q_first, P (which must then be
+ *           passed, else AMGS_ERR_ARG) holds their p_i, and R[:first, :first]
+ *           their R; none of these is read from Z or written.  Columns
+ *           first..n-1 of Z are orthonormalised against them and against
+ *           each other, each receiving its projections in ascending i as in
+ *           the column algorithm, so the new columns equal those of one call
+ *           on all n columns.  0 <= first <= n (else AMGS_ERR_ARG); with
+ *           panel != 0, AMGS_ERR_UNSUPPORTED. */
 typedef struct {
     int32_t reorth;
     int32_t panel;
     int32_t cgs;
-    int32_t reserved2;
+    int32_t first;
 } amgs_opts_t;
 
 /* Counters of the most recent amgs_qr_* call on a handle. */

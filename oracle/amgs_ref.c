@@ -256,17 +256,18 @@ static int anorm(const double *z, const double *x, int64_t m, double *rjj)
 
 /* ------------------------------------------------------------ driver */
 /* Column-oriented: Alg. 3 (naive), Alg. 5 (HA), Alg. 6 (HP). */
-static int qr_col(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq, double *R,
-                  int64_t ldr, double *P, int64_t ldp, double *X, int variant, int reorth,
-                  int prec, int64_t *mv_calls, int64_t *mv_cols)
+static int qr_col(const ref_op *A, int64_t m, int64_t n, int64_t first, double *Q, int64_t ldq,
+                  double *R, int64_t ldr, double *P, int64_t ldp, double *X, int variant,
+                  int reorth, int prec, int64_t *mv_calls, int64_t *mv_cols)
 {
     double *x = (double *)malloc((size_t)m * sizeof(double));
     if (variant == REF_HP) {            /* Alg. 6 first line: X = A Z, one block MV */
-        for (int64_t j = 0; j < n; ++j) mv_st(A, Q + j * ldq, X + j * m, prec);
-        *mv_calls += 1; *mv_cols += n;
+        for (int64_t j = first; j < n; ++j) mv_st(A, Q + j * ldq, X + j * m, prec);
+        *mv_calls += 1; *mv_cols += n - first;
     }
     int info = 0;
-    for (int64_t j = 0; j < n && !info; ++j) {
+    /* columns before first are final (successive orthogonalisation) */
+    for (int64_t j = first; j < n && !info; ++j) {
         double *z = Q + j * ldq;        /* holds z_j^{(i)}; overwritten by q_j */
         double *Rc = R + j * ldr;
         for (int64_t i = 0; i < j; ++i) {           /* projections */
@@ -415,17 +416,17 @@ static int qr_panel(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ld
 }
 
 /* Classical Gram-Schmidt, column form (orientation 3). */
-static int qr_cgs(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq, double *R,
-                  int64_t ldr, double *P, int64_t ldp, double *X, int variant, int reorth,
-                  int prec, int64_t *mv_calls, int64_t *mv_cols)
+static int qr_cgs(const ref_op *A, int64_t m, int64_t n, int64_t first, double *Q, int64_t ldq,
+                  double *R, int64_t ldr, double *P, int64_t ldp, double *X, int variant,
+                  int reorth, int prec, int64_t *mv_calls, int64_t *mv_cols)
 {
     double *x = (double *)malloc((size_t)m * sizeof(double));
     if (variant == REF_HP) {
-        for (int64_t j = 0; j < n; ++j) mv_st(A, Q + j * ldq, X + j * m, prec);
-        *mv_calls += 1; *mv_cols += n;
+        for (int64_t j = first; j < n; ++j) mv_st(A, Q + j * ldq, X + j * m, prec);
+        *mv_calls += 1; *mv_cols += n - first;
     }
     int info = 0;
-    for (int64_t j = 0; j < n && !info; ++j) {
+    for (int64_t j = first; j < n && !info; ++j) {
         double *z = Q + j * ldq;        /* z_j^{(0)}, corrected in place */
         double *Rc = R + j * ldr;
         double *xr = NULL;
@@ -455,21 +456,25 @@ static int qr_cgs(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq,
     return info;
 }
 
-static int run(const ref_op *A, int64_t n, const double *Z, int64_t ldz, double *Q, int64_t ldq,
-               double *R, int64_t ldr, double *P, int64_t ldp, int variant, int orientation,
-               int reorth, int prec, int64_t *stats)
+static int run(const ref_op *A, int64_t n, int64_t first, const double *Z, int64_t ldz,
+               double *Q, int64_t ldq, double *R, int64_t ldr, double *P, int64_t ldp,
+               int variant, int orientation, int reorth, int prec, int64_t *stats)
 {
     int64_t m = A->m;
     if (m < 0 || n < 0 || n > m || ldz < m || ldq < m || ldr < n) return -1;
     if (variant < 0 || variant > 2 || orientation < 0 || orientation > 3) return -1;
     if (orientation == REF_PANEL && reorth) return -1;
     if (prec < 0 || prec > 1) return -1;
+    /* successive orthogonalisation: columns before first are final in Q, P
+     * and R (column and classical forms only) */
+    if (first < 0 || first > n) return -1;
+    if (first > 0 && (!P || (orientation != REF_COL && orientation != REF_CGS))) return -1;
     if (n == 0) { if (stats) stats[0] = stats[1] = 0; return 0; }
     if (!Z || !Q || !R) return -1;
     /* a0: working copy (Q holds z_j^{(i)}), R zeroed; inputs rounded to storage */
-    for (int64_t j = 0; j < n; ++j)
+    for (int64_t j = first; j < n; ++j)
         for (int64_t k = 0; k < m; ++k) Q[j * ldq + k] = st(Z[j * ldz + k], prec);
-    for (int64_t j = 0; j < n; ++j) memset(R + j * ldr, 0, (size_t)n * sizeof(double));
+    for (int64_t j = first; j < n; ++j) memset(R + j * ldr, 0, (size_t)n * sizeof(double));
     double *Pw = P;
     int64_t ldpw = ldp;
     if (!Pw) { Pw = (double *)calloc((size_t)m * n, sizeof(double)); ldpw = m; }
@@ -477,12 +482,12 @@ static int run(const ref_op *A, int64_t n, const double *Z, int64_t ldz, double 
     if (variant == REF_HP) X = (double *)malloc((size_t)m * n * sizeof(double));
     int64_t calls = 0, cols = 0;
     int info = orientation == REF_COL
-        ? qr_col(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols)
+        ? qr_col(A, m, n, first, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols)
         : orientation == REF_ROW
         ? qr_row(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols)
         : orientation == REF_PANEL
         ? qr_panel(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, prec, &calls, &cols)
-        : qr_cgs(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols);
+        : qr_cgs(A, m, n, first, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols);
     if (stats) { stats[0] = calls; stats[1] = cols; }
     free(X);
     if (!P) free(Pw);
@@ -501,11 +506,13 @@ static double *rounded_copy(const double *v, int64_t len, int prec)
 /* Dense symmetric A (column-major, lda >= m).  Returns 0 on success, j >= 1 if
  * column j broke down (columns before j are valid), -1 on a bad argument.
  * stats (nullable, 2 entries): number of MV calls (a block product counts
- * once) and number of MV columns. */
+ * once) and number of MV columns.  first > 0: columns before first are final
+ * in Q, P and R on entry (successive orthogonalisation; column and classical
+ * forms). */
 int amgs_ref_qr_dense(int64_t m, const double *a, int64_t lda, int64_t n, const double *Z,
                       int64_t ldz, double *Q, int64_t ldq, double *R, int64_t ldr, double *P,
                       int64_t ldp, int variant, int orientation, int reorth, int precision,
-                      int64_t *stats)
+                      int64_t *stats, int64_t first)
 {
     if (!a || lda < m) return -1;
     ref_op A = {0};
@@ -513,7 +520,7 @@ int amgs_ref_qr_dense(int64_t m, const double *a, int64_t lda, int64_t n, const 
     double *ar = NULL;
     if (precision == REF_FP32) { ar = rounded_copy(a, lda * m, precision); A.a = ar; }
     else A.a = a;
-    int info = run(&A, n, Z, ldz, Q, ldq, R, ldr, P, ldp, variant, orientation, reorth,
+    int info = run(&A, n, first, Z, ldz, Q, ldq, R, ldr, P, ldp, variant, orientation, reorth,
                    precision, stats);
     free(ar);
     return info;
@@ -523,7 +530,7 @@ int amgs_ref_qr_dense(int64_t m, const double *a, int64_t lda, int64_t n, const 
 int amgs_ref_qr_csr(int64_t m, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
                     const double *vals, int64_t n, const double *Z, int64_t ldz, double *Q,
                     int64_t ldq, double *R, int64_t ldr, double *P, int64_t ldp, int variant,
-                    int orientation, int reorth, int precision, int64_t *stats)
+                    int orientation, int reorth, int precision, int64_t *stats, int64_t first)
 {
     if (!row_ptr || (nnz > 0 && (!col_idx || !vals))) return -1;
     if (row_ptr[0] != 0 || row_ptr[m] != nnz) return -1;
@@ -532,7 +539,7 @@ int amgs_ref_qr_csr(int64_t m, int64_t nnz, const int32_t *row_ptr, const int32_
     double *vr = NULL;
     if (precision == REF_FP32) { vr = rounded_copy(vals, nnz, precision); A.vals = vr; }
     else A.vals = vals;
-    int info = run(&A, n, Z, ldz, Q, ldq, R, ldr, P, ldp, variant, orientation, reorth,
+    int info = run(&A, n, first, Z, ldz, Q, ldq, R, ldr, P, ldp, variant, orientation, reorth,
                    precision, stats);
     free(vr);
     return info;

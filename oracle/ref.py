@@ -39,15 +39,15 @@ def load(path: Optional[str] = None):
     if path is None and _lib is not None:
         return _lib
     p = path or _LIB_PATH
-    if not os.path.exists(p):
-        build(out=p)
+    if path is None and (not os.path.exists(p) or os.path.getmtime(p) < os.path.getmtime(_SRC)):
+        build(out=p)   # missing, or older than its source
     lib = C.CDLL(p)
     i64, dp, ip = C.c_int64, C.POINTER(C.c_double), C.POINTER(C.c_int32)
     lib.amgs_ref_qr_dense.argtypes = [i64, dp, i64, i64, dp, i64, dp, i64, dp, i64, dp, i64,
-                                      C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(i64)]
+                                      C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(i64), i64]
     lib.amgs_ref_qr_dense.restype = C.c_int
     lib.amgs_ref_qr_csr.argtypes = [i64, i64, ip, ip, dp, i64, dp, i64, dp, i64, dp, i64, dp,
-                                    i64, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(i64)]
+                                    i64, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(i64), i64]
     lib.amgs_ref_qr_csr.restype = C.c_int
     lib.amgs_ref_mv_csr.argtypes = [i64, ip, ip, dp, dp, dp, C.c_int]
     lib.amgs_ref_num_threads.restype = C.c_int
@@ -72,19 +72,25 @@ class Result:
 
 def qr(Z: np.ndarray, dense: Optional[np.ndarray] = None, csr=None, variant: str = "ha",
        orientation: str = "col", reorth: bool = False, precision: str = "fp64",
-       lib=None) -> Result:
+       lib=None, first: int = 0, Q0=None, P0=None, R0=None) -> Result:
     """Run the oracle.  ``dense`` is an m x m symmetric matrix; ``csr`` is an
-    object with ``m, row_ptr, col_idx, vals``.  Returns Q, R, P = AQ, info."""
+    object with ``m, row_ptr, col_idx, vals``.  Returns Q, R, P = AQ, info.
+    first > 0: Q0, P0, R0 hold the final leading columns (successive
+    orthogonalisation)."""
     lib = lib or load()
     Z = np.asfortranarray(Z, dtype=np.float64)
     m, n = Z.shape
     Q = np.zeros((m, n), dtype=np.float64, order="F")
     R = np.zeros((n, n), dtype=np.float64, order="F")
     P = np.zeros((m, n), dtype=np.float64, order="F")
+    if first:
+        Q[:, :first] = Q0[:, :first]
+        P[:, :first] = P0[:, :first]
+        R[:first, :first] = R0[:first, :first]
     stats = (C.c_int64 * 2)()
     ld = max(m, 1)
     args = (n, _d(Z), ld, _d(Q), ld, _d(R), max(n, 1), _d(P), ld, VARIANTS[variant],
-            ORIENT[orientation], int(bool(reorth)), PRECISION[precision], stats)
+            ORIENT[orientation], int(bool(reorth)), PRECISION[precision], stats, int(first))
     if dense is not None:
         A = np.asfortranarray(dense, dtype=np.float64)
         info = lib.amgs_ref_qr_dense(m, _d(A), max(m, 1), *args)

@@ -30,7 +30,7 @@ class AmgsError(RuntimeError):
 
 class Opts(C.Structure):
     _fields_ = [("reorth", C.c_int32), ("panel", C.c_int32), ("cgs", C.c_int32),
-                ("reserved2", C.c_int32)]
+                ("first", C.c_int32)]
 
 
 class Stats(C.Structure):
@@ -194,13 +194,13 @@ class QRResult:
     stats: Stats
 
 
-def _prep(Z, precision, device, Q, P, return_p):
+def _prep(Z, precision, device, Q, P, return_p, R=None):
     torch = _torch()
     dt = torch.float64 if precision == "fp64" else torch.float32
     Zc = colmajor(Z.to(device), dt)
     m, n = Zc.shape
     Qc = Q if Q is not None else empty_colmajor(m, n, dt, device)
-    R = empty_colmajor(n, n, torch.float64, device)
+    R = R if R is not None else empty_colmajor(n, n, torch.float64, device)
     Pc = P if P is not None else (empty_colmajor(m, n, dt, device) if return_p else None)
     info = torch.zeros(1, dtype=torch.int32, device=device)
     return dt, Zc, Qc, R, Pc, info, m, n
@@ -208,18 +208,19 @@ def _prep(Z, precision, device, Q, P, return_p):
 
 def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=False,
            return_p=False, Q=None, P=None, work=None, stream=None, device=None,
-           panel=0, cgs=False) -> QRResult:
+           panel=0, cgs=False, first=0, R=None) -> QRResult:
     """A-orthonormalise the columns of Z (device tensors; A in CSR).
     panel: 0 for the column schedule, 4 for the panel schedule; cgs: classical
-    instead of modified Gram-Schmidt."""
+    instead of modified Gram-Schmidt; first > 0: columns before it are final
+    in the Q, P and R passed in (successive orthogonalisation)."""
     torch = _torch()
     device = device or Z.device
-    dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p)
+    dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p, R)
     vals = vals.to(device=device, dtype=dt).contiguous()
     row_ptr = row_ptr.to(device=device, dtype=torch.int32).contiguous()
     col_idx = col_idx.to(device=device, dtype=torch.int32).contiguous()
     h = handle(device.index or 0)
-    opts = Opts(int(bool(reorth)), int(panel), int(bool(cgs)), 0)
+    opts = Opts(int(bool(reorth)), int(panel), int(bool(cgs)), int(first))
     v, p = VARIANTS[variant], PRECISIONS[precision]
     wb = amgs_workspace_bytes(h, m, n, 0, v, p, int(Pc is not None), opts)
     if work is None:
@@ -236,16 +237,18 @@ def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=Fal
 
 
 def qr_dense(A, Z, variant="ha", precision="fp64", reorth=False, return_p=False, Q=None,
-             P=None, work=None, stream=None, device=None, panel=0, cgs=False) -> QRResult:
+             P=None, work=None, stream=None, device=None, panel=0, cgs=False, first=0,
+             R=None) -> QRResult:
     """A-orthonormalise the columns of Z (device tensors; A dense symmetric).
     panel: 0 for the column schedule, 4 for the panel schedule; cgs: classical
-    instead of modified Gram-Schmidt."""
+    instead of modified Gram-Schmidt; first > 0: columns before it are final
+    in the Q, P and R passed in (successive orthogonalisation)."""
     torch = _torch()
     device = device or Z.device
-    dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p)
+    dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p, R)
     Ac = colmajor(A.to(device), dt)
     h = handle(device.index or 0)
-    opts = Opts(int(bool(reorth)), int(panel), int(bool(cgs)), 0)
+    opts = Opts(int(bool(reorth)), int(panel), int(bool(cgs)), int(first))
     v, p = VARIANTS[variant], PRECISIONS[precision]
     wb = amgs_workspace_bytes(h, m, n, 1, v, p, int(Pc is not None), opts)
     if work is None:

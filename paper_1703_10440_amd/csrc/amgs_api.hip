@@ -144,10 +144,23 @@ amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
         else launch_csr_spmm<T>(c);
         st.kernel_launches++;
         st.mv_calls += 1;
-        st.mv_columns += c.n;
-        st.mv_bytes += mvA + 2.0 * (double)c.m * c.n * w;
+        st.mv_columns += c.n - c.first;
+        st.mv_bytes += mvA + 2.0 * (double)c.m * (c.n - c.first) * w;
     }
-    for (int64_t j = 0; j < c.n; ++j) {
+    // successive orthogonalisation: the final columns j < first project the
+    // new columns in the same right-looking order (no column kernel, so the
+    // finished row r_{j-1, first..} is published by a small kernel)
+    for (int64_t j = 0; j < c.first; ++j) {
+        if (j > 0) {
+            launch_publish<T>(c, j - 1);
+            st.kernel_launches++;
+        }
+        launch_sweep<T>(c, j, variant, 0);
+        st.kernel_launches++;
+        st.sweep_launches++;
+        if (variant == VAR_HP && launch_hp_xblock<T>(c, j)) st.kernel_launches++;
+    }
+    for (int64_t j = c.first; j < c.n; ++j) {
         int64_t n_rr;
         {
             ProfScope ps(h, variant == VAR_HP ? 1 : -1, c.stream);
@@ -373,11 +386,11 @@ amgs_status_t run_cgs(amgs_handle *h, Ctx &c, int variant, int reorth)
         else launch_csr_spmm<T>(c);
         st.kernel_launches++;
         st.mv_calls += 1;
-        st.mv_columns += c.n;
-        st.mv_bytes += mvA + 2.0 * (double)c.m * c.n * w;
+        st.mv_columns += c.n - c.first;
+        st.mv_bytes += mvA + 2.0 * (double)c.m * (c.n - c.first) * w;
     }
     const int passes = reorth ? 2 : 1;
-    for (int64_t j = 0; j < c.n; ++j) {
+    for (int64_t j = c.first; j < c.n; ++j) {
         int64_t n_rr;
         if (j > 0) {
             // classical passes: zt = z_j, then zt (HA) or Q[:, j] (HP) corrected
@@ -431,9 +444,13 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
     const int reorth = o ? (o->reorth != 0) : 0;
     const int panel = o ? o->panel : 0;
     const int cgs = o ? o->cgs : 0;
+    const int64_t first = o ? o->first : 0;
     if (panel != 0 && panel != PANEL_B) return AMGS_ERR_ARG;
     if (cgs != 0 && cgs != 1) return AMGS_ERR_ARG;
-    if (panel && (reorth || cgs)) return AMGS_ERR_UNSUPPORTED;
+    if (first < 0 || first > c.n) return AMGS_ERR_ARG;
+    if (first > 0 && !P_given) return AMGS_ERR_ARG;   // p_i of the final columns are needed
+    if (panel && (reorth || cgs || first)) return AMGS_ERR_UNSUPPORTED;
+    if (first == c.n) return AMGS_OK;
     const size_t w = p == AMGS_FP64 ? 8 : 4;
     c.geo = make_geo(c.m, c.nnz, c.is_dense);
     Layout L = layout(c.m, c.n, c.geo, (int)v, w, P_given, reorth || cgs, panel);
@@ -443,6 +460,7 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
     c.sp.g = c.geo.g_rows;
     c.panel = panel;
     c.cgs = cgs;
+    c.first = first;
     c.z_in_zt = 0;
     c.x_from = -1;
     c.n_pub = c.n;

@@ -108,6 +108,8 @@ struct SweepArgs {
     const double *rr_part;
     int64_t n_rr;
     int64_t cpw;
+    int64_t c_lo;     // first later column (j + 1, or the first new column)
+    int32_t norm;     // 0: column j is already final (successive orthogonalisation)
 };
 
 // One step of the panel schedule (see k_psweep): normalise column j, apply
@@ -175,6 +177,7 @@ struct Ctx {
     int64_t x_from;   // HP column kernel: first recurrence term it applies (-1: column schedule)
     int64_t n_pub;    // column kernels publish r_{j-1,c} for c < n_pub
     int cgs;          // classical Gram-Schmidt (no pending MGS update in k_reorth_a)
+    int64_t first;    // columns [0, first) are already final (successive orthogonalisation)
     int z_in_zt;      // k_reorth_a reads z_j from zt
     hipStream_t stream;
     // when set, the sweep is launched with these events bound to its own
@@ -192,6 +195,7 @@ void launch_reorth_fin(const Ctx &c, int64_t j);
 template <typename T> void launch_reorth_b(const Ctx &c, int64_t j, bool hp);
 template <typename T> void launch_sweep(const Ctx &c, int64_t j, int variant, int64_t n_rr);
 template <typename T> bool launch_hp_xblock(const Ctx &c, int64_t s);
+template <typename T> void launch_publish(const Ctx &c, int64_t jrow);
 template <typename T> void launch_csr_spmm(const Ctx &c);
 template <typename T> void launch_dense_gemm(const Ctx &c);
 template <typename T> void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,

@@ -28,24 +28,35 @@ namespace amgs {
 // ----------------------------------------------------------------- init
 // Q <- Z (unless aliased), R <- 0, info <- 0.
 template <typename T>
-__global__ __launch_bounds__(256) void k_init(int64_t m, int64_t n, const T *__restrict__ Z,
-                                              int64_t ldz, T *__restrict__ Q, int64_t ldq,
+__global__ __launch_bounds__(256) void k_init(int64_t m, int64_t n, int64_t first,
+                                              const T *__restrict__ Z, int64_t ldz,
+                                              T *__restrict__ Q, int64_t ldq,
                                               double *__restrict__ R, int64_t ldr, int32_t *info,
                                               int copy)
 {
+    // columns [0, first) are final already and left untouched
+    const int64_t nn = n - first;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (copy)
-        for (int64_t e = t0; e < m * n; e += stride) {
-            int64_t j = e / m, k = e - j * m;
+        for (int64_t e = t0; e < m * nn; e += stride) {
+            int64_t j = first + e / m, k = e % m;
             Q[k + j * ldq] = Z[k + j * ldz];
         }
-    for (int64_t e = t0; e < n * n; e += stride) {
-        int64_t j = e / n, i = e - j * n;
+    for (int64_t e = t0; e < n * nn; e += stride) {
+        int64_t j = first + e / n, i = e % n;
         R[i + j * ldr] = 0.0;
     }
     if (t0 == 0) *info = 0;
 }
+
+// R[jrow, c] for c in [c0, n) from the sweep partials, when no column kernel
+// runs between two sweeps (the final columns of successive
+// orthogonalisation).
+template <typename T>
+__global__ __launch_bounds__(256) void k_publish(SweepPart sp, int64_t jrow, int64_t c0, int64_t n,
+                                                 double *__restrict__ R, int64_t ldr,
+                                                 const int32_t *info);
 
 // ------------------------------------------------- publish finished r_{j-1,c}
 // Spread over all waves of the launching grid: wave w of the grid finalises
@@ -61,6 +72,15 @@ __device__ __forceinline__ void publish_row(const SweepPart &sp, int64_t jrow, i
         T s = wave_reduce_seq(part + c * sp.g, sp.g);
         if ((threadIdx.x & (WAVE - 1)) == 0) R[jrow + c * ldr] = (double)s;
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_publish(SweepPart sp, int64_t jrow, int64_t c0, int64_t n,
+                                                 double *__restrict__ R, int64_t ldr,
+                                                 const int32_t *info)
+{
+    if (*info) return;
+    publish_row<T>(sp, jrow, c0, n, R, ldr);
 }
 
 // ------------------------------------------------------- CSR MV (column kernel)
@@ -647,17 +667,18 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
     const bool own = blockIdx.y == 0;
     const T *__restrict__ zsrc = VAR == VAR_HP ? Q + j * a.ldq : (const T *)a.zt;
     const T *__restrict__ xsrc = VAR == VAR_HP ? (const T *)a.X + j * a.ldx : (const T *)a.xv;
-    // issue the vector loads before waiting for r_jj
+    // issue the vector loads before waiting for r_jj; a column that is
+    // already final (norm = 0) only supplies its stored p_j
     T xs[U], zs[U], qp[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
         const bool in = k < m;
-        xs[u] = in ? (VAR == VAR_NAIVE ? P[k + j * a.ldp] : xsrc[k]) : (T)0;
-        zs[u] = (in && own) ? zsrc[k] : (T)0;
+        xs[u] = in ? ((VAR == VAR_NAIVE || !a.norm) ? P[k + j * a.ldp] : xsrc[k]) : (T)0;
+        zs[u] = (in && own && a.norm) ? zsrc[k] : (T)0;
         qp[u] = (in && j > 0) ? Q[k + (j - 1) * a.ldq] : (T)0;
     }
-    const int64_t c0 = j + 1 + (int64_t)blockIdx.y * a.cpw;
+    const int64_t c0 = a.c_lo + (int64_t)blockIdx.y * a.cpw;
     const int64_t c1 = (c0 + a.cpw < a.n) ? c0 + a.cpw : a.n;
     const bool full_rows = row0 + 256 * U <= m;
     // start streaming the first group of later columns before waiting for
@@ -672,29 +693,34 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
             zv[t][u] = (c0 + t < c1 && (full_rows || k < m)) ? ld_stream<NTS>(Zc + k) : (T)0;
         }
     }
-    if (wave == 0) {
-        const double rr = wave_reduce_seq(a.rr_part, a.n_rr);
-        if (tid == 0) s_rr = rr;
-    }
-    __syncthreads();
-    const double rr = s_rr;
-    if (!norm_ok(rr)) {
-        if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) *a.info = (int32_t)(j + 1);
-        return;
-    }
-    const double rjj = sqrt(rr);
-    if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) a.R[j + j * a.ldr] = rjj;
     T p[U];
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const int64_t k = row0 + u * 256 + tid;
-        p[u] = VAR == VAR_NAIVE ? xs[u] : scale_div(xs[u], rjj);
-        if (own && k < m) {
-            // only the owning workgroup reads z_j: for HP it is overwritten
-            // in place by q_j
-            Q[k + j * a.ldq] = scale_div(zs[u], rjj);
-            if (VAR != VAR_NAIVE) P[k + j * a.ldp] = p[u];
+    if (a.norm) {
+        if (wave == 0) {
+            const double rr = wave_reduce_seq(a.rr_part, a.n_rr);
+            if (tid == 0) s_rr = rr;
         }
+        __syncthreads();
+        const double rr = s_rr;
+        if (!norm_ok(rr)) {
+            if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) *a.info = (int32_t)(j + 1);
+            return;
+        }
+        const double rjj = sqrt(rr);
+        if (blockIdx.x == 0 && blockIdx.y == 0 && tid == 0) a.R[j + j * a.ldr] = rjj;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = row0 + u * 256 + tid;
+            p[u] = VAR == VAR_NAIVE ? xs[u] : scale_div(xs[u], rjj);
+            if (own && k < m) {
+                // only the owning workgroup reads z_j: for HP it is
+                // overwritten in place by q_j
+                Q[k + j * a.ldq] = scale_div(zs[u], rjj);
+                if (VAR != VAR_NAIVE) P[k + j * a.ldp] = p[u];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < U; ++u) p[u] = xs[u];
     }
     if (c0 >= c1) return;
     for (int64_t cb = c0; cb < c1; cb += SWEEP_CB) {
@@ -754,7 +780,8 @@ __global__ __launch_bounds__(256) void k_sweep(SweepArgs a)
 // recurrence, while each p_i is streamed once per block instead of once per
 // column.
 template <typename T>
-__global__ __launch_bounds__(256) void k_hp_xblock(int64_t m, int64_t n, int64_t s, int64_t cpw,
+__global__ __launch_bounds__(256) void k_hp_xblock(int64_t m, int64_t n, int64_t s, int64_t c_lo,
+                                                   int64_t cpw,
                                                    const T *__restrict__ P, int64_t ldp,
                                                    T *__restrict__ X, int64_t ldx,
                                                    const double *__restrict__ R, int64_t ldr,
@@ -762,7 +789,7 @@ __global__ __launch_bounds__(256) void k_hp_xblock(int64_t m, int64_t n, int64_t
 {
     if (*info) return;
     const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t c0 = s + 1 + (int64_t)blockIdx.y * cpw;
+    const int64_t c0 = c_lo + (int64_t)blockIdx.y * cpw;
     const int64_t c1 = (c0 + cpw < n) ? c0 + cpw : n;
     if (k >= m || c0 >= c1) return;
     T pv[HP_XB];
@@ -860,12 +887,22 @@ __global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
 template <typename T>
 void launch_init(const Ctx &c, int copy)
 {
-    int64_t work = copy ? c.m * c.n : c.n * c.n;
+    const int64_t nn = c.n - c.first;
+    int64_t work = copy ? c.m * nn : c.n * nn;
     int64_t blocks = (work + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_init<T>, dim3((unsigned)blocks), dim3(256), 0, c.stream, c.m, c.n,
-                       (const T *)c.Z, c.ldz, (T *)c.Q, c.ldq, c.R, c.ldr, c.info, copy);
+                       c.first, (const T *)c.Z, c.ldz, (T *)c.Q, c.ldq, c.R, c.ldr, c.info, copy);
+}
+
+template <typename T>
+void launch_publish(const Ctx &c, int64_t jrow)
+{
+    const int64_t ncols = c.n - c.first;
+    const int64_t blocks = (ncols + 3) / 4;
+    hipLaunchKernelGGL(k_publish<T>, dim3((unsigned)(blocks > 0 ? blocks : 1)), dim3(256), 0,
+                       c.stream, c.sp, jrow, c.first, c.n, c.R, c.ldr, c.info);
 }
 
 // Launch on the context's stream; with profiling events set, the events are
@@ -1026,14 +1063,18 @@ void launch_sweep(const Ctx &c, int64_t j, int variant, int64_t n_rr)
     a.m = c.m; a.n = c.n; a.j = j; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp;
     a.X = c.X; a.ldx = c.m; a.zt = c.zt; a.xv = c.xv; a.R = c.R; a.ldr = c.ldr;
     a.info = c.info; a.sp = c.sp; a.rr_part = c.rr_part; a.n_rr = n_rr;
+    // a column before c.first is final: only its projections onto the new
+    // columns [first, n) remain
+    a.norm = j >= c.first ? 1 : 0;
+    a.c_lo = j >= c.first ? j + 1 : c.first;
     int64_t gy, cpw;
-    sweep_cols(c, c.n - j - 1, gy, cpw);
+    sweep_cols(c, c.n - a.c_lo, gy, cpw);
     a.cpw = cpw;
     const dim3 grid((unsigned)c.geo.g_rows, (unsigned)gy), block(256);
     // later columns that no longer fit the last-level cache are streamed with
     // non-temporal loads and stores; smaller trailing blocks stay cached for
     // the next step
-    const bool nts = (double)(c.n - j - 1) * (double)c.m * sizeof(T) > SWEEP_NT_BYTES;
+    const bool nts = (double)(c.n - a.c_lo) * (double)c.m * sizeof(T) > SWEEP_NT_BYTES;
 #define AMGS_SWEEP_V(V_, NT_)                                                                     \
     AMGS_DISPATCH_U(c.geo.U, if (c.ev_start) hipExtLaunchKernelGGL((k_sweep<T, UU, V_, NT_>),     \
         grid, block, 0, c.stream, c.ev_start, c.ev_stop, 0, a);                                   \
@@ -1053,8 +1094,9 @@ void launch_sweep(const Ctx &c, int64_t j, int variant, int64_t n_rr)
 template <typename T>
 bool launch_hp_xblock(const Ctx &c, int64_t s)
 {
-    if (s < HP_XB || s % HP_XB != 0 || s + 1 >= c.n) return false;
-    const int64_t ncols = c.n - s - 1;
+    const int64_t c_lo = s + 1 > c.first ? s + 1 : c.first;
+    if (s < HP_XB || s % HP_XB != 0 || c_lo >= c.n) return false;
+    const int64_t ncols = c.n - c_lo;
     const int64_t gx = (c.m + 255) / 256;
     int64_t gy = (SWEEP_TARGET_WG + gx - 1) / gx;
     const int64_t max_gy = (ncols + 3) / 4;
@@ -1063,17 +1105,21 @@ bool launch_hp_xblock(const Ctx &c, int64_t s)
     int64_t cpw = (ncols + gy - 1) / gy;
     gy = (ncols + cpw - 1) / cpw;
     hipLaunchKernelGGL(k_hp_xblock<T>, dim3((unsigned)gx, (unsigned)gy), dim3(256), 0, c.stream,
-                       c.m, c.n, s, cpw, (const T *)c.P, c.ldp, (T *)c.X, c.m, c.R, c.ldr, c.info);
+                       c.m, c.n, s, c_lo, cpw, (const T *)c.P, c.ldp, (T *)c.X, c.m, c.R, c.ldr,
+                       c.info);
     return true;
 }
 
 template <typename T>
 void launch_csr_spmm(const Ctx &c)
 {
-    const dim3 grid((unsigned)((c.m + 255) / 256), (unsigned)((c.n + SPMM_C - 1) / SPMM_C)),
+    // the new columns [first, n) only
+    const int64_t nn = c.n - c.first;
+    const dim3 grid((unsigned)((c.m + 255) / 256), (unsigned)((nn + SPMM_C - 1) / SPMM_C)),
         block(256);
-    hipLaunchKernelGGL(k_csr_spmm<T>, grid, block, 0, c.stream, c.m, c.n, c.row_ptr, c.col_idx,
-                       (const T *)c.vals, (const T *)c.Q, c.ldq, (T *)c.X, c.m);
+    hipLaunchKernelGGL(k_csr_spmm<T>, grid, block, 0, c.stream, c.m, nn, c.row_ptr, c.col_idx,
+                       (const T *)c.vals, (const T *)c.Q + c.first * c.ldq, c.ldq,
+                       (T *)c.X + c.first * c.m, c.m);
 }
 
 void launch_csr_check(int64_t m, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
@@ -1090,6 +1136,8 @@ void launch_csr_check(int64_t m, int64_t nnz, const int32_t *row_ptr, const int3
 
 template void launch_init<double>(const Ctx &, int);
 template void launch_init<float>(const Ctx &, int);
+template void launch_publish<double>(const Ctx &, int64_t);
+template void launch_publish<float>(const Ctx &, int64_t);
 template void launch_mv<double>(const Ctx &, int64_t, int);
 template void launch_mv<float>(const Ctx &, int64_t, int);
 template void launch_col_hp<double>(const Ctx &, int64_t, bool);

@@ -458,7 +458,39 @@ def pin_cgs(lib) -> list:
     return fails
 
 
+def pin_successive(lib) -> list:
+    """Successive orthogonalisation (Section 2.1: the column form suits it):
+    column j of the column algorithm depends only on columns before it, so
+    orthonormalising the first k columns and then appending the rest
+    (first = k, the k final columns passed in) must reproduce the one-call
+    result bit for bit, for every variant, the classical form and the second
+    pass; on a well-conditioned problem the appended result also equals the
+    closed form R = chol(Z^T A Z)."""
+    fails = []
+    for p in (inputs.random_dense_problem(60, 11, 13), inputs.random_csr_problem(300, 10, 9, 14)):
+        Ad = p.dense if p.dense is not None else p.csr.to_dense()
+        Rc = _chol_R(p.Z, Ad)
+        for o in ("col", "cgs"):
+            for v in VARIANTS:
+                for re_ in (False, True):
+                    for prec in ("fp64", "fp32"):
+                        kw = dict(dense=p.dense, csr=p.csr, variant=v, orientation=o, reorth=re_,
+                                  precision=prec, lib=lib)
+                        full = ref.qr(p.Z, **kw)
+                        for k in (1, 4):
+                            part = ref.qr(p.Z[:, :k], **kw)
+                            succ = ref.qr(p.Z, first=k, Q0=part.Q, P0=part.P, R0=part.R, **kw)
+                            tag = f"{p.name} {o}/{v}/reorth={re_}/{prec}/first={k}"
+                            if succ.info != 0 or not (np.array_equal(succ.Q, full.Q)
+                                                      and np.array_equal(succ.R, full.R)
+                                                      and np.array_equal(succ.P, full.P)):
+                                fails.append(f"successive {tag}: differs from one call")
+                            if prec == "fp64" and _rel(np.triu(succ.R), Rc) > 1e-13:
+                                fails.append(f"successive {tag}: R vs chol {_rel(np.triu(succ.R), Rc)}")
+    return fails
+
+
 ALL_PINS = [pin_hand_example, pin_cholesky, pin_identity_householder, pin_cholesky_factor,
             pin_col_row_bitwise, pin_mv_counts, pin_scaling, pin_first_column,
             pin_residual_and_reorth, pin_exp2_accuracy, pin_fp32_accumulation, pin_fp32_vs_fp64, pin_breakdown,
-            pin_panel, pin_cgs]
+            pin_panel, pin_cgs, pin_successive]

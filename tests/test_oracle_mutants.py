@@ -49,6 +49,9 @@ MUTANTS = [
     ("classical Gram-Schmidt leaves the HP x column uncorrected",
      "        /* r_ij = p_i^T z_j^{(0)} for every i < j, then one correction */\n        reorth_pass(z, xr, j,",
      "        /* r_ij = p_i^T z_j^{(0)} for every i < j, then one correction */\n        reorth_pass(z, NULL, j,"),
+    ("appended columns skip the projections onto the final columns",
+     "for (int64_t i = 0; i < j; ++i) {           /* projections */",
+     "for (int64_t i = first; i < j; ++i) {           /* projections */"),
     ("panel block step skips the last panel column",
      "for (int i = 0; i < b; ++i) axpy_st(z, st(r[i], prec), Q + (s + i) * ldq, m, prec);",
      "for (int i = 0; i + 1 < b; ++i) axpy_st(z, st(r[i], prec), Q + (s + i) * ldq, m, prec);"),
