@@ -15,7 +15,7 @@ constexpr double SWEEP_NT_BYTES = 192.0 * (1 << 20); // trailing block streamed 
 constexpr int HP_XB = 8;       // HP recurrence terms applied per blocked update
 constexpr int RE_GROUP = 8;    // second-pass coefficients per workgroup row
 constexpr int DENSE_CB = 16;   // outputs per dense-MV workgroup pass
-constexpr int SPMM_C = 8;      // columns per CSR block-product thread
+constexpr int SPMM_C = 4;      // columns per CSR block-product load group
 constexpr int MAX_G_MV = 512;  // partials of an MV column kernel
 constexpr int MV_TILE = 512;   // rows (= threads) per CSR-stream MV workgroup
 constexpr int STREAM_CAP = 8 * MV_TILE; // CSR entries staged per tile

@@ -816,9 +816,12 @@ __global__ __launch_bounds__(256) void k_hp_xblock(int64_t m, int64_t n, int64_t
 }
 
 // ------------------------------------------------- HP block product, CSR
-// X = A Z for all n columns (Alg. 6, first line).  Thread per row and grid
-// row y per group of SPMM_C columns; a row's entries are staged in registers
-// eight at a time so that all loads of Z for them are in flight together.
+// X = A Z for all n columns (Alg. 6, first line).  Thread per row; the
+// row's entries are read once: rows of at most eight entries keep their
+// indices and values in registers for every column, longer rows are taken
+// eight entries at a time per group of columns (those re-reads stay in the
+// thread's cache).  Columns go in groups of SPMM_C with every load of Z for
+// a group in flight together.
 template <typename T>
 __global__ __launch_bounds__(256) void k_csr_spmm(int64_t m, int64_t n, const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ col_idx,
@@ -827,31 +830,51 @@ __global__ __launch_bounds__(256) void k_csr_spmm(int64_t m, int64_t n, const in
 {
     constexpr int C = SPMM_C;
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t c0 = (int64_t)blockIdx.y * C;
     if (row >= m) return;
     const int32_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
-    const int nc = (int)(n - c0 < C ? n - c0 : C);
-    const T *__restrict__ Zc = Z + c0 * ldz;
-    T acc[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = 0;
-    for (int32_t eb = e0; eb < e1; eb += 8) {
+    if (e1 - e0 <= 8) {
         int64_t l[8];
         T v[8];
 #pragma unroll
         for (int t = 0; t < 8; ++t) {
-            const bool in = eb + t < e1;
-            l[t] = in ? col_idx[eb + t] : 0;
-            v[t] = in ? vals[eb + t] : (T)0;
+            const bool in = e0 + t < e1;
+            l[t] = in ? col_idx[e0 + t] : 0;
+            v[t] = in ? vals[e0 + t] : (T)0;
         }
-        // entries past the row's end are skipped, not multiplied by zero
-        if (nc == C) {
+        for (int64_t c0 = 0; c0 < n; c0 += C) {
+            const int nc = (int)(n - c0 < C ? n - c0 : C);
+            const T *__restrict__ Zc = Z + c0 * ldz;
+            T acc[C];
+#pragma unroll
+            for (int c = 0; c < C; ++c) acc[c] = 0;
+            // entries past the row's end are skipped, not multiplied by zero
 #pragma unroll
             for (int c = 0; c < C; ++c)
+                if (c < nc)
 #pragma unroll
-                for (int t = 0; t < 8; ++t)
-                    if (eb + t < e1) acc[c] += v[t] * Zc[l[t] + c * ldz];
-        } else {
+                    for (int t = 0; t < 8; ++t)
+                        if (e0 + t < e1) acc[c] += v[t] * Zc[l[t] + c * ldz];
+#pragma unroll
+            for (int c = 0; c < C; ++c)
+                if (c < nc) X[row + (c0 + c) * ldx] = acc[c];
+        }
+        return;
+    }
+    for (int64_t c0 = 0; c0 < n; c0 += C) {
+        const int nc = (int)(n - c0 < C ? n - c0 : C);
+        const T *__restrict__ Zc = Z + c0 * ldz;
+        T acc[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) acc[c] = 0;
+        for (int32_t eb = e0; eb < e1; eb += 8) {
+            int64_t l[8];
+            T v[8];
+#pragma unroll
+            for (int t = 0; t < 8; ++t) {
+                const bool in = eb + t < e1;
+                l[t] = in ? col_idx[eb + t] : 0;
+                v[t] = in ? vals[eb + t] : (T)0;
+            }
 #pragma unroll
             for (int c = 0; c < C; ++c)
                 if (c < nc)
@@ -859,10 +882,10 @@ __global__ __launch_bounds__(256) void k_csr_spmm(int64_t m, int64_t n, const in
                     for (int t = 0; t < 8; ++t)
                         if (eb + t < e1) acc[c] += v[t] * Zc[l[t] + c * ldz];
         }
-    }
 #pragma unroll
-    for (int c = 0; c < C; ++c)
-        if (c < nc) X[row + (c0 + c) * ldx] = acc[c];
+        for (int c = 0; c < C; ++c)
+            if (c < nc) X[row + (c0 + c) * ldx] = acc[c];
+    }
 }
 
 // --------------------------------------------------------- CSR validation
@@ -1115,8 +1138,7 @@ void launch_csr_spmm(const Ctx &c)
 {
     // the new columns [first, n) only
     const int64_t nn = c.n - c.first;
-    const dim3 grid((unsigned)((c.m + 255) / 256), (unsigned)((nn + SPMM_C - 1) / SPMM_C)),
-        block(256);
+    const dim3 grid((unsigned)((c.m + 255) / 256)), block(256);
     hipLaunchKernelGGL(k_csr_spmm<T>, grid, block, 0, c.stream, c.m, nn, c.row_ptr, c.col_idx,
                        (const T *)c.vals, (const T *)c.Q + c.first * c.ldq, c.ldq,
                        (T *)c.X + c.first * c.m, c.m);
