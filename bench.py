@@ -250,6 +250,16 @@ def bench_single(args, torch, amgs):
         for v in ("naive", "ha", "hp"):
             variants[f"{v}_fp32"]["speedup_vs_fp64"] = round(
                 variants[f"{v}_fp64"]["ms"] / variants[f"{v}_fp32"]["ms"], 3)
+        # fastest modified Gram-Schmidt configuration per precision (either
+        # schedule, no second pass)
+        best = {}
+        for p in ("fp64", "fp32"):
+            keys = [k for k in variants if not k.startswith("cgs_") and "reorth" not in k
+                    and k.split("_")[1] == p]
+            k = max(keys, key=lambda k: variants[k]["cols_per_s"])
+            best[p] = {"variant": k, "cols_per_s": variants[k]["cols_per_s"],
+                       "ms": variants[k]["ms"], "orth_loss": variants[k]["orth_loss"]}
+        variants["best"] = best
 
     cpu = None
     if not args.no_cpu:
