@@ -228,7 +228,7 @@ def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=Fal
     s = stream if stream is not None else torch.cuda.current_stream(device).cuda_stream
     st = amgs_qr_csr(h, m, int(vals.numel()), row_ptr.data_ptr(), col_idx.data_ptr(),
                      vals.data_ptr(), n, Zc.data_ptr(), max(Zc.stride(1), m), Qc.data_ptr(),
-                     max(Qc.stride(1), m), R.data_ptr(), max(n, 1),
+                     max(Qc.stride(1), m), R.data_ptr(), max(R.stride(1), n, 1),
                      Pc.data_ptr() if Pc is not None else None,
                      max(Pc.stride(1), m) if Pc is not None else 0, v, p, C.byref(opts),
                      work.data_ptr(), work.numel(), info.data_ptr(), s)
@@ -256,7 +256,7 @@ def qr_dense(A, Z, variant="ha", precision="fp64", reorth=False, return_p=False,
     s = stream if stream is not None else torch.cuda.current_stream(device).cuda_stream
     st = amgs_qr_dense(h, m, Ac.data_ptr(), max(Ac.stride(1), m), n, Zc.data_ptr(),
                        max(Zc.stride(1), m), Qc.data_ptr(), max(Qc.stride(1), m), R.data_ptr(),
-                       max(n, 1), Pc.data_ptr() if Pc is not None else None,
+                       max(R.stride(1), n, 1), Pc.data_ptr() if Pc is not None else None,
                        max(Pc.stride(1), m) if Pc is not None else 0, v, p, C.byref(opts),
                        work.data_ptr(), work.numel(), info.data_ptr(), s)
     _check(st, "amgs_qr_dense")

@@ -218,6 +218,57 @@ def test_argument_errors():
     assert st == 0
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_padded_leading_dimensions(variant):
+    """Z, Q, P and R given with leading dimensions larger than their row
+    counts: the results equal those of unpadded buffers bit for bit, and the
+    padding rows are left untouched."""
+    for p in (SMALL[0], SMALL[3]):
+        m, n = p.Z.shape
+        ref_run = gpu_run(p, variant)
+
+        def padded(rows, cols, pad, dtype=torch.float64):
+            buf = torch.full((cols, rows + pad), float("nan"), dtype=dtype, device=DEV).t()
+            return buf, buf[:rows, :]
+
+        zb, Zv = padded(m, n, 7)
+        Zv.copy_(torch.from_numpy(np.ascontiguousarray(p.Z)))
+        qb, Qv = padded(m, n, 3)
+        pb, Pv = padded(m, n, 5)
+        rb, Rv = padded(n, n, 2)
+        kw = dict(variant=variant, Q=Qv, P=Pv, R=Rv)
+        print(f"[gpu] padded {p.name} {variant}", flush=True)
+        if p.csr is not None:
+            out = amgs.qr_csr(torch.from_numpy(p.csr.row_ptr).to(DEV),
+                              torch.from_numpy(p.csr.col_idx).to(DEV),
+                              torch.from_numpy(p.csr.vals).to(DEV), Zv, **kw)
+        else:
+            out = amgs.qr_dense(torch.from_numpy(np.ascontiguousarray(p.dense)).to(DEV), Zv, **kw)
+        torch.cuda.synchronize()
+        assert int(out.info.item()) == 0
+        assert np.array_equal(Qv.cpu().numpy(), ref_run[0])
+        assert np.array_equal(Rv.cpu().numpy(), ref_run[1])
+        assert np.array_equal(Pv.cpu().numpy(), ref_run[2])
+        for buf, rows in ((qb, m), (pb, m), (rb, n)):
+            assert torch.isnan(buf[rows:, :]).all()
+
+
+def test_size_limits():
+    """Row counts and entry counts beyond int32 are rejected before any
+    memory is touched."""
+    h = amgs.handle(0)
+    info = torch.zeros(1, dtype=torch.int32, device=DEV)
+    Z = torch.zeros(16, dtype=torch.float64, device=DEV)
+    big = (1 << 31) + 1
+    ptr = Z.data_ptr()
+    st = amgs.amgs_qr_csr(h, big, 10, ptr, ptr, ptr, 4, ptr, big, ptr, big, ptr, 4, None, 0,
+                          1, 0, None, ptr, 1 << 20, info.data_ptr(), None)
+    assert st == -1
+    st = amgs.amgs_qr_csr(h, 100, big, ptr, ptr, ptr, 4, ptr, 100, ptr, 100, ptr, 4, None, 0,
+                          1, 0, None, ptr, 1 << 20, info.data_ptr(), None)
+    assert st == -1
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("variant", VARIANTS)
 def test_second_pass_many_workgroups(variant, precision):
