@@ -182,7 +182,7 @@ def mv_roofline(data, precision, amgs, torch):
     avg_s = ms / 1e3 / max(launches, 1)
     bpl = st.mv_bytes / max(st.mv_calls, 1)
     ach = bpl / avg_s / 1e9
-    return {"bound": "hbm", "kernel": "k_csr_mv_stream / k_dense_mv (HA column MV)",
+    return {"bound": "hbm", "kernel": "k_csr_mv_ell / k_dense_mv (HA column MV)",
             "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(ach / HBM_PEAK_GBS, 4), "avg_us": round(avg_s * 1e6, 3),
             "launches": int(launches), "bytes_per_launch": bpl}

@@ -65,7 +65,7 @@ struct ProfScope {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t part, s_part, rr_part, S, zt, xv, X, P, wpart, lpart, total;
+    size_t part, s_part, rr_part, S, zt, xv, X, P, wpart, lpart, ell_col, ell_val, tile_long, total;
 };
 
 // Row chunks of the panel-schedule sweeps (256 threads of panel_rows rows).
@@ -77,7 +77,7 @@ int64_t panel_chunks(int64_t m, size_t w)
 }
 
 Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_given, int reorth,
-              int panel)
+              int panel, int is_dense)
 {
     Layout L{};
     size_t off = 0;
@@ -100,6 +100,12 @@ Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_g
     L.P = P_given ? off : take((size_t)m * n * w);
     L.wpart = panel ? take((size_t)n * PANEL_B * g_p * 8) : off;
     L.lpart = panel ? take((size_t)PANEL_B * PANEL_B * g_p * 8) : off;
+    // padded copy of a CSR A for the column MV (naive and HA; the size does
+    // not depend on nnz, which only decides whether the copy is used)
+    const bool ell = !is_dense && variant != VAR_HP;
+    L.ell_col = ell ? take((size_t)ELL_K * m * 4) : off;
+    L.ell_val = ell ? take((size_t)ELL_K * m * w) : off;
+    L.tile_long = ell ? take((size_t)((m + MV_TILE - 1) / MV_TILE) * 4) : off;
     L.total = off;
     return L;
 }
@@ -136,6 +142,10 @@ amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
     st = amgs_stats_t{};
     launch_init<T>(c, c.Z != c.Q);
     st.kernel_launches++;
+    if (c.ell_k) {
+        launch_csr_to_ell<T>(c);
+        st.kernel_launches++;
+    }
     const double mvA = c.is_dense ? (double)c.m * (double)c.m * w
                                   : (double)c.nnz * (w + 4) + 4.0 * (double)(c.m + 1);
     if (variant == VAR_HP) {
@@ -266,6 +276,10 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant)
     st = amgs_stats_t{};
     launch_init<T>(c, c.Z != c.Q);
     st.kernel_launches++;
+    if (c.ell_k) {
+        launch_csr_to_ell<T>(c);
+        st.kernel_launches++;
+    }
     const double mvA = c.is_dense ? (double)c.m * (double)c.m * w
                                   : (double)c.nnz * (w + 4) + 4.0 * (double)(c.m + 1);
     if (variant == VAR_HP) {
@@ -378,6 +392,10 @@ amgs_status_t run_cgs(amgs_handle *h, Ctx &c, int variant, int reorth)
     st = amgs_stats_t{};
     launch_init<T>(c, c.Z != c.Q);
     st.kernel_launches++;
+    if (c.ell_k) {
+        launch_csr_to_ell<T>(c);
+        st.kernel_launches++;
+    }
     const double mvA = c.is_dense ? (double)c.m * (double)c.m * w
                                   : (double)c.nnz * (w + 4) + 4.0 * (double)(c.m + 1);
     if (variant == VAR_HP) {
@@ -453,7 +471,7 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
     if (first == c.n) return AMGS_OK;
     const size_t w = p == AMGS_FP64 ? 8 : 4;
     c.geo = make_geo(c.m, c.nnz, c.is_dense);
-    Layout L = layout(c.m, c.n, c.geo, (int)v, w, P_given, reorth || cgs, panel);
+    Layout L = layout(c.m, c.n, c.geo, (int)v, w, P_given, reorth || cgs, panel, c.is_dense);
     if (!work || work_bytes < L.total) return AMGS_ERR_WORKSPACE;
     char *base = (char *)work;
     c.sp.part = base + L.part;
@@ -482,6 +500,16 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
         c.ldp = c.m;
     }
     c.n_rr_mv = c.is_dense ? c.geo.g_dense : c.geo.g_csr;
+    c.ell_k = 0;
+    if (!c.is_dense && v != AMGS_HP && c.geo.lanes == 0) {
+        // K = the mean row length rounded up (at most ELL_K here); longer
+        // rows keep their remaining entries in the CSR arrays
+        int64_t k = (c.nnz + c.m - 1) / c.m;
+        c.ell_k = (int32_t)(k < 1 ? 1 : k > ELL_K ? ELL_K : k);
+        c.ell_col = (int32_t *)(base + L.ell_col);
+        c.ell_val = base + L.ell_val;
+        c.tile_long = (int32_t *)(base + L.tile_long);
+    }
     DeviceGuard dg(h->device);
     return p == AMGS_FP64 ? run_single<double>(h, c, (int)v, reorth)
                           : run_single<float>(h, c, (int)v, reorth);
@@ -584,7 +612,7 @@ size_t amgs_workspace_bytes(amgs_handle_t h, int64_t m, int64_t n, int32_t is_de
     if (panel != 0 && panel != PANEL_B) return 0;
     if (cgs != 0 && cgs != 1) return 0;
     Layout L = layout(m, n, g, (int)v, p == AMGS_FP64 ? 8 : 4, P_given,
-                      (o ? o->reorth != 0 : 0) || cgs, panel);
+                      (o ? o->reorth != 0 : 0) || cgs, panel, is_dense);
     return L.total;
 }
 

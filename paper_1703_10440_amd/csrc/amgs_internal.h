@@ -17,8 +17,8 @@ constexpr int RE_GROUP = 8;    // second-pass coefficients per workgroup row
 constexpr int DENSE_CB = 16;   // outputs per dense-MV workgroup pass
 constexpr int SPMM_C = 4;      // columns per CSR block-product load group
 constexpr int MAX_G_MV = 512;  // partials of an MV column kernel
-constexpr int MV_TILE = 512;   // rows (= threads) per CSR-stream MV workgroup
-constexpr int STREAM_CAP = 8 * MV_TILE; // CSR entries staged per tile
+constexpr int MV_TILE = 512;   // rows (= threads) per padded-copy MV workgroup
+constexpr int ELL_K = 8;       // most entries per row held in the padded copy of A
 constexpr int PANEL_B = 4;     // columns per panel of the panel schedule
 constexpr int PS_CB = 2;       // later columns streamed together by a panel-sweep thread
 constexpr int PS_MAXC = 64;    // later columns per panel-sweep workgroup (max)
@@ -54,6 +54,11 @@ struct CsrMvArgs {
     const double *rr_part;
     int64_t n_rr;
     double *rr_out;
+    // padded copy of A: entry k of row r at k*m + r (column -1 past the end)
+    const int32_t *ell_col;
+    const void *ell_val;
+    const int32_t *tile_long;  // per MV_TILE rows: some row has more than ell_k entries
+    int32_t ell_k;
 };
 
 struct DenseMvArgs {
@@ -179,6 +184,11 @@ struct Ctx {
     int cgs;          // classical Gram-Schmidt (no pending MGS update in k_reorth_a)
     int64_t first;    // columns [0, first) are already final (successive orthogonalisation)
     int z_in_zt;      // k_reorth_a reads z_j from zt
+    // padded copy of a CSR A for the column MV (ell_k = 0: not used)
+    int32_t *ell_col;
+    void *ell_val;
+    int32_t *tile_long;
+    int32_t ell_k;
     hipStream_t stream;
     // when set, the sweep is launched with these events bound to its own
     // dispatch (exact kernel start and end, no extra stream markers)
@@ -188,6 +198,7 @@ struct Ctx {
 Geo make_geo(int64_t m, int64_t nnz, int is_dense);
 
 template <typename T> void launch_init(const Ctx &c, int copy);
+template <typename T> void launch_csr_to_ell(const Ctx &c);
 template <typename T> void launch_mv(const Ctx &c, int64_t j, int src_mode);
 template <typename T> void launch_col_hp(const Ctx &c, int64_t j, bool reorth_a);
 template <typename T> void launch_reorth_a(const Ctx &c, int64_t j);

@@ -160,84 +160,110 @@ __global__ __launch_bounds__(512) void k_csr_mv(CsrMvArgs a)
     if (SRC == SRC_UPD && qprev) publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
 }
 
-// CSR MV for short rows ("CSR stream"): a workgroup takes MV_TILE consecutive
-// rows, stages their entries (at most STREAM_CAP) in LDS with coalesced
-// loads, then each thread sums its own row from LDS in stored order.  Same
-// contract as k_csr_mv; a tile with more entries than fit is summed straight
-// from memory.
-template <typename T, int SRC, bool RR>
-__global__ __launch_bounds__(MV_TILE) void k_csr_mv_stream(CsrMvArgs a)
+// CSR MV for short rows, through a padded copy of A.  Once per call the
+// first K entries of every row are copied into a column-major array (entry k
+// of row r at k*m + r, column -1 past the row's end), so a thread finds its
+// row's entries without reading the row bounds first: the entries and the
+// row's own z are requested together, then every gather.  Entries past K
+// (rows longer than K, flagged per tile of MV_TILE rows) are read from the
+// CSR arrays.  Same contract as k_csr_mv; the sum runs in stored order.
+template <typename T>
+__global__ __launch_bounds__(MV_TILE) void k_csr_to_ell(int64_t m, int32_t K,
+                                                        const int32_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col_idx,
+                                                        const T *__restrict__ vals,
+                                                        int32_t *__restrict__ ell_col,
+                                                        T *__restrict__ ell_val,
+                                                        int32_t *__restrict__ tile_long)
 {
-    constexpr int PER = STREAM_CAP / MV_TILE;
-    __shared__ int32_t s_col[STREAM_CAP];
-    __shared__ T s_val[STREAM_CAP];
+    const int64_t row = (int64_t)blockIdx.x * MV_TILE + threadIdx.x;
+    int lng = 0;
+    if (row < m) {
+        const int32_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
+        for (int k = 0; k < K; ++k) {
+            const int32_t e = e0 + k;
+            int32_t cv = -1;
+            T v = 0;
+            if (e < e1) {
+                cv = col_idx[e];
+                v = vals[e];
+            }
+            ell_col[(int64_t)k * m + row] = cv;
+            ell_val[(int64_t)k * m + row] = v;
+        }
+        lng = e1 - e0 > K;
+    }
+    lng = __syncthreads_or(lng);
+    if (threadIdx.x == 0) tile_long[blockIdx.x] = lng;
+}
+
+// RPT rows per thread: the thread's rows in RPT consecutive grid-stride
+// tiles are requested together (more loads in flight per wave).
+template <typename T, int SRC, bool RR, int RPT>
+__global__ __launch_bounds__(MV_TILE) void k_csr_mv_ell(CsrMvArgs a)
+{
     __shared__ double lds[MV_TILE / WAVE];
     __shared__ T s_r;
     __shared__ double s_rr;
     if (*a.info) return;
     const T *__restrict__ vals = (const T *)a.vals;
+    const int32_t *__restrict__ ecol = a.ell_col;
+    const T *__restrict__ eval = (const T *)a.ell_val;
     const T *__restrict__ src = (const T *)a.src;
     const T *__restrict__ qprev = (const T *)a.qprev;
     T *__restrict__ y = (T *)a.y;
     T *__restrict__ zt = (T *)a.zt;
     const bool with_upd = SRC == SRC_UPD && qprev;
     const int tid = threadIdx.x;
+    const int K = a.ell_k;
+    const int64_t m = a.m;
+    const int64_t stride = (int64_t)gridDim.x * MV_TILE;
     T r = 0;
     double rjj = 1.0;
     double acc = 0.0;
     bool first = true;
-    for (int64_t row0 = (int64_t)blockIdx.x * MV_TILE; row0 < a.m; row0 += (int64_t)gridDim.x * MV_TILE) {
-        const int64_t row = row0 + tid;
-        const int64_t rend = row0 + MV_TILE < a.m ? row0 + MV_TILE : a.m;
+    for (int64_t row0 = (int64_t)blockIdx.x * MV_TILE; row0 < m; row0 += RPT * stride) {
         // everything that does not depend on the coefficient is requested
-        // first: the tile's bounds, this thread's row bounds and own entry,
-        // and the tile's column indices and values
-        const int32_t t0 = a.row_ptr[row0], t1 = a.row_ptr[rend];
-        int32_t e0 = 0, e1 = 0;
-        T own_s = 0, own_q = 0;
-        if (row < a.m) {
-            e0 = a.row_ptr[row];
-            e1 = a.row_ptr[row + 1];
-            if (SRC == SRC_UPD || RR) {
-                own_s = src[row];
-                if (with_upd) own_q = qprev[row];
-            }
-        }
-        const bool staged = t1 - t0 <= STREAM_CAP;
-        int32_t cl[PER];
-        T vl[PER];
-        if (staged) {
+        // first: the rows' entries and their own z (and q_{j-1})
+        int32_t col[RPT][ELL_K];
+        T av[RPT][ELL_K];
+        T own_s[RPT], own_q[RPT];
+        int lng[RPT];
 #pragma unroll
-            for (int t = 0; t < PER; ++t) {
-                const int32_t e = t0 + tid + t * MV_TILE;
-                cl[t] = e < t1 ? a.col_idx[e] : 0;
-                vl[t] = e < t1 ? vals[e] : (T)0;
+        for (int u = 0; u < RPT; ++u) {
+            const int64_t t0 = row0 + u * stride;
+            const int64_t row = t0 + tid;
+            const bool live = row < m;
+            lng[u] = t0 < m ? a.tile_long[t0 / MV_TILE] : 0;
+            own_s[u] = 0;
+            own_q[u] = 0;
+#pragma unroll
+            for (int k = 0; k < ELL_K; ++k) {
+                col[u][k] = -1;
+                av[u][k] = 0;
+                if (live && k < K) {
+                    col[u][k] = ecol[(int64_t)k * m + row];
+                    av[u][k] = eval[(int64_t)k * m + row];
+                }
+            }
+            if (live && (SRC == SRC_UPD || RR)) {
+                own_s[u] = src[row];
+                if (with_upd) own_q[u] = qprev[row];
             }
         }
         // the coefficient r_{j-1,j} (or r_jj for the naive second MV) is
         // re-reduced by wave 0 while those loads are in flight
-        if (first && (with_upd || SRC == SRC_DIV) && tid < WAVE) {
-            if (with_upd) {
-                const T v = wave_reduce_seq((const T *)a.sp.part + a.j * a.sp.g, a.sp.g);
-                if (tid == 0) s_r = v;
-            } else {
-                const double v = wave_reduce_seq(a.rr_part, a.n_rr);
-                if (tid == 0) s_rr = v;
-            }
-        }
-        if (staged) {
-#pragma unroll
-            for (int t = 0; t < PER; ++t) {
-                const int32_t e = t0 + tid + t * MV_TILE;
-                if (e < t1) {
-                    s_col[e - t0] = cl[t];
-                    s_val[e - t0] = vl[t];
+        if (first && (with_upd || SRC == SRC_DIV)) {
+            if (tid < WAVE) {
+                if (with_upd) {
+                    const T v = wave_reduce_seq((const T *)a.sp.part + a.j * a.sp.g, a.sp.g);
+                    if (tid == 0) s_r = v;
+                } else {
+                    const double v = wave_reduce_seq(a.rr_part, a.n_rr);
+                    if (tid == 0) s_rr = v;
                 }
             }
-        }
-        __syncthreads();
-        if (first) {
-            first = false;
+            __syncthreads();
             if (with_upd) r = s_r;
             if (SRC == SRC_DIV) {
                 const double rr = s_rr;
@@ -245,42 +271,56 @@ __global__ __launch_bounds__(MV_TILE) void k_csr_mv_stream(CsrMvArgs a)
                 rjj = sqrt(rr);
             }
         }
+        first = false;
         auto load = [&](int64_t l) -> T {
             T v = src[l];
             if (with_upd) v = upd(v, r, qprev[l]);
             if (SRC == SRC_DIV) v = scale_div(v, rjj);
             return v;
         };
-        if (row < a.m) {
+        T xv[RPT][ELL_K];
+#pragma unroll
+        for (int u = 0; u < RPT; ++u)
+#pragma unroll
+            for (int k = 0; k < ELL_K; ++k) xv[u][k] = col[u][k] >= 0 ? load(col[u][k]) : (T)0;
+#pragma unroll
+        for (int u = 0; u < RPT; ++u) {
+            const int64_t row = row0 + u * stride + tid;
+            if (row >= m) continue;
+            // padding only follows a row's last entry: it is skipped, not
+            // multiplied by zero
             T s = 0;
-            // eight entries at a time: indices and values first, then every
-            // gather in flight, then the sum in stored order (entries past
-            // the row's end are skipped, not multiplied by zero)
-            for (int32_t eb = e0; eb < e1; eb += 8) {
-                int64_t col[8];
-                T av[8], xv[8];
 #pragma unroll
-                for (int t = 0; t < 8; ++t) {
-                    const bool in = eb + t < e1;
-                    col[t] = in ? (staged ? s_col[eb + t - t0] : a.col_idx[eb + t]) : row;
-                    av[t] = in ? (staged ? s_val[eb + t - t0] : vals[eb + t]) : (T)0;
+            for (int k = 0; k < ELL_K; ++k)
+                if (col[u][k] >= 0) s += av[u][k] * xv[u][k];
+            if (lng[u]) {
+                // the row's entries past the first K, eight at a time
+                const int32_t e1 = a.row_ptr[row + 1];
+                for (int32_t eb = a.row_ptr[row] + K; eb < e1; eb += 8) {
+                    int64_t cl[8];
+                    T cv[8], gv[8];
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) {
+                        const bool in = eb + t < e1;
+                        cl[t] = in ? a.col_idx[eb + t] : row;
+                        cv[t] = in ? vals[eb + t] : (T)0;
+                    }
+#pragma unroll
+                    for (int t = 0; t < 8; ++t) gv[t] = load(cl[t]);
+#pragma unroll
+                    for (int t = 0; t < 8; ++t)
+                        if (eb + t < e1) s += cv[t] * gv[t];
                 }
-#pragma unroll
-                for (int t = 0; t < 8; ++t) xv[t] = load(col[t]);
-#pragma unroll
-                for (int t = 0; t < 8; ++t)
-                    if (eb + t < e1) s += av[t] * xv[t];
             }
             y[row] = s;
             if (SRC == SRC_UPD || RR) {
-                T zs = own_s;
-                if (with_upd) zs = upd(zs, r, own_q);
+                T zs = own_s[u];
+                if (with_upd) zs = upd(zs, r, own_q[u]);
                 if (SRC == SRC_DIV) zs = scale_div(zs, rjj);
                 if (SRC == SRC_UPD) zt[row] = zs;
                 if (RR) acc += (double)zs * (double)s;
             }
         }
-        __syncthreads();
     }
     if (RR) {
         double t = block_sum<double, MV_TILE>(acc, lds);
@@ -919,6 +959,17 @@ void launch_init(const Ctx &c, int copy)
                        c.first, (const T *)c.Z, c.ldz, (T *)c.Q, c.ldq, c.R, c.ldr, c.info, copy);
 }
 
+// The padded copy of A used by the short-row column MV: one workgroup per
+// tile of MV_TILE rows.
+template <typename T>
+void launch_csr_to_ell(const Ctx &c)
+{
+    const int64_t tiles = (c.m + MV_TILE - 1) / MV_TILE;
+    hipLaunchKernelGGL(k_csr_to_ell<T>, dim3((unsigned)tiles), dim3(MV_TILE), 0, c.stream, c.m,
+                       c.ell_k, c.row_ptr, c.col_idx, (const T *)c.vals, c.ell_col,
+                       (T *)c.ell_val, c.tile_long);
+}
+
 template <typename T>
 void launch_publish(const Ctx &c, int64_t jrow)
 {
@@ -941,8 +992,15 @@ template <typename T, int SRC, bool RR>
 static void launch_csr_mv_L(const Ctx &c, CsrMvArgs &a)
 {
     const dim3 grid((unsigned)c.geo.g_csr), block(512);
-    switch (c.geo.lanes) {
-    case 0: launch_k(c, k_csr_mv_stream<T, SRC, RR>, grid, dim3(MV_TILE), a); break;
+    // short rows go through the padded copy; without one, a lane per row
+    switch (c.geo.lanes == 0 && c.ell_k == 0 ? 1 : c.geo.lanes) {
+    case 0:
+        // two rows per thread once every workgroup has two tiles or more
+        if (c.m > 2 * (int64_t)c.geo.g_csr * MV_TILE - MV_TILE)
+            launch_k(c, k_csr_mv_ell<T, SRC, RR, 2>, grid, dim3(MV_TILE), a);
+        else
+            launch_k(c, k_csr_mv_ell<T, SRC, RR, 1>, grid, dim3(MV_TILE), a);
+        break;
     case 1: launch_k(c, k_csr_mv<T, 1, SRC, RR>, grid, block, a); break;
     case 2: launch_k(c, k_csr_mv<T, 2, SRC, RR>, grid, block, a); break;
     case 4: launch_k(c, k_csr_mv<T, 4, SRC, RR>, grid, block, a); break;
@@ -979,6 +1037,7 @@ void launch_mv(const Ctx &c, int64_t j, int src_mode)
     } else {
         CsrMvArgs a{};
         a.m = c.m; a.n = c.n_pub; a.j = j; a.row_ptr = c.row_ptr; a.col_idx = c.col_idx; a.vals = c.vals;
+        a.ell_col = c.ell_col; a.ell_val = c.ell_val; a.tile_long = c.tile_long; a.ell_k = c.ell_k;
         a.info = c.info; a.R = c.R; a.ldr = c.ldr; a.sp = c.sp;
         a.rr_part = c.rr_part; a.n_rr = c.n_rr_mv; a.rr_out = c.rr_part;
         if (src_mode == SRC_UPD) {
@@ -1158,6 +1217,8 @@ void launch_csr_check(int64_t m, int64_t nnz, const int32_t *row_ptr, const int3
 
 template void launch_init<double>(const Ctx &, int);
 template void launch_init<float>(const Ctx &, int);
+template void launch_csr_to_ell<double>(const Ctx &);
+template void launch_csr_to_ell<float>(const Ctx &);
 template void launch_publish<double>(const Ctx &, int64_t);
 template void launch_publish<float>(const Ctx &, int64_t);
 template void launch_mv<double>(const Ctx &, int64_t, int);

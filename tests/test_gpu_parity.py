@@ -71,6 +71,7 @@ def small_problems():
         inputs.random_csr_problem(2003, 9, 220, seed=9),                    # 32 lanes/row
         inputs.dense_gram_problem(512, 32, seed=1),                         # dense 512 x 32
         inputs.random_dense_problem(333, 21, seed=10),                      # ragged GEMM tiles
+        inputs.random_csr_problem(3001, 11, 5, seed=12),                    # short rows, some past K
     ]
 
 
@@ -251,6 +252,68 @@ def test_padded_leading_dimensions(variant):
         assert np.array_equal(Pv.cpu().numpy(), ref_run[2])
         for buf, rows in ((qb, m), (pb, m), (rb, n)):
             assert torch.isnan(buf[rows:, :]).all()
+
+
+def _arrow(m):
+    """Row and column 0 full, diagonal m+1 there and 3 elsewhere: strictly
+    diagonally dominant, so spd.  Mean row length ~3, one row of m entries."""
+    rows, cols, vals = [], [], []
+    for i in range(m):
+        if i == 0:
+            rows += [0] * m
+            cols += list(range(m))
+            vals += [m + 1.0] + [-1.0] * (m - 1)
+        else:
+            rows += [i, i]
+            cols += [0, i]
+            vals += [-1.0, 3.0]
+    row_ptr = np.zeros(m + 1, dtype=np.int64)
+    np.add.at(row_ptr, np.array(rows) + 1, 1)
+    return inputs.CSR(m, np.cumsum(row_ptr).astype(np.int32), np.array(cols, dtype=np.int32),
+                      np.array(vals))
+
+
+@pytest.mark.parametrize("variant", ["naive", "ha"])
+def test_short_rows_with_long_tails(variant):
+    """The column MV for short rows reads the first K entries of each row
+    from a padded copy and the rest from CSR: one row of every entry (arrow
+    matrix, K = 3), and rows of exactly K and K + 1 entries."""
+    g = inputs.rng(21)
+    for A in (_arrow(2500), _arrow(513)):
+        Z = np.asfortranarray(g.standard_normal((A.m, 7)))
+        p = inputs.Problem(f"arrow{A.m}", Z, csr=A)
+        want = ref.qr_problem(p, variant=variant)
+        Q, R, P, info, _ = gpu_run(p, variant)
+        assert info == 0 and want.info == 0
+        eR, eQ, eP = _rel(R, want.R), _rel(Q, want.Q), _rel(P, want.P)
+        print(f"  {p.name}: R {eR:.2e} Q {eQ:.2e} P {eP:.2e}")
+        assert eR <= 1e-10 and eQ <= 1e-10 and eP <= 1e-10
+    # tridiagonal (K = 3, rows of 2 and 3) with a few rows of 4 entries
+    m = 1500
+    D = np.diag(np.full(m, 4.0)) + np.diag(np.full(m - 1, -1.0), 1) + np.diag(np.full(m - 1, -1.0), -1)
+    for i in (5, 700, 1499):
+        j = (i + 37) % m
+        D[i, j] = D[j, i] = -0.5
+    Z = np.asfortranarray(g.standard_normal((m, 9)))
+    p = inputs.Problem("tri_plus", Z, csr=inputs.csr_from_dense(D))
+    want = ref.qr_problem(p, variant=variant)
+    Q, R, P, info, _ = gpu_run(p, variant)
+    assert info == 0 and want.info == 0
+    assert _rel(R, want.R) <= 1e-10 and _rel(Q, want.Q) <= 1e-10 and _rel(P, want.P) <= 1e-10
+
+
+@pytest.mark.parametrize("variant", ["naive", "ha"])
+def test_short_rows_several_tiles_per_workgroup(variant):
+    """Laplacian 96^3 (884,736 rows): 1728 tiles of the short-row column MV
+    over at most 512 workgroups, so each thread takes rows of two tiles at
+    once, and the last pair of some workgroups has one tile."""
+    p = inputs.laplacian_graded_problem(N=96, n=6, decades=1.0, seed=23)
+    want = ref.qr_problem(p, variant=variant)
+    Q, R, P, info, _ = gpu_run(p, variant)
+    assert info == 0 and want.info == 0
+    eR, eQ, eP = _rel(R, want.R), _rel(Q, want.Q), _rel(P, want.P)
+    print(f"  R {eR:.2e} Q {eQ:.2e} P {eP:.2e}")
+    assert eR <= 1e-10 and eQ <= 1e-10 and eP <= 1e-10
 
 
 def test_size_limits():
