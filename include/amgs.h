@@ -144,7 +144,11 @@ amgs_status_t amgs_destroy(amgs_handle_t h);
 
 /* Bytes of device workspace needed by amgs_qr_csr (is_dense = 0) or
  * amgs_qr_dense (is_dense = 1) for these sizes; P_given = 1 if the caller
- * passes its own P (= AQ) buffer.  Returns 0 for invalid arguments. */
+ * passes its own P (= AQ) buffer.  Returns 0 for invalid arguments.  The
+ * workspace holds reduction partials, the HP block X, P when not given and,
+ * for CSR with the naive and HA variants, a padded copy of up to 8 entries
+ * per row of A (8 m (4 + element size) bytes) that the column MV reads; its
+ * contents do not need to be preserved between calls. */
 size_t amgs_workspace_bytes(amgs_handle_t h, int64_t m, int64_t n, int32_t is_dense,
                             amgs_variant_t v, amgs_precision_t p, int32_t P_given,
                             const amgs_opts_t *o);
