@@ -36,6 +36,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "A-orthonormalised cols/s + %HBM roofline: HA/HP n-MV vs 2n-MV, FP64 vs FP32"
 HBM_PEAK_GBS = 8000.0
+# dense matrix-core peaks of MI355X (TFLOP/s) for the block product's dtype
+MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_lap64_traffic.json")
 
 
@@ -188,6 +190,26 @@ def mv_roofline(data, precision, amgs, torch):
             "launches": int(launches), "bytes_per_launch": bpl}
 
 
+def gemm_roofline(runner, m, n, precision, amgs, torch):
+    """The HP block product X = A Z for dense A on the matrix cores: its
+    duration from HIP events recorded around the launch on the call's
+    stream, and its 2 m^2 n flops."""
+    h = amgs.handle(0)
+    amgs.amgs_profile_reset(h)
+    amgs.amgs_profile_enable(h, 1)
+    runner()
+    torch.cuda.synchronize()
+    amgs.amgs_profile_enable(h, 0)
+    ms, launches = amgs.amgs_profile_read(h, 2)
+    avg_s = ms / 1e3 / max(launches, 1)
+    tflops = 2.0 * m * m * n / avg_s / 1e12
+    peak = MFMA_PEAK_TFLOPS[precision]
+    return {"bound": "mfma", "kernel": "k_gemm_atb (HP block product)", "achieved": round(tflops, 2),
+            "peak": peak, "unit": "TFLOP/s", "frac": round(tflops / peak, 4),
+            "avg_us": round(avg_s * 1e6, 2), "launches": int(launches),
+            "flops_per_launch": 2.0 * m * m * n}
+
+
 def cpu_baseline(prob, variant, budget_s=10.0):
     """The oracle as it stands, repeated on the full workload until about
     budget_s seconds of host time have passed."""
@@ -221,6 +243,10 @@ def bench_single(args, torch, amgs):
     log(f"[bench] {head_v}/{head_p}: {t * 1e3:.3f} ms/step info={info}")
     roof = sweep_roofline(run, amgs, torch)
     log(f"[bench] sweep roofline {roof}")
+    gemmroof = None
+    if prob.csr is None and head_v == "hp":
+        gemmroof = gemm_roofline(run, prob.m, prob.n, head_p, amgs, torch)
+        log(f"[bench] gemm roofline {gemmroof}")
     del run
     mvroof = mv_roofline(data, head_p, amgs, torch)
     log(f"[bench] mv roofline {mvroof}")
@@ -270,11 +296,14 @@ def bench_single(args, torch, amgs):
            "A": "csr" if prob.csr is not None else "dense", "nnz": int(big),
            "variant": head_v, "precision": head_p, "reorth": bool(args.reorth),
            "schedule": f"panel{args.panel}" if args.panel else "column"}
-    return {"metric": METRIC, "value": round(prob.n / t, 2), "unit": "cols/s", "n_gpus": 1,
+    line = {"metric": METRIC, "value": round(prob.n / t, 2), "unit": "cols/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t * 1e3, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64" if head_p == "fp64" else "f32", "data": "synthetic", "config": cfg,
             "roofline": roof, "mv_roofline": mvroof, "cpu_baseline": cpu, "variants": variants}
+    if gemmroof is not None:
+        line["gemm_roofline"] = gemmroof
+    return line
 
 
 # --------------------------------------------------------------------- batched
@@ -378,7 +407,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lap64_n64",
                     choices=["lap64_n64", "lap128_n128", "dense512_n32", "dense16k_n256",
-                             "batch2048", "copy1g", "exp2"])
+                             "batch2048", "copy1g", "stream", "exp2"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-variants", action="store_true")
@@ -404,6 +433,24 @@ def main():
         print(json.dumps({"workload": "copy1g", "bytes_read": 1 << 30, "bytes_written": 1 << 30,
                           "ms": round(t * 1e3, 4), "GB_per_s": round(2 * (1 << 30) / t / 1e9, 1)}),
               flush=True)
+        return
+    if args.workload == "stream":
+        # what plain streaming kernels (torch's own) reach on this GPU: an
+        # in-place read-modify-write (the access pattern of a sweep), a copy
+        # and a read-only sum, at a size that fits the 256 MB last-level
+        # cache and at one that does not
+        out = {"workload": "stream", "kernels": "torch add_ / copy_ / sum", "rates_GB_per_s": {}}
+        for mib in (128, 2048):
+            x = torch.ones(mib << 17, dtype=torch.float64, device="cuda:0")
+            y = torch.empty_like(x)
+            nb = x.numel() * 8
+            for name, fn, moved in (("rmw", lambda: x.add_(1.0), 2 * nb),
+                                    ("copy", lambda: y.copy_(x), 2 * nb),
+                                    ("read", lambda: x.sum(), nb)):
+                t, _ = time_steps(fn, max(args.steps, 20), args.warmup, torch)
+                out["rates_GB_per_s"][f"{name}_{mib}MiB"] = round(moved / t / 1e9, 1)
+            del x, y
+        print(json.dumps(out), flush=True)
         return
     if args.workload == "exp2":
         print(json.dumps(bench_exp2(args, torch, amgs)), flush=True)

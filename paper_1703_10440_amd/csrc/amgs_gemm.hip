@@ -8,6 +8,8 @@
 // (v_mfma_f64_16x16x4f64 in binary64, v_mfma_f32_16x16x4f32 in binary32);
 // K is consumed in slabs of 16 staged through LDS (double-buffered), each
 // thread loading a run of consecutive k values of one column.
+#include <type_traits>
+
 #include "amgs_device.h"
 #include "amgs_internal.h"
 
@@ -45,7 +47,7 @@ constexpr int GB_K = 16;
 // (TM/2) x (TN/2) block of (TM/32) x (TN/32) MFMA tiles.  Larger tiles read
 // A fewer times (once per TN columns of X) and feed more MFMAs per LDS read.
 template <typename T, int TM, int TN>
-__global__ __launch_bounds__(256) void k_gemm_atb(int64_t m, int64_t n, const T *__restrict__ A,
+__global__ __launch_bounds__(256, 2) void k_gemm_atb(int64_t m, int64_t n, const T *__restrict__ A,
                                                   int64_t lda, const T *__restrict__ Z,
                                                   int64_t ldz, T *__restrict__ X, int64_t ldx)
 {
@@ -78,49 +80,86 @@ __global__ __launch_bounds__(256) void k_gemm_atb(int64_t m, int64_t n, const T 
 #pragma unroll
             for (int v = 0; v < 4; ++v) acc[a][b][v] = 0;
 
-    T ra[A_PER], rb[B_PER];
-    auto gload = [&](int64_t k0) {
-        const bool full = k0 + GB_K <= m;
-#pragma unroll
-        for (int t = 0; t < A_PER; ++t) {
-            const int64_t k = k0 + ak + t;
-            ra[t] = (a_ok && (full || k < m)) ? Acol[k] : (T)0;
-        }
-#pragma unroll
-        for (int t = 0; t < B_PER; ++t) {
-            const int64_t k = k0 + bk + t;
-            rb[t] = (b_ok && (full || k < m)) ? Zcol[k] : (T)0;
-        }
-    };
-    auto lstore = [&](int buf) {
-#pragma unroll
-        for (int t = 0; t < A_PER; ++t) As[buf][ak + t][ac] = ra[t];
-#pragma unroll
-        for (int t = 0; t < B_PER; ++t) Bs[buf][bk + t][bc] = rb[t];
-    };
+    // Two register sets of staged loads: slab kt+2 is requested while slab
+    // kt is multiplied and slab kt+1 waits in registers, so the loads have
+    // two slabs of MFMA work to arrive.  Every load is issued on every path
+    // (a slab past the end re-reads the last one, whose values are never
+    // used), so the wait before each LDS store covers only the older set.
+    // Interior tiles (every row, column and slab inside the matrix) load
+    // without any test; edge tiles clamp the index to a valid element and
+    // zero the value.
     const int64_t nk = (m + GB_K - 1) / GB_K;
-    gload(0);
-    lstore(0);
-    __syncthreads();
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        const int buf = (int)(kt & 1);
-        if (kt + 1 < nk) gload((kt + 1) * GB_K);
+    const int64_t klast = (nk - 1) * GB_K;
+    auto run = [&](auto edge_tag) {
+        constexpr bool EDGE = decltype(edge_tag)::value;
+        T ra[2][A_PER], rb[2][B_PER];
+        auto gload = [&](int set, int64_t k0) {
+            k0 = k0 < klast ? k0 : klast;
 #pragma unroll
-        for (int ks = 0; ks < GB_K; ks += 4) {
-            const int kk = ks + (lane >> 4);
-            T av[FM], bv[FN];
+            for (int t = 0; t < A_PER; ++t) {
+                const int64_t k = k0 + ak + t;
+                if (EDGE) {
+                    const bool ok = a_ok && k < m;
+                    const T v = Acol[ok ? k : 0];
+                    ra[set][t] = ok ? v : (T)0;
+                } else {
+                    ra[set][t] = Acol[k];
+                }
+            }
 #pragma unroll
-            for (int a = 0; a < FM; ++a) av[a] = As[buf][kk][wm + a * 16 + (lane & 15)];
+            for (int t = 0; t < B_PER; ++t) {
+                const int64_t k = k0 + bk + t;
+                if (EDGE) {
+                    const bool ok = b_ok && k < m;
+                    const T v = Zcol[ok ? k : 0];
+                    rb[set][t] = ok ? v : (T)0;
+                } else {
+                    rb[set][t] = Zcol[k];
+                }
+            }
+        };
+        auto lstore = [&](int set, int buf) {
 #pragma unroll
-            for (int b = 0; b < FN; ++b) bv[b] = Bs[buf][kk][wn + b * 16 + (lane & 15)];
+            for (int t = 0; t < A_PER; ++t) As[buf][ak + t][ac] = ra[set][t];
 #pragma unroll
-            for (int a = 0; a < FM; ++a)
+            for (int t = 0; t < B_PER; ++t) Bs[buf][bk + t][bc] = rb[set][t];
+        };
+        auto compute = [&](int buf) {
 #pragma unroll
-                for (int b = 0; b < FN; ++b) acc[a][b] = Mfma<T>::op(av[a], bv[b], acc[a][b]);
-        }
-        if (kt + 1 < nk) lstore(buf ^ 1);
+            for (int ks = 0; ks < GB_K; ks += 4) {
+                const int kk = ks + (lane >> 4);
+                T av[FM], bv[FN];
+#pragma unroll
+                for (int a = 0; a < FM; ++a) av[a] = As[buf][kk][wm + a * 16 + (lane & 15)];
+#pragma unroll
+                for (int b = 0; b < FN; ++b) bv[b] = Bs[buf][kk][wn + b * 16 + (lane & 15)];
+#pragma unroll
+                for (int a = 0; a < FM; ++a)
+#pragma unroll
+                    for (int b = 0; b < FN; ++b) acc[a][b] = Mfma<T>::op(av[a], bv[b], acc[a][b]);
+            }
+        };
+        gload(0, 0);
+        lstore(0, 0);
+        gload(1, GB_K);
         __syncthreads();
-    }
+        // LDS buffer 0 holds even slabs, buffer 1 odd ones; register set 0
+        // stages even slabs, set 1 odd ones
+        for (int64_t kt = 0; kt < nk; kt += 2) {
+            gload(0, (kt + 2) * GB_K);
+            compute(0);
+            if (kt + 1 >= nk) break;
+            lstore(1, 1);
+            __syncthreads();
+            gload(1, (kt + 3) * GB_K);
+            compute(1);
+            lstore(0, 0);
+            __syncthreads();
+        }
+    };
+    const bool interior = m % GB_K == 0 && m0 + TM <= m && n0 + TN <= n;
+    if (interior) run(std::integral_constant<bool, false>{});
+    else run(std::integral_constant<bool, true>{});
     // store each 16x16 tile
 #pragma unroll
     for (int a = 0; a < FM; ++a)
