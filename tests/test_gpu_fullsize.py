@@ -10,7 +10,9 @@ grids), against the oracle run on the whole problem:
   within 1e-10 of the oracle element by element;
 * Laplacian 128^3 + 1e-2 I, Z 2097152 x 128, kappa(Z) ~ 1e4: HA in the
   binary32 form, both schedules -- against the oracle's binary32 emulation
-  on the same binary32 inputs: residual and orthogonality within 10x.
+  on the same binary32 inputs: residual and orthogonality within 10x;
+* the same problem in binary64, HA and HP, both schedules: residual and
+  orthogonality within 10x of the oracle's (kappa(Z) > 1e3).
 """
 import numpy as np
 import pytest
@@ -106,3 +108,23 @@ def test_lap128_fp32_full(lap128_fp32, panel):
     print(f"  residual {res_g:.2e} (oracle {res_o:.2e}) orth {o_g:.2e} (oracle {o_o:.2e})")
     assert res_g <= 10 * res_o
     assert o_g <= 10 * o_o
+
+
+@pytest.fixture(scope="module")
+def lap128_fp64():
+    return inputs.WORKLOADS["lap128_n128"]()
+
+
+@pytest.mark.parametrize("panel", [0, 4])
+@pytest.mark.parametrize("variant", ["hp", "ha"])
+def test_lap128_fp64_full(lap128_fp64, variant, panel):
+    p = lap128_fp64
+    want = ref.qr_problem(p, variant=variant, orientation="panel" if panel else "col")
+    Q, R, info = _run(p, variant, "fp64", panel)
+    assert info == 0 and want.info == 0
+    res_g, res_o = ref.residual(p.Z, Q, R), ref.residual(p.Z, want.Q, want.R)
+    o_g, o_o = ref.orth_loss(Q, csr=p.csr), ref.orth_loss(want.Q, csr=p.csr)
+    print(f"  residual {res_g:.2e} (oracle {res_o:.2e}) orth {o_g:.2e} (oracle {o_o:.2e}) "
+          f"R rel {_rel(R, want.R):.2e}")
+    assert res_g <= max(1e-12, 10 * res_o)
+    assert o_g <= max(1e-13, 10 * o_o)
