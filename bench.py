@@ -422,6 +422,52 @@ def bench_batched(args, torch, amgs):
             "variants": results}
 
 
+# ------------------------------------------------------ timing experiment
+def bench_exp1(args, torch, amgs):
+    """Experiment I (Section 4) in shape: the time of naive, HA and HP in
+    binary64 against the number of columns n, on a dense spd A = B B^T/m + I
+    with m = 10000 and on a sparse spd stand-in for the paper's sparse matrix
+    (m = 9180, about 387 entries per row, symmetric and strictly diagonally
+    dominant: only its size and density follow the paper's matrix).  Z is
+    Gaussian.  Reports ms per call and the speed-up of HA and HP over naive."""
+    import numpy as np
+    from paper_1703_10440_amd import inputs
+    dev = torch.device("cuda:0")
+    ns = [5, 10, 20, 50, 100, 200, 500, 1000, 2000]
+    out = {"workload": "exp1", "precision": "fp64", "ns": ns, "results": {}}
+    log("[bench] exp1: building A (dense 10000, sparse 9180)")
+    A = torch.from_numpy(inputs.gram_spd(inputs.rng(11), 10000, device="cuda:0")).to(dev)
+    A = amgs.colmajor(A, torch.float64)
+    sp = inputs.random_csr_problem(9180, 1, 387, seed=12).csr
+    out["sparse_nnz"] = int(sp.nnz)
+    csr = {"row_ptr": torch.from_numpy(sp.row_ptr).to(dev),
+           "col_idx": torch.from_numpy(sp.col_idx).to(dev),
+           "vals": torch.from_numpy(sp.vals).to(dev)}
+    for name, m, dense in (("dense_m10000", 10000, True), ("sparse_m9180", 9180, False)):
+        Zall = inputs.rng(13).standard_normal((m, max(ns)))
+        rec = {}
+        for n in ns:
+            data = {"Z": torch.from_numpy(np.ascontiguousarray(Zall[:, :n])).to(dev)}
+            if dense:
+                data["A"] = A
+            else:
+                data.update(csr)
+            row = {}
+            for v in ("naive", "ha", "hp"):
+                r = Runner(data, v, "fp64", torch, amgs)
+                t, o = time_steps(r, 3, 1, torch)
+                if int(o.info.item()) != 0:
+                    raise RuntimeError(f"exp1 {name} n={n} {v}: breakdown")
+                row[v] = round(t * 1e3, 4)
+                del r, o
+            row["ha_over_naive"] = round(row["naive"] / row["ha"], 2)
+            row["hp_over_naive"] = round(row["naive"] / row["hp"], 2)
+            rec[str(n)] = row
+            log(f"[bench] exp1 {name} n={n}: {row}")
+        out["results"][name] = rec
+    return out
+
+
 # ------------------------------------------------------- accuracy experiment
 def bench_exp2(args, torch, amgs):
     """Experiments II/III (Section 4) on the GPU binary64 path: m = 100,
@@ -476,7 +522,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="lap64_n64",
                     choices=["lap64_n64", "lap128_n128", "dense512_n32", "dense16k_n256",
-                             "batch2048", "copy1g", "stream", "exp2"])
+                             "batch2048", "copy1g", "stream", "exp1", "exp2"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-variants", action="store_true")
@@ -520,6 +566,9 @@ def main():
                 out["rates_GB_per_s"][f"{name}_{mib}MiB"] = round(moved / t / 1e9, 1)
             del x, y
         print(json.dumps(out), flush=True)
+        return
+    if args.workload == "exp1":
+        print(json.dumps(bench_exp1(args, torch, amgs)), flush=True)
         return
     if args.workload == "exp2":
         print(json.dumps(bench_exp2(args, torch, amgs)), flush=True)

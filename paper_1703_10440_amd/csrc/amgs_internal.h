@@ -16,6 +16,7 @@ constexpr int HP_XB = 8;       // HP recurrence terms applied per blocked update
 constexpr int RE_GROUP = 8;    // second-pass coefficients per workgroup row
 constexpr int DENSE_CB = 16;   // outputs per dense-MV workgroup pass
 constexpr int SPMM_C = 4;      // columns per CSR block-product load group
+constexpr int SPMM_LC = 8;     // columns per pass of the multi-lane CSR block product
 constexpr int MAX_G_MV = 512;  // partials of an MV column kernel
 constexpr int MV_TILE = 512;   // rows (= threads) per padded-copy MV workgroup
 constexpr int ELL_K = 8;       // most entries per row held in the padded copy of A

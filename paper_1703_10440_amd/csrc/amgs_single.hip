@@ -928,6 +928,65 @@ __global__ __launch_bounds__(256) void k_csr_spmm(int64_t m, int64_t n, const in
     }
 }
 
+// HP block product for longer rows: L lanes share a row (L from the mean
+// row length, as for the column MV), each lane takes every L-th entry and
+// applies it to SPMM_LC columns of Z at once, so an entry is read once per
+// column group; the lanes' sums are then combined with shuffles.  Grid:
+// (row groups of 256 / L rows, column groups of SPMM_LC).
+template <typename T, int L>
+__global__ __launch_bounds__(256) void k_csr_spmm_lanes(int64_t m, int64_t n,
+                                                        const int32_t *__restrict__ row_ptr,
+                                                        const int32_t *__restrict__ col_idx,
+                                                        const T *__restrict__ vals,
+                                                        const T *__restrict__ Z, int64_t ldz,
+                                                        T *__restrict__ X, int64_t ldx)
+{
+    constexpr int C = SPMM_LC;
+    constexpr int E = 4;   // entries per lane in flight
+    const int g = threadIdx.x / L, lig = threadIdx.x % L;
+    const int64_t row = (int64_t)blockIdx.x * (256 / L) + g;
+    const int64_t c0 = (int64_t)blockIdx.y * C;
+    const int nc = (int)(n - c0 < C ? n - c0 : C);
+    const bool live = row < m;   // uniform over the L lanes of a row
+    T acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0;
+    if (live) {
+        const int32_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
+        const T *__restrict__ Zc = Z + c0 * ldz;
+        for (int32_t eb = e0 + lig; eb < e1; eb += E * L) {
+            int64_t l[E];
+            T v[E];
+#pragma unroll
+            for (int t = 0; t < E; ++t) {
+                const bool in = eb + t * L < e1;
+                l[t] = in ? col_idx[eb + t * L] : row;
+                v[t] = in ? vals[eb + t * L] : (T)0;
+            }
+            T zg[E][C];
+#pragma unroll
+            for (int t = 0; t < E; ++t)
+#pragma unroll
+                for (int c = 0; c < C; ++c) zg[t][c] = c < nc ? Zc[l[t] + c * ldz] : (T)0;
+            // entries past the row's end are skipped, not multiplied by zero
+#pragma unroll
+            for (int t = 0; t < E; ++t)
+                if (eb + t * L < e1)
+#pragma unroll
+                    for (int c = 0; c < C; ++c) acc[c] += v[t] * zg[t][c];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int off = L / 2; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, L);
+    if (live && lig == 0) {
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (c < nc) X[row + (c0 + c) * ldx] = acc[c];
+    }
+}
+
 // --------------------------------------------------------- CSR validation
 __global__ __launch_bounds__(256) void k_csr_check(int64_t m, int64_t nnz, const int32_t *__restrict__ row_ptr,
                                                    const int32_t *__restrict__ col_idx,
@@ -1197,10 +1256,31 @@ void launch_csr_spmm(const Ctx &c)
 {
     // the new columns [first, n) only
     const int64_t nn = c.n - c.first;
-    const dim3 grid((unsigned)((c.m + 255) / 256)), block(256);
-    hipLaunchKernelGGL(k_csr_spmm<T>, grid, block, 0, c.stream, c.m, nn, c.row_ptr, c.col_idx,
-                       (const T *)c.vals, (const T *)c.Q + c.first * c.ldq, c.ldq,
-                       (T *)c.X + c.first * c.m, c.m);
+    const T *Zn = (const T *)c.Q + c.first * c.ldq;
+    T *Xn = (T *)c.X + c.first * c.m;
+    const int L = c.geo.lanes;
+    if (L <= 1) {
+        // short rows: a thread per row (entries in registers for <= 8)
+        const dim3 grid((unsigned)((c.m + 255) / 256)), block(256);
+        hipLaunchKernelGGL(k_csr_spmm<T>, grid, block, 0, c.stream, c.m, nn, c.row_ptr,
+                           c.col_idx, (const T *)c.vals, Zn, c.ldq, Xn, c.m);
+        return;
+    }
+    const int64_t rows = 256 / L;
+    const dim3 grid((unsigned)((c.m + rows - 1) / rows), (unsigned)((nn + SPMM_LC - 1) / SPMM_LC));
+    const dim3 block(256);
+#define AMGS_SPMM_L(LL)                                                                            \
+    hipLaunchKernelGGL((k_csr_spmm_lanes<T, LL>), grid, block, 0, c.stream, c.m, nn, c.row_ptr,   \
+                       c.col_idx, (const T *)c.vals, Zn, c.ldq, Xn, c.m)
+    switch (L) {
+    case 2: AMGS_SPMM_L(2); break;
+    case 4: AMGS_SPMM_L(4); break;
+    case 8: AMGS_SPMM_L(8); break;
+    case 16: AMGS_SPMM_L(16); break;
+    case 32: AMGS_SPMM_L(32); break;
+    default: AMGS_SPMM_L(64); break;
+    }
+#undef AMGS_SPMM_L
 }
 
 void launch_csr_check(int64_t m, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,
