@@ -483,14 +483,17 @@ def bench_exp2(args, torch, amgs):
     out = {}
     t0 = time.perf_counter()
     for case in (1, 2):
-        rec = {v: [] for v in ("naive", "ha", "hp")}
+        rec = {v: [] for v in ("naive", "ha", "hp", "cgs_naive")}
         for ia, ka in enumerate(grid):
             for iz, kz in enumerate(grid):
                 p = inputs.exp2_problem(100, 20, ka, kz, case, seed=10000 * case + 100 * ia + iz)
                 A = torch.from_numpy(np.ascontiguousarray(p.dense)).to(dev)
                 Zt = torch.from_numpy(np.ascontiguousarray(p.Z)).to(dev)
                 for v in rec:
-                    o = amgs.qr_dense(A, Zt, variant=v)
+                    if v == "cgs_naive":
+                        o = amgs.qr_dense(A, Zt, variant="naive", cgs=True)
+                    else:
+                        o = amgs.qr_dense(A, Zt, variant=v)
                     Q, R = o.Q, o.R
                     G = Q.T @ (A @ Q)
                     loss = float(torch.linalg.matrix_norm(G - torch.eye(20, dtype=G.dtype, device=dev), ord=2))
@@ -506,6 +509,16 @@ def bench_exp2(args, torch, amgs):
                        "median_loss_over_delta1": float(np.median(lo / d1)),
                        "max_loss_over_delta1": float(np.max(lo / d1)),
                        "median_loss_over_delta2": float(np.median(lo / d2))}
+            # least-squares exponents of the loss in kappa(A) and kappa(A^{1/2} Z)
+            # over the problems above rounding level and below saturation
+            fit = [r for r in ok if 1e-13 < r[2] < 1e-2]
+            if len(fit) >= 10:
+                M = np.array([[1.0, np.log10(r[0]), np.log10(r[1])] for r in fit])
+                y = np.array([np.log10(r[2]) for r in fit])
+                coef = np.linalg.lstsq(M, y, rcond=None)[0]
+                summ[v]["fit_exponent_kappa_A"] = round(float(coef[1]), 2)
+                summ[v]["fit_exponent_kappa_A12Z"] = round(float(coef[2]), 2)
+                summ[v]["fit_points"] = len(fit)
         n = len(rec["ha"])
         better = sum(1 for a, b in zip(rec["ha"], rec["naive"]) if a[2] < b[2])
         summ["ha_more_accurate_than_naive"] = f"{better}/{n}"

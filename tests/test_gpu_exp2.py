@@ -12,7 +12,10 @@ eigenvalues.  Checked on a reduced grid of condition numbers:
   naive (Section 4, experiment II);
 * where HP's recurrence cancels so far that a squared A-norm is not
   positive (delta_1 >> 1), the oracle reports a breakdown, and so must the
-  GPU.
+  GPU;
+* the loss of MGS grows linearly in kappa(A^{1/2} Z) and that of classical
+  Gram-Schmidt quadratically (Section 4): the fitted exponents on a
+  kappa(Z) sweep at fixed kappa(A).
 """
 import numpy as np
 import pytest
@@ -68,3 +71,32 @@ def test_exp2_grid(case):
                 loss[v] = g
             if case == 2 and ka >= 1e6 and kz >= 1e6:
                 assert loss["ha"] < 1e-2 * loss["naive"], loss
+
+
+def test_mgs_linear_cgs_quadratic():
+    """kappa(A) = 1e2, kappa(Z) = 1e3 .. 1e6 (case 1): the exponent of the
+    loss in kappa(A^{1/2} Z) is about 1 for MGS-naive and about 2 for
+    CGS-naive, on the GPU and in the oracle alike."""
+    A_k = 1e2
+    rows = {"mgs": [], "cgs": []}
+    for i, kz in enumerate([1e3, 1e4, 1e5, 1e6]):
+        p = inputs.exp2_problem(100, 20, A_k, kz, 1, seed=700 + i)
+        A = torch.from_numpy(np.ascontiguousarray(p.dense)).to(DEV)
+        Zt = torch.from_numpy(np.ascontiguousarray(p.Z)).to(DEV)
+        for key, cgs in (("mgs", False), ("cgs", True)):
+            out = amgs.qr_dense(A, Zt, variant="naive", cgs=cgs)
+            torch.cuda.synchronize()
+            assert int(out.info.item()) == 0
+            Q, R = out.Q.cpu().numpy(), out.R.cpu().numpy()
+            g = ref.orth_loss(Q, dense=p.dense)
+            want = ref.qr_problem(p, variant="naive", orientation="cgs" if cgs else "col")
+            o = ref.orth_loss(want.Q, dense=p.dense)
+            kAZ = np.linalg.cond(R)
+            print(f"[gpu] kZ {kz:.0e} {key}: gpu {g:.2e} oracle {o:.2e} kappa(A^1/2 Z) {kAZ:.2e}",
+                  flush=True)
+            assert g <= max(10 * o, 1e-13)
+            rows[key].append((np.log10(kAZ), np.log10(g)))
+    slope = {k: np.polyfit([r[0] for r in v], [r[1] for r in v], 1)[0] for k, v in rows.items()}
+    print(f"[gpu] fitted exponents {slope}")
+    assert 0.6 < slope["mgs"] < 1.5, slope
+    assert 1.6 < slope["cgs"] < 2.6, slope
