@@ -147,8 +147,12 @@ amgs_status_t amgs_destroy(amgs_handle_t h);
  * passes its own P (= AQ) buffer.  Returns 0 for invalid arguments.  The
  * workspace holds reduction partials, the HP block X, P when not given and,
  * for CSR with the naive and HA variants, a padded copy of up to 8 entries
- * per row of A (8 m (4 + element size) bytes) that the column MV reads; its
- * contents do not need to be preserved between calls. */
+ * per row of A that the column MV reads.  That copy comes last and takes
+ * 8 m (4 + element size) + 4 ceil(m / 512) bytes, each of the three parts
+ * rounded up to a multiple of 256.  A workspace that lacks exactly that room
+ * is still accepted: the column MV then reads the CSR arrays directly
+ * (slower for rows of at most 8 entries, the same results bit for bit).
+ * The contents need not be preserved between calls. */
 size_t amgs_workspace_bytes(amgs_handle_t h, int64_t m, int64_t n, int32_t is_dense,
                             amgs_variant_t v, amgs_precision_t p, int32_t P_given,
                             const amgs_opts_t *o);

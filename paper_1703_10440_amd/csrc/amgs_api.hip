@@ -65,7 +65,9 @@ struct ProfScope {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t part, s_part, rr_part, S, zt, xv, X, P, wpart, lpart, ell_col, ell_val, tile_long, total;
+    size_t part, s_part, rr_part, S, zt, xv, X, P, wpart, lpart, ell_col, ell_val, tile_long;
+    size_t base;    // bytes without the padded copy of A
+    size_t total;   // bytes with it (the size the query reports)
 };
 
 // Row chunks of the panel-schedule sweeps (256 threads of panel_rows rows).
@@ -100,8 +102,10 @@ Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_g
     L.P = P_given ? off : take((size_t)m * n * w);
     L.wpart = panel ? take((size_t)n * PANEL_B * g_p * 8) : off;
     L.lpart = panel ? take((size_t)PANEL_B * PANEL_B * g_p * 8) : off;
-    // padded copy of a CSR A for the column MV (naive and HA; the size does
-    // not depend on nnz, which only decides whether the copy is used)
+    L.base = off;
+    // padded copy of a CSR A for the column MV (naive and HA), last, so that
+    // a smaller workspace can leave it out; the size does not depend on nnz,
+    // which only decides whether the copy is used
     const bool ell = !is_dense && variant != VAR_HP;
     L.ell_col = ell ? take((size_t)ELL_K * m * 4) : off;
     L.ell_val = ell ? take((size_t)ELL_K * m * w) : off;
@@ -472,7 +476,7 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
     const size_t w = p == AMGS_FP64 ? 8 : 4;
     c.geo = make_geo(c.m, c.nnz, c.is_dense);
     Layout L = layout(c.m, c.n, c.geo, (int)v, w, P_given, reorth || cgs, panel, c.is_dense);
-    if (!work || work_bytes < L.total) return AMGS_ERR_WORKSPACE;
+    if (!work || work_bytes < L.base) return AMGS_ERR_WORKSPACE;
     char *base = (char *)work;
     c.sp.part = base + L.part;
     c.sp.g = c.geo.g_rows;
@@ -501,7 +505,7 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
     }
     c.n_rr_mv = c.is_dense ? c.geo.g_dense : c.geo.g_csr;
     c.ell_k = 0;
-    if (!c.is_dense && v != AMGS_HP && c.geo.lanes == 0) {
+    if (!c.is_dense && v != AMGS_HP && c.geo.lanes == 0 && work_bytes >= L.total) {
         // K = the mean row length rounded up (at most ELL_K here); longer
         // rows keep their remaining entries in the CSR arrays
         int64_t k = (c.nnz + c.m - 1) / c.m;

@@ -316,6 +316,43 @@ def test_short_rows_several_tiles_per_workgroup(variant):
     assert eR <= 1e-10 and eQ <= 1e-10 and eP <= 1e-10
 
 
+def _align256(x):
+    return (x + 255) // 256 * 256
+
+
+@pytest.mark.parametrize("panel", [0, 4])
+@pytest.mark.parametrize("variant", ["naive", "ha"])
+def test_workspace_without_padded_copy(variant, panel):
+    """A workspace without room for the padded copy of A is accepted; the
+    column MV then reads CSR directly, in the same stored order, so Q, R and
+    P equal the full-workspace call bit for bit.  One byte less is refused."""
+    for p in (SMALL[0], SMALL[5]):
+        m, n = p.Z.shape
+        rp = torch.from_numpy(p.csr.row_ptr).to(DEV)
+        ci = torch.from_numpy(p.csr.col_idx).to(DEV)
+        va = torch.from_numpy(p.csr.vals).to(DEV)
+        Z = torch.from_numpy(np.ascontiguousarray(p.Z)).to(DEV)
+        h = amgs.handle(0)
+        opts = amgs.Opts(0, panel, 0, 0)
+        full = amgs.amgs_workspace_bytes(h, m, n, 0, amgs.VARIANTS[variant],
+                                         amgs.PRECISIONS["fp64"], 1, opts)   # P passed
+        copy = _align256(8 * m * 4) + _align256(8 * m * 8) + _align256((m + 511) // 512 * 4)
+        base = full - copy
+        print(f"[gpu] workspace {p.name} {variant} panel={panel}: full {full} base {base}",
+              flush=True)
+        ref_out = amgs.qr_csr(rp, ci, va, Z, variant=variant, panel=panel, return_p=True)
+        small = torch.empty(base, dtype=torch.uint8, device=DEV)
+        out = amgs.qr_csr(rp, ci, va, Z, variant=variant, panel=panel, return_p=True, work=small)
+        torch.cuda.synchronize()
+        assert int(out.info.item()) == 0
+        assert torch.equal(out.Q, ref_out.Q) and torch.equal(out.R, ref_out.R)
+        assert torch.equal(out.P, ref_out.P)
+        too_small = torch.empty(base - 1, dtype=torch.uint8, device=DEV)
+        with pytest.raises(amgs.AmgsError):
+            amgs.qr_csr(rp, ci, va, Z, variant=variant, panel=panel, return_p=True,
+                        work=too_small)
+
+
 def test_size_limits():
     """Row counts and entry counts beyond int32 are rejected before any
     memory is touched."""
