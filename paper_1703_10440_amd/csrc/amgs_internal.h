@@ -37,7 +37,7 @@ struct Geo {
     int U2;         // rows per thread of the column / second-pass kernels (<= 4)
     int64_t g_rows2;// their row chunks of 256*U2 rows
     int64_t g_rows1;// 256-row chunks (one row per thread)
-    int lanes;      // lanes per CSR row in the MV kernel (0: 512-row tiles staged in LDS)
+    int lanes;      // lanes per CSR row in the MV kernel (0: a row per thread, through the padded copy)
     int64_t g_csr;  // workgroups of the CSR MV kernel
     int64_t g_dense;// workgroups of the dense MV kernel
 };
