@@ -172,7 +172,7 @@ amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
         launch_sweep<T>(c, j, variant, 0);
         st.kernel_launches++;
         st.sweep_launches++;
-        if (variant == VAR_HP && launch_hp_xblock<T>(c, j)) st.kernel_launches++;
+        if (variant == VAR_HP && launch_hp_xblock<T>(c, j, j + 1)) st.kernel_launches++;
     }
     for (int64_t j = c.first; j < c.n; ++j) {
         int64_t n_rr;
@@ -245,7 +245,7 @@ amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
         st.kernel_launches++;
         if (variant == VAR_HP) {
             ProfScope ps(h, 1, c.stream);
-            if (launch_hp_xblock<T>(c, j)) st.kernel_launches++;
+            if (launch_hp_xblock<T>(c, j, j + 1)) st.kernel_launches++;
         }
         st.sweep_launches++;
         st.sweep_bytes += sweep_bytes(c.m, c.n, j, w, variant);
@@ -262,9 +262,7 @@ double psweep_bytes(int64_t m, size_t w, int64_t ncols, int64_t kw, int64_t bd, 
 {
     const double col = (double)m * (double)w;
     double per_col = kw > 0 ? 2.0 : 1.0;
-    if (variant == VAR_HP && kw > 0) per_col += 2.0;
-    double vec = (variant == VAR_NAIVE ? 3.0 : 4.0) + (double)kw * (variant == VAR_HP ? 2.0 : 1.0)
-               + (double)(bd - 1);
+    double vec = (variant == VAR_NAIVE ? 3.0 : 4.0) + (double)kw + (double)(bd - 1);
     return (double)ncols * per_col * col + vec * col;
 }
 
@@ -295,6 +293,7 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant)
         st.mv_columns += c.n;
         st.mv_bytes += mvA + 2.0 * (double)c.m * c.n * w;
     }
+    static_assert(HP_XB % PANEL_B == 0, "x-block passes fall on panel boundaries");
     const int64_t B = PANEL_B;
     for (int64_t s = 0; s < c.n; s += B) {
         const int64_t e = s + B < c.n ? s + B : c.n;
@@ -307,14 +306,14 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant)
             {
                 ProfScope ps(h, variant == VAR_HP ? 1 : -1, c.stream);
                 if (first_blk) {
-                    launch_pcol_blk<T>(c, variant, j, prev, s);
+                    // HP: the x terms of the previous panel unless an x-block
+                    // pass at s has applied them
+                    launch_pcol_blk<T>(c, variant, j, prev, s, s % HP_XB == 0 ? s : prev);
                     st.kernel_launches++;
                     n_rr = pcol_blk_partials(c);
                 } else if (variant == VAR_HP) {
-                    // the sweeps have applied every recurrence term but j-1
-                    c.x_from = j > 0 ? j - 1 : 0;
+                    // the recurrence terms since the last x-block pass
                     launch_col_hp<T>(c, j, false);
-                    c.x_from = -1;
                     st.kernel_launches++;
                     n_rr = c.geo.g_rows2;
                 }
@@ -377,6 +376,9 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant)
             if (panel_end) {
                 launch_pfin<T>(c, s, e);
                 st.kernel_launches++;
+                // HP: once r_{i,c} of the last HP_XB columns are final, their
+                // recurrence terms go to every x column from e on
+                if (variant == VAR_HP && launch_hp_xblock<T>(c, e, e)) st.kernel_launches++;
             }
         }
     }

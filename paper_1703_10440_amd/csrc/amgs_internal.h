@@ -206,14 +206,15 @@ template <typename T> void launch_reorth_a(const Ctx &c, int64_t j);
 void launch_reorth_fin(const Ctx &c, int64_t j);
 template <typename T> void launch_reorth_b(const Ctx &c, int64_t j, bool hp);
 template <typename T> void launch_sweep(const Ctx &c, int64_t j, int variant, int64_t n_rr);
-template <typename T> bool launch_hp_xblock(const Ctx &c, int64_t s);
+template <typename T> bool launch_hp_xblock(const Ctx &c, int64_t s, int64_t c_from);
 template <typename T> void launch_publish(const Ctx &c, int64_t jrow);
 template <typename T> void launch_csr_spmm(const Ctx &c);
 template <typename T> void launch_dense_gemm(const Ctx &c);
 template <typename T> void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
                                          int64_t d0, int64_t l0, int64_t c0, int64_t c1, int64_t n_rr);
 template <typename T> void launch_pfin(const Ctx &c, int64_t s, int64_t e);
-template <typename T> void launch_pcol_blk(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1);
+template <typename T> void launch_pcol_blk(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
+                                            int64_t xk0);
 int64_t pcol_blk_partials(const Ctx &c);
 int panel_rows_for(int fp64);
 void launch_csr_check(int64_t m, int64_t nnz, const int32_t *row_ptr, const int32_t *col_idx,

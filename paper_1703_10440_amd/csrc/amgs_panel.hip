@@ -12,9 +12,12 @@
 // coefficients as the column algorithm in exact arithmetic, obtained with one
 // pass over the later columns per panel instead of one per column.
 //
-// For HP the x columns follow the z columns: wherever z_c -= r_ic q_i is
-// applied, x_c -= r_ic p_i is applied with the same coefficient, so every x_c
-// receives the terms of eq. (5) once each in ascending i.
+// For HP the sweeps leave the x columns alone.  The recurrence of eq. (5)
+// is applied as in the column schedule: after every second panel (once the
+// coefficients are final) k_hp_xblock applies the last HP_XB terms to every
+// later x column, and the column kernels add the terms since then, so each
+// x_c receives every term once, in ascending i.  The x columns are streamed
+// once per HP_XB columns instead of once per panel.
 #include <hip/hip_ext.h>
 
 #include "amgs_device.h"
@@ -23,7 +26,7 @@
 namespace amgs {
 
 // Rows per thread of the panel kernels: each thread holds, per row, the
-// pending q_k (and p_k for HP) and the dot vectors p_d in registers.
+// pending q_k and the dot vectors p_d in registers.
 template <typename T>
 constexpr int panel_rows() { return sizeof(T) == 8 ? 2 : 4; }
 
@@ -37,7 +40,6 @@ template <typename T, int U, int VAR, bool NTS, int DB>
 __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
 {
     constexpr int KB = PANEL_B;
-    constexpr bool HPX = VAR == VAR_HP;
     constexpr int DL = DB > 1 ? DB - 1 : 1;
     static_assert(DB == 1 || DB == 4, "block dots are reduced four at a time");
     __shared__ T red[256 / WAVE][PS_MAXC * DB];
@@ -56,7 +58,7 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
     const T *__restrict__ zsrc = VAR == VAR_HP ? Q + j * a.ldq : (const T *)a.zt;
     const T *__restrict__ xsrc = VAR == VAR_HP ? (const T *)X + j * a.ldx : (const T *)a.xv;
     // every vector load is issued before waiting for r_jj
-    T xs[U], zs[U], qk[KB][U], pk[HPX ? KB : 1][U], pd[DL][U];
+    T xs[U], zs[U], qk[KB][U], pd[DL][U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
@@ -64,10 +66,7 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
         xs[u] = in ? (VAR == VAR_NAIVE ? P[k + j * a.ldp] : xsrc[k]) : (T)0;
         zs[u] = (in && own) ? zsrc[k] : (T)0;
 #pragma unroll
-        for (int t = 0; t < KB; ++t) {
-            qk[t][u] = (in && t < kw) ? Q[k + (a.k0 + t) * a.ldq] : (T)0;
-            if (HPX) pk[t][u] = (in && t < kw) ? P[k + (a.k0 + t) * a.ldp] : (T)0;
-        }
+        for (int t = 0; t < KB; ++t) qk[t][u] = (in && t < kw) ? Q[k + (a.k0 + t) * a.ldq] : (T)0;
 #pragma unroll
         for (int t = 0; t < DL; ++t) pd[t][u] = (in && t < bd - 1) ? P[k + (a.d0 + t) * a.ldp] : (T)0;
     }
@@ -85,7 +84,7 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
     const int64_t c1 = (c0 + a.cpw < a.c1) ? c0 + a.cpw : a.c1;
     const bool full_rows = row0 + 256 * U <= m;
     // the first group of later columns is requested before waiting for r_jj
-    T zv[PS_CB][U], xv[HPX ? PS_CB : 1][U];
+    T zv[PS_CB][U];
     auto load_group = [&](int64_t cb) {
 #pragma unroll
         for (int t = 0; t < PS_CB; ++t) {
@@ -94,7 +93,6 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
                 const int64_t k = row0 + u * 256 + tid;
                 const bool in = cb + t < c1 && (full_rows || k < m);
                 zv[t][u] = in ? ld_stream<NTS>(Q + (cb + t) * a.ldq + k) : (T)0;
-                if (HPX) xv[t][u] = (in && kw > 0) ? ld_stream<NTS>(X + (cb + t) * a.ldx + k) : (T)0;
             }
         }
     };
@@ -144,13 +142,6 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
                     for (int i = 0; i < KB; ++i)
                         if (i < kw) z = upd(z, rc[i], qk[i][u]);
                     st_stream<NTS>(Q + (cb + t) * a.ldq + k, z);
-                    if (HPX) {
-                        T x = xv[t][u];
-#pragma unroll
-                        for (int i = 0; i < KB; ++i)
-                            if (i < kw) x = upd(x, rc[i], pk[i][u]);
-                        st_stream<NTS>(X + (cb + t) * a.ldx + k, x);
-                    }
                 }
 #pragma unroll
                 for (int d = 0; d < DB; ++d) {
@@ -260,8 +251,9 @@ __global__ __launch_bounds__(256) void k_pfin(int64_t s, int64_t e, const T *__r
 
 // First column j of a panel: z_j -= sum_k r_kj q_k over the previous panel
 // [k0, k1) (coefficients final in R, ascending k); for HP also
-// x_j -= sum_k r_kj p_k, both in place, and the partial of z_j^T x_j.  For
-// naive / HA the corrected z_j goes to zt, from where the column MV reads it.
+// x_j -= sum_k r_kj p_k for the terms k >= a.x_from that no x-block pass has
+// applied, both in place, and the partial of z_j^T x_j.  For naive / HA the
+// corrected z_j goes to zt, from where the column MV reads it.
 template <typename T, int U, int VAR>
 __global__ __launch_bounds__(256) void k_pcol_blk(RowArgs a, int64_t k0, int64_t k1)
 {
@@ -290,7 +282,7 @@ __global__ __launch_bounds__(256) void k_pcol_blk(RowArgs a, int64_t k0, int64_t
 #pragma unroll
         for (int i = 0; i < KB; ++i) {
             qv[i][u] = (in && i < kw) ? Q[k + (k0 + i) * a.ldq] : (T)0;
-            if (HP) pv[i][u] = (in && i < kw) ? P[k + (k0 + i) * a.ldp] : (T)0;
+            if (HP) pv[i][u] = (in && i < kw && k0 + i >= a.x_from) ? P[k + (k0 + i) * a.ldp] : (T)0;
         }
     }
     double acc = 0.0;
@@ -302,7 +294,7 @@ __global__ __launch_bounds__(256) void k_pcol_blk(RowArgs a, int64_t k0, int64_t
         for (int i = 0; i < KB; ++i) {
             if (i < kw) {
                 z[u] = upd(z[u], r[i], qv[i][u]);
-                if (HP) x[u] = upd(x[u], r[i], pv[i][u]);
+                if (HP && k0 + i >= a.x_from) x[u] = upd(x[u], r[i], pv[i][u]);
             }
         }
         if (HP) {
@@ -387,12 +379,12 @@ void launch_pfin(const Ctx &c, int64_t s, int64_t e)
 int64_t pcol_blk_partials(const Ctx &c) { return c.geo.g_rows2; }
 
 template <typename T>
-void launch_pcol_blk(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1)
+void launch_pcol_blk(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1, int64_t xk0)
 {
     RowArgs a{};
     a.m = c.m; a.n = c.n; a.j = j; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp;
     a.X = c.X; a.ldx = c.m; a.zt = c.zt; a.R = c.R; a.ldr = c.ldr; a.info = c.info;
-    a.sp = c.sp; a.rr_out = c.rr_part; a.x_from = -1;
+    a.sp = c.sp; a.rr_out = c.rr_part; a.x_from = xk0;
     const dim3 grid((unsigned)c.geo.g_rows2), block(256);
 #define AMGS_PCB(V_)                                                                              \
     switch (c.geo.U2) {                                                                           \
@@ -411,8 +403,8 @@ template void launch_psweep<float>(const Ctx &, int, int64_t, int64_t, int64_t, 
                                    int64_t, int64_t, int64_t);
 template void launch_pfin<double>(const Ctx &, int64_t, int64_t);
 template void launch_pfin<float>(const Ctx &, int64_t, int64_t);
-template void launch_pcol_blk<double>(const Ctx &, int, int64_t, int64_t, int64_t);
-template void launch_pcol_blk<float>(const Ctx &, int, int64_t, int64_t, int64_t);
+template void launch_pcol_blk<double>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t);
+template void launch_pcol_blk<float>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t);
 
 int panel_rows_for(int fp64) { return fp64 ? panel_rows<double>() : panel_rows<float>(); }
 

@@ -1233,9 +1233,10 @@ void launch_sweep(const Ctx &c, int64_t j, int variant, int64_t n_rr)
 }
 
 template <typename T>
-bool launch_hp_xblock(const Ctx &c, int64_t s)
+bool launch_hp_xblock(const Ctx &c, int64_t s, int64_t c_from)
 {
-    const int64_t c_lo = s + 1 > c.first ? s + 1 : c.first;
+    // terms [s - HP_XB, s) on the columns c >= c_from (and >= first)
+    const int64_t c_lo = c_from > c.first ? c_from : c.first;
     if (s < HP_XB || s % HP_XB != 0 || c_lo >= c.n) return false;
     const int64_t ncols = c.n - c_lo;
     const int64_t gx = (c.m + 255) / 256;
@@ -1311,8 +1312,8 @@ template void launch_reorth_b<double>(const Ctx &, int64_t, bool);
 template void launch_reorth_b<float>(const Ctx &, int64_t, bool);
 template void launch_sweep<double>(const Ctx &, int64_t, int, int64_t);
 template void launch_sweep<float>(const Ctx &, int64_t, int, int64_t);
-template bool launch_hp_xblock<double>(const Ctx &, int64_t);
-template bool launch_hp_xblock<float>(const Ctx &, int64_t);
+template bool launch_hp_xblock<double>(const Ctx &, int64_t, int64_t);
+template bool launch_hp_xblock<float>(const Ctx &, int64_t, int64_t);
 template void launch_csr_spmm<double>(const Ctx &);
 template void launch_csr_spmm<float>(const Ctx &);
 
