@@ -316,6 +316,21 @@ def test_short_rows_several_tiles_per_workgroup(variant):
     assert eR <= 1e-10 and eQ <= 1e-10 and eP <= 1e-10
 
 
+@pytest.mark.parametrize("per_row", [10, 20, 40, 80, 150, 300, 500])
+def test_hp_block_product_lane_widths(per_row):
+    """HP's block product X = AZ for CSR picks a thread per row (mean row
+    length <= 12) or L = 2 .. 64 lanes per row from the mean row length, and
+    takes Z in groups of 8 columns: every lane width, n = 11 (a ragged last
+    group), against the oracle."""
+    p = inputs.random_csr_problem(1500, 11, per_row, seed=30 + per_row)
+    want = ref.qr_problem(p, variant="hp")
+    Q, R, P, info, _ = gpu_run(p, "hp")
+    assert info == 0 and want.info == 0
+    eR, eQ, eP = _rel(R, want.R), _rel(Q, want.Q), _rel(P, want.P)
+    print(f"  mean row length {p.csr.nnz / p.m:.1f}: R {eR:.2e} Q {eQ:.2e} P {eP:.2e}")
+    assert eR <= 1e-10 and eQ <= 1e-10 and eP <= 1e-10
+
+
 def _align256(x):
     return (x + 255) // 256 * 256
 
