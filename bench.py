@@ -228,6 +228,36 @@ def cpu_baseline(prob, variant, budget_s=10.0):
             "sample": f"full workload, {variant} binary64, {runs} run(s) in {total:.1f} s"}
 
 
+def cpu_baseline_one_thread(workload, variant, budget_s=5.0):
+    """The same oracle on one host thread (the paper timed one core), in a
+    child process so that OpenMP starts with one thread; the child builds the
+    workload itself and never touches the GPU."""
+    import subprocess
+    code = (
+        "import json, sys, time\n"
+        f"sys.path.insert(0, {ROOT!r})\n"
+        "from oracle import ref\n"
+        "from paper_1703_10440_amd import inputs\n"
+        f"p = inputs.WORKLOADS[{workload!r}]()\n"
+        "runs, total = 0, 0.0\n"
+        f"while total < {budget_s} and runs < 1000:\n"
+        "    t0 = time.perf_counter()\n"
+        f"    r = ref.qr_problem(p, variant={variant!r})\n"
+        "    total += time.perf_counter() - t0\n"
+        "    runs += 1\n"
+        "    assert r.info == 0\n"
+        "print(json.dumps({'runs': runs, 'total': total, 'n': p.n, 'threads': ref.num_threads()}))\n")
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True,
+                       timeout=600)
+    if r.returncode != 0:
+        return None
+    d = json.loads(r.stdout.strip().splitlines()[-1])
+    return {"value": round(d["runs"] * d["n"] / d["total"], 2), "unit": "cols/s",
+            "cores": d["threads"], "kind": "oracle",
+            "sample": f"full workload, {variant} binary64, {d['runs']} run(s) in {d['total']:.1f} s"}
+
+
 # -------------------------------------------------------------- single problem
 def bench_single(args, torch, amgs):
     dev = torch.device("cuda:0")
@@ -292,6 +322,10 @@ def bench_single(args, torch, amgs):
         log("[bench] timing the CPU oracle")
         cpu = cpu_baseline(prob, head_v, args.cpu_budget)
         log(f"[bench] cpu {cpu}")
+    cpu1 = None
+    if not args.no_cpu and args.workload in ("lap64_n64", "dense512_n32"):
+        cpu1 = cpu_baseline_one_thread(args.workload, head_v)
+        log(f"[bench] cpu, one thread {cpu1}")
     cfg = {"workload": args.workload, "m": prob.m, "n": prob.n,
            "A": "csr" if prob.csr is not None else "dense", "nnz": int(big),
            "variant": head_v, "precision": head_p, "reorth": bool(args.reorth),
@@ -303,6 +337,8 @@ def bench_single(args, torch, amgs):
             "roofline": roof, "mv_roofline": mvroof, "cpu_baseline": cpu, "variants": variants}
     if gemmroof is not None:
         line["gemm_roofline"] = gemmroof
+    if cpu1 is not None:
+        line["cpu_baseline_one_thread"] = cpu1
     return line
 
 
