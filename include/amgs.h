@@ -170,7 +170,7 @@ amgs_status_t amgs_qr_csr(amgs_handle_t h, int64_t m, int64_t nnz, const int32_t
                           size_t work_bytes, int32_t *info, void *stream);
 
 /* Same for a dense symmetric A (column-major, lda >= m); the block product
- * X = A Z of HP (Alg. 6, first line) runs on the matrix cores. */
+ * X = A Z of HP (Alg. 6) runs on the matrix cores. */
 amgs_status_t amgs_qr_dense(amgs_handle_t h, int64_t m, const void *A, int64_t lda, int64_t n,
                             const void *Z, int64_t ldz, void *Q, int64_t ldq, double *R,
                             int64_t ldr, void *P, int64_t ldp, amgs_variant_t v,

@@ -261,7 +261,7 @@ static int qr_col(const ref_op *A, int64_t m, int64_t n, int64_t first, double *
                   int reorth, int prec, int64_t *mv_calls, int64_t *mv_cols)
 {
     double *x = (double *)malloc((size_t)m * sizeof(double));
-    if (variant == REF_HP) {            /* Alg. 6 first line: X = A Z, one block MV */
+    if (variant == REF_HP) {            /* Alg. 6: X = A Z, one block MV */
         for (int64_t j = first; j < n; ++j) mv_st(A, Q + j * ldq, X + j * m, prec);
         *mv_calls += 1; *mv_cols += n - first;
     }

@@ -1,5 +1,5 @@
 // amgs_gemm.hip -- the HP block product X = A Z for dense A on the matrix
-// cores (Alg. 6, first line: the n MV of the method issued as one
+// cores (Alg. 6: the n MV of the method issued as one
 // matrix-matrix product, which Section 2.3 expects to run much faster than
 // n sequential MV).
 //

@@ -856,7 +856,7 @@ __global__ __launch_bounds__(256) void k_hp_xblock(int64_t m, int64_t n, int64_t
 }
 
 // ------------------------------------------------- HP block product, CSR
-// X = A Z for all n columns (Alg. 6, first line).  Thread per row; the
+// X = A Z for all n columns (the block product of Alg. 6).  Thread per row; the
 // row's entries are read once: rows of at most eight entries keep their
 // indices and values in registers for every column, longer rows are taken
 // eight entries at a time per group of columns (those re-reads stay in the
