@@ -45,7 +45,9 @@
  * L_ik = p_i^T q_k (k < i, both inside the panel), r_ic = W_i -
  * sum_{k<i} L_ik r_kc (forward substitution, binary64), then z_c -= r_ic q_i
  * for i ascending (HP: also x_c -= r_ic p_i).  In exact arithmetic this is
- * the column algorithm, since z_c^{(i-1)} = z_c - sum_{k<i} r_kc q_k.
+ * the column algorithm, since z_c^{(i-1)} = z_c - sum_{k<i} r_kc q_k.  The
+ * optional second pass below runs on column j at the same point as in the
+ * column form (after its projections, before its MV).
  *
  * Orientation 3 is classical Gram-Schmidt with the same three variants
  * (Section 2: the n-MV idea applied to CGS; Section 3, analysis of CGS):
@@ -350,8 +352,8 @@ static int qr_row(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq,
 
 /* Panel schedule (orientation 2): see the header comment. */
 static int qr_panel(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq, double *R,
-                    int64_t ldr, double *P, int64_t ldp, double *X, int variant, int prec,
-                    int64_t *mv_calls, int64_t *mv_cols)
+                    int64_t ldr, double *P, int64_t ldp, double *X, int variant, int reorth,
+                    int prec, int64_t *mv_calls, int64_t *mv_cols)
 {
     double *x = (double *)malloc((size_t)m * sizeof(double));
     if (variant == REF_HP) {
@@ -369,11 +371,16 @@ static int qr_panel(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ld
                 Rc[i] = dot_st(P + i * ldp, z, m, prec);
                 axpy_st(z, Rc[i], Q + i * ldq, m, prec);
             }
+            double *xr = NULL;
             if (variant == REF_HP) {
                 /* X[:, j] already holds the terms of the earlier panels */
                 memcpy(x, X + j * m, (size_t)m * sizeof(double));
                 for (int64_t i = s; i < j; ++i) axpy_st(x, st(Rc[i], prec), P + i * ldp, m, prec);
-            } else {
+                xr = x;
+            }
+            /* the optional second pass, at the same point as in the column form */
+            if (reorth) reorth_pass(z, xr, j, Q, ldq, P, ldp, Rc, m, prec);
+            if (variant != REF_HP) {
                 mv_st(A, z, x, prec);
                 *mv_calls += 1; *mv_cols += 1;
             }
@@ -463,7 +470,6 @@ static int run(const ref_op *A, int64_t n, int64_t first, const double *Z, int64
     int64_t m = A->m;
     if (m < 0 || n < 0 || n > m || ldz < m || ldq < m || ldr < n) return -1;
     if (variant < 0 || variant > 2 || orientation < 0 || orientation > 3) return -1;
-    if (orientation == REF_PANEL && reorth) return -1;
     if (prec < 0 || prec > 1) return -1;
     /* successive orthogonalisation: columns before first are final in Q, P
      * and R (column and classical forms only) */
@@ -486,7 +492,7 @@ static int run(const ref_op *A, int64_t n, int64_t first, const double *Z, int64
         : orientation == REF_ROW
         ? qr_row(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols)
         : orientation == REF_PANEL
-        ? qr_panel(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, prec, &calls, &cols)
+        ? qr_panel(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols)
         : qr_cgs(A, m, n, first, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols);
     if (stats) { stats[0] = calls; stats[1] = cols; }
     free(X);

@@ -391,6 +391,32 @@ def pin_panel(lib) -> list:
         lp = ref.orth_loss(r.Q, dense=p.dense)
         if r.info != 0 or not (lp <= 30 * lc and lp <= 10 * d1):
             fails.append(f"panel exp2 {v}: loss {lp} (column {lc}, 10 delta1 {10 * d1})")
+    # with the second pass: the closed forms, one panel equal to the column
+    # form bit for bit, and the pass restoring orthogonality in the binary32
+    # form on an ill-conditioned problem
+    for p in (inputs.random_dense_problem(60, 9, 13), inputs.random_csr_problem(300, 14, 9, 13)):
+        Ad = p.dense if p.dense is not None else p.csr.to_dense()
+        Rc = _chol_R(p.Z, Ad)
+        for v in VARIANTS:
+            r = ref.qr(p.Z, dense=p.dense, csr=p.csr, variant=v, orientation="panel", reorth=True,
+                       lib=lib)
+            e, eq = _rel(np.triu(r.R), Rc), _rel(r.Q, np.linalg.solve(Rc.T, p.Z.T).T)
+            if r.info != 0 or not (e <= 1e-13 and eq <= 1e-12):
+                fails.append(f"panel reorth chol {p.name} {v}: R {e} Q {eq} info {r.info}")
+    p = inputs.random_dense_problem(40, 4, 5)
+    for v in VARIANTS:
+        a = ref.qr(p.Z, dense=p.dense, variant=v, reorth=True, lib=lib)
+        b = ref.qr(p.Z, dense=p.dense, variant=v, orientation="panel", reorth=True, lib=lib)
+        if not (np.array_equal(a.R, b.R) and np.array_equal(a.Q, b.Q)):
+            fails.append(f"panel reorth single panel {v}: differs from the column algorithm")
+    q = inputs.laplacian_graded_problem(N=10, n=12, decades=4.0, seed=3)
+    for v in ("naive", "ha"):
+        o0 = ref.orth_loss(ref.qr_problem(q, variant=v, orientation="panel", precision="fp32",
+                                          lib=lib).Q, csr=q.csr)
+        o1 = ref.orth_loss(ref.qr_problem(q, variant=v, orientation="panel", precision="fp32",
+                                          reorth=True, lib=lib).Q, csr=q.csr)
+        if not o1 < 1e-2 * o0:
+            fails.append(f"panel reorth binary32 orthogonality {v}: {o0} -> {o1}")
     return fails
 
 
