@@ -284,7 +284,7 @@ def bench_single(args, torch, amgs):
     variants = {}
     if not args.no_variants:
         combos = [(v, p, False, 0, False) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
-        combos += [(v, "fp32", True, 0, False) for v in ("ha", "hp")]
+        combos += [(v, "fp32", True, pan, False) for pan in (0, 4) for v in ("ha", "hp")]
         combos += [(v, p, False, 4, False) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
         combos += [(v, "fp64", ro, 0, True) for ro in (False, True) for v in ("naive", "ha", "hp")]
         for v, p, ro, pan, cgs in combos:

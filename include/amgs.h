@@ -82,7 +82,9 @@ typedef enum {
 typedef struct amgs_handle *amgs_handle_t;
 
 /* Per-call options; passing NULL means all zero.
- *   reorth  1: second (reorthogonalisation) pass per column (see above).
+ *   reorth  1: second (reorthogonalisation) pass per column (see above),
+ *           in either schedule: it runs on column j after the column's
+ *           projections and before its MV.
  *   panel   0: the column algorithm's own order of operations (default).
  *           4: panel schedule.  Columns are taken in panels of four; inside
  *           a panel every step is the column algorithm's.  The effect of a
@@ -91,12 +93,13 @@ typedef struct amgs_handle *amgs_handle_t;
  *           L = strict_lower(P_I^T Q_I), the coefficients r_{I,c} solve
  *           (I + L) r_{I,c} = W by forward substitution, which in exact
  *           arithmetic are the modified Gram-Schmidt coefficients
- *           r_ic = p_i^T z_c^{(i-1)}; then z_c -= Q_I r_{I,c} (and for HP
- *           x_c -= P_I r_{I,c}, the terms of eq. (5) in ascending i).  Each
- *           later column is then read and written once per panel instead of
- *           once per column.  Rounding differs from the column order;
+ *           r_ic = p_i^T z_c^{(i-1)}; then z_c -= Q_I r_{I,c}.  For HP the
+ *           terms of eq. (5) reach each x_c in ascending i, every 8 columns
+ *           as a block and the rest in the column step.  Each later column
+ *           is then read and written once per panel instead of once per
+ *           column.  Rounding differs from the column order;
  *           A-orthogonality stays at the level of the column algorithm.
- *           Not combined with reorth or cgs (AMGS_ERR_UNSUPPORTED); other
+ *           Not combined with cgs or first (AMGS_ERR_UNSUPPORTED); other
  *           values are AMGS_ERR_ARG.
  *   cgs     0: modified Gram-Schmidt (Algs. 3/5/6, default).
  *           1: classical Gram-Schmidt with the same variants (Section 2, the

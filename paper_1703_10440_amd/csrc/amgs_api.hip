@@ -131,7 +131,7 @@ double sweep_bytes(int64_t m, int64_t n, int64_t j, size_t w, int variant)
 }
 
 template <typename T>
-amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant);
+amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth);
 
 template <typename T>
 amgs_status_t run_cgs(amgs_handle *h, Ctx &c, int variant, int reorth);
@@ -139,7 +139,7 @@ amgs_status_t run_cgs(amgs_handle *h, Ctx &c, int variant, int reorth);
 template <typename T>
 amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
 {
-    if (c.panel) return run_panel<T>(h, c, variant);
+    if (c.panel) return run_panel<T>(h, c, variant, reorth);
     if (c.cgs) return run_cgs<T>(h, c, variant, reorth);
     const size_t w = sizeof(T);
     amgs_stats_t &st = h->stats;
@@ -271,7 +271,7 @@ double psweep_bytes(int64_t m, size_t w, int64_t ncols, int64_t kw, int64_t bd, 
 // previous panel to every later column and forms the dots with this panel's
 // p vectors, and k_pfin turns them into the coefficients r_{I,c}.
 template <typename T>
-amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant)
+amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
 {
     const size_t w = sizeof(T);
     amgs_stats_t &st = h->stats;
@@ -305,17 +305,46 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant)
             c.n_pub = e;
             {
                 ProfScope ps(h, variant == VAR_HP ? 1 : -1, c.stream);
+                // the optional second pass runs on column j after its
+                // projections, before its MV, as in the column schedule
+                const bool ro = reorth && j > 0;
                 if (first_blk) {
                     // HP: the x terms of the previous panel unless an x-block
                     // pass at s has applied them
                     launch_pcol_blk<T>(c, variant, j, prev, s, s % HP_XB == 0 ? s : prev);
                     st.kernel_launches++;
                     n_rr = pcol_blk_partials(c);
+                    if (ro) {
+                        // the block-corrected z_j is in zt (naive, HA) or in
+                        // Q (HP), with no single pending term left
+                        c.no_pend = 1;
+                        c.z_in_zt = variant == VAR_HP ? 0 : 1;
+                        launch_reorth_a<T>(c, j);
+                        c.no_pend = 0;
+                        c.z_in_zt = 0;
+                        launch_reorth_fin(c, j);
+                        launch_reorth_b<T>(c, j, variant == VAR_HP);
+                        st.kernel_launches += 3;
+                        n_rr = c.geo.g_rows1;   // A-norm partials of k_reorth_b (HP)
+                    }
                 } else if (variant == VAR_HP) {
                     // the recurrence terms since the last x-block pass
-                    launch_col_hp<T>(c, j, false);
-                    st.kernel_launches++;
-                    n_rr = c.geo.g_rows2;
+                    if (ro) {
+                        launch_col_hp<T>(c, j, true);
+                        launch_reorth_fin(c, j);
+                        launch_reorth_b<T>(c, j, true);
+                        st.kernel_launches += 3;
+                        n_rr = c.geo.g_rows1;
+                    } else {
+                        launch_col_hp<T>(c, j, false);
+                        st.kernel_launches++;
+                        n_rr = c.geo.g_rows2;
+                    }
+                } else if (ro) {
+                    launch_reorth_a<T>(c, j);
+                    launch_reorth_fin(c, j);
+                    launch_reorth_b<T>(c, j, false);
+                    st.kernel_launches += 3;
                 }
                 if (variant != VAR_HP) {
                     hipEvent_t m0 = nullptr, m1 = nullptr;
@@ -325,13 +354,13 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant)
                     }
                     c.ev_start = m0;
                     c.ev_stop = m1;
-                    launch_mv<T>(c, j, first_blk ? SRC_VEC : SRC_UPD);
+                    launch_mv<T>(c, j, (first_blk || ro) ? SRC_VEC : SRC_UPD);
                     c.ev_start = c.ev_stop = nullptr;
                     if (m0 && m1) h->recs.push_back({1, m0, m1});
                     st.kernel_launches++;
                     st.mv_calls += 1;
                     st.mv_columns += 1;
-                    st.mv_bytes += mvA + (first_blk ? 2.0 : (j > 0 ? 4.0 : 3.0)) * (double)c.m * w;
+                    st.mv_bytes += mvA + ((first_blk || ro) ? 2.0 : (j > 0 ? 4.0 : 3.0)) * (double)c.m * w;
                     if (variant == VAR_NAIVE) {
                         launch_mv<T>(c, j, SRC_DIV);
                         st.kernel_launches++;
@@ -473,7 +502,7 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
     if (cgs != 0 && cgs != 1) return AMGS_ERR_ARG;
     if (first < 0 || first > c.n) return AMGS_ERR_ARG;
     if (first > 0 && !P_given) return AMGS_ERR_ARG;   // p_i of the final columns are needed
-    if (panel && (reorth || cgs || first)) return AMGS_ERR_UNSUPPORTED;
+    if (panel && (cgs || first)) return AMGS_ERR_UNSUPPORTED;
     if (first == c.n) return AMGS_OK;
     const size_t w = p == AMGS_FP64 ? 8 : 4;
     c.geo = make_geo(c.m, c.nnz, c.is_dense);

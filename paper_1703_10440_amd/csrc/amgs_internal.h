@@ -185,6 +185,7 @@ struct Ctx {
     int cgs;          // classical Gram-Schmidt (no pending MGS update in k_reorth_a)
     int64_t first;    // columns [0, first) are already final (successive orthogonalisation)
     int z_in_zt;      // k_reorth_a reads z_j from zt
+    int no_pend;      // k_reorth_a: column j has no single pending update (first column of a panel)
     // padded copy of a CSR A for the column MV (ell_k = 0: not used)
     int32_t *ell_col;
     void *ell_val;

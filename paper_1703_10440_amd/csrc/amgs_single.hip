@@ -1117,7 +1117,7 @@ static RowArgs row_args(const Ctx &c, int64_t j)
 {
     RowArgs a{};
     a.m = c.m; a.n = c.n_pub; a.j = j; a.x_from = c.x_from;
-    a.pend = c.cgs ? 0 : 1;
+    a.pend = (c.cgs || c.no_pend) ? 0 : 1;
     a.z_in_zt = c.z_in_zt; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp;
     a.X = c.X; a.ldx = c.m; a.zt = c.zt; a.R = c.R; a.ldr = c.ldr; a.info = c.info;
     a.sp = c.sp; a.rr_out = c.rr_part; a.s_part = c.s_part; a.S = c.S;

@@ -33,25 +33,27 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb else 1.0))
 
 
-def gpu_run(prob, variant, precision="fp64", panel=PANEL):
+def gpu_run(prob, variant, precision="fp64", panel=PANEL, reorth=False):
     Zt = torch.from_numpy(np.ascontiguousarray(prob.Z)).to(DEV)
-    print(f"[gpu] panel={panel} {prob.name} m={prob.m} n={prob.n} {variant} {precision}",
-          flush=True)
+    print(f"[gpu] panel={panel} {prob.name} m={prob.m} n={prob.n} {variant} {precision} "
+          f"reorth={reorth}", flush=True)
     if prob.csr is not None:
         out = amgs.qr_csr(torch.from_numpy(prob.csr.row_ptr).to(DEV),
                           torch.from_numpy(prob.csr.col_idx).to(DEV),
                           torch.from_numpy(prob.csr.vals).to(DEV), Zt, variant=variant,
-                          precision=precision, return_p=True, panel=panel)
+                          precision=precision, return_p=True, panel=panel, reorth=reorth)
     else:
         out = amgs.qr_dense(torch.from_numpy(np.ascontiguousarray(prob.dense)).to(DEV), Zt,
-                            variant=variant, precision=precision, return_p=True, panel=panel)
+                            variant=variant, precision=precision, return_p=True, panel=panel,
+                            reorth=reorth)
     torch.cuda.synchronize()
     return (out.Q.double().cpu().numpy(), out.R.cpu().numpy(), out.P.double().cpu().numpy(),
             int(out.info.item()), out.stats)
 
 
-def oracle(prob, variant, precision="fp64"):
-    return ref.qr_problem(prob, variant=variant, orientation="panel", precision=precision)
+def oracle(prob, variant, precision="fp64", reorth=False):
+    return ref.qr_problem(prob, variant=variant, orientation="panel", precision=precision,
+                          reorth=reorth)
 
 
 def orth(prob, Q):
@@ -71,12 +73,13 @@ def small_problems():
 SMALL = small_problems()
 
 
+@pytest.mark.parametrize("reorth", [False, True])
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("pi", range(len(SMALL)), ids=[p.name for p in SMALL])
-def test_panel_fp64_parity(pi, variant):
+def test_panel_fp64_parity(pi, variant, reorth):
     p = SMALL[pi]
-    want = oracle(p, variant)
-    Q, R, P, info, st = gpu_run(p, variant)
+    want = oracle(p, variant, reorth=reorth)
+    Q, R, P, info, st = gpu_run(p, variant, reorth=reorth)
     assert info == 0 and want.info == 0
     eR, eQ, eP = _rel(R, want.R), _rel(Q, want.Q), _rel(P, want.P)
     print(f"  R {eR:.2e} Q {eQ:.2e} P {eP:.2e} |Q^TAQ-I| {orth(p, Q):.2e}")
@@ -85,12 +88,13 @@ def test_panel_fp64_parity(pi, variant):
     assert st.mv_calls == {"naive": 2 * p.n, "ha": p.n, "hp": 1}[variant]
 
 
+@pytest.mark.parametrize("reorth", [False, True])
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_panel_graded_ill_conditioned(variant):
+def test_panel_graded_ill_conditioned(variant, reorth):
     """kappa(Z) ~ 1e6, 6 panels: residual and orthogonality at the oracle's level."""
     p = inputs.laplacian_graded_problem(N=16, n=24, decades=6.0, seed=11)
-    want = oracle(p, variant)
-    Q, R, P, info, _ = gpu_run(p, variant)
+    want = oracle(p, variant, reorth=reorth)
+    Q, R, P, info, _ = gpu_run(p, variant, reorth=reorth)
     assert info == 0
     res_g, res_o = ref.residual(p.Z, Q, R), ref.residual(p.Z, want.Q, want.R)
     o_g, o_o = orth(p, Q), orth(p, want.Q)
@@ -99,9 +103,10 @@ def test_panel_graded_ill_conditioned(variant):
     assert o_g <= max(1e-13, 10 * o_o)
 
 
+@pytest.mark.parametrize("reorth", [False, True])
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("pi", [0, 1, 3], ids=[SMALL[i].name for i in (0, 1, 3)])
-def test_panel_fp32_form(pi, variant):
+def test_panel_fp32_form(pi, variant, reorth):
     p = SMALL[pi]
     Z32 = np.asfortranarray(p.Z.astype(np.float32).astype(np.float64))
     if p.csr is not None:
@@ -110,9 +115,9 @@ def test_panel_fp32_form(pi, variant):
     else:
         p32 = inputs.Problem(p.name, Z32, dense=np.asfortranarray(
             p.dense.astype(np.float32).astype(np.float64)))
-    want32 = oracle(p32, variant, "fp32")
+    want32 = oracle(p32, variant, "fp32", reorth=reorth)
     kappa = np.linalg.cond(oracle(p32, variant).R)
-    Q, R, P, info, _ = gpu_run(p32, variant, precision="fp32")
+    Q, R, P, info, _ = gpu_run(p32, variant, precision="fp32", reorth=reorth)
     assert info == 0
     tol = 64 * U32 * kappa * np.sqrt(p.n)
     e32 = _rel(R, want32.R)
@@ -180,11 +185,13 @@ def test_panel_argument_errors():
     info = torch.zeros(1, dtype=torch.int32, device=DEV)
     Z = torch.zeros(10, 4, dtype=torch.float64, device=DEV)
     work = torch.empty(1 << 20, dtype=torch.uint8, device=DEV)
-    for panel, reorth, want in ((3, 0, -1), (8, 0, -1), (4, 1, -4)):
-        opts = amgs.Opts(reorth, panel, 0, 0)
+    # panel widths other than 4 are invalid; the panel schedule with classical
+    # Gram-Schmidt is not supported (with the second pass it is)
+    for panel, cgs, want in ((3, 0, -1), (8, 0, -1), (4, 1, -4)):
+        opts = amgs.Opts(0, panel, cgs, 0)
         st = amgs.amgs_qr_dense(h, 10, Z.data_ptr(), 10, 4, Z.data_ptr(), 10, Z.data_ptr(), 10,
                                 Z.data_ptr(), 4, None, 0, 1, 0, C.byref(opts), work.data_ptr(),
                                 work.numel(), info.data_ptr(), None)
-        assert st == want, (panel, reorth, st)
+        assert st == want, (panel, cgs, st)
     assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(0, 3, 0, 0)) == 0
     assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(0, 4, 0, 0)) > 0
