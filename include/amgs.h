@@ -163,6 +163,8 @@ size_t amgs_workspace_bytes(amgs_handle_t h, int64_t m, int64_t n, int32_t is_de
 /* Z = QR, Q^T A Q = I for CSR A (Alg. 3 / 5 / 6, eq. (1)).
  *   row_ptr[m+1], col_idx[nnz]: int32; vals[nnz]: binary64 (AMGS_FP64) or
  *   binary32 (AMGS_FP32), matching `p`.  Z, Q, P: element type of `p`.
+ *   m <= 2^31 - 1 and nnz <= 2^31 - 1025 (int32 indices with headroom for
+ *   the kernels' entry stepping), else AMGS_ERR_ARG.
  *   P (nullable, ld ldp): receives the auxiliary vectors p_j = A q_j
  *   (Section 2.1); when NULL the workspace holds them. */
 amgs_status_t amgs_qr_csr(amgs_handle_t h, int64_t m, int64_t nnz, const int32_t *row_ptr,

@@ -659,7 +659,9 @@ amgs_status_t amgs_qr_csr(amgs_handle_t h, int64_t m, int64_t nnz, const int32_t
                           void *stream)
 {
     if (!common_args_ok(h, m, n, Z, ldz, Q, ldq, R, ldr, P, ldp, v, p, info)) return AMGS_ERR_ARG;
-    if (nnz < 0 || nnz > (int64_t)0x7fffffff) return AMGS_ERR_ARG;
+    // entry positions are int32 in the kernels, which step up to 512 past a
+    // row's end before testing it: keep that headroom below 2^31
+    if (nnz < 0 || nnz > (int64_t)0x7fffffff - 1024) return AMGS_ERR_ARG;
     if (n == 0) return AMGS_OK;
     if (!row_ptr || (nnz > 0 && (!col_idx || !vals))) return AMGS_ERR_ARG;
     Ctx c{};

@@ -369,8 +369,9 @@ def test_workspace_without_padded_copy(variant, panel):
 
 
 def test_size_limits():
-    """Row counts and entry counts beyond int32 are rejected before any
-    memory is touched."""
+    """Row counts beyond int32, and entry counts within 1024 of 2^31 (the
+    kernels step entry positions up to 512 past a row's end in int32), are
+    rejected before any memory is touched."""
     h = amgs.handle(0)
     info = torch.zeros(1, dtype=torch.int32, device=DEV)
     Z = torch.zeros(16, dtype=torch.float64, device=DEV)
@@ -379,9 +380,10 @@ def test_size_limits():
     st = amgs.amgs_qr_csr(h, big, 10, ptr, ptr, ptr, 4, ptr, big, ptr, big, ptr, 4, None, 0,
                           1, 0, None, ptr, 1 << 20, info.data_ptr(), None)
     assert st == -1
-    st = amgs.amgs_qr_csr(h, 100, big, ptr, ptr, ptr, 4, ptr, 100, ptr, 100, ptr, 4, None, 0,
-                          1, 0, None, ptr, 1 << 20, info.data_ptr(), None)
-    assert st == -1
+    for nnz in (big, (1 << 31) - 1, (1 << 31) - 1024):
+        st = amgs.amgs_qr_csr(h, 100, nnz, ptr, ptr, ptr, 4, ptr, 100, ptr, 100, ptr, 4, None, 0,
+                              1, 0, None, ptr, 1 << 20, info.data_ptr(), None)
+        assert st == -1, nnz
 
 
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
