@@ -417,3 +417,38 @@ def test_second_pass_many_workgroups(variant, precision):
         print(f"  R vs fp32 oracle {e:.2e} tol {tol:.2e} orth {o_g:.2e} (oracle {o_o:.2e})")
         assert e <= tol
         assert o_g <= max(10 * o_o, 1e-6)
+
+
+@pytest.mark.parametrize("panel", [0, 4])
+@pytest.mark.parametrize("form", ["fp64_reorth", "fp32", "fp32_reorth"])
+def test_edge_shapes_other_forms(form, panel):
+    """The edge shapes (n = 1, a one-column last panel, square m = n, m
+    below one wave) in the binary32 form and with the second pass, in both
+    schedules, dense and CSR, against the oracle in the matching
+    orientation and precision."""
+    precision = "fp32" if form.startswith("fp32") else "fp64"
+    reorth = form.endswith("reorth")
+    orient = "panel" if panel else "col"
+    g = inputs.rng(17)
+    for m, n in ((700, 1), (300, 5), (40, 40), (5, 3)):
+        A = inputs.gram_spd(g, m)
+        Z = np.asfortranarray(g.standard_normal((m, n)))
+        if precision == "fp32":
+            A = np.asfortranarray(A.astype(np.float32).astype(np.float64))
+            Z = np.asfortranarray(Z.astype(np.float32).astype(np.float64))
+        for prob in (inputs.Problem(f"edge{m}x{n}", Z, dense=A),
+                     inputs.Problem(f"edgecsr{m}x{n}", Z, csr=inputs.csr_from_dense(A))):
+            for v in VARIANTS:
+                want = ref.qr_problem(prob, variant=v, orientation=orient, precision=precision,
+                                      reorth=reorth)
+                Q, R, P, info, _ = gpu_run(prob, v, precision=precision, reorth=reorth,
+                                           panel=panel)
+                assert info == 0 and want.info == 0
+                if precision == "fp64":
+                    assert _rel(R, want.R) <= 1e-10, (prob.name, v, _rel(R, want.R))
+                    assert _rel(Q, want.Q) <= 1e-10, (prob.name, v, _rel(Q, want.Q))
+                else:
+                    kappa = np.linalg.cond(want.R)
+                    tol = 64 * U32 * kappa * np.sqrt(n)
+                    assert _rel(R, want.R) <= tol, (prob.name, v, _rel(R, want.R), tol)
+                    assert orth(prob, Q) <= max(10 * orth(prob, want.Q), 1e-6), (prob.name, v)
