@@ -98,7 +98,7 @@ def test_batched_fp64(variant):
     print(f"  worst R rel {worst:.2e} tiles {plan.tiles()}")
 
 
-@pytest.mark.parametrize("variant", ["ha", "hp"])
+@pytest.mark.parametrize("variant", ["naive", "ha", "hp"])
 def test_batched_reorth_and_fp32(variant):
     print(f"[gpu] batched {variant} reorth / fp32", flush=True)
     Qs, Rs, info, plan, keep = amgs.qr_batched(to_dev(BATCH), variant=variant, reorth=True)
@@ -108,6 +108,11 @@ def test_batched_reorth_and_fp32(variant):
                                                precision="fp32")
     torch.cuda.synchronize()
     check_instances(BATCH, Qs, Rs, info, variant, precision="fp32")
+    print(f"[gpu] batched {variant} fp32 + reorth", flush=True)
+    Qs, Rs, info, plan, keep = amgs.qr_batched(to_dev(BATCH, "fp32"), variant=variant,
+                                               precision="fp32", reorth=True)
+    torch.cuda.synchronize()
+    check_instances(BATCH, Qs, Rs, info, variant, reorth=True, precision="fp32")
 
 
 def test_batched_autotune_and_graph_replay():
