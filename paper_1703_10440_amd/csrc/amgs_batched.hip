@@ -126,24 +126,36 @@ __global__ __launch_bounds__(BT_NT) void k_batched(const amgs_batch_desc_t *__re
                     zb[b][u] = in ? Z[r + (j0 + b) * ldz] : (T)0;
                     if (VAR == VAR_HP) xb[b][u] = in ? X[r + (j0 + b) * m] : (T)0;
                 }
-            // earlier columns, i ascending: one reduction of bw dots per i;
-            // the loads of p_{i+1}, q_{i+1} are issued before the reduction
-            T pn[BT_RPT], qn[BT_RPT];
+            // earlier columns, i ascending: one reduction of bw dots per i.
+            // The loads of p_{i+1}, q_{i+1} are issued before the reduction,
+            // except in binary32 once the block (z, and x for HP) holds 8
+            // columns: there the extra registers cost more than the overlap
+            // gains (HP binary32 with 4-wide blocks is faster without them),
+            // while in binary64 the overlap pays even where it spills.
+            constexpr bool PF = (BMAX * (VAR == VAR_HP ? 2 : 1) < 8) || sizeof(T) == 8;
+            T pn[PF ? BT_RPT : 1], qn[PF ? BT_RPT : 1];
+            if (PF) {
 #pragma unroll
-            for (int u = 0; u < BT_RPT; ++u) {
-                const int64_t r = tid + u * BT_NT;
-                pn[u] = (j0 > 0 && r < m) ? P[r] : (T)0;
-                qn[u] = (j0 > 0 && r < m) ? Q[r] : (T)0;
+                for (int u = 0; u < BT_RPT; ++u) {
+                    const int64_t r = tid + u * BT_NT;
+                    pn[PF ? u : 0] = (j0 > 0 && r < m) ? P[r] : (T)0;
+                    qn[PF ? u : 0] = (j0 > 0 && r < m) ? Q[r] : (T)0;
+                }
             }
             for (int64_t i = 0; i < j0; ++i) {
                 T pr[BT_RPT], qr[BT_RPT], dots[BMAX], rvals[BMAX];
 #pragma unroll
                 for (int u = 0; u < BT_RPT; ++u) {
-                    pr[u] = pn[u];
-                    qr[u] = qn[u];
                     const int64_t r = tid + u * BT_NT;
-                    pn[u] = (i + 1 < j0 && r < m) ? P[r + (i + 1) * m] : (T)0;
-                    qn[u] = (i + 1 < j0 && r < m) ? Q[r + (i + 1) * ldq] : (T)0;
+                    if (PF) {
+                        pr[u] = pn[PF ? u : 0];
+                        qr[u] = qn[PF ? u : 0];
+                        pn[PF ? u : 0] = (i + 1 < j0 && r < m) ? P[r + (i + 1) * m] : (T)0;
+                        qn[PF ? u : 0] = (i + 1 < j0 && r < m) ? Q[r + (i + 1) * ldq] : (T)0;
+                    } else {
+                        pr[u] = r < m ? P[r + i * m] : (T)0;
+                        qr[u] = r < m ? Q[r + i * ldq] : (T)0;
+                    }
                 }
 #pragma unroll
                 for (int b = 0; b < BMAX; ++b) {
