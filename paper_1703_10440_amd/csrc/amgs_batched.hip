@@ -128,11 +128,11 @@ __global__ __launch_bounds__(BT_NT) void k_batched(const amgs_batch_desc_t *__re
                 }
             // earlier columns, i ascending: one reduction of bw dots per i.
             // The loads of p_{i+1}, q_{i+1} are issued before the reduction,
-            // except in binary32 once the block (z, and x for HP) holds 8
-            // columns: there the extra registers cost more than the overlap
-            // gains (HP binary32 with 4-wide blocks is faster without them),
-            // while in binary64 the overlap pays even where it spills.
-            constexpr bool PF = (BMAX * (VAR == VAR_HP ? 2 : 1) < 8) || sizeof(T) == 8;
+            // except in binary32 once the block (z, and x for HP) holds 4 or
+            // more columns: there the registers they take cost a wave per
+            // SIMD or more than the overlap gains, while in binary64 the
+            // overlap pays even where it spills.
+            constexpr bool PF = (BMAX * (VAR == VAR_HP ? 2 : 1) < 4) || sizeof(T) == 8;
             T pn[PF ? BT_RPT : 1], qn[PF ? BT_RPT : 1];
             if (PF) {
 #pragma unroll
