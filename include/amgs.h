@@ -220,6 +220,9 @@ size_t amgs_batch_workspace_bytes(amgs_batch_plan_t plan);
 /* Run every instance of the plan: desc is a DEVICE array of `batch`
  * descriptors in the order the sizes were given; info is a DEVICE int32
  * array of `batch` entries (per-instance breakdown index, 0 = success).
+ * desc[k].m and desc[k].n must be the sizes the plan was created with: the
+ * plan's workspace offsets are laid out for them, and the descriptors are
+ * device memory, which the call does not read back to check.
  * The first call for a given (desc, work, info, stream) captures the
  * launch into a HIP graph; later calls replay it. */
 amgs_status_t amgs_qr_batched(amgs_batch_plan_t plan, const amgs_batch_desc_t *desc,

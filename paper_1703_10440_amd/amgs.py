@@ -194,11 +194,44 @@ class QRResult:
     stats: Stats
 
 
+def _check_out(t, name, rows, cols, dtype, device):
+    """A caller's output buffer must be exactly what the kernels write: the C
+    ABI takes a bare pointer and a leading dimension and cannot check it."""
+    if not (t.dim() == 2 and tuple(t.shape) == (rows, cols)):
+        raise ValueError(f"{name} must be {rows} x {cols}, got {tuple(t.shape)}")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype}, got {t.dtype}")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device}, got {t.device}")
+    if rows > 0 and cols > 0 and not (t.stride(0) == 1 and (cols == 1 or t.stride(1) >= rows)):
+        raise ValueError(f"{name} must be column-major (stride(0) == 1, stride(1) >= {rows}), "
+                         f"got strides {t.stride()}")
+
+
+def _workspace(work, wb, device):
+    """The caller's workspace (its size in bytes is what the library checks),
+    or a new one of wb bytes."""
+    if work is None:
+        return _torch().empty(max(wb, 1), dtype=_torch().uint8, device=device)
+    if not work.is_contiguous():
+        raise ValueError("work must be contiguous")
+    if work.device != device:
+        raise ValueError(f"work must be on {device}, got {work.device}")
+    return work
+
+
 def _prep(Z, precision, device, Q, P, return_p, R=None):
     torch = _torch()
+    if precision not in PRECISIONS:
+        raise ValueError(f"precision must be one of {sorted(PRECISIONS)}, got {precision!r}")
     dt = torch.float64 if precision == "fp64" else torch.float32
     Zc = colmajor(Z.to(device), dt)
     m, n = Zc.shape
+    device = Zc.device
+    for t, name, rows, cols, tdt in ((Q, "Q", m, n, dt), (P, "P", m, n, dt),
+                                     (R, "R", n, n, torch.float64)):
+        if t is not None:
+            _check_out(t, name, rows, cols, tdt, device)
     Qc = Q if Q is not None else empty_colmajor(m, n, dt, device)
     R = R if R is not None else empty_colmajor(n, n, torch.float64, device)
     Pc = P if P is not None else (empty_colmajor(m, n, dt, device) if return_p else None)
@@ -216,6 +249,7 @@ def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=Fal
     torch = _torch()
     device = device or Z.device
     dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p, R)
+    device = Zc.device
     vals = vals.to(device=device, dtype=dt).contiguous()
     row_ptr = row_ptr.to(device=device, dtype=torch.int32).contiguous()
     col_idx = col_idx.to(device=device, dtype=torch.int32).contiguous()
@@ -223,15 +257,14 @@ def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=Fal
     opts = Opts(int(bool(reorth)), int(panel), int(bool(cgs)), int(first))
     v, p = VARIANTS[variant], PRECISIONS[precision]
     wb = amgs_workspace_bytes(h, m, n, 0, v, p, int(Pc is not None), opts)
-    if work is None:
-        work = torch.empty(max(wb, 1), dtype=torch.uint8, device=device)
+    work = _workspace(work, wb, device)
     s = stream if stream is not None else torch.cuda.current_stream(device).cuda_stream
     st = amgs_qr_csr(h, m, int(vals.numel()), row_ptr.data_ptr(), col_idx.data_ptr(),
                      vals.data_ptr(), n, Zc.data_ptr(), max(Zc.stride(1), m), Qc.data_ptr(),
                      max(Qc.stride(1), m), R.data_ptr(), max(R.stride(1), n, 1),
                      Pc.data_ptr() if Pc is not None else None,
                      max(Pc.stride(1), m) if Pc is not None else 0, v, p, C.byref(opts),
-                     work.data_ptr(), work.numel(), info.data_ptr(), s)
+                     work.data_ptr(), work.numel() * work.element_size(), info.data_ptr(), s)
     _check(st, "amgs_qr_csr")
     return QRResult(Qc, R, Pc, info, amgs_get_stats(h))
 
@@ -246,19 +279,19 @@ def qr_dense(A, Z, variant="ha", precision="fp64", reorth=False, return_p=False,
     torch = _torch()
     device = device or Z.device
     dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p, R)
+    device = Zc.device
     Ac = colmajor(A.to(device), dt)
     h = handle(device.index or 0)
     opts = Opts(int(bool(reorth)), int(panel), int(bool(cgs)), int(first))
     v, p = VARIANTS[variant], PRECISIONS[precision]
     wb = amgs_workspace_bytes(h, m, n, 1, v, p, int(Pc is not None), opts)
-    if work is None:
-        work = torch.empty(max(wb, 1), dtype=torch.uint8, device=device)
+    work = _workspace(work, wb, device)
     s = stream if stream is not None else torch.cuda.current_stream(device).cuda_stream
     st = amgs_qr_dense(h, m, Ac.data_ptr(), max(Ac.stride(1), m), n, Zc.data_ptr(),
                        max(Zc.stride(1), m), Qc.data_ptr(), max(Qc.stride(1), m), R.data_ptr(),
                        max(R.stride(1), n, 1), Pc.data_ptr() if Pc is not None else None,
                        max(Pc.stride(1), m) if Pc is not None else 0, v, p, C.byref(opts),
-                       work.data_ptr(), work.numel(), info.data_ptr(), s)
+                       work.data_ptr(), work.numel() * work.element_size(), info.data_ptr(), s)
     _check(st, "amgs_qr_dense")
     return QRResult(Qc, R, Pc, info, amgs_get_stats(h))
 
@@ -309,7 +342,8 @@ class BatchPlan:
                  device=0):
         self.h = handle(device)
         self.batch = len(ms)
-        self.variant, self.precision = variant, precision
+        self.ms, self.ns = [int(x) for x in ms], [int(x) for x in ns]
+        self.variant, self.precision, self.reorth = variant, precision, bool(reorth)
         self.opts = Opts(int(bool(reorth)), 0, 0, 0)
         self.plan = amgs_batch_plan_create(self.h, self.batch, list(ms), list(ns),
                                            VARIANTS[variant], PRECISIONS[precision], self.opts,
@@ -325,7 +359,8 @@ class BatchPlan:
         torch = _torch()
         s = stream if stream is not None else torch.cuda.current_stream(desc.device).cuda_stream
         _check(amgs_qr_batched(self.plan, desc.data_ptr(), work.data_ptr() if work is not None
-                               else None, work.numel() if work is not None else 0,
+                               else None, work.numel() * work.element_size()
+                               if work is not None else 0,
                                info.data_ptr(), s), "amgs_qr_batched")
 
     def __del__(self):
@@ -372,9 +407,13 @@ def qr_batched(instances, variant="ha", precision="fp64", reorth=False, autotune
                           vals=va.to(dt).contiguous(), Z=Zc, Q=Q, R=R))
         Qs.append(Q)
         Rs.append(R)
+    ms, ns = [it["Z"].shape[0] for it in items], [it["Z"].shape[1] for it in items]
     if plan is None:
-        plan = BatchPlan([it["Z"].shape[0] for it in items], [it["Z"].shape[1] for it in items],
-                         variant, precision, reorth, autotune, dev.index or 0)
+        plan = BatchPlan(ms, ns, variant, precision, reorth, autotune, dev.index or 0)
+    elif (plan.ms, plan.ns) != (ms, ns) or (plan.variant, plan.precision, plan.reorth) != \
+            (variant, precision, bool(reorth)):
+        # the plan's workspace offsets are laid out for its own sizes
+        raise ValueError("plan was created for other instance sizes or options")
     desc = pack_descriptors(items, dev)
     work = torch.empty(max(plan.workspace_bytes(), 1), dtype=torch.uint8, device=dev)
     info = torch.full((len(items),), -7, dtype=torch.int32, device=dev)

@@ -56,3 +56,34 @@ def test_oracle_and_library_share_nothing():
         assert "oracle" not in open(os.path.join(csrc, f)).read(), f
     for f in ("amgs.py", "build_lib.py", "__init__.py"):
         assert "oracle" not in open(os.path.join(ROOT, "paper_1703_10440_amd", f)).read(), f
+
+
+def test_binding_rejects_bad_output_buffers():
+    """The C ABI takes bare pointers, so the binding checks a caller's Q, P, R
+    against what the kernels write before anything is launched (host tensors
+    stand in for device ones: only shape, dtype, device and strides count)."""
+    import pytest
+    import torch
+    cpu = torch.device("cpu")
+    m, n = 7, 3
+    good = amgs.empty_colmajor(m, n, torch.float64, cpu)
+    amgs._check_out(good, "Q", m, n, torch.float64, cpu)
+    padded = torch.empty((n, m + 5), dtype=torch.float64).t()[:m, :]
+    amgs._check_out(padded, "Q", m, n, torch.float64, cpu)
+    amgs._check_out(torch.empty(m, 1, dtype=torch.float64), "Q", m, 1, torch.float64, cpu)
+    bad = [
+        (amgs.empty_colmajor(m, n - 1, torch.float64, cpu), "must be 7 x 3"),     # too few columns
+        (amgs.empty_colmajor(m - 1, n, torch.float64, cpu), "must be 7 x 3"),     # too few rows
+        (torch.empty(m * n, dtype=torch.float64), "must be 7 x 3"),               # flat
+        (amgs.empty_colmajor(m, n, torch.float32, cpu), "must be torch.float64"), # binary32 for binary64
+        (torch.empty(m, n, dtype=torch.float64), "column-major"),                 # row-major
+    ]
+    for t, msg in bad:
+        with pytest.raises(ValueError, match=msg):
+            amgs._check_out(t, "Q", m, n, torch.float64, cpu)
+    with pytest.raises(ValueError, match="must be on"):
+        amgs._check_out(good, "Q", m, n, torch.float64, torch.device("meta"))
+    with pytest.raises(ValueError, match="contiguous"):
+        amgs._workspace(torch.empty(64, dtype=torch.uint8)[::2], 16, cpu)
+    w = torch.empty(64, dtype=torch.uint8)
+    assert amgs._workspace(w, 16, cpu) is w

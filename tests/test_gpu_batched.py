@@ -173,3 +173,19 @@ def test_batched_sampled_full_config():
     sub = [b.problems[k] for k in sample]
     check_instances(sub, [Qs[k] for k in sample], [Rs[k] for k in sample],
                     info[torch.tensor(sample, device=DEV)], "ha")
+
+
+def test_batched_plan_must_match_instances():
+    """A plan's workspace offsets are laid out for its own sizes: the binding
+    refuses a plan made for other sizes or options."""
+    print("[gpu] batched plan mismatch", flush=True)
+    probs = BATCH[:3]
+    plan = amgs.BatchPlan([p.m for p in probs], [p.n + (k == 1) for k, p in enumerate(probs)])
+    with pytest.raises(ValueError, match="other instance sizes"):
+        amgs.qr_batched(to_dev(probs), plan=plan)
+    plan = amgs.BatchPlan([p.m for p in probs], [p.n for p in probs], variant="hp")
+    with pytest.raises(ValueError, match="other instance sizes or options"):
+        amgs.qr_batched(to_dev(probs), variant="ha", plan=plan)
+    Qs, Rs, info, plan, keep = amgs.qr_batched(to_dev(probs), variant="hp", plan=plan)
+    torch.cuda.synchronize()
+    check_instances(probs, Qs, Rs, info, "hp")

@@ -452,3 +452,31 @@ def test_edge_shapes_other_forms(form, panel):
                     tol = 64 * U32 * kappa * np.sqrt(n)
                     assert _rel(R, want.R) <= tol, (prob.name, v, _rel(R, want.R), tol)
                     assert orth(prob, Q) <= max(10 * orth(prob, want.Q), 1e-6), (prob.name, v)
+
+
+def test_binding_rejects_bad_buffers_before_launch():
+    """Output buffers of the wrong dtype, shape or layout would be written past
+    their end by the kernels; the binding refuses them before any launch."""
+    p = SMALL[0]
+    m, n = p.Z.shape
+    rp = torch.from_numpy(p.csr.row_ptr).to(DEV)
+    ci = torch.from_numpy(p.csr.col_idx).to(DEV)
+    va = torch.from_numpy(p.csr.vals).to(DEV)
+    Z = torch.from_numpy(np.ascontiguousarray(p.Z)).to(DEV)
+    print(f"[gpu] binding checks {p.name}", flush=True)
+    cases = (
+        (dict(Q=amgs.empty_colmajor(m, n, torch.float32, DEV)), "Q must be torch.float64"),
+        (dict(Q=amgs.empty_colmajor(m, n - 1, torch.float64, DEV)), "Q must be"),
+        (dict(P=torch.empty(m, n, dtype=torch.float64, device=DEV)), "P must be column-major"),
+        (dict(R=amgs.empty_colmajor(n, n, torch.float32, DEV)), "R must be torch.float64"),
+        (dict(Q=amgs.empty_colmajor(m, n, torch.float64, DEV), precision="fp32"),
+         "Q must be torch.float32"),
+        (dict(work=torch.empty(1 << 20, dtype=torch.uint8, device=DEV)[::2]), "contiguous"),
+    )
+    for kw, msg in cases:
+        with pytest.raises(ValueError, match=msg):
+            amgs.qr_csr(rp, ci, va, Z, variant="ha", **kw)
+    with pytest.raises(ValueError, match="Q must be"):
+        amgs.qr_dense(torch.eye(m, dtype=torch.float64, device=DEV), Z, variant="hp",
+                      Q=amgs.empty_colmajor(m + 1, n, torch.float64, DEV))
+    torch.cuda.synchronize()
