@@ -297,6 +297,62 @@ def pin_fp32_accumulation(lib) -> list:
     return fails
 
 
+def pin_fp32_mv_axpy_rounding(lib) -> list:
+    """Binary32 form: the MV sums each row left to right in binary32, and the
+    projection update z -= r q rounds the product and then the difference to
+    binary32 (two roundings).  Both worked out by hand on exact values.
+
+    MV: A = [[1, e, e], [e, 1, 0], [e, 0, 1]] with e = 2^-24 (spd, values
+    exact in binary32), z = (1, 1, 1), n = 1.  Row 0 in stored order:
+    1 + 2^-24 is a tie and rounds to 1 (even), and again for the second e,
+    so x_0 = 1; rows 1 and 2 give 1 + 2^-24 -> 1.  Hence z^T x = 3 exactly
+    and r_11 = sqrt(3).  A row sum accumulated in binary64 and rounded once
+    gives x_0 = 1 + 2^-23 and r_11 = sqrt(3 + 2^-23); summed from the right,
+    e + e = 2^-23 and x_0 = 1 + 2^-23 as well.
+
+    AXPY: A = I_2, z_1 = (3, 4), z_2 = (1, -27).  r_11 = 5, q_1 = p_1 =
+    (fl(3/5), fl(4/5)) = (10066330, 13421773) 2^-24.  r_12 = p_1^T z_2 in
+    binary32: fl(13421773 * 2^-24 * -27) = -11324621 * 2^-19, and
+    10066330 * 2^-24 - 11324621 * 2^-19 = -352321542 * 2^-24 rounds to -21
+    exactly.  Second entry of z_2 - r_12 q_1: the product 21 q_12 =
+    281857233 * 2^-24 rounds to 8808039 * 2^-19, and -27 + 8808039 * 2^-19 =
+    -10695474 * 2^-20 is exact; one binary64 rounding of -27 + 21 q_12 =
+    -171127599 * 2^-24 would instead give -10695475 * 2^-20.  The first entry,
+    1 + 21 q_11 -> 1 + 13212058 * 2^-20 = 14260634 * 2^-20, is the same either
+    way.  Then r_22 = sqrt(z'^T z') in binary64 and q_2 = z' / r_22 rounded
+    to binary32; every variant agrees (A = I)."""
+    fails = []
+    e = 2.0 ** -24
+    A = np.asfortranarray(np.array([[1, e, e], [e, 1, 0], [e, 0, 1]], float))
+    z = np.asfortranarray(np.ones((3, 1)))
+    want = math.sqrt(3.0)
+    for v in VARIANTS:
+        for kind, kw in (("csr", dict(csr=inputs.csr_from_dense(A))), ("dense", dict(dense=A))):
+            r = ref.qr(z, variant=v, precision="fp32", lib=lib, **kw)
+            if r.info != 0 or r.R[0, 0] != want:
+                fails.append(f"fp32 MV row sum {v}/{kind}: r_11 {r.R[0, 0]!r} != sqrt(3)")
+            qv = float(np.float32(1.0 / want))
+            if not np.all(r.Q[:, 0] == qv):
+                fails.append(f"fp32 MV row sum {v}/{kind}: q_1 {r.Q[:, 0].tolist()}")
+    I2 = np.asfortranarray(np.eye(2))
+    Z = np.asfortranarray(np.array([[3.0, 1.0], [4.0, -27.0]]))
+    zp = np.array([14260634 * 2.0 ** -20, -10695474 * 2.0 ** -20])
+    r22 = math.sqrt(zp[0] * zp[0] + zp[1] * zp[1])
+    q2 = np.array([float(np.float32(zp[k] / r22)) for k in range(2)])
+    for v in VARIANTS:
+        for kind, kw in (("csr", dict(csr=inputs.csr_from_dense(I2))), ("dense", dict(dense=I2))):
+            for o in ORIENTS:
+                r = ref.qr(Z, variant=v, orientation=o, precision="fp32", lib=lib, **kw)
+                tag = f"{v}/{kind}/{o}"
+                if r.info != 0 or r.R[0, 0] != 5.0 or r.R[0, 1] != -21.0:
+                    fails.append(f"fp32 axpy {tag}: R[0, :] {r.R[0].tolist()}")
+                if r.R[1, 1] != r22:
+                    fails.append(f"fp32 axpy {tag}: r_22 {r.R[1, 1]!r} != {r22!r}")
+                if not np.array_equal(r.Q[:, 1], q2):
+                    fails.append(f"fp32 axpy {tag}: q_2 {r.Q[:, 1].tolist()} != {q2.tolist()}")
+    return fails
+
+
 def pin_fp32_vs_fp64(lib) -> list:
     """The binary32 form agrees with binary64 to the accuracy binary32 allows
     on a well-conditioned problem (inputs rounded to binary32 first)."""
@@ -518,5 +574,6 @@ def pin_successive(lib) -> list:
 
 ALL_PINS = [pin_hand_example, pin_cholesky, pin_identity_householder, pin_cholesky_factor,
             pin_col_row_bitwise, pin_mv_counts, pin_scaling, pin_first_column,
-            pin_residual_and_reorth, pin_exp2_accuracy, pin_fp32_accumulation, pin_fp32_vs_fp64, pin_breakdown,
+            pin_residual_and_reorth, pin_exp2_accuracy, pin_fp32_accumulation,
+            pin_fp32_mv_axpy_rounding, pin_fp32_vs_fp64, pin_breakdown,
             pin_panel, pin_cgs, pin_successive]

@@ -52,6 +52,40 @@ MUTANTS = [
     ("appended columns skip the projections onto the final columns",
      "for (int64_t i = 0; i < j; ++i) {           /* projections */",
      "for (int64_t i = first; i < j; ++i) {           /* projections */"),
+    ("binary32 CSR MV row sum accumulated in binary64 and rounded once",
+     "                float s = 0.0f;\n"
+     "                for (int32_t e = A->row_ptr[k]; e < A->row_ptr[k + 1]; ++e) {\n"
+     "                    float prod = (float)A->vals[e] * (float)v[A->col_idx[e]];\n"
+     "                    s = s + prod;\n"
+     "                }\n"
+     "                y[k] = s;",
+     "                double s = 0.0;\n"
+     "                for (int32_t e = A->row_ptr[k]; e < A->row_ptr[k + 1]; ++e) {\n"
+     "                    float prod = (float)A->vals[e] * (float)v[A->col_idx[e]];\n"
+     "                    s = s + prod;\n"
+     "                }\n"
+     "                y[k] = (float)s;"),
+    ("binary32 dense MV row sum accumulated in binary64 and rounded once",
+     "                float s = 0.0f;\n"
+     "                for (int64_t l = 0; l < m; ++l) {\n"
+     "                    float prod = (float)col[l] * (float)v[l];\n"
+     "                    s = s + prod;\n"
+     "                }\n"
+     "                y[k] = s;",
+     "                double s = 0.0;\n"
+     "                for (int64_t l = 0; l < m; ++l) {\n"
+     "                    float prod = (float)col[l] * (float)v[l];\n"
+     "                    s = s + prod;\n"
+     "                }\n"
+     "                y[k] = (float)s;"),
+    ("binary32 CSR MV row summed from its last entry",
+     "                for (int32_t e = A->row_ptr[k]; e < A->row_ptr[k + 1]; ++e) {\n"
+     "                    float prod",
+     "                for (int32_t e = A->row_ptr[k + 1] - 1; e >= A->row_ptr[k]; --e) {\n"
+     "                    float prod"),
+    ("binary32 projection update with one binary64 rounding",
+     "            float zk = (float)z[k] - prod;",
+     "            float zk = (float)(z[k] - (double)rf * q[k]);"),
     ("panel block step skips the last panel column",
      "for (int i = 0; i < b; ++i) axpy_st(z, st(r[i], prec), Q + (s + i) * ldq, m, prec);",
      "for (int i = 0; i + 1 < b; ++i) axpy_st(z, st(r[i], prec), Q + (s + i) * ldq, m, prec);"),
