@@ -5,15 +5,16 @@ workload, every step of the method included (block product or per-column
 MV, projections, A-norms, normalisation), with the inputs resident in device
 memory.  The headline line is the default workload:
 
-  lap64_n64      7-point 3-D Laplacian on a 64^3 grid + 1e-2 I (CSR,
-                 m = 262144, nnz = 1,810,432), Z 262144 x 64 with kappa(Z) ~ 1e6,
-                 HP form in binary64 (value), plus naive / HA / HP in binary64
-                 and in the binary32-storage form.
+  lap128_n128    7-point 3-D Laplacian on a 128^3 grid + 1e-2 I (CSR,
+                 m = 2,097,152, nnz = 14,581,760), Z 2097152 x 128 with
+                 kappa(Z) ~ 1e4, HA form in binary64 in the panel schedule
+                 (value: the fastest n-MV configuration, gated against the
+                 column algorithm at this size in the GPU tests), plus naive /
+                 HA / HP in binary64 and in the binary32-storage form, with
+                 and without the binary64 second pass, in both schedules.
 
 Other workloads (same JSON shape, reported in the design notes):
-  lap128_n128    Laplacian 128^3 + 1e-2 I, Z 2097152 x 128, kappa(Z) ~ 1e4;
-                 binary32 form with and without the binary64 second pass vs
-                 binary64.
+  lap64_n64      Laplacian 64^3 + 1e-2 I, Z 262144 x 64, kappa(Z) ~ 1e6.
   dense512_n32   dense spd 512 x 512 (B B^T/m + I), Z 512 x 32.
   dense16k_n256  dense spd 16384 x 16384, Z 16384 x 256 (HP block product on
                  the matrix cores).
@@ -38,7 +39,17 @@ METRIC = "A-orthonormalised cols/s + %HBM roofline: HA/HP n-MV vs 2n-MV, FP64 vs
 HBM_PEAK_GBS = 8000.0
 # dense matrix-core peaks of MI355X (TFLOP/s) for the block product's dtype
 MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sweep_lap64_traffic.json")
+# HBM byte counters of the dominant kernel (rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# scaled by a plain copy's reading), per kernel and workload, with a hash of
+# the kernel's sources: a record whose sources have changed is not used
+TRAFFIC_FILES = {
+    ("sweep", "lap64_n64"): os.path.join(ROOT, "profiles", "sweep_lap64_traffic.json"),
+    ("block_sweep", "lap128_n128"): os.path.join(ROOT, "profiles", "psweep_lap128_traffic.json"),
+}
+KERNEL_SOURCES = {
+    "sweep": ("amgs_single.hip", "amgs_device.h", "amgs_internal.h"),
+    "block_sweep": ("amgs_panel.hip", "amgs_device.h", "amgs_internal.h"),
+}
 
 
 def log(*a):
@@ -130,36 +141,47 @@ def accuracy(data, out, torch):
     return float(orth), float(res)
 
 
-def source_sha():
+def source_sha(kind="sweep"):
     h = hashlib.sha256()
-    for f in ("amgs_single.hip", "amgs_device.h", "amgs_internal.h"):
+    for f in KERNEL_SOURCES[kind]:
         with open(os.path.join(ROOT, "paper_1703_10440_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def sweep_roofline(runner, amgs, torch):
-    """Average duration of the projection-sweep kernel, from HIP events that
-    the library binds to each sweep dispatch on the call's stream
-    (hipExtLaunchKernel start/stop events), and its algorithmic bytes per
-    launch."""
+def sweep_roofline(runner, amgs, torch, workload):
+    """The dominant kernel of the call: the projection sweep (column
+    schedule) or the block sweep after each panel's last column (panel
+    schedule).  Its average duration comes from HIP events that the library
+    binds to each dispatch on the call's stream (hipExtLaunchKernel
+    start/stop events); its algorithmic bytes per launch from the library's
+    counters."""
     h = amgs.handle(0)
     amgs.amgs_profile_reset(h)
     amgs.amgs_profile_enable(h, 1)
     out = runner()
     torch.cuda.synchronize()
     amgs.amgs_profile_enable(h, 0)
-    ms, launches = amgs.amgs_profile_read(h, 0)
     st = out.stats
+    if runner.panel:
+        kind, kernel = "block_sweep", "k_psweep (block sweep after each panel)"
+        ms, launches = amgs.amgs_profile_read(h, 3)
+        nbytes, nl = st.block_sweep_bytes, st.block_sweep_launches
+    else:
+        kind, kernel = "sweep", "k_sweep"
+        ms, launches = amgs.amgs_profile_read(h, 0)
+        nbytes, nl = st.sweep_bytes, st.sweep_launches
     avg_s = ms / 1e3 / max(launches, 1)
-    bytes_per_launch = st.sweep_bytes / max(st.sweep_launches, 1)
+    bytes_per_launch = nbytes / max(nl, 1)
     achieved = bytes_per_launch / avg_s / 1e9
     traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        rec = json.load(open(TRAFFIC_FILE))
-        if rec.get("source_sha") == source_sha():
+    path = TRAFFIC_FILES.get((kind, workload))
+    if path and os.path.exists(path):
+        rec = json.load(open(path))
+        if rec.get("source_sha") == source_sha(kind) and rec.get("precision", "fp64") == \
+                runner.precision and rec.get("variant", runner.variant) == runner.variant:
             traffic = rec.get("traffic_bytes_per_launch")
-    return {"bound": "hbm", "kernel": "k_sweep", "achieved": round(achieved, 1),
+    return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
             "traffic": traffic, "avg_us": round(avg_s * 1e6, 3), "launches": int(launches),
             "bytes_per_launch": bytes_per_launch}
@@ -271,7 +293,7 @@ def bench_single(args, torch, amgs):
     t, out = time_steps(run, args.steps, args.warmup, torch)
     info = int(out.info.item())
     log(f"[bench] {head_v}/{head_p}: {t * 1e3:.3f} ms/step info={info}")
-    roof = sweep_roofline(run, amgs, torch)
+    roof = sweep_roofline(run, amgs, torch, args.workload)
     log(f"[bench] sweep roofline {roof}")
     gemmroof = None
     if prob.csr is None and head_v == "hp":
@@ -284,7 +306,8 @@ def bench_single(args, torch, amgs):
     variants = {}
     if not args.no_variants:
         combos = [(v, p, False, 0, False) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
-        combos += [(v, "fp32", True, pan, False) for pan in (0, 4) for v in ("ha", "hp")]
+        combos += [(v, p, True, pan, False) for p in ("fp32", "fp64") for pan in (0, 4)
+                   for v in ("ha", "hp")]
         combos += [(v, p, False, 4, False) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
         combos += [(v, "fp64", ro, 0, True) for ro in (False, True) for v in ("naive", "ha", "hp")]
         for v, p, ro, pan, cgs in combos:
@@ -299,13 +322,22 @@ def bench_single(args, torch, amgs):
                              "orth_loss": orth, "residual": res, "info": int(o.info.item())}
             log(f"[bench] {key}: {tv * 1e3:.3f} ms  |QtAQ-I| {orth:.2e}  res {res:.2e}")
             del r, o
-        for p in ("fp64", "fp32"):
-            nv = variants[f"naive_{p}"]["ms"]
+        for sfx in ("", "_panel4"):
+            for p in ("fp64", "fp32"):
+                nv = variants[f"naive_{p}{sfx}"]["ms"]
+                for v in ("ha", "hp"):
+                    e = variants[f"{v}_{p}{sfx}"]
+                    e["speedup_vs_naive"] = round(nv / e["ms"], 3)
+            for v in ("naive", "ha", "hp"):
+                variants[f"{v}_fp32{sfx}"]["speedup_vs_fp64"] = round(
+                    variants[f"{v}_fp64{sfx}"]["ms"] / variants[f"{v}_fp32{sfx}"]["ms"], 3)
+            # the binary32 form with the binary64 second pass against plain
+            # binary64 in the same schedule
             for v in ("ha", "hp"):
-                variants[f"{v}_{p}"]["speedup_vs_naive"] = round(nv / variants[f"{v}_{p}"]["ms"], 3)
-        for v in ("naive", "ha", "hp"):
-            variants[f"{v}_fp32"]["speedup_vs_fp64"] = round(
-                variants[f"{v}_fp64"]["ms"] / variants[f"{v}_fp32"]["ms"], 3)
+                k = f"{v}_fp32_reorth{sfx}"
+                if k in variants:
+                    variants[k]["speedup_vs_fp64"] = round(
+                        variants[f"{v}_fp64{sfx}"]["ms"] / variants[k]["ms"], 3)
         # fastest modified Gram-Schmidt configuration per precision (either
         # schedule, no second pass)
         best = {}
@@ -569,16 +601,16 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="lap64_n64",
+    ap.add_argument("--workload", default="lap128_n128",
                     choices=["lap64_n64", "lap128_n128", "dense512_n32", "dense16k_n256",
                              "batch2048", "copy1g", "stream", "exp1", "exp2"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=10.0)
     ap.add_argument("--no-variants", action="store_true")
-    ap.add_argument("--variant", default="hp", choices=["naive", "ha", "hp"])
+    ap.add_argument("--variant", default="ha", choices=["naive", "ha", "hp"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--reorth", action="store_true", help="second pass in the headline run")
-    ap.add_argument("--panel", type=int, default=0, choices=[0, 4],
+    ap.add_argument("--panel", type=int, default=4, choices=[0, 4],
                     help="schedule of the headline run: 0 column order, 4 panels of four")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -137,6 +137,8 @@ typedef struct {
     int64_t sweep_launches;  /* projection-sweep kernels enqueued */
     double  sweep_bytes;     /* algorithmic HBM bytes of all sweeps (see below) */
     double  mv_bytes;        /* algorithmic HBM bytes of all MV / block products */
+    int64_t block_sweep_launches; /* panel schedule: sweeps after a panel's last column */
+    double  block_sweep_bytes;    /* their algorithmic HBM bytes (part of sweep_bytes) */
 } amgs_stats_t;
 
 /* Handle bound to a device (HIP ordinal).  Returns AMGS_ERR_ARG for a bad
@@ -223,8 +225,13 @@ size_t amgs_batch_workspace_bytes(amgs_batch_plan_t plan);
  * desc[k].m and desc[k].n must be the sizes the plan was created with: the
  * plan's workspace offsets are laid out for them, and the descriptors are
  * device memory, which the call does not read back to check.
- * The first call for a given (desc, work, info, stream) captures the
- * launch into a HIP graph; later calls replay it. */
+ * The first call for a given (desc, work, info) captures the launch into a
+ * HIP graph; later calls replay it on the stream they pass.  Every pass of a
+ * plan uses the plan's one work-queue counter, so a pass waits (on the
+ * device) for the previous pass of the same plan to end, whatever stream
+ * either was enqueued on; a call made while `stream` is being captured
+ * leaves that ordering to the caller's graph.  One plan may be used from one
+ * host thread at a time. */
 amgs_status_t amgs_qr_batched(amgs_batch_plan_t plan, const amgs_batch_desc_t *desc,
                               void *work, size_t work_bytes, int32_t *info, void *stream);
 
@@ -240,10 +247,12 @@ const char *amgs_status_string(amgs_status_t s);
 
 /* Kernel timing with HIP events recorded on the call's stream around each
  * launch of a kernel category (0 = projection sweep, 1 = MV / column
- * kernels, 2 = block product X = AZ).  amgs_profile_enable(h, 1) starts
- * recording for subsequent calls; amgs_profile_read() synchronises on the
- * recorded events and returns the summed milliseconds and launch count of a
- * category since the last reset. */
+ * kernels, 2 = block product X = AZ, 3 = the panel schedule's block sweep
+ * after a panel's last column, which also counts in category 0).
+ * amgs_profile_enable(h, 1) starts recording for subsequent calls;
+ * amgs_profile_read() synchronises on the recorded events and returns the
+ * summed milliseconds and launch count of a category since the last reset
+ * (AMGS_ERR_ARG for a category outside 0..3). */
 amgs_status_t amgs_profile_enable(amgs_handle_t h, int32_t on);
 amgs_status_t amgs_profile_read(amgs_handle_t h, int32_t category, double *total_ms,
                                 int64_t *launches);

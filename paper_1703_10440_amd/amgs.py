@@ -10,6 +10,7 @@ is no other implementation to fall back to.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes as C
 import os
 from dataclasses import dataclass
@@ -36,7 +37,8 @@ class Opts(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("mv_calls", C.c_int64), ("mv_columns", C.c_int64),
                 ("kernel_launches", C.c_int64), ("sweep_launches", C.c_int64),
-                ("sweep_bytes", C.c_double), ("mv_bytes", C.c_double)]
+                ("sweep_bytes", C.c_double), ("mv_bytes", C.c_double),
+                ("block_sweep_launches", C.c_int64), ("block_sweep_bytes", C.c_double)]
 
 
 class BatchDesc(C.Structure):
@@ -208,6 +210,34 @@ def _check_out(t, name, rows, cols, dtype, device):
                          f"got strides {t.stride()}")
 
 
+@contextlib.contextmanager
+def _on_stream(stream, device, caller_tensors):
+    """Run a call's preparation and launches on `stream` (None: torch's
+    current stream; else a torch stream or a raw hipStream_t handle).  A
+    stream other than the current one first waits for the current stream, so
+    the caller's inputs are complete; the conversions, outputs and workspace
+    the binding allocates are then made on that stream, and the caller's own
+    tensors are recorded as in use by it, so the caching allocator does not
+    hand their memory out again before the stream has finished with it.
+    Yields the raw stream handle to pass to the library."""
+    torch = _torch()
+    cur = torch.cuda.current_stream(device)
+    if stream is None:
+        yield cur.cuda_stream
+        return
+    if not isinstance(stream, torch.cuda.Stream):
+        stream = torch.cuda.ExternalStream(int(stream), device=device)
+    if stream.cuda_stream == cur.cuda_stream:
+        yield cur.cuda_stream
+        return
+    stream.wait_stream(cur)
+    with torch.cuda.stream(stream):
+        yield stream.cuda_stream
+    for t in caller_tensors:
+        if t is not None and t.is_cuda:
+            t.record_stream(stream)
+
+
 def _workspace(work, wb, device):
     """The caller's workspace (its size in bytes is what the library checks),
     or a new one of wb bytes."""
@@ -245,26 +275,28 @@ def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=Fal
     """A-orthonormalise the columns of Z (device tensors; A in CSR).
     panel: 0 for the column schedule, 4 for the panel schedule; cgs: classical
     instead of modified Gram-Schmidt; first > 0: columns before it are final
-    in the Q, P and R passed in (successive orthogonalisation)."""
+    in the Q, P and R passed in (successive orthogonalisation).  stream: a
+    torch stream or raw hipStream_t to run on (default: torch's current
+    stream); the results are ready once that stream has reached them."""
     torch = _torch()
     device = device or Z.device
-    dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p, R)
-    device = Zc.device
-    vals = vals.to(device=device, dtype=dt).contiguous()
-    row_ptr = row_ptr.to(device=device, dtype=torch.int32).contiguous()
-    col_idx = col_idx.to(device=device, dtype=torch.int32).contiguous()
-    h = handle(device.index or 0)
-    opts = Opts(int(bool(reorth)), int(panel), int(bool(cgs)), int(first))
-    v, p = VARIANTS[variant], PRECISIONS[precision]
-    wb = amgs_workspace_bytes(h, m, n, 0, v, p, int(Pc is not None), opts)
-    work = _workspace(work, wb, device)
-    s = stream if stream is not None else torch.cuda.current_stream(device).cuda_stream
-    st = amgs_qr_csr(h, m, int(vals.numel()), row_ptr.data_ptr(), col_idx.data_ptr(),
-                     vals.data_ptr(), n, Zc.data_ptr(), max(Zc.stride(1), m), Qc.data_ptr(),
-                     max(Qc.stride(1), m), R.data_ptr(), max(R.stride(1), n, 1),
-                     Pc.data_ptr() if Pc is not None else None,
-                     max(Pc.stride(1), m) if Pc is not None else 0, v, p, C.byref(opts),
-                     work.data_ptr(), work.numel() * work.element_size(), info.data_ptr(), s)
+    with _on_stream(stream, device, (row_ptr, col_idx, vals, Z, Q, P, work, R)) as s:
+        dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p, R)
+        device = Zc.device
+        vals = vals.to(device=device, dtype=dt).contiguous()
+        row_ptr = row_ptr.to(device=device, dtype=torch.int32).contiguous()
+        col_idx = col_idx.to(device=device, dtype=torch.int32).contiguous()
+        h = handle(device.index or 0)
+        opts = Opts(int(bool(reorth)), int(panel), int(bool(cgs)), int(first))
+        v, p = VARIANTS[variant], PRECISIONS[precision]
+        wb = amgs_workspace_bytes(h, m, n, 0, v, p, int(Pc is not None), opts)
+        work = _workspace(work, wb, device)
+        st = amgs_qr_csr(h, m, int(vals.numel()), row_ptr.data_ptr(), col_idx.data_ptr(),
+                         vals.data_ptr(), n, Zc.data_ptr(), max(Zc.stride(1), m), Qc.data_ptr(),
+                         max(Qc.stride(1), m), R.data_ptr(), max(R.stride(1), n, 1),
+                         Pc.data_ptr() if Pc is not None else None,
+                         max(Pc.stride(1), m) if Pc is not None else 0, v, p, C.byref(opts),
+                         work.data_ptr(), work.numel() * work.element_size(), info.data_ptr(), s)
     _check(st, "amgs_qr_csr")
     return QRResult(Qc, R, Pc, info, amgs_get_stats(h))
 
@@ -275,23 +307,25 @@ def qr_dense(A, Z, variant="ha", precision="fp64", reorth=False, return_p=False,
     """A-orthonormalise the columns of Z (device tensors; A dense symmetric).
     panel: 0 for the column schedule, 4 for the panel schedule; cgs: classical
     instead of modified Gram-Schmidt; first > 0: columns before it are final
-    in the Q, P and R passed in (successive orthogonalisation)."""
-    torch = _torch()
+    in the Q, P and R passed in (successive orthogonalisation).  stream: as
+    for qr_csr."""
     device = device or Z.device
-    dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p, R)
-    device = Zc.device
-    Ac = colmajor(A.to(device), dt)
-    h = handle(device.index or 0)
-    opts = Opts(int(bool(reorth)), int(panel), int(bool(cgs)), int(first))
-    v, p = VARIANTS[variant], PRECISIONS[precision]
-    wb = amgs_workspace_bytes(h, m, n, 1, v, p, int(Pc is not None), opts)
-    work = _workspace(work, wb, device)
-    s = stream if stream is not None else torch.cuda.current_stream(device).cuda_stream
-    st = amgs_qr_dense(h, m, Ac.data_ptr(), max(Ac.stride(1), m), n, Zc.data_ptr(),
-                       max(Zc.stride(1), m), Qc.data_ptr(), max(Qc.stride(1), m), R.data_ptr(),
-                       max(R.stride(1), n, 1), Pc.data_ptr() if Pc is not None else None,
-                       max(Pc.stride(1), m) if Pc is not None else 0, v, p, C.byref(opts),
-                       work.data_ptr(), work.numel() * work.element_size(), info.data_ptr(), s)
+    with _on_stream(stream, device, (A, Z, Q, P, work, R)) as s:
+        dt, Zc, Qc, R, Pc, info, m, n = _prep(Z, precision, device, Q, P, return_p, R)
+        device = Zc.device
+        Ac = colmajor(A.to(device), dt)
+        h = handle(device.index or 0)
+        opts = Opts(int(bool(reorth)), int(panel), int(bool(cgs)), int(first))
+        v, p = VARIANTS[variant], PRECISIONS[precision]
+        wb = amgs_workspace_bytes(h, m, n, 1, v, p, int(Pc is not None), opts)
+        work = _workspace(work, wb, device)
+        st = amgs_qr_dense(h, m, Ac.data_ptr(), max(Ac.stride(1), m), n, Zc.data_ptr(),
+                           max(Zc.stride(1), m), Qc.data_ptr(), max(Qc.stride(1), m),
+                           R.data_ptr(), max(R.stride(1), n, 1),
+                           Pc.data_ptr() if Pc is not None else None,
+                           max(Pc.stride(1), m) if Pc is not None else 0, v, p, C.byref(opts),
+                           work.data_ptr(), work.numel() * work.element_size(), info.data_ptr(),
+                           s)
     _check(st, "amgs_qr_dense")
     return QRResult(Qc, R, Pc, info, amgs_get_stats(h))
 
@@ -356,12 +390,12 @@ class BatchPlan:
         return amgs_batch_plan_tiles(self.plan)
 
     def run(self, desc, work, info, stream=None):
-        torch = _torch()
-        s = stream if stream is not None else torch.cuda.current_stream(desc.device).cuda_stream
-        _check(amgs_qr_batched(self.plan, desc.data_ptr(), work.data_ptr() if work is not None
-                               else None, work.numel() * work.element_size()
-                               if work is not None else 0,
-                               info.data_ptr(), s), "amgs_qr_batched")
+        """One pass over the plan's instances on `stream` (as for qr_csr)."""
+        with _on_stream(stream, desc.device, (desc, work, info)) as s:
+            _check(amgs_qr_batched(self.plan, desc.data_ptr(), work.data_ptr() if work is not None
+                                   else None, work.numel() * work.element_size()
+                                   if work is not None else 0,
+                                   info.data_ptr(), s), "amgs_qr_batched")
 
     def __del__(self):
         try:
@@ -392,31 +426,38 @@ def pack_descriptors(items, device):
 def qr_batched(instances, variant="ha", precision="fp64", reorth=False, autotune=False,
                plan=None, stream=None):
     """instances: list of (row_ptr, col_idx, vals, Z) device tensors (CSR A, Z
-    m x n).  Returns (Qs, Rs, info, plan)."""
+    m x n).  Returns (Qs, Rs, info, plan, keep), keep holding the operands the
+    launch uses.  stream: as for qr_csr; the descriptor copy, the outputs and
+    the workspace are made on that stream."""
     torch = _torch()
     dt = torch.float64 if precision == "fp64" else torch.float32
     dev = instances[0][3].device
-    items, Qs, Rs = [], [], []
-    for rp, ci, va, Z in instances:
-        Zc = colmajor(Z, dt)
-        m, n = Zc.shape
-        Q = empty_colmajor(m, n, dt, dev)
-        R = empty_colmajor(n, n, torch.float64, dev)
-        items.append(dict(row_ptr=rp.to(torch.int32).contiguous(),
-                          col_idx=ci.to(torch.int32).contiguous(),
-                          vals=va.to(dt).contiguous(), Z=Zc, Q=Q, R=R))
-        Qs.append(Q)
-        Rs.append(R)
-    ms, ns = [it["Z"].shape[0] for it in items], [it["Z"].shape[1] for it in items]
+    ms = [int(Z.shape[0]) if Z.dim() == 2 else int(Z.numel()) for _, _, _, Z in instances]
+    ns = [int(Z.shape[1]) if Z.dim() == 2 else 1 for _, _, _, Z in instances]
     if plan is None:
         plan = BatchPlan(ms, ns, variant, precision, reorth, autotune, dev.index or 0)
     elif (plan.ms, plan.ns) != (ms, ns) or (plan.variant, plan.precision, plan.reorth) != \
             (variant, precision, bool(reorth)):
         # the plan's workspace offsets are laid out for its own sizes
         raise ValueError("plan was created for other instance sizes or options")
-    desc = pack_descriptors(items, dev)
-    work = torch.empty(max(plan.workspace_bytes(), 1), dtype=torch.uint8, device=dev)
-    info = torch.full((len(items),), -7, dtype=torch.int32, device=dev)
-    plan.run(desc, work, info, stream)
+    caller = [t for inst in instances for t in inst]
+    with _on_stream(stream, dev, caller) as s:
+        items, Qs, Rs = [], [], []
+        for rp, ci, va, Z in instances:
+            Zc = colmajor(Z, dt)
+            m, n = Zc.shape
+            Q = empty_colmajor(m, n, dt, dev)
+            R = empty_colmajor(n, n, torch.float64, dev)
+            items.append(dict(row_ptr=rp.to(torch.int32).contiguous(),
+                              col_idx=ci.to(torch.int32).contiguous(),
+                              vals=va.to(dt).contiguous(), Z=Zc, Q=Q, R=R))
+            Qs.append(Q)
+            Rs.append(R)
+        desc = pack_descriptors(items, dev)
+        work = torch.empty(max(plan.workspace_bytes(), 1), dtype=torch.uint8, device=dev)
+        info = torch.full((len(items),), -7, dtype=torch.int32, device=dev)
+        _check(amgs_qr_batched(plan.plan, desc.data_ptr(), work.data_ptr(),
+                               work.numel() * work.element_size(), info.data_ptr(), s),
+               "amgs_qr_batched")
     # keep the operands alive with the outputs
     return Qs, Rs, info, plan, (items, desc, work)

@@ -58,7 +58,7 @@ struct ProfScope {
     {
         if (!h->profiling || cat < 0 || !a || !b) return;
         (void)hipEventRecord(b, s);
-        h->recs.push_back({cat, a, b});
+        h->recs.push_back({cat, a, b, -1});
     }
 };
 
@@ -213,7 +213,7 @@ amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
                     st.kernel_launches += 1;
                 }
                 c.ev_start = c.ev_stop = nullptr;
-                if (m0 && m1) h->recs.push_back({1, m0, m1});
+                if (m0 && m1) h->recs.push_back({1, m0, m1, -1});
                 st.mv_calls += 1;
                 st.mv_columns += 1;
                 // A once; z_j and q_{j-1} read (z_j only at j = 0, or the
@@ -238,7 +238,7 @@ amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
             c.ev_stop = e1;
             launch_sweep<T>(c, j, variant, n_rr);
             c.ev_start = c.ev_stop = nullptr;
-            if (e0 && e1) h->recs.push_back({0, e0, e1});
+            if (e0 && e1) h->recs.push_back({0, e0, e1, -1});
         } else {
             launch_sweep<T>(c, j, variant, n_rr);
         }
@@ -356,7 +356,7 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
                     c.ev_stop = m1;
                     launch_mv<T>(c, j, (first_blk || ro) ? SRC_VEC : SRC_UPD);
                     c.ev_start = c.ev_stop = nullptr;
-                    if (m0 && m1) h->recs.push_back({1, m0, m1});
+                    if (m0 && m1) h->recs.push_back({1, m0, m1, -1});
                     st.kernel_launches++;
                     st.mv_calls += 1;
                     st.mv_columns += 1;
@@ -395,13 +395,18 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
                 c.ev_stop = e1;
                 launch_psweep<T>(c, variant, j, k0, k1, d0, s, c0, c1, n_rr);
                 c.ev_start = c.ev_stop = nullptr;
-                if (e0 && e1) h->recs.push_back({0, e0, e1});
+                if (e0 && e1) h->recs.push_back({0, e0, e1, panel_end ? 3 : -1});
             } else {
                 launch_psweep<T>(c, variant, j, k0, k1, d0, s, c0, c1, n_rr);
             }
             st.kernel_launches++;
             st.sweep_launches++;
-            st.sweep_bytes += psweep_bytes(c.m, w, c1 > c0 ? c1 - c0 : 0, k1 - k0, j - d0 + 1, variant);
+            const double pb = psweep_bytes(c.m, w, c1 > c0 ? c1 - c0 : 0, k1 - k0, j - d0 + 1, variant);
+            st.sweep_bytes += pb;
+            if (panel_end) {
+                st.block_sweep_launches++;
+                st.block_sweep_bytes += pb;
+            }
             if (panel_end) {
                 launch_pfin<T>(c, s, e);
                 st.kernel_launches++;
@@ -614,7 +619,7 @@ amgs_status_t amgs_create(amgs_handle_t *out, int device)
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) h->num_cu = prop.multiProcessorCount;
     h->stats = amgs_stats_t{};
     h->profiling = 0;
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < AMGS_PROF_NCAT; ++i) {
         h->prof_ms[i] = 0.0;
         h->prof_n[i] = 0;
     }
@@ -726,7 +731,7 @@ amgs_status_t amgs_profile_enable(amgs_handle_t h, int32_t on)
 amgs_status_t amgs_profile_read(amgs_handle_t h, int32_t category, double *total_ms,
                                 int64_t *launches)
 {
-    if (!h || category < 0 || category > 2) return AMGS_ERR_ARG;
+    if (!h || category < 0 || category >= AMGS_PROF_NCAT) return AMGS_ERR_ARG;
     DeviceGuard dg(h->device);
     for (auto &r : h->recs) {
         if (hipEventSynchronize(r.b) != hipSuccess) return AMGS_ERR_HIP;
@@ -734,6 +739,10 @@ amgs_status_t amgs_profile_read(amgs_handle_t h, int32_t category, double *total
         if (hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) return AMGS_ERR_HIP;
         h->prof_ms[r.cat] += ms;
         h->prof_n[r.cat] += 1;
+        if (r.cat2 >= 0) {
+            h->prof_ms[r.cat2] += ms;
+            h->prof_n[r.cat2] += 1;
+        }
         h->pool.push_back(r.a);
         h->pool.push_back(r.b);
     }
@@ -749,7 +758,7 @@ amgs_status_t amgs_profile_reset(amgs_handle_t h)
     double ms;
     int64_t n;
     amgs_status_t s = amgs_profile_read(h, 0, &ms, &n);
-    for (int i = 0; i < 3; ++i) {
+    for (int i = 0; i < AMGS_PROF_NCAT; ++i) {
         h->prof_ms[i] = 0.0;
         h->prof_n[i] = 0;
     }

@@ -433,8 +433,12 @@ struct amgs_batch_plan {
     int bmax;
     int grid;
     int class_B[amgs::BT_NCLASS];
-    // cached graph for one (desc, work, info, stream)
+    // cached graph for one (desc, work, info); it replays on any stream
     hipStream_t cap_stream;
+    // recorded after every launch: the next launch (on whatever stream) waits
+    // for it, so two passes never share the work-queue counter at once
+    hipEvent_t done;
+    int launched;
     hipGraph_t graph;
     hipGraphExec_t exec;
     const void *g_desc;
@@ -500,6 +504,8 @@ void build_items(amgs_batch_plan *pl)
 
 void release_graph(amgs_batch_plan *pl)
 {
+    // the graph may still be running from the last launch
+    if (pl->launched && pl->done) (void)hipEventSynchronize(pl->done);
     if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
     if (pl->graph) (void)hipGraphDestroy(pl->graph);
     pl->exec = nullptr;
@@ -685,6 +691,8 @@ amgs_status_t amgs_batch_plan_create(amgs_handle_t h, int32_t batch, const int64
     pl->d_items = nullptr;
     pl->d_counter = nullptr;
     pl->cap_stream = nullptr;
+    pl->done = nullptr;
+    pl->launched = 0;
     pl->graph = nullptr;
     pl->exec = nullptr;
     pl->g_desc = nullptr;
@@ -702,7 +710,8 @@ amgs_status_t amgs_batch_plan_create(amgs_handle_t h, int32_t batch, const int64
         hipMalloc((void **)&pl->d_counter, 4) != hipSuccess ||
         (batch > 0 && hipMemcpy(pl->d_items, pl->items.data(), pl->items.size() * sizeof(BatchItem),
                                 hipMemcpyHostToDevice) != hipSuccess) ||
-        hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+        hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&pl->done, hipEventDisableTiming) != hipSuccess) {
         amgs_batch_plan_destroy(pl);
         return AMGS_ERR_HIP;
     }
@@ -718,6 +727,7 @@ amgs_status_t amgs_batch_plan_destroy(amgs_batch_plan_t pl)
     if (pl->d_items) (void)hipFree(pl->d_items);
     if (pl->d_counter) (void)hipFree(pl->d_counter);
     if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+    if (pl->done) (void)hipEventDestroy(pl->done);
     delete pl;
     return AMGS_OK;
 }
@@ -758,7 +768,19 @@ amgs_status_t amgs_qr_batched(amgs_batch_plan_t pl, const amgs_batch_desc_t *des
         pl->g_work = work;
         pl->g_info = info;
     }
+    // successive passes of one plan share its work-queue counter: a pass
+    // starts only after the previous one (possibly on another stream) ended.
+    // Under a caller's stream capture the caller's graph orders the passes.
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing((hipStream_t)stream, &cs) != hipSuccess) return AMGS_ERR_HIP;
+    const bool capturing = cs != hipStreamCaptureStatusNone;
+    if (!capturing && pl->launched && hipStreamWaitEvent((hipStream_t)stream, pl->done, 0) != hipSuccess)
+        return AMGS_ERR_HIP;
     if (hipGraphLaunch(pl->exec, (hipStream_t)stream) != hipSuccess) return AMGS_ERR_HIP;
+    if (!capturing) {
+        if (hipEventRecord(pl->done, (hipStream_t)stream) != hipSuccess) return AMGS_ERR_HIP;
+        pl->launched = 1;
+    }
     pl->h->stats = amgs_stats_t{};
     pl->h->stats.kernel_launches = 2;
     return AMGS_OK;

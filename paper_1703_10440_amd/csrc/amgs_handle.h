@@ -6,6 +6,9 @@
 
 #include "../../include/amgs.h"
 
+// kernel categories of amgs_profile_read
+constexpr int AMGS_PROF_NCAT = 4;
+
 struct amgs_handle {
     int device;
     int num_cu;
@@ -14,9 +17,10 @@ struct amgs_handle {
     struct Rec {
         int cat;
         hipEvent_t a, b;
+        int cat2;   // a second category the launch also counts in (-1: none)
     };
     std::vector<Rec> recs;        // recorded since the last read/reset
     std::vector<hipEvent_t> pool; // idle events
-    double prof_ms[3];
-    int64_t prof_n[3];
+    double prof_ms[AMGS_PROF_NCAT];
+    int64_t prof_n[AMGS_PROF_NCAT];
 };

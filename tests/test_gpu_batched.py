@@ -157,22 +157,32 @@ def test_batched_plan_rejects_bad_shapes():
         amgs.BatchPlan([5000], [4])             # m above the per-workgroup limit
 
 
-def test_batched_sampled_full_config():
+@pytest.fixture(scope="module")
+def batch2048():
+    return inputs.pentadiag_batch(batch=2048, seed=5)
+
+
+@pytest.mark.parametrize("variant,precision", [("ha", "fp64"), ("hp", "fp64"), ("ha", "fp32"),
+                                               ("hp", "fp32")])
+def test_batched_sampled_full_config(batch2048, variant, precision):
     """The 2048-instance pentadiagonal batch in the benchmark's launch
-    configuration; sampled instances (the largest, the smallest, and a
-    spread in between) against the oracle one by one."""
-    b = inputs.pentadiag_batch(batch=2048, seed=5)
-    dev_probs = to_dev(b.problems)
-    print("[gpu] batched full 2048 ha", flush=True)
-    Qs, Rs, info, plan, keep = amgs.qr_batched(dev_probs, variant="ha", autotune=True)
+    configuration (autotuned tiles, as bench.py runs it); sampled instances
+    (the largest, the smallest, and a spread in between) against the oracle
+    one by one."""
+    b = batch2048
+    dev_probs = to_dev(b.problems, precision)
+    print(f"[gpu] batched full 2048 {variant} {precision}", flush=True)
+    Qs, Rs, info, plan, keep = amgs.qr_batched(dev_probs, variant=variant, precision=precision,
+                                               autotune=True)
     torch.cuda.synchronize()
+    print(f"  tiles {plan.tiles()}", flush=True)
     assert int(info.abs().max().item()) == 0
     costs = [p.m * p.n * p.n for p in b.problems]
     order = np.argsort(costs)
     sample = sorted(set([int(order[-1]), int(order[0])] + [int(i) for i in order[::256]]))
     sub = [b.problems[k] for k in sample]
     check_instances(sub, [Qs[k] for k in sample], [Rs[k] for k in sample],
-                    info[torch.tensor(sample, device=DEV)], "ha")
+                    info[torch.tensor(sample, device=DEV)], variant, precision=precision)
 
 
 def test_batched_plan_must_match_instances():

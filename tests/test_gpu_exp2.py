@@ -57,7 +57,9 @@ def test_exp2_grid(case):
                 if want.info != 0:
                     print(f"[gpu] case {case} kA {ka:.0e} kZ {kz:.0e} {v}: breakdown "
                           f"(oracle column {want.info}, gpu column {info})", flush=True)
-                    assert info != 0
+                    # the recurrence cancels below zero at the same column in
+                    # both: every earlier column had a positive squared A-norm
+                    assert info == want.info, (case, ka, kz, v, info, want.info)
                     continue
                 assert info == 0
                 g = ref.orth_loss(Q, dense=p.dense)
