@@ -176,6 +176,36 @@ amgs_status_t amgs_qr_csr(amgs_handle_t h, int64_t m, int64_t nnz, const int32_t
                           amgs_precision_t p, const amgs_opts_t *o, void *work,
                           size_t work_bytes, int32_t *info, void *stream);
 
+/* Size of the per-GPU static scratch array of amgs_qr_csr_static: 64 MiB. */
+#define AMGS_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * computation, arguments and results as amgs_qr_csr, without the work /
+ * work_bytes pair.  The workspace is a static device array of
+ * AMGS_STATIC_SCRATCH_BYTES bytes that the library holds on every GPU it
+ * runs on until the process ends (its address is looked up once per device
+ * by amgs_create).  The call allocates and frees nothing and never
+ * synchronises; the caller still passes every input and output buffer.
+ *   - Size limit: AMGS_ERR_WORKSPACE, before any launch, when the
+ *     workspace these sizes need without the padded copy of A (see
+ *     amgs_workspace_bytes) exceeds AMGS_STATIC_SCRATCH_BYTES.  When the
+ *     array also holds the padded copy the column MV reads it, else CSR
+ *     directly; results equal amgs_qr_csr's bit for bit either way.
+ *   - Sharing: every call on one GPU uses that GPU's one array, which keeps
+ *     the previous call's contents (nothing in it needs to start at zero).
+ *     Calls that overlap on one GPU -- on two streams, from two host
+ *     threads, or two graphs replayed concurrently -- race on it; order
+ *     them on one stream or with events.
+ *   - AMGS_ERR_UNSUPPORTED for a device ordinal of 64 or more (no scratch
+ *     address kept for it). */
+amgs_status_t amgs_qr_csr_static(amgs_handle_t h, int64_t m, int64_t nnz,
+                                 const int32_t *row_ptr, const int32_t *col_idx,
+                                 const void *vals, int64_t n, const void *Z, int64_t ldz, void *Q,
+                                 int64_t ldq, double *R, int64_t ldr, void *P, int64_t ldp,
+                                 amgs_variant_t v, amgs_precision_t p, const amgs_opts_t *o,
+                                 int32_t *info, void *stream);
+
 /* Same for a dense symmetric A (column-major, lda >= m); the block product
  * X = A Z of HP (Alg. 6) runs on the matrix cores. */
 amgs_status_t amgs_qr_dense(amgs_handle_t h, int64_t m, const void *A, int64_t lda, int64_t n,

@@ -60,6 +60,9 @@ _SIGS = [
     ("amgs_qr_csr", C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
                               _i64, _vp, _i64, C.c_int, C.c_int, C.POINTER(Opts), _vp, _sz, _vp,
                               _vp]),
+    ("amgs_qr_csr_static", C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _i64, _vp, _i64, _vp,
+                                     _i64, _vp, _i64, _vp, _i64, C.c_int, C.c_int,
+                                     C.POINTER(Opts), _vp, _vp]),
     ("amgs_qr_dense", C.c_int, [_vp, _i64, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64, _vp,
                                 _i64, C.c_int, C.c_int, C.POINTER(Opts), _vp, _sz, _vp, _vp]),
     ("amgs_csr_check", C.c_int, [_vp, _i64, _i64, _vp, _vp, _vp, _vp]),
@@ -120,6 +123,10 @@ def amgs_workspace_bytes(h, m, n, is_dense, variant, precision, P_given, opts=No
 
 def amgs_qr_csr(*args) -> int:
     return load().amgs_qr_csr(*args)
+
+
+def amgs_qr_csr_static(*args) -> int:
+    return load().amgs_qr_csr_static(*args)
 
 
 def amgs_qr_dense(*args) -> int:

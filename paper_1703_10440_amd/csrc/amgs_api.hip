@@ -3,6 +3,7 @@
 // the single-problem solver.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -11,9 +12,21 @@
 #include "amgs_batched.h"
 #include "amgs_handle.h"
 
+// Scratch of amgs_qr_csr_static: a file-scope device array, one copy per
+// GPU at that GPU's own address, held by the loaded code object until the
+// process ends.  On the host the name is only a stand-in for the symbol, not
+// a device address, so host code never hands it to a kernel or a copy:
+// amgs_create looks up each device's address once, with that device
+// current, and every later use goes through the pointer kept for it.
+__device__ __align__(256) char scratch[AMGS_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 using namespace amgs;
+
+constexpr int SCRATCH_MAX_DEV = 64;
+std::mutex g_scratch_mu;
+void *g_scratch[SCRATCH_MAX_DEV];   // device address of `scratch` per ordinal
 
 struct DeviceGuard {
     int prev = -1;
@@ -617,6 +630,21 @@ amgs_status_t amgs_create(amgs_handle_t *out, int device)
     h->num_cu = 0;
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) h->num_cu = prop.multiProcessorCount;
+    h->scratch = nullptr;
+    if (device < SCRATCH_MAX_DEV) {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (!g_scratch[device]) {
+            DeviceGuard dg(device);
+            void *ptr = nullptr;
+            if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) {
+                (void)hipGetLastError();
+                delete h;
+                return AMGS_ERR_HIP;
+            }
+            g_scratch[device] = ptr;
+        }
+        h->scratch = g_scratch[device];
+    }
     h->stats = amgs_stats_t{};
     h->profiling = 0;
     for (int i = 0; i < AMGS_PROF_NCAT; ++i) {
@@ -675,6 +703,22 @@ amgs_status_t amgs_qr_csr(amgs_handle_t h, int64_t m, int64_t nnz, const int32_t
     c.Z = Z; c.ldz = ldz; c.Q = Q; c.ldq = ldq; c.R = R; c.ldr = ldr;
     c.P = P; c.ldp = ldp; c.info = info; c.stream = (hipStream_t)stream;
     return qr_common(h, c, v, p, o, work, work_bytes, P != nullptr);
+}
+
+amgs_status_t amgs_qr_csr_static(amgs_handle_t h, int64_t m, int64_t nnz,
+                                 const int32_t *row_ptr, const int32_t *col_idx,
+                                 const void *vals, int64_t n, const void *Z, int64_t ldz, void *Q,
+                                 int64_t ldq, double *R, int64_t ldr, void *P, int64_t ldp,
+                                 amgs_variant_t v, amgs_precision_t p, const amgs_opts_t *o,
+                                 int32_t *info, void *stream)
+{
+    // the same kernels as amgs_qr_csr, with this device's scratch array as
+    // the workspace; a problem needing more than the array holds is
+    // rejected by the workspace check (AMGS_ERR_WORKSPACE) before any launch
+    if (!h) return AMGS_ERR_ARG;
+    if (!h->scratch) return AMGS_ERR_UNSUPPORTED;
+    return amgs_qr_csr(h, m, nnz, row_ptr, col_idx, vals, n, Z, ldz, Q, ldq, R, ldr, P, ldp, v,
+                       p, o, h->scratch, AMGS_STATIC_SCRATCH_BYTES, info, stream);
 }
 
 amgs_status_t amgs_qr_dense(amgs_handle_t h, int64_t m, const void *A, int64_t lda, int64_t n,

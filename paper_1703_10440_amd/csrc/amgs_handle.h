@@ -12,6 +12,7 @@ constexpr int AMGS_PROF_NCAT = 4;
 struct amgs_handle {
     int device;
     int num_cu;
+    void *scratch;   // this device's static scratch array (amgs_qr_csr_static)
     amgs_stats_t stats;
     int profiling;
     struct Rec {
