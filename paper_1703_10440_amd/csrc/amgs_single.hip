@@ -856,14 +856,37 @@ __global__ __launch_bounds__(256) void k_hp_xblock(int64_t m, int64_t n, int64_t
 }
 
 // ------------------------------------------------- HP block product, CSR
-// X = A Z for all n columns (the block product of Alg. 6).  Thread per row; the
-// row's entries are read once: rows of at most eight entries keep their
-// indices and values in registers for every column, longer rows are taken
-// eight entries at a time per group of columns (those re-reads stay in the
-// thread's cache).  Columns go in groups of SPMM_C with every load of Z for
-// a group in flight together.
+// X = A Z for all n columns (the block product of Alg. 6).  Thread per row.
+// Every load of a column group is issued without a branch, so that all of
+// them are in flight together: an entry slot past the row's end reads a
+// valid entry (the row's last one, or entry 0 for an empty row) and its
+// product is then dropped by a select, not multiplied by zero.  Rows of at
+// most eight entries keep their indices and values in registers for every
+// column group; longer rows are taken eight entries at a time per group
+// (those re-reads stay in the caches).  Columns go in groups of SPMM_C.
 template <typename T>
-__global__ __launch_bounds__(256) void k_csr_spmm(int64_t m, int64_t n, const int32_t *__restrict__ row_ptr,
+__device__ __forceinline__ void spmm_group(const T *__restrict__ Zc, int64_t ldz, int nc,
+                                          const int64_t (&l)[8], const T (&v)[8],
+                                          const bool (&in)[8], T (&acc)[SPMM_C])
+{
+    constexpr int C = SPMM_C;
+    T zz[C][8];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) zz[c][t] = Zc[l[t] + (int64_t)(c < nc ? c : 0) * ldz];
+#pragma unroll
+    for (int c = 0; c < C; ++c)
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            const T p = acc[c] + v[t] * zz[c][t];
+            acc[c] = in[t] ? p : acc[c];
+        }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_csr_spmm(int64_t m, int64_t n, int64_t nnz,
+                                                  const int32_t *__restrict__ row_ptr,
                                                   const int32_t *__restrict__ col_idx,
                                                   const T *__restrict__ vals, const T *__restrict__ Z,
                                                   int64_t ldz, T *__restrict__ X, int64_t ldx)
@@ -871,56 +894,39 @@ __global__ __launch_bounds__(256) void k_csr_spmm(int64_t m, int64_t n, const in
     constexpr int C = SPMM_C;
     const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (row >= m) return;
-    const int32_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
-    if (e1 - e0 <= 8) {
-        int64_t l[8];
-        T v[8];
-#pragma unroll
-        for (int t = 0; t < 8; ++t) {
-            const bool in = e0 + t < e1;
-            l[t] = in ? col_idx[e0 + t] : 0;
-            v[t] = in ? vals[e0 + t] : (T)0;
-        }
-        for (int64_t c0 = 0; c0 < n; c0 += C) {
-            const int nc = (int)(n - c0 < C ? n - c0 : C);
-            const T *__restrict__ Zc = Z + c0 * ldz;
-            T acc[C];
-#pragma unroll
-            for (int c = 0; c < C; ++c) acc[c] = 0;
-            // entries past the row's end are skipped, not multiplied by zero
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (c < nc)
-#pragma unroll
-                    for (int t = 0; t < 8; ++t)
-                        if (e0 + t < e1) acc[c] += v[t] * Zc[l[t] + c * ldz];
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (c < nc) X[row + (c0 + c) * ldx] = acc[c];
-        }
+    if (nnz == 0) {
+        for (int64_t c = 0; c < n; ++c) X[row + c * ldx] = (T)0;
         return;
     }
+    const int32_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
+    const int32_t safe = e1 > 0 ? e1 - 1 : 0;   // a valid entry for the unused slots
+    int64_t l[8];
+    T v[8];
+    bool in[8];
+    auto load_entries = [&](int32_t eb) {
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
+            in[t] = eb + t < e1;
+            const int32_t ei = in[t] ? eb + t : safe;
+            l[t] = col_idx[ei];
+            v[t] = vals[ei];
+        }
+    };
+    const bool short_row = e1 - e0 <= 8;
+    if (short_row) load_entries(e0);
     for (int64_t c0 = 0; c0 < n; c0 += C) {
         const int nc = (int)(n - c0 < C ? n - c0 : C);
         const T *__restrict__ Zc = Z + c0 * ldz;
         T acc[C];
 #pragma unroll
         for (int c = 0; c < C; ++c) acc[c] = 0;
-        for (int32_t eb = e0; eb < e1; eb += 8) {
-            int64_t l[8];
-            T v[8];
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const bool in = eb + t < e1;
-                l[t] = in ? col_idx[eb + t] : 0;
-                v[t] = in ? vals[eb + t] : (T)0;
+        if (short_row) {
+            spmm_group<T>(Zc, ldz, nc, l, v, in, acc);
+        } else {
+            for (int32_t eb = e0; eb < e1; eb += 8) {
+                load_entries(eb);
+                spmm_group<T>(Zc, ldz, nc, l, v, in, acc);
             }
-#pragma unroll
-            for (int c = 0; c < C; ++c)
-                if (c < nc)
-#pragma unroll
-                    for (int t = 0; t < 8; ++t)
-                        if (eb + t < e1) acc[c] += v[t] * Zc[l[t] + c * ldz];
         }
 #pragma unroll
         for (int c = 0; c < C; ++c)
@@ -1263,7 +1269,7 @@ void launch_csr_spmm(const Ctx &c)
     if (L <= 1) {
         // short rows: a thread per row (entries in registers for <= 8)
         const dim3 grid((unsigned)((c.m + 255) / 256)), block(256);
-        hipLaunchKernelGGL(k_csr_spmm<T>, grid, block, 0, c.stream, c.m, nn, c.row_ptr,
+        hipLaunchKernelGGL(k_csr_spmm<T>, grid, block, 0, c.stream, c.m, nn, c.nnz, c.row_ptr,
                            c.col_idx, (const T *)c.vals, Zn, c.ldq, Xn, c.m);
         return;
     }
