@@ -39,7 +39,7 @@
  *
  * Orientation 2 is the panel schedule of the GPU library (not in the paper;
  * a regrouping of the column algorithm's projections): columns are taken in
- * panels of PANEL_B; inside a panel the column algorithm runs on the panel's
+ * panels of 4; inside a panel the column algorithm runs on the panel's
  * columns only; after a panel [s, e) is finished, every later column c gets
  * the panel's effect as one block: W_i = p_i^T z_c (the same z_c for all i),
  * L_ik = p_i^T q_k (k < i, both inside the panel), r_ic = W_i -
@@ -48,6 +48,15 @@
  * the column algorithm, since z_c^{(i-1)} = z_c - sum_{k<i} r_kc q_k.  The
  * optional second pass below runs on column j at the same point as in the
  * column form (after its projections, before its MV).
+ *
+ * Orientation 4 is the same regrouping on two levels: panels of 8 columns,
+ * each taken apart as two panels of 4 exactly as in orientation 2 but with
+ * blocks acting only on the columns of the same 8-panel, and each finished
+ * 8-panel acting on every later column as one block of 8 (W, L, r as above
+ * with 8 columns).  A column therefore receives, in this order: the blocks
+ * of every earlier 8-panel, the block of the earlier 4-panel of its own
+ * 8-panel, then the column algorithm's projections inside its 4-panel.
+ * With n <= 8 it is orientation 2.
  *
  * Orientation 3 is classical Gram-Schmidt with the same three variants
  * (Section 2: the n-MV idea applied to CGS; Section 3, analysis of CGS):
@@ -82,7 +91,7 @@
 #define REF_ROW 1
 #define REF_PANEL 2
 #define REF_CGS 3
-#define PANEL_B 4
+#define REF_PANEL2 4
 #define REF_FP64 0
 #define REF_FP32 1
 #define DOT_BLOCK 1024
@@ -350,74 +359,118 @@ static int qr_row(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq,
     return info;
 }
 
-/* Panel schedule (orientation 2): see the header comment. */
+/* Panel schedule (orientations 2 and 4): see the header comment. */
+typedef struct {
+    const ref_op *A;
+    int64_t m, n;
+    double *Q, *R, *P, *X, *x;
+    int64_t ldq, ldr, ldp;
+    int variant, reorth, prec;
+    int64_t *mv_calls, *mv_cols;
+    int nlev;
+    const int *width;   /* panel widths, outermost first; each divides the one before */
+} panel_ctx;
+
+/* The column algorithm on the columns [s, e) of a finished-below panel: each
+ * column j gets its projections onto the panel's earlier columns i in [s, j),
+ * then (HP) the same terms of eq. (5) on x_j, the optional second pass, its
+ * MV (naive, HA), its A-norm and normalisation. */
+static int panel_columns(const panel_ctx *c, int64_t s, int64_t e)
+{
+    const int64_t m = c->m;
+    for (int64_t j = s; j < e; ++j) {
+        double *z = c->Q + j * c->ldq;
+        double *Rc = c->R + j * c->ldr;
+        for (int64_t i = s; i < j; ++i) {
+            Rc[i] = dot_st(c->P + i * c->ldp, z, m, c->prec);
+            axpy_st(z, Rc[i], c->Q + i * c->ldq, m, c->prec);
+        }
+        double *xr = NULL;
+        if (c->variant == REF_HP) {
+            /* X[:, j] already holds the terms of the earlier panels */
+            memcpy(c->x, c->X + j * m, (size_t)m * sizeof(double));
+            for (int64_t i = s; i < j; ++i)
+                axpy_st(c->x, st(Rc[i], c->prec), c->P + i * c->ldp, m, c->prec);
+            xr = c->x;
+        }
+        /* the optional second pass, at the same point as in the column form */
+        if (c->reorth) reorth_pass(z, xr, j, c->Q, c->ldq, c->P, c->ldp, Rc, m, c->prec);
+        if (c->variant != REF_HP) {
+            mv_st(c->A, z, c->x, c->prec);
+            *c->mv_calls += 1; *c->mv_cols += 1;
+        }
+        double rjj;
+        if (!anorm(z, c->x, m, &rjj)) return (int)(j + 1);
+        Rc[j] = rjj;
+        scale(z, z, rjj, m, c->prec);
+        if (c->variant == REF_NAIVE) {
+            mv_st(c->A, z, c->P + j * c->ldp, c->prec);
+            *c->mv_calls += 1; *c->mv_cols += 1;
+        } else {
+            scale(c->P + j * c->ldp, c->x, rjj, m, c->prec);
+        }
+    }
+    return 0;
+}
+
+/* The finished panel [s, e) acting on the columns [c0, c1) as one block:
+ * W_i = p_i^T z_c, L_ik = p_i^T q_k (k < i, both in the panel), r_ic = W_i -
+ * sum_{k<i} L_ik r_kc (binary64), z_c -= r_ic q_i for i ascending (HP also
+ * x_c -= r_ic p_i). */
+static void panel_block(const panel_ctx *c, int64_t s, int64_t e, int64_t c0, int64_t c1)
+{
+    const int64_t m = c->m;
+    const int b = (int)(e - s);
+    double *L = (double *)malloc((size_t)b * b * sizeof(double));
+    double *W = (double *)malloc((size_t)b * sizeof(double));
+    double *r = (double *)malloc((size_t)b * sizeof(double));
+    for (int i = 0; i < b; ++i)
+        for (int k = 0; k < i; ++k)
+            L[i * b + k] = dot_st(c->P + (s + i) * c->ldp, c->Q + (s + k) * c->ldq, m, c->prec);
+    for (int64_t col = c0; col < c1; ++col) {
+        double *z = c->Q + col * c->ldq;
+        for (int i = 0; i < b; ++i) W[i] = dot_st(c->P + (s + i) * c->ldp, z, m, c->prec);
+        for (int i = 0; i < b; ++i) {
+            double t = W[i];
+            for (int k = 0; k < i; ++k) t = t - L[i * b + k] * r[k];
+            r[i] = t;
+            c->R[col * c->ldr + s + i] = t;
+        }
+        for (int i = 0; i < b; ++i) axpy_st(z, st(r[i], c->prec), c->Q + (s + i) * c->ldq, m, c->prec);
+        if (c->variant == REF_HP)
+            for (int i = 0; i < b; ++i)
+                axpy_st(c->X + col * m, st(r[i], c->prec), c->P + (s + i) * c->ldp, m, c->prec);
+    }
+    free(L); free(W); free(r);
+}
+
+/* Columns [S, E) at level lev: panels of width[lev] in order; each is taken
+ * apart at the next level (the column algorithm below the last one), and
+ * once finished acts as one block on the remaining columns of [S, E). */
+static int panel_range(const panel_ctx *c, int64_t S, int64_t E, int lev)
+{
+    const int64_t B = c->width[lev];
+    for (int64_t s = S; s < E; s += B) {
+        const int64_t e = s + B < E ? s + B : E;
+        const int info = lev + 1 < c->nlev ? panel_range(c, s, e, lev + 1) : panel_columns(c, s, e);
+        if (info) return info;
+        if (e < E) panel_block(c, s, e, e, E);
+    }
+    return 0;
+}
+
 static int qr_panel(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ldq, double *R,
                     int64_t ldr, double *P, int64_t ldp, double *X, int variant, int reorth,
-                    int prec, int64_t *mv_calls, int64_t *mv_cols)
+                    int prec, int nlev, const int *width, int64_t *mv_calls, int64_t *mv_cols)
 {
     double *x = (double *)malloc((size_t)m * sizeof(double));
     if (variant == REF_HP) {
         for (int64_t j = 0; j < n; ++j) mv_st(A, Q + j * ldq, X + j * m, prec);
         *mv_calls += 1; *mv_cols += n;
     }
-    int info = 0;
-    for (int64_t s = 0; s < n && !info; s += PANEL_B) {
-        const int64_t e = s + PANEL_B < n ? s + PANEL_B : n;
-        /* the column algorithm on the panel's own columns */
-        for (int64_t j = s; j < e; ++j) {
-            double *z = Q + j * ldq;
-            double *Rc = R + j * ldr;
-            for (int64_t i = s; i < j; ++i) {
-                Rc[i] = dot_st(P + i * ldp, z, m, prec);
-                axpy_st(z, Rc[i], Q + i * ldq, m, prec);
-            }
-            double *xr = NULL;
-            if (variant == REF_HP) {
-                /* X[:, j] already holds the terms of the earlier panels */
-                memcpy(x, X + j * m, (size_t)m * sizeof(double));
-                for (int64_t i = s; i < j; ++i) axpy_st(x, st(Rc[i], prec), P + i * ldp, m, prec);
-                xr = x;
-            }
-            /* the optional second pass, at the same point as in the column form */
-            if (reorth) reorth_pass(z, xr, j, Q, ldq, P, ldp, Rc, m, prec);
-            if (variant != REF_HP) {
-                mv_st(A, z, x, prec);
-                *mv_calls += 1; *mv_cols += 1;
-            }
-            double rjj;
-            if (!anorm(z, x, m, &rjj)) { info = (int)(j + 1); break; }
-            Rc[j] = rjj;
-            scale(z, z, rjj, m, prec);
-            if (variant == REF_NAIVE) {
-                mv_st(A, z, P + j * ldp, prec);
-                *mv_calls += 1; *mv_cols += 1;
-            } else {
-                scale(P + j * ldp, x, rjj, m, prec);
-            }
-        }
-        if (info || e >= n) break;
-        /* the finished panel's effect on every later column, as one block */
-        const int b = (int)(e - s);
-        double L[PANEL_B][PANEL_B];
-        for (int i = 0; i < b; ++i)
-            for (int k = 0; k < i; ++k)
-                L[i][k] = dot_st(P + (s + i) * ldp, Q + (s + k) * ldq, m, prec);
-        for (int64_t c = e; c < n; ++c) {
-            double *z = Q + c * ldq;
-            double W[PANEL_B], r[PANEL_B];
-            for (int i = 0; i < b; ++i) W[i] = dot_st(P + (s + i) * ldp, z, m, prec);
-            for (int i = 0; i < b; ++i) {
-                double t = W[i];
-                for (int k = 0; k < i; ++k) t = t - L[i][k] * r[k];
-                r[i] = t;
-                R[c * ldr + s + i] = t;
-            }
-            for (int i = 0; i < b; ++i) axpy_st(z, st(r[i], prec), Q + (s + i) * ldq, m, prec);
-            if (variant == REF_HP)
-                for (int i = 0; i < b; ++i)
-                    axpy_st(X + c * m, st(r[i], prec), P + (s + i) * ldp, m, prec);
-        }
-    }
+    panel_ctx c = {A, m, n, Q, R, P, X, x, ldq, ldr, ldp, variant, reorth, prec,
+                   mv_calls, mv_cols, nlev, width};
+    const int info = panel_range(&c, 0, n, 0);
     free(x);
     return info;
 }
@@ -469,7 +522,7 @@ static int run(const ref_op *A, int64_t n, int64_t first, const double *Z, int64
 {
     int64_t m = A->m;
     if (m < 0 || n < 0 || n > m || ldz < m || ldq < m || ldr < n) return -1;
-    if (variant < 0 || variant > 2 || orientation < 0 || orientation > 3) return -1;
+    if (variant < 0 || variant > 2 || orientation < 0 || orientation > 4) return -1;
     if (prec < 0 || prec > 1) return -1;
     /* successive orthogonalisation: columns before first are final in Q, P
      * and R (column and classical forms only) */
@@ -487,12 +540,17 @@ static int run(const ref_op *A, int64_t n, int64_t first, const double *Z, int64
     double *X = NULL;
     if (variant == REF_HP) X = (double *)malloc((size_t)m * n * sizeof(double));
     int64_t calls = 0, cols = 0;
+    static const int one_level[1] = {4}, two_level[2] = {8, 4};
     int info = orientation == REF_COL
         ? qr_col(A, m, n, first, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols)
         : orientation == REF_ROW
         ? qr_row(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols)
         : orientation == REF_PANEL
-        ? qr_panel(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols)
+        ? qr_panel(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, 1, one_level,
+                   &calls, &cols)
+        : orientation == REF_PANEL2
+        ? qr_panel(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, 2, two_level,
+                   &calls, &cols)
         : qr_cgs(A, m, n, first, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols);
     if (stats) { stats[0] = calls; stats[1] = cols; }
     free(X);

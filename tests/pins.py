@@ -46,9 +46,9 @@ def pin_hand_example(lib, golden) -> list:
     A, Z = golden["A"], golden["Z"]
     csr = inputs.csr_from_dense(A)
     for v in VARIANTS:
-        for o in ORIENTS + ("panel", "cgs"):
+        for o in ORIENTS + ("panel", "panel8", "cgs"):
             for prec in ("fp64", "fp32"):
-                for re_ in ((False, True) if o != "panel" else (False,)):
+                for re_ in ((False, True) if o not in ("panel", "panel8") else (False,)):
                     for kind in ("dense", "csr"):
                         kw = dict(dense=A) if kind == "dense" else dict(csr=csr)
                         r = ref.qr(Z, variant=v, orientation=o, reorth=re_, precision=prec,
@@ -476,6 +476,87 @@ def pin_panel(lib) -> list:
     return fails
 
 
+def pin_panel8(lib) -> list:
+    """Two-level panel schedule (orientation "panel8": panels of 8 columns,
+    each taken apart as two panels of 4).  Every regrouping gives the column
+    algorithm's coefficients in exact arithmetic, so: R = chol(Z^T A Z),
+    Q = Z R^{-1}, P = AQ on well-conditioned problems spanning several
+    8-panels with ragged last 8- and 4-panels (n = 21 = 8 + 8 + 4 + 1), with
+    and without the second pass; Householder QR for A = I with the three
+    variants equal bit for bit; MV counts 2n / n / one block; with n <= 8 it
+    is the one-level panel orientation bit for bit (a single 8-panel is two
+    4-panels); with n > 8 it is not (the 8-panel blocks are in use) yet agrees
+    to rounding level; on an experiment-II problem (case 2, kappa(A) =
+    kappa(Z) = 1e8) the loss stays within a small factor of the column
+    algorithm's and below 10 delta_1; and the second pass restores
+    orthogonality in the binary32 form."""
+    fails = []
+    for seed in (31, 32):
+        for p in (inputs.random_dense_problem(60, 21, seed), inputs.random_csr_problem(300, 21, 9, seed)):
+            Ad = p.dense if p.dense is not None else p.csr.to_dense()
+            Rc = _chol_R(p.Z, Ad)
+            for v in VARIANTS:
+                for re_ in (False, True):
+                    r = ref.qr(p.Z, dense=p.dense, csr=p.csr, variant=v, orientation="panel8",
+                               reorth=re_, lib=lib)
+                    e, eq, ep = (_rel(np.triu(r.R), Rc), _rel(r.Q, np.linalg.solve(Rc.T, p.Z.T).T),
+                                 _rel(r.P, Ad @ r.Q))
+                    if r.info != 0 or not (e <= 1e-13 and eq <= 1e-12 and ep <= 1e-12):
+                        fails.append(f"panel8 chol {p.name} {v} reorth={re_}: R {e} Q {eq} P {ep} "
+                                     f"info {r.info}")
+                    want_calls = {"naive": 2 * p.n, "ha": p.n, "hp": 1}[v]
+                    if r.mv_calls != want_calls:
+                        fails.append(f"panel8 MV count {p.name} {v}: {r.mv_calls} != {want_calls}")
+                r1 = ref.qr(p.Z, dense=p.dense, csr=p.csr, variant=v, orientation="panel", lib=lib)
+                r2 = ref.qr(p.Z, dense=p.dense, csr=p.csr, variant=v, orientation="panel8", lib=lib)
+                if np.array_equal(r1.R, r2.R):
+                    fails.append(f"panel8 {p.name} {v}: identical to the one-level form at n = 21")
+                if _rel(np.triu(r2.R), np.triu(r1.R)) > 1e-13:
+                    fails.append(f"panel8 {p.name} {v}: R differs from the one-level form by "
+                                 f"{_rel(np.triu(r2.R), np.triu(r1.R))}")
+    g = inputs.rng(23)
+    m, n = 150, 19
+    Z = np.asfortranarray(g.standard_normal((m, n)))
+    eye = inputs.CSR(m, np.arange(m + 1, dtype=np.int32), np.arange(m, dtype=np.int32), np.ones(m))
+    Qh, Rh = np.linalg.qr(Z)
+    D = np.sign(np.diag(Rh))
+    Qh, Rh = Qh * D[None, :], Rh * D[:, None]
+    outs = {v: ref.qr(Z, csr=eye, variant=v, orientation="panel8", lib=lib) for v in VARIANTS}
+    for v, r in outs.items():
+        if _rel(np.triu(r.R), Rh) > 1e-14 or _rel(r.Q, Qh) > 1e-13:
+            fails.append(f"panel8 identity {v}: R {_rel(np.triu(r.R), Rh)} Q {_rel(r.Q, Qh)}")
+        if not (np.array_equal(r.R, outs["naive"].R) and np.array_equal(r.Q, outs["naive"].Q)):
+            fails.append(f"panel8 identity: {v} differs bitwise from naive")
+    for nn in (3, 7, 8):
+        p = inputs.random_dense_problem(40, nn, 6)
+        for v in VARIANTS:
+            for re_ in (False, True):
+                a = ref.qr(p.Z, dense=p.dense, variant=v, orientation="panel", reorth=re_, lib=lib)
+                b = ref.qr(p.Z, dense=p.dense, variant=v, orientation="panel8", reorth=re_, lib=lib)
+                if not (np.array_equal(a.R, b.R) and np.array_equal(a.Q, b.Q)
+                        and np.array_equal(a.P, b.P)):
+                    fails.append(f"panel8 n={nn} {v} reorth={re_}: differs from the one-level form")
+    u = 2.0 ** -53
+    p = inputs.exp2_problem(100, 20, 1e8, 1e8, 2, 7)
+    w, V = np.linalg.eigh(p.dense)
+    d1 = u * float(w[-1] / w[0]) * _kappa((V * np.sqrt(w)[None, :]) @ V.T @ p.Z)
+    for v in ("naive", "ha"):
+        lc = ref.orth_loss(ref.qr_problem(p, variant=v, lib=lib).Q, dense=p.dense)
+        r = ref.qr_problem(p, variant=v, orientation="panel8", lib=lib)
+        lp = ref.orth_loss(r.Q, dense=p.dense)
+        if r.info != 0 or not (lp <= 30 * lc and lp <= 10 * d1):
+            fails.append(f"panel8 exp2 {v}: loss {lp} (column {lc}, 10 delta1 {10 * d1})")
+    q = inputs.laplacian_graded_problem(N=10, n=20, decades=4.0, seed=3)
+    for v in ("naive", "ha"):
+        o0 = ref.orth_loss(ref.qr_problem(q, variant=v, orientation="panel8", precision="fp32",
+                                          lib=lib).Q, csr=q.csr)
+        o1 = ref.orth_loss(ref.qr_problem(q, variant=v, orientation="panel8", precision="fp32",
+                                          reorth=True, lib=lib).Q, csr=q.csr)
+        if not o1 < 1e-2 * o0:
+            fails.append(f"panel8 reorth binary32 orthogonality {v}: {o0} -> {o1}")
+    return fails
+
+
 def pin_cgs(lib) -> list:
     """Classical Gram-Schmidt (orientation "cgs"): the closed forms on
     well-conditioned problems (with and without the second pass), Householder
@@ -576,4 +657,4 @@ ALL_PINS = [pin_hand_example, pin_cholesky, pin_identity_householder, pin_choles
             pin_col_row_bitwise, pin_mv_counts, pin_scaling, pin_first_column,
             pin_residual_and_reorth, pin_exp2_accuracy, pin_fp32_accumulation,
             pin_fp32_mv_axpy_rounding, pin_fp32_vs_fp64, pin_breakdown,
-            pin_panel, pin_cgs, pin_successive]
+            pin_panel, pin_panel8, pin_cgs, pin_successive]

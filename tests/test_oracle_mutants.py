@@ -41,11 +41,11 @@ MUTANTS = [
     ("dense MV walks a row of the wrong matrix (transposed operand of a non-symmetric read)",
      "const double *col = A->a + k * A->lda;", "const double *col = A->a + k;"),
     ("panel block step without the triangular correction",
-     "for (int k = 0; k < i; ++k) t = t - L[i][k] * r[k];",
+     "for (int k = 0; k < i; ++k) t = t - L[i * b + k] * r[k];",
      "for (int k = 0; k < i; ++k) t = t - 0.0 * r[k];"),
     ("panel block step updates x with q instead of p",
-     "axpy_st(X + c * m, st(r[i], prec), P + (s + i) * ldp, m, prec);",
-     "axpy_st(X + c * m, st(r[i], prec), Q + (s + i) * ldq, m, prec);"),
+     "axpy_st(c->X + col * m, st(r[i], c->prec), c->P + (s + i) * c->ldp, m, c->prec);",
+     "axpy_st(c->X + col * m, st(r[i], c->prec), c->Q + (s + i) * c->ldq, m, c->prec);"),
     ("classical Gram-Schmidt leaves the HP x column uncorrected",
      "        /* r_ij = p_i^T z_j^{(0)} for every i < j, then one correction */\n        reorth_pass(z, xr, j,",
      "        /* r_ij = p_i^T z_j^{(0)} for every i < j, then one correction */\n        reorth_pass(z, NULL, j,"),
@@ -87,8 +87,14 @@ MUTANTS = [
      "            float zk = (float)z[k] - prod;",
      "            float zk = (float)(z[k] - (double)rf * q[k]);"),
     ("panel block step skips the last panel column",
-     "for (int i = 0; i < b; ++i) axpy_st(z, st(r[i], prec), Q + (s + i) * ldq, m, prec);",
-     "for (int i = 0; i + 1 < b; ++i) axpy_st(z, st(r[i], prec), Q + (s + i) * ldq, m, prec);"),
+     "for (int i = 0; i < b; ++i) axpy_st(z, st(r[i], c->prec), c->Q + (s + i) * c->ldq, m, c->prec);",
+     "for (int i = 0; i + 1 < b; ++i) axpy_st(z, st(r[i], c->prec), c->Q + (s + i) * c->ldq, m, c->prec);"),
+    ("two-level panels: a 4-panel block also acts beyond its own 8-panel",
+     "if (e < E) panel_block(c, s, e, e, E);",
+     "if (e < E) panel_block(c, s, e, e, lev > 0 ? c->n : E);"),
+    ("two-level panels: a finished 8-panel never acts on the later columns",
+     "if (e < E) panel_block(c, s, e, e, E);",
+     "if (e < E && lev > 0) panel_block(c, s, e, e, E);"),
 ]
 
 
