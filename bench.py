@@ -45,10 +45,12 @@ MFMA_PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3}
 TRAFFIC_FILES = {
     ("sweep", "lap64_n64"): os.path.join(ROOT, "profiles", "sweep_lap64_traffic.json"),
     ("block_sweep", "lap128_n128"): os.path.join(ROOT, "profiles", "psweep_lap128_traffic.json"),
+    ("block_sweep8", "lap128_n128"): os.path.join(ROOT, "profiles", "bsweep_lap128_traffic.json"),
 }
 KERNEL_SOURCES = {
     "sweep": ("amgs_single.hip", "amgs_device.h", "amgs_internal.h"),
     "block_sweep": ("amgs_panel.hip", "amgs_device.h", "amgs_internal.h"),
+    "block_sweep8": ("amgs_panel.hip", "amgs_device.h", "amgs_internal.h"),
 }
 
 
@@ -163,7 +165,11 @@ def sweep_roofline(runner, amgs, torch, workload):
     torch.cuda.synchronize()
     amgs.amgs_profile_enable(h, 0)
     st = out.stats
-    if runner.panel:
+    if runner.panel == 8:
+        kind, kernel = "block_sweep8", "k_bsweep (block sweep after each panel of eight)"
+        ms, launches = amgs.amgs_profile_read(h, 3)
+        nbytes, nl = st.block_sweep_bytes, st.block_sweep_launches
+    elif runner.panel:
         kind, kernel = "block_sweep", "k_psweep (block sweep after each panel)"
         ms, launches = amgs.amgs_profile_read(h, 3)
         nbytes, nl = st.block_sweep_bytes, st.block_sweep_launches
@@ -306,9 +312,10 @@ def bench_single(args, torch, amgs):
     variants = {}
     if not args.no_variants:
         combos = [(v, p, False, 0, False) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
-        combos += [(v, p, True, pan, False) for p in ("fp32", "fp64") for pan in (0, 4)
+        combos += [(v, p, True, pan, False) for p in ("fp32", "fp64") for pan in (0, 4, 8)
                    for v in ("ha", "hp")]
-        combos += [(v, p, False, 4, False) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
+        combos += [(v, p, False, pan, False) for pan in (4, 8) for p in ("fp64", "fp32")
+                   for v in ("naive", "ha", "hp")]
         combos += [(v, "fp64", ro, 0, True) for ro in (False, True) for v in ("naive", "ha", "hp")]
         for v, p, ro, pan, cgs in combos:
             r = Runner(data, v, p, torch, amgs, reorth=ro, panel=pan, cgs=cgs)
@@ -322,7 +329,7 @@ def bench_single(args, torch, amgs):
                              "orth_loss": orth, "residual": res, "info": int(o.info.item())}
             log(f"[bench] {key}: {tv * 1e3:.3f} ms  |QtAQ-I| {orth:.2e}  res {res:.2e}")
             del r, o
-        for sfx in ("", "_panel4"):
+        for sfx in ("", "_panel4", "_panel8"):
             for p in ("fp64", "fp32"):
                 nv = variants[f"naive_{p}{sfx}"]["ms"]
                 for v in ("ha", "hp"):
@@ -610,8 +617,9 @@ def main():
     ap.add_argument("--variant", default="ha", choices=["naive", "ha", "hp"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--reorth", action="store_true", help="second pass in the headline run")
-    ap.add_argument("--panel", type=int, default=4, choices=[0, 4],
-                    help="schedule of the headline run: 0 column order, 4 panels of four")
+    ap.add_argument("--panel", type=int, default=4, choices=[0, 4, 8],
+                    help="schedule of the headline run: 0 column order, 4 panels of four, "
+                         "8 panels of eight taken apart as panels of four")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported here "

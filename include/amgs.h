@@ -99,6 +99,16 @@ typedef struct amgs_handle *amgs_handle_t;
  *           is then read and written once per panel instead of once per
  *           column.  Rounding differs from the column order;
  *           A-orthogonality stays at the level of the column algorithm.
+ *           8: two-level panel schedule.  Columns are taken in panels of
+ *           eight, each taken apart as two panels of four exactly as above
+ *           except that a four-column block acts only on the columns of its
+ *           own eight-panel; a finished eight-panel then acts on every later
+ *           column as one block of eight (W = P_I^T z_c, L, (I + L) r = W as
+ *           above, with eight columns).  A column receives the blocks of
+ *           the earlier eight-panels, then the block of the earlier
+ *           four-panel of its own eight-panel, then the column steps of its
+ *           four-panel.  Each later column is read and written once per
+ *           eight columns; the block step runs on the matrix cores.
  *           Not combined with cgs or first (AMGS_ERR_UNSUPPORTED); other
  *           values are AMGS_ERR_ARG.
  *   cgs     0: modified Gram-Schmidt (Algs. 3/5/6, default).

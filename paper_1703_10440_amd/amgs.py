@@ -280,7 +280,8 @@ def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=Fal
            return_p=False, Q=None, P=None, work=None, stream=None, device=None,
            panel=0, cgs=False, first=0, R=None) -> QRResult:
     """A-orthonormalise the columns of Z (device tensors; A in CSR).
-    panel: 0 for the column schedule, 4 for the panel schedule; cgs: classical
+    panel: 0 for the column schedule, 4 for the panel schedule, 8 for the
+    two-level panel schedule (panels of eight, each as two of four); cgs: classical
     instead of modified Gram-Schmidt; first > 0: columns before it are final
     in the Q, P and R passed in (successive orthogonalisation).  stream: a
     torch stream or raw hipStream_t to run on (default: torch's current
@@ -312,7 +313,8 @@ def qr_dense(A, Z, variant="ha", precision="fp64", reorth=False, return_p=False,
              P=None, work=None, stream=None, device=None, panel=0, cgs=False, first=0,
              R=None) -> QRResult:
     """A-orthonormalise the columns of Z (device tensors; A dense symmetric).
-    panel: 0 for the column schedule, 4 for the panel schedule; cgs: classical
+    panel: 0 for the column schedule, 4 for the panel schedule, 8 for the
+    two-level panel schedule (panels of eight, each as two of four); cgs: classical
     instead of modified Gram-Schmidt; first > 0: columns before it are final
     in the Q, P and R passed in (successive orthogonalisation).  stream: as
     for qr_csr."""

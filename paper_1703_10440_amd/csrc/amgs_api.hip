@@ -78,7 +78,7 @@ struct ProfScope {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t part, s_part, rr_part, S, zt, xv, X, P, wpart, lpart, ell_col, ell_val, tile_long;
+    size_t part, s_part, rr_part, S, zt, xv, X, P, wpart, lpart, lred, ell_col, ell_val, tile_long;
     size_t base;    // bytes without the padded copy of A
     size_t total;   // bytes with it (the size the query reports)
 };
@@ -113,8 +113,12 @@ Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_g
     L.xv = variant != VAR_HP ? take((size_t)m * w) : off;
     L.X = variant == VAR_HP ? take((size_t)m * n * w) : off;
     L.P = P_given ? off : take((size_t)m * n * w);
-    L.wpart = panel ? take((size_t)n * PANEL_B * g_p * 8) : off;
-    L.lpart = panel ? take((size_t)PANEL_B * PANEL_B * g_p * 8) : off;
+    const size_t pb = panel == PANEL_B1 ? PANEL_B1 : PANEL_B;
+    // the outer block sweep may use more row chunks than the panel sweeps
+    const int64_t g_w = panel == PANEL_B1 && bsweep_chunks(m, w) > g_p ? bsweep_chunks(m, w) : g_p;
+    L.wpart = panel ? take((size_t)n * pb * g_w * 8) : off;
+    L.lpart = panel ? take(pb * pb * g_p * 8) : off;
+    L.lred = panel == PANEL_B1 ? take((size_t)PANEL_B1 * PANEL_B1 * 8) : off;
     L.base = off;
     // padded copy of a CSR A for the column MV (naive and HA), last, so that
     // a smaller workspace can leave it out; the size does not depend on nnz,
@@ -279,10 +283,19 @@ double psweep_bytes(int64_t m, size_t w, int64_t ncols, int64_t kw, int64_t bd, 
     return (double)ncols * per_col * col + vec * col;
 }
 
-// Panel schedule (opts->panel): the column algorithm inside each panel of
-// PANEL_B columns; after a panel's last column one sweep applies the
-// previous panel to every later column and forms the dots with this panel's
-// p vectors, and k_pfin turns them into the coefficients r_{I,c}.
+// Panel schedule (opts->panel).  One level (panel = 4): the column
+// algorithm inside each panel of PANEL_B columns; after a panel's last column
+// one sweep applies the previous panel to every later column and forms the
+// dots with this panel's p vectors, and k_pfin turns them into the
+// coefficients r_{I,c}.  Two levels (panel = 8): outer panels of PANEL_B1
+// columns, each taken apart as inner panels of PANEL_B exactly as above but
+// with the inner blocks acting only on the columns of the same outer panel;
+// after an outer panel's last column, k_bsweep applies the previous outer
+// panel to every later column and forms the dots with this outer panel's p
+// vectors, and k_lfin + k_pfin2 solve for the coefficients.  A column thus
+// receives the blocks of the earlier outer panels, then the block of the
+// earlier inner panel of its own outer panel, then the column steps of its
+// inner panel: the order of the oracle's panel orientations.
 template <typename T>
 amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
 {
@@ -306,126 +319,163 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
         st.mv_columns += c.n;
         st.mv_bytes += mvA + 2.0 * (double)c.m * c.n * w;
     }
-    static_assert(HP_XB % PANEL_B == 0, "x-block passes fall on panel boundaries");
+    static_assert(HP_XB % PANEL_B == 0 && HP_XB % PANEL_B1 == 0,
+                  "x-block passes fall on (outer) panel boundaries");
+    const bool two = c.panel == PANEL_B1;
     const int64_t B = PANEL_B;
-    for (int64_t s = 0; s < c.n; s += B) {
-        const int64_t e = s + B < c.n ? s + B : c.n;
-        const int64_t prev = s - B;   // start of the previous panel (s > 0)
-        for (int64_t j = s; j < e; ++j) {
-            const bool first_blk = j == s && s > 0;
-            int64_t n_rr = 0;
-            // column kernels publish r_{j-1,c} only inside the panel
-            c.n_pub = e;
-            {
-                ProfScope ps(h, variant == VAR_HP ? 1 : -1, c.stream);
-                // the optional second pass runs on column j after its
-                // projections, before its MV, as in the column schedule
-                const bool ro = reorth && j > 0;
-                if (first_blk) {
-                    // HP: the x terms of the previous panel unless an x-block
-                    // pass at s has applied them
-                    launch_pcol_blk<T>(c, variant, j, prev, s, s % HP_XB == 0 ? s : prev);
-                    st.kernel_launches++;
-                    n_rr = pcol_blk_partials(c);
-                    if (ro) {
-                        // the block-corrected z_j is in zt (naive, HA) or in
-                        // Q (HP), with no single pending term left
-                        c.no_pend = 1;
-                        c.z_in_zt = variant == VAR_HP ? 0 : 1;
-                        launch_reorth_a<T>(c, j);
-                        c.no_pend = 0;
-                        c.z_in_zt = 0;
-                        launch_reorth_fin(c, j);
-                        launch_reorth_b<T>(c, j, variant == VAR_HP);
-                        st.kernel_launches += 3;
-                        n_rr = c.geo.g_rows1;   // A-norm partials of k_reorth_b (HP)
-                    }
-                } else if (variant == VAR_HP) {
-                    // the recurrence terms since the last x-block pass
-                    if (ro) {
-                        launch_col_hp<T>(c, j, true);
-                        launch_reorth_fin(c, j);
-                        launch_reorth_b<T>(c, j, true);
-                        st.kernel_launches += 3;
-                        n_rr = c.geo.g_rows1;
-                    } else {
-                        launch_col_hp<T>(c, j, false);
+    const int64_t B1 = two ? PANEL_B1 : PANEL_B;   // outer panel width (= B for one level)
+    // launch with HIP events bound to the dispatch when profiling (category
+    // 0, and 3 for the block sweep after an outer panel)
+    auto profiled = [&](bool block, auto &&launch) {
+        if (h->profiling) {
+            hipEvent_t e0 = take_event(h), e1 = take_event(h);
+            c.ev_start = e0;
+            c.ev_stop = e1;
+            launch();
+            c.ev_start = c.ev_stop = nullptr;
+            if (e0 && e1) h->recs.push_back({0, e0, e1, block ? 3 : -1});
+        } else {
+            launch();
+        }
+    };
+    for (int64_t S = 0; S < c.n; S += B1) {
+        const int64_t E = S + B1 < c.n ? S + B1 : c.n;
+        const int64_t bp0 = S > 0 ? S - B1 : S;   // the previous outer panel [bp0, S)
+        for (int64_t s = S; s < E; s += B) {
+            const int64_t e = s + B < E ? s + B : E;
+            // the block still pending for this panel's columns: the previous
+            // outer panel for the first inner panel, else the previous inner one
+            const int64_t pk0 = s == S ? bp0 : s - B, pk1 = s;
+            for (int64_t j = s; j < e; ++j) {
+                const bool first_blk = j == s && pk1 > pk0;
+                int64_t n_rr = 0;
+                // column kernels publish r_{j-1,c} only inside the panel
+                c.n_pub = e;
+                {
+                    ProfScope ps(h, variant == VAR_HP ? 1 : -1, c.stream);
+                    // the optional second pass runs on column j after its
+                    // projections, before its MV, as in the column schedule
+                    const bool ro = reorth && j > 0;
+                    if (first_blk) {
+                        // HP: the x terms of the pending block unless an
+                        // x-block pass at s has applied them
+                        launch_pcol_blk<T>(c, variant, j, pk0, pk1, s % HP_XB == 0 ? s : pk0);
                         st.kernel_launches++;
-                        n_rr = c.geo.g_rows2;
+                        n_rr = pcol_blk_partials(c);
+                        if (ro) {
+                            // the block-corrected z_j is in zt (naive, HA) or in
+                            // Q (HP), with no single pending term left
+                            c.no_pend = 1;
+                            c.z_in_zt = variant == VAR_HP ? 0 : 1;
+                            launch_reorth_a<T>(c, j);
+                            c.no_pend = 0;
+                            c.z_in_zt = 0;
+                            launch_reorth_fin(c, j);
+                            launch_reorth_b<T>(c, j, variant == VAR_HP);
+                            st.kernel_launches += 3;
+                            n_rr = c.geo.g_rows1;   // A-norm partials of k_reorth_b (HP)
+                        }
+                    } else if (variant == VAR_HP) {
+                        // the recurrence terms since the last x-block pass
+                        if (ro) {
+                            launch_col_hp<T>(c, j, true);
+                            launch_reorth_fin(c, j);
+                            launch_reorth_b<T>(c, j, true);
+                            st.kernel_launches += 3;
+                            n_rr = c.geo.g_rows1;
+                        } else {
+                            launch_col_hp<T>(c, j, false);
+                            st.kernel_launches++;
+                            n_rr = c.geo.g_rows2;
+                        }
+                    } else if (ro) {
+                        launch_reorth_a<T>(c, j);
+                        launch_reorth_fin(c, j);
+                        launch_reorth_b<T>(c, j, false);
+                        st.kernel_launches += 3;
                     }
-                } else if (ro) {
-                    launch_reorth_a<T>(c, j);
-                    launch_reorth_fin(c, j);
-                    launch_reorth_b<T>(c, j, false);
-                    st.kernel_launches += 3;
-                }
-                if (variant != VAR_HP) {
-                    hipEvent_t m0 = nullptr, m1 = nullptr;
-                    if (h->profiling) {
-                        m0 = take_event(h);
-                        m1 = take_event(h);
-                    }
-                    c.ev_start = m0;
-                    c.ev_stop = m1;
-                    launch_mv<T>(c, j, (first_blk || ro) ? SRC_VEC : SRC_UPD);
-                    c.ev_start = c.ev_stop = nullptr;
-                    if (m0 && m1) h->recs.push_back({1, m0, m1, -1});
-                    st.kernel_launches++;
-                    st.mv_calls += 1;
-                    st.mv_columns += 1;
-                    st.mv_bytes += mvA + ((first_blk || ro) ? 2.0 : (j > 0 ? 4.0 : 3.0)) * (double)c.m * w;
-                    if (variant == VAR_NAIVE) {
-                        launch_mv<T>(c, j, SRC_DIV);
+                    if (variant != VAR_HP) {
+                        hipEvent_t m0 = nullptr, m1 = nullptr;
+                        if (h->profiling) {
+                            m0 = take_event(h);
+                            m1 = take_event(h);
+                        }
+                        c.ev_start = m0;
+                        c.ev_stop = m1;
+                        launch_mv<T>(c, j, (first_blk || ro) ? SRC_VEC : SRC_UPD);
+                        c.ev_start = c.ev_stop = nullptr;
+                        if (m0 && m1) h->recs.push_back({1, m0, m1, -1});
                         st.kernel_launches++;
                         st.mv_calls += 1;
                         st.mv_columns += 1;
-                        st.mv_bytes += mvA + 2.0 * (double)c.m * w;
+                        st.mv_bytes += mvA + ((first_blk || ro) ? 2.0 : (j > 0 ? 4.0 : 3.0)) * (double)c.m * w;
+                        if (variant == VAR_NAIVE) {
+                            launch_mv<T>(c, j, SRC_DIV);
+                            st.kernel_launches++;
+                            st.mv_calls += 1;
+                            st.mv_columns += 1;
+                            st.mv_bytes += mvA + 2.0 * (double)c.m * w;
+                        }
+                        n_rr = c.n_rr_mv;
                     }
-                    n_rr = c.n_rr_mv;
                 }
-            }
-            c.n_pub = c.n;
-            // a step inside the panel (also the last column of the last
-            // panel), or the sweep after the panel's last column
-            const bool panel_end = j == e - 1 && e < c.n;
-            int64_t k0, k1, d0, c0, c1;
-            if (!panel_end) {
-                k0 = j == s ? (s > 0 ? prev : s) : j - 1;
-                k1 = j == s ? s : j;
-                d0 = j;
-                c0 = j + 1;
-                c1 = e;
-            } else {
-                k0 = s > 0 ? prev : s;
-                k1 = s;
-                d0 = s;
-                c0 = e;
-                c1 = c.n;
-            }
-            if (h->profiling) {
-                hipEvent_t e0 = take_event(h), e1 = take_event(h);
-                c.ev_start = e0;
-                c.ev_stop = e1;
-                launch_psweep<T>(c, variant, j, k0, k1, d0, s, c0, c1, n_rr);
-                c.ev_start = c.ev_stop = nullptr;
-                if (e0 && e1) h->recs.push_back({0, e0, e1, panel_end ? 3 : -1});
-            } else {
-                launch_psweep<T>(c, variant, j, k0, k1, d0, s, c0, c1, n_rr);
-            }
-            st.kernel_launches++;
-            st.sweep_launches++;
-            const double pb = psweep_bytes(c.m, w, c1 > c0 ? c1 - c0 : 0, k1 - k0, j - d0 + 1, variant);
-            st.sweep_bytes += pb;
-            if (panel_end) {
-                st.block_sweep_launches++;
-                st.block_sweep_bytes += pb;
-            }
-            if (panel_end) {
-                launch_pfin<T>(c, s, e);
+                c.n_pub = c.n;
+                // the sweep of step j: inside a panel (also the last column
+                // of the matrix); after an inner panel of an outer one (the
+                // block of the inner panel for the rest of the outer panel);
+                // after an outer panel (one level: the block sweep itself;
+                // two levels: normalisation and the L row only, k_bsweep follows)
+                const bool inner_end = j == e - 1 && e < E;
+                const bool outer_end = j == e - 1 && e == E && E < c.n;
+                int64_t k0, k1, d0, c0, c1;
+                if (inner_end) {
+                    k0 = pk0; k1 = pk1; d0 = s; c0 = e; c1 = E;
+                } else if (outer_end && two) {
+                    k0 = k1 = j; d0 = j; c0 = c1 = E;
+                } else if (outer_end) {
+                    k0 = bp0; k1 = S; d0 = s; c0 = E; c1 = c.n;
+                } else {
+                    k0 = j == s ? pk0 : j - 1;
+                    k1 = j == s ? pk1 : j;
+                    d0 = j; c0 = j + 1; c1 = e;
+                }
+                const bool block1 = outer_end && !two;
+                profiled(block1, [&] { launch_psweep<T>(c, variant, j, k0, k1, d0, S, c0, c1, n_rr); });
                 st.kernel_launches++;
-                // HP: once r_{i,c} of the last HP_XB columns are final, their
-                // recurrence terms go to every x column from e on
-                if (variant == VAR_HP && launch_hp_xblock<T>(c, e, e)) st.kernel_launches++;
+                st.sweep_launches++;
+                const double pb = psweep_bytes(c.m, w, c1 > c0 ? c1 - c0 : 0, k1 - k0, j - d0 + 1, variant);
+                st.sweep_bytes += pb;
+                if (block1) {
+                    st.block_sweep_launches++;
+                    st.block_sweep_bytes += pb;
+                }
+                if (inner_end) {
+                    launch_lfin<T>(c, S, s, e);
+                    launch_pfin2<T>(c, s, e, e, E, c.g_p);
+                    st.kernel_launches += 2;
+                }
+                if (outer_end) {
+                    if (two) {
+                        profiled(true, [&] { launch_bsweep<T>(c, bp0, S, S, E, E, c.n); });
+                        const double col = (double)c.m * (double)w;
+                        const double bb = (double)(c.n - E) * (S > bp0 ? 2.0 : 1.0) * col
+                                          + (double)((S - bp0) + (E - S)) * col;
+                        st.kernel_launches++;
+                        st.sweep_launches++;
+                        st.sweep_bytes += bb;
+                        st.block_sweep_launches++;
+                        st.block_sweep_bytes += bb;
+                        launch_lfin<T>(c, S, S, E);
+                        launch_pfin2<T>(c, S, E, E, c.n, c.g_b);
+                        st.kernel_launches += 2;
+                    } else {
+                        launch_pfin<T>(c, s, e);
+                        st.kernel_launches++;
+                    }
+                    // HP: once r_{i,c} of the last HP_XB columns are final,
+                    // their recurrence terms go to every x column from E on
+                    if (variant == VAR_HP && launch_hp_xblock<T>(c, E, E)) st.kernel_launches++;
+                }
             }
         }
     }
@@ -516,7 +566,7 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
     const int panel = o ? o->panel : 0;
     const int cgs = o ? o->cgs : 0;
     const int64_t first = o ? o->first : 0;
-    if (panel != 0 && panel != PANEL_B) return AMGS_ERR_ARG;
+    if (panel != 0 && panel != PANEL_B && panel != PANEL_B1) return AMGS_ERR_ARG;
     if (cgs != 0 && cgs != 1) return AMGS_ERR_ARG;
     if (first < 0 || first > c.n) return AMGS_ERR_ARG;
     if (first > 0 && !P_given) return AMGS_ERR_ARG;   // p_i of the final columns are needed
@@ -541,6 +591,8 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
         c.sp.g = c.g_p;
         c.wpart = base + L.wpart;
         c.lpart = base + L.lpart;
+        c.lred = (double *)(base + L.lred);
+        c.g_b = bsweep_chunks(c.m, w);
     }
     c.s_part = (double *)(base + L.s_part);
     c.rr_part = (double *)(base + L.rr_part);
@@ -677,7 +729,7 @@ size_t amgs_workspace_bytes(amgs_handle_t h, int64_t m, int64_t n, int32_t is_de
     Geo g = make_geo(m, is_dense ? 0 : m, is_dense);
     const int panel = o ? o->panel : 0;
     const int cgs = o ? o->cgs : 0;
-    if (panel != 0 && panel != PANEL_B) return 0;
+    if (panel != 0 && panel != PANEL_B && panel != PANEL_B1) return 0;
     if (cgs != 0 && cgs != 1) return 0;
     Layout L = layout(m, n, g, (int)v, p == AMGS_FP64 ? 8 : 4, P_given,
                       (o ? o->reorth != 0 : 0) || cgs, panel, is_dense);

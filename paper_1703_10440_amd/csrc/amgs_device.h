@@ -156,6 +156,32 @@ __device__ __forceinline__ void st_stream(T *p, T v)
     else *p = v;
 }
 
+// Matrix-core 16x16x4 instructions (v_mfma_f64_16x16x4f64 in binary64,
+// v_mfma_f32_16x16x4f32 in binary32): D = C + A B with lane l supplying
+// A[l%16][l/16] and B[l/16][l%16].  Result rows: register v of lane l holds
+// row 4*v + l/16 for the binary64 instruction and row 4*(l/16) + v for the
+// binary32 one (column l%16 in both), as measured on gfx950.
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+    typedef d4 acc_t;
+    static __device__ __forceinline__ acc_t op(double a, double b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * v + (lane >> 4); }
+};
+template <> struct Mfma<float> {
+    typedef f4 acc_t;
+    static __device__ __forceinline__ acc_t op(float a, float b, acc_t c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ int row(int lane, int v) { return 4 * (lane >> 4) + v; }
+};
+
 __device__ __forceinline__ bool norm_ok(double rr) { return rr > 0.0 && rr <= 1.7976931348623157e308; }
 
 } // namespace amgs

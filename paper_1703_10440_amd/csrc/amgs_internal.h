@@ -20,7 +20,13 @@ constexpr int SPMM_LC = 8;     // columns per pass of the multi-lane CSR block p
 constexpr int MAX_G_MV = 512;  // partials of an MV column kernel
 constexpr int MV_TILE = 512;   // rows (= threads) per padded-copy MV workgroup
 constexpr int ELL_K = 8;       // most entries per row held in the padded copy of A
-constexpr int PANEL_B = 4;     // columns per panel of the panel schedule
+constexpr int PANEL_B = 4;     // columns per panel of the panel schedule (inner panels of the two-level one)
+constexpr int PANEL_B1 = 8;    // columns per outer panel of the two-level panel schedule
+#ifndef AMGS_BS_ST
+#define AMGS_BS_ST 4
+#endif
+constexpr int BS_ST = AMGS_BS_ST; // 16-row tiles per wave of the outer block sweep
+constexpr int BS_MAXC = 64;    // later columns per outer-block-sweep workgroup (max, a multiple of 16)
 constexpr int PS_CB = 2;       // later columns streamed together by a panel-sweep thread
 constexpr int PS_MAXC = 64;    // later columns per panel-sweep workgroup (max)
 
@@ -142,7 +148,27 @@ struct PSweepArgs {
     void *part;       // dot partials: part[(c * pstride + d - d0) * g + w]
     int64_t pstride;
     int64_t g;
-    void *lpart;      // lpart[((j - l0) * PANEL_B + k - l0) * g + w]
+    void *lpart;      // lpart[((j - l0) * lstride + k - l0) * g + w]
+    int64_t lstride;  // PANEL_B (one level) or PANEL_B1 (two levels)
+};
+
+// Outer block sweep of the two-level panel schedule (see k_bsweep): apply the
+// pending block [k0, k1) (coefficients final in R) to the later columns
+// [c0, c1) and form their dots with p_d, d in [d0, d0 + nd).
+struct BSweepArgs {
+    int64_t m;
+    void *Q;
+    int64_t ldq;
+    const void *P;
+    int64_t ldp;
+    const double *R;
+    int64_t ldr;
+    const int32_t *info;
+    int64_t k0, k1;   // pending block, k1 - k0 <= PANEL_B1
+    int64_t d0, nd;   // dot columns, nd <= PANEL_B1
+    int64_t c0, c1, cpw;
+    void *part;       // part[(c * PANEL_B1 + d - d0) * g + w]
+    int64_t g;
 };
 
 // Everything one amgs_qr_* call needs on the host side.
@@ -174,12 +200,14 @@ struct Ctx {
     double *S;
     int32_t *info;
     Geo geo;
-    // panel schedule (panel = 0: column schedule)
+    // panel schedule (panel = 0: column schedule; 4: one level; 8: two levels)
     int panel;
     int Up;           // rows per thread of the panel sweeps
     int64_t g_p;      // their row chunks
-    void *wpart;      // panel-sweep dot partials [n][PANEL_B][g_p]
-    void *lpart;      // partials of strict_lower(P_I^T Q_I) [PANEL_B][PANEL_B][g_p]
+    void *wpart;      // panel-sweep dot partials [n][PANEL_B or PANEL_B1][g_p]
+    void *lpart;      // partials of strict_lower(P_I^T Q_I) [lb][lb][g_p], lb = PANEL_B or PANEL_B1
+    double *lred;     // a reduced block of L [PANEL_B1][PANEL_B1] (two-level schedule)
+    int64_t g_b;      // row chunks of the outer block sweep (two-level schedule)
     int64_t x_from;   // HP column kernel: first recurrence term it applies (-1: column schedule)
     int64_t n_pub;    // column kernels publish r_{j-1,c} for c < n_pub
     int cgs;          // classical Gram-Schmidt (no pending MGS update in k_reorth_a)
@@ -214,6 +242,12 @@ template <typename T> void launch_dense_gemm(const Ctx &c);
 template <typename T> void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
                                          int64_t d0, int64_t l0, int64_t c0, int64_t c1, int64_t n_rr);
 template <typename T> void launch_pfin(const Ctx &c, int64_t s, int64_t e);
+template <typename T> void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0,
+                                         int64_t d1, int64_t c0, int64_t c1);
+template <typename T> void launch_lfin(const Ctx &c, int64_t l0, int64_t s, int64_t e);
+template <typename T> void launch_pfin2(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1,
+                                        int64_t g);
+int64_t bsweep_chunks(int64_t m, size_t w);
 template <typename T> void launch_pcol_blk(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
                                             int64_t xk0);
 int64_t pcol_blk_partials(const Ctx &c);

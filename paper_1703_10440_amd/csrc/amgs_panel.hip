@@ -36,14 +36,15 @@ constexpr int panel_rows() { return sizeof(T) == 8 ? 2 : 4; }
 // p_d, d in [d0, j], partials part[(c * PANEL_B + d - d0) * g + w]).
 // Every launch also writes the partials of p_j^T q_k, k in [l0, j) (one row
 // of strict_lower(P_I^T Q_I)), from the workgroups of grid row 0.
-template <typename T, int U, int VAR, bool NTS, int DB>
+// KB: most pending columns; LB: most columns of the panel whose L row is
+// formed (PANEL_B for the one-level schedule, PANEL_B1 for two levels).
+template <typename T, int U, int VAR, bool NTS, int DB, int KB, int LB>
 __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
 {
-    constexpr int KB = PANEL_B;
     constexpr int DL = DB > 1 ? DB - 1 : 1;
     static_assert(DB == 1 || DB == 4, "block dots are reduced four at a time");
     __shared__ T red[256 / WAVE][PS_MAXC * DB];
-    __shared__ T lred[256 / WAVE][KB];
+    __shared__ T lred[256 / WAVE][LB];
     __shared__ double s_rr;
     if (*a.info) return;
     const int64_t j = a.j, m = a.m;
@@ -72,9 +73,9 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
     }
     // q_k for the row of strict_lower(P_I^T Q_I), k in [l0, j)
     const int nl = (int)(j - a.l0);
-    T ql[KB - 1][U];
+    T ql[LB - 1][U];
 #pragma unroll
-    for (int i = 0; i < KB - 1; ++i)
+    for (int i = 0; i < LB - 1; ++i)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t k = row0 + u * 256 + tid;
@@ -178,7 +179,7 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
     // row j of strict_lower(P_I^T Q_I): p_j^T q_k for k in [l0, j)
     if (own && nl > 0) {
 #pragma unroll
-        for (int i = 0; i < KB - 1; ++i) {
+        for (int i = 0; i < LB - 1; ++i) {
             if (i < nl) {
                 T s = 0;
 #pragma unroll
@@ -192,7 +193,7 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
             T s = lred[0][tid];
 #pragma unroll
             for (int w = 1; w < 256 / WAVE; ++w) s += lred[w][tid];
-            ((T *)a.lpart)[(nl * PANEL_B + tid) * a.g + blockIdx.x] = s;
+            ((T *)a.lpart)[(nl * a.lstride + tid) * a.g + blockIdx.x] = s;
         }
     }
 }
@@ -254,10 +255,9 @@ __global__ __launch_bounds__(256) void k_pfin(int64_t s, int64_t e, const T *__r
 // x_j -= sum_k r_kj p_k for the terms k >= a.x_from that no x-block pass has
 // applied, both in place, and the partial of z_j^T x_j.  For naive / HA the
 // corrected z_j goes to zt, from where the column MV reads it.
-template <typename T, int U, int VAR>
+template <typename T, int U, int VAR, int KB>
 __global__ __launch_bounds__(256) void k_pcol_blk(RowArgs a, int64_t k0, int64_t k1)
 {
-    constexpr int KB = PANEL_B;
     constexpr bool HP = VAR == VAR_HP;
     __shared__ double lds[256 / WAVE];
     if (*a.info) return;
@@ -311,6 +311,191 @@ __global__ __launch_bounds__(256) void k_pcol_blk(RowArgs a, int64_t k0, int64_t
     }
 }
 
+// ------------------------------------- outer block of the two-level schedule
+// After an outer panel I = [d0, d0 + nd) is finished, one pass over every
+// later column c (the columns of grid row y) applies the pending outer panel
+// I-1 = [k0, k1) as a block, z_c -= Q_{I-1} r_{I-1,c} (coefficients final in
+// R), and forms the partials of W_c = P_I^T z_c.  Both are small dense
+// contractions and run on the matrix cores, on tiles of 16 rows x 16 later
+// columns: the update is D = Z + Q_{I-1} (-R_{I-1,tile}) (two 16x16x4 steps
+// over the eight pending columns, Z entering as the accumulator), and the
+// dots W += P_I^T D take D's registers directly as the B operand (four
+// 16x16x4 steps over the tile's rows, rows 8..15 of W unused).  For that the
+// tile's rows are permuted so that register v of lane l holds matrix row
+// 4 (l/16) + v of the tile: tile row i of the update's A operand is matrix
+// row bs_act(i).  A wave owns BS_ST consecutive 16-row tiles (64 rows) and
+// walks the workgroup's later columns 16 at a time.  Each column of such a
+// 64 x 16 block is read and written with whole-wave contiguous accesses and
+// moved between that layout and the matrix-core layout through the wave's
+// own LDS tile.  Each later column is read and written once per outer
+// panel.  The per-wave W tiles are added in wave order through LDS.
+template <typename T>
+__device__ __forceinline__ int bs_act(int i)
+{
+    // binary64 results: register v of lane l is tile row 4 v + l/16
+    return sizeof(T) == 8 ? 4 * (i & 3) + (i >> 2) : i;
+}
+
+template <typename T, bool NTS>
+__global__ __launch_bounds__(256) void k_bsweep(BSweepArgs a)
+{
+    typedef typename Mfma<T>::acc_t acc_t;
+    constexpr int ST = BS_ST;
+    constexpr int WR = ST * 16;         // rows per wave
+    constexpr int LD = WR + 4;          // padded LDS column (16-byte aligned)
+    constexpr int BB = PANEL_B1;
+    static_assert(WR == WAVE, "one row per lane in the contiguous accesses");
+    __shared__ T red[256 / WAVE][BS_MAXC * BB];
+    __shared__ __attribute__((aligned(16))) T tile[256 / WAVE][16][LD];
+    if (*a.info) return;
+    const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
+    const int g4 = lane >> 4, jl = lane & 15;
+    T *__restrict__ Q = (T *)a.Q;
+    const T *__restrict__ P = (const T *)a.P;
+    const int64_t m = a.m, ldq = a.ldq;
+    const int64_t wrow0 = ((int64_t)blockIdx.x * (256 / WAVE) + wave) * WR;
+    const int64_t myrow = wrow0 + lane;
+    const bool rin = myrow < m;
+    const int kw = (int)(a.k1 - a.k0), nd = (int)a.nd;
+    T(*tl)[LD] = tile[wave];
+    // A operands of the wave's tiles: q_{k0+4s+l/16} at tile row l%16
+    // (update) and p_{d0+l%16} at matrix row 4 (l/16) + v (dots, step v)
+    T qa[ST][2], pa[ST][4];
+#pragma unroll
+    for (int st = 0; st < ST; ++st) {
+        const int64_t r0 = wrow0 + st * 16;
+        const int64_t ra = r0 + bs_act<T>(jl);
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int kk = 4 * s + g4;
+            qa[st][s] = (ra < m && kk < kw) ? Q[ra + (a.k0 + kk) * ldq] : (T)0;
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int64_t rr = r0 + 4 * g4 + v;
+            pa[st][v] = (rr < m && jl < nd) ? P[rr + (a.d0 + jl) * a.ldp] : (T)0;
+        }
+    }
+    const int64_t cA = a.c0 + (int64_t)blockIdx.y * a.cpw;
+    const int64_t cB = (cA + a.cpw < a.c1) ? cA + a.cpw : a.c1;
+    for (int64_t ct = cA; ct < cB; ct += 16) {
+        const int nc = (int)(cB - ct < 16 ? cB - ct : 16);
+        // the wave's 64 x 16 block, one contiguous column access per column
+        T zl[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            zl[c] = (c < nc && rin) ? ld_stream<NTS>(Q + (ct + c) * ldq + myrow) : (T)0;
+        __syncthreads();   // the previous block's LDS reads are done
+#pragma unroll
+        for (int c = 0; c < 16; ++c) tl[c][lane] = zl[c];
+        __syncthreads();
+        const int64_t col = ct + jl;
+        const bool cin = jl < nc;
+        // B operand of the update: -r_{k0+4s+l/16, col}
+        T rb[2];
+#pragma unroll
+        for (int s = 0; s < 2; ++s) {
+            const int kk = 4 * s + g4;
+            rb[s] = (cin && kk < kw) ? -(T)a.R[(a.k0 + kk) + col * a.ldr] : (T)0;
+        }
+        acc_t w = {0, 0, 0, 0};
+#pragma unroll
+        for (int st = 0; st < ST; ++st) {
+            acc_t z;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) z[v] = tl[jl][st * 16 + 4 * g4 + v];
+            if (kw > 0) {
+                z = Mfma<T>::op(qa[st][0], rb[0], z);
+                if (kw > 4) z = Mfma<T>::op(qa[st][1], rb[1], z);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) tl[jl][st * 16 + 4 * g4 + v] = (T)z[v];
+            }
+#pragma unroll
+            for (int v = 0; v < 4; ++v) w = Mfma<T>::op(pa[st][v], (T)z[v], w);
+        }
+        if (kw > 0) {
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                if (c < nc && rin) st_stream<NTS>(Q + (ct + c) * ldq + myrow, tl[c][lane]);
+        }
+        // W[i, col] for i = Mfma<T>::row(lane, v) < PANEL_B1
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = Mfma<T>::row(lane, v);
+            if (i < BB && cin) red[wave][(col - cA) * BB + i] = (T)w[v];
+        }
+    }
+    __syncthreads();
+    const int ncols = cA < cB ? (int)(cB - cA) : 0;
+    for (int idx = tid; idx < ncols * BB; idx += 256) {
+        const int cl = idx / BB, d = idx - cl * BB;
+        if (d >= nd) continue;
+        T s = red[0][idx];
+#pragma unroll
+        for (int w = 1; w < 256 / WAVE; ++w) s += red[w][idx];
+        ((T *)a.part)[((cA + cl) * BB + d) * a.g + blockIdx.x] = s;
+    }
+}
+
+// The strictly lower block of L = strict_lower(P_I^T Q_I) for the columns
+// [s, s + b) of an outer panel starting at l0: each entry re-reduced from
+// its partials (fixed order) into lred[i * PANEL_B1 + k], binary64.
+template <typename T>
+__global__ __launch_bounds__(256) void k_lfin(const T *__restrict__ lpart, int64_t g, int off,
+                                              int b, double *__restrict__ lred,
+                                              const int32_t *info)
+{
+    if (*info) return;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    const int nitems = b * (b - 1) / 2;
+    for (int it = wave; it < nitems; it += 256 / WAVE) {
+        int q = it, i = 1;
+        while (q >= i) {
+            q -= i;
+            ++i;
+        }
+        const T v = wave_reduce_seq(lpart + ((int64_t)(off + i) * PANEL_B1 + off + q) * g, g);
+        if (lane == 0) lred[i * PANEL_B1 + q] = (double)v;
+    }
+}
+
+// r_{[s, s+b), c} for every later column c = c0 + blockIdx.x: the block dots
+// W_c re-reduced from their partials (stride B per column), then
+// (I + L) r = W solved by forward substitution in binary64 with the reduced
+// L of k_lfin, and written to R.
+template <typename T, int B>
+__global__ __launch_bounds__(256) void k_pfin2(int64_t s, int b, int64_t c0,
+                                               const T *__restrict__ wpart, int64_t g,
+                                               const double *__restrict__ lred,
+                                               double *__restrict__ R, int64_t ldr,
+                                               const int32_t *info)
+{
+    __shared__ double wv[B];
+    if (*info) return;
+    const int64_t c = c0 + blockIdx.x;
+    const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    for (int it = wave; it < b; it += 256 / WAVE) {
+        const T v = wave_reduce_seq(wpart + (c * B + it) * g, g);
+        if (lane == 0) wv[it] = (double)v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double r[B];
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            if (i < b) {
+                double t = wv[i];
+#pragma unroll
+                for (int k = 0; k < B; ++k)
+                    if (k < i) t = __builtin_fma(-lred[i * PANEL_B1 + k], r[k], t);
+                r[i] = t;
+                R[(s + i) + c * ldr] = t;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------- launchers
 template <typename T>
 void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1, int64_t d0,
@@ -327,6 +512,8 @@ void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
     a.pstride = block_dots ? PANEL_B : 1;
     a.g = c.g_p;
     a.lpart = c.lpart;
+    const bool two = c.panel == PANEL_B1;
+    a.lstride = two ? PANEL_B1 : PANEL_B;
     const int64_t ncols = a.c1 - a.c0;
     int64_t gy = 1, cpw = PS_CB;
     if (ncols > 0) {
@@ -342,13 +529,19 @@ void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
     a.cpw = cpw;
     const dim3 grid((unsigned)c.g_p, (unsigned)gy), block(256);
     const bool nts = (double)ncols * (double)c.m * sizeof(T) > SWEEP_NT_BYTES;
-#define AMGS_PS_LAUNCH(V_, NT_, DB_)                                                              \
+#define AMGS_PS_LAUNCH2(V_, NT_, DB_, KB_)                                                       \
     do {                                                                                          \
         if (c.ev_start)                                                                           \
-            hipExtLaunchKernelGGL((k_psweep<T, U, V_, NT_, DB_>), grid, block, 0, c.stream,       \
-                                  c.ev_start, c.ev_stop, 0, a);                                   \
+            hipExtLaunchKernelGGL((k_psweep<T, U, V_, NT_, DB_, KB_, KB_>), grid, block, 0,       \
+                                  c.stream, c.ev_start, c.ev_stop, 0, a);                         \
         else                                                                                      \
-            hipLaunchKernelGGL((k_psweep<T, U, V_, NT_, DB_>), grid, block, 0, c.stream, a);      \
+            hipLaunchKernelGGL((k_psweep<T, U, V_, NT_, DB_, KB_, KB_>), grid, block, 0,          \
+                               c.stream, a);                                                      \
+    } while (0)
+#define AMGS_PS_LAUNCH(V_, NT_, DB_)                                                              \
+    do {                                                                                          \
+        if (two) AMGS_PS_LAUNCH2(V_, NT_, DB_, PANEL_B1);                                         \
+        else AMGS_PS_LAUNCH2(V_, NT_, DB_, PANEL_B);                                              \
     } while (0)
 #define AMGS_PS_DB(V_, NT_)                                                                       \
     do {                                                                                          \
@@ -366,6 +559,7 @@ void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
 #undef AMGS_PS_NT
 #undef AMGS_PS_DB
 #undef AMGS_PS_LAUNCH
+#undef AMGS_PS_LAUNCH2
 }
 
 template <typename T>
@@ -374,6 +568,74 @@ void launch_pfin(const Ctx &c, int64_t s, int64_t e)
     if (e >= c.n) return;
     hipLaunchKernelGGL(k_pfin<T>, dim3((unsigned)(c.n - e)), dim3(256), 0, c.stream, s, e,
                        (const T *)c.wpart, (const T *)c.lpart, c.g_p, c.R, c.ldr, c.info);
+}
+
+int64_t bsweep_chunks(int64_t m, size_t w)
+{
+    (void)w;
+    const int64_t rows = (int64_t)(256 / WAVE) * BS_ST * 16;
+    const int64_t g = (m + rows - 1) / rows;
+    return g < 1 ? 1 : g;
+}
+
+template <typename T>
+void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0, int64_t d1, int64_t c0,
+                   int64_t c1)
+{
+    BSweepArgs a{};
+    a.m = c.m; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp; a.R = c.R; a.ldr = c.ldr;
+    a.info = c.info; a.k0 = k0; a.k1 = k1; a.d0 = d0; a.nd = d1 - d0;
+    a.c0 = c0; a.c1 = c1 > c0 ? c1 : c0; a.part = c.wpart; a.g = c.g_b;
+    const int64_t ncols = a.c1 - a.c0;
+    // column groups: multiples of 16, at most BS_MAXC, enough workgroups
+    int64_t gy = 1, cpw = 16;
+    if (ncols > 0) {
+        gy = (SWEEP_TARGET_WG + c.g_b - 1) / c.g_b;
+        const int64_t max_gy = (ncols + 15) / 16;
+        if (gy > max_gy) gy = max_gy;
+        if (gy < 1) gy = 1;
+        cpw = (ncols + gy - 1) / gy;
+        cpw = (cpw + 15) / 16 * 16;
+        if (cpw > BS_MAXC) cpw = BS_MAXC;
+        gy = (ncols + cpw - 1) / cpw;
+    }
+    a.cpw = cpw;
+    const dim3 grid((unsigned)c.g_b, (unsigned)gy), block(256);
+    const bool nts = (double)ncols * (double)c.m * sizeof(T) > SWEEP_NT_BYTES;
+#define AMGS_BS(NT_)                                                                              \
+    do {                                                                                          \
+        if (c.ev_start)                                                                           \
+            hipExtLaunchKernelGGL((k_bsweep<T, NT_>), grid, block, 0, c.stream, c.ev_start,       \
+                                  c.ev_stop, 0, a);                                               \
+        else                                                                                      \
+            hipLaunchKernelGGL((k_bsweep<T, NT_>), grid, block, 0, c.stream, a);                  \
+    } while (0)
+    if (nts) AMGS_BS(true);
+    else AMGS_BS(false);
+#undef AMGS_BS
+}
+
+template <typename T>
+void launch_lfin(const Ctx &c, int64_t l0, int64_t s, int64_t e)
+{
+    if (e - s < 2) return;
+    hipLaunchKernelGGL(k_lfin<T>, dim3(1), dim3(256), 0, c.stream, (const T *)c.lpart, c.g_p,
+                       (int)(s - l0), (int)(e - s), c.lred, c.info);
+}
+
+// g: partials per dot (row chunks of the sweep that wrote them)
+template <typename T>
+void launch_pfin2(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1, int64_t g)
+{
+    if (c1 <= c0) return;
+    const int b = (int)(e - s);
+    const dim3 grid((unsigned)(c1 - c0)), block(256);
+    if (b > PANEL_B)
+        hipLaunchKernelGGL((k_pfin2<T, PANEL_B1>), grid, block, 0, c.stream, s, b, c0,
+                           (const T *)c.wpart, g, (const double *)c.lred, c.R, c.ldr, c.info);
+    else
+        hipLaunchKernelGGL((k_pfin2<T, PANEL_B>), grid, block, 0, c.stream, s, b, c0,
+                           (const T *)c.wpart, g, (const double *)c.lred, c.R, c.ldr, c.info);
 }
 
 int64_t pcol_blk_partials(const Ctx &c) { return c.geo.g_rows2; }
@@ -386,15 +648,21 @@ void launch_pcol_blk(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k
     a.X = c.X; a.ldx = c.m; a.zt = c.zt; a.R = c.R; a.ldr = c.ldr; a.info = c.info;
     a.sp = c.sp; a.rr_out = c.rr_part; a.x_from = xk0;
     const dim3 grid((unsigned)c.geo.g_rows2), block(256);
-#define AMGS_PCB(V_)                                                                              \
+#define AMGS_PCB2(V_, KB_)                                                                        \
     switch (c.geo.U2) {                                                                           \
-    case 1: hipLaunchKernelGGL((k_pcol_blk<T, 1, V_>), grid, block, 0, c.stream, a, k0, k1); break; \
-    case 2: hipLaunchKernelGGL((k_pcol_blk<T, 2, V_>), grid, block, 0, c.stream, a, k0, k1); break; \
-    default: hipLaunchKernelGGL((k_pcol_blk<T, 4, V_>), grid, block, 0, c.stream, a, k0, k1); break; \
+    case 1: hipLaunchKernelGGL((k_pcol_blk<T, 1, V_, KB_>), grid, block, 0, c.stream, a, k0, k1); break; \
+    case 2: hipLaunchKernelGGL((k_pcol_blk<T, 2, V_, KB_>), grid, block, 0, c.stream, a, k0, k1); break; \
+    default: hipLaunchKernelGGL((k_pcol_blk<T, 4, V_, KB_>), grid, block, 0, c.stream, a, k0, k1); break; \
     }
+#define AMGS_PCB(V_)                                                                              \
+    do {                                                                                          \
+        if (k1 - k0 > PANEL_B) { AMGS_PCB2(V_, PANEL_B1); }                                       \
+        else { AMGS_PCB2(V_, PANEL_B); }                                                          \
+    } while (0)
     if (variant == VAR_HP) { AMGS_PCB(VAR_HP); }
     else { AMGS_PCB(VAR_HA); }
 #undef AMGS_PCB
+#undef AMGS_PCB2
 }
 
 template void launch_psweep<double>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t, int64_t,
@@ -402,6 +670,12 @@ template void launch_psweep<double>(const Ctx &, int, int64_t, int64_t, int64_t,
 template void launch_psweep<float>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t, int64_t,
                                    int64_t, int64_t, int64_t);
 template void launch_pfin<double>(const Ctx &, int64_t, int64_t);
+template void launch_bsweep<double>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t);
+template void launch_bsweep<float>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t);
+template void launch_lfin<double>(const Ctx &, int64_t, int64_t, int64_t);
+template void launch_lfin<float>(const Ctx &, int64_t, int64_t, int64_t);
+template void launch_pfin2<double>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t);
+template void launch_pfin2<float>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t);
 template void launch_pfin<float>(const Ctx &, int64_t, int64_t);
 template void launch_pcol_blk<double>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t);
 template void launch_pcol_blk<float>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t);

@@ -1,4 +1,6 @@
-"""Panel schedule (opts.panel = 4) of the GPU path against the oracle.
+"""Panel schedules of the GPU path against the oracle: one level (opts.panel
+= 4, panels of four columns) and two levels (opts.panel = 8, panels of eight
+columns each taken apart as two panels of four).
 
 Every GPU panel result is gated against the paper's column algorithms
 (Alg. 3/5/6, the oracle's "col" orientation), with the tolerances of the
@@ -7,8 +9,9 @@ Frobenius) for kappa(Z) <= 1e3; for kappa(Z) > 1e3 the residual and
 ||Q^T A Q - I||_2 within max(floor, 10x) the column oracle's; the binary32
 form within 64 u_32 kappa(A^{1/2} Z) sqrt(n) of the column oracle's binary32
 emulation, orthogonality within 10x.  As an extra check the same bounds are
-applied against the oracle's panel orientation, which performs the same
-regrouped operations step by step (pinned in tests/pins.py, pin_panel).
+applied against the oracle's panel orientation of the same schedule ("panel"
+or "panel8"), which performs the same regrouped operations step by step
+(pinned in tests/pins.py, pin_panel and pin_panel8).
 """
 import numpy as np
 import pytest
@@ -27,7 +30,8 @@ from paper_1703_10440_amd import amgs  # noqa: E402
 DEV = torch.device("cuda:0")
 VARIANTS = ("naive", "ha", "hp")
 U32 = 2.0 ** -24
-PANEL = 4
+PANELS = (4, 8)
+ORIENT = {4: "panel", 8: "panel8"}
 
 
 def _rel(a, b):
@@ -35,7 +39,7 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / (nb if nb else 1.0))
 
 
-def gpu_run(prob, variant, precision="fp64", panel=PANEL, reorth=False):
+def gpu_run(prob, variant, precision="fp64", panel=4, reorth=False):
     Zt = torch.from_numpy(np.ascontiguousarray(prob.Z)).to(DEV)
     print(f"[gpu] panel={panel} {prob.name} m={prob.m} n={prob.n} {variant} {precision} "
           f"reorth={reorth}", flush=True)
@@ -53,8 +57,8 @@ def gpu_run(prob, variant, precision="fp64", panel=PANEL, reorth=False):
             int(out.info.item()), out.stats)
 
 
-def oracle(prob, variant, precision="fp64", reorth=False):
-    return ref.qr_problem(prob, variant=variant, orientation="panel", precision=precision,
+def oracle(prob, variant, precision="fp64", reorth=False, panel=4):
+    return ref.qr_problem(prob, variant=variant, orientation=ORIENT[panel], precision=precision,
                           reorth=reorth)
 
 
@@ -98,14 +102,15 @@ def small_problems():
 SMALL = small_problems()
 
 
+@pytest.mark.parametrize("panel", PANELS)
 @pytest.mark.parametrize("reorth", [False, True])
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("pi", range(len(SMALL)), ids=[p.name for p in SMALL])
-def test_panel_fp64_parity(pi, variant, reorth):
+def test_panel_fp64_parity(pi, variant, reorth, panel):
     p = SMALL[pi]
     col = oracle_col(p, variant, reorth=reorth)
-    want = oracle(p, variant, reorth=reorth)
-    Q, R, P, info, st = gpu_run(p, variant, reorth=reorth)
+    want = oracle(p, variant, reorth=reorth, panel=panel)
+    Q, R, P, info, st = gpu_run(p, variant, reorth=reorth, panel=panel)
     assert info == 0 and want.info == 0 and col.info == 0
     print(f"  |Q^TAQ-I| {orth(p, Q):.2e}")
     close_1e10(R, Q, P, col, "column algorithm")
@@ -114,23 +119,26 @@ def test_panel_fp64_parity(pi, variant, reorth):
     assert st.mv_calls == {"naive": 2 * p.n, "ha": p.n, "hp": 1}[variant]
 
 
+@pytest.mark.parametrize("panel", PANELS)
 @pytest.mark.parametrize("reorth", [False, True])
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_panel_graded_ill_conditioned(variant, reorth):
-    """kappa(Z) ~ 1e6, 6 panels: residual and orthogonality at the oracle's level."""
+def test_panel_graded_ill_conditioned(variant, reorth, panel):
+    """kappa(Z) ~ 1e6, 6 panels of four (3 of eight): residual and
+    orthogonality at the oracle's level."""
     p = inputs.laplacian_graded_problem(N=16, n=24, decades=6.0, seed=11)
     col = oracle_col(p, variant, reorth=reorth)
-    want = oracle(p, variant, reorth=reorth)
-    Q, R, P, info, _ = gpu_run(p, variant, reorth=reorth)
+    want = oracle(p, variant, reorth=reorth, panel=panel)
+    Q, R, P, info, _ = gpu_run(p, variant, reorth=reorth, panel=panel)
     assert info == 0
     at_oracle_level(p, Q, R, col, "column algorithm")
     at_oracle_level(p, Q, R, want, "panel orientation")
 
 
+@pytest.mark.parametrize("panel", PANELS)
 @pytest.mark.parametrize("reorth", [False, True])
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("pi", [0, 1, 3], ids=[SMALL[i].name for i in (0, 1, 3)])
-def test_panel_fp32_form(pi, variant, reorth):
+def test_panel_fp32_form(pi, variant, reorth, panel):
     p = SMALL[pi]
     Z32 = np.asfortranarray(p.Z.astype(np.float32).astype(np.float64))
     if p.csr is not None:
@@ -140,12 +148,13 @@ def test_panel_fp32_form(pi, variant, reorth):
         p32 = inputs.Problem(p.name, Z32, dense=np.asfortranarray(
             p.dense.astype(np.float32).astype(np.float64)))
     kappa = np.linalg.cond(oracle_col(p32, variant).R)
-    Q, R, P, info, _ = gpu_run(p32, variant, precision="fp32", reorth=reorth)
+    Q, R, P, info, _ = gpu_run(p32, variant, precision="fp32", reorth=reorth, panel=panel)
     assert info == 0
     tol = 64 * U32 * kappa * np.sqrt(p.n)
     o_g = orth(p32, Q)
     for what, want32 in (("column algorithm", oracle_col(p32, variant, "fp32", reorth=reorth)),
-                         ("panel orientation", oracle(p32, variant, "fp32", reorth=reorth))):
+                         ("panel orientation", oracle(p32, variant, "fp32", reorth=reorth,
+                                                      panel=panel))):
         e32 = _rel(R, want32.R)
         o_o = orth(p32, want32.Q)
         print(f"  R vs fp32 {what} {e32:.2e} tol {tol:.2e} orth {o_g:.2e} (oracle {o_o:.2e})")
@@ -153,38 +162,44 @@ def test_panel_fp32_form(pi, variant, reorth):
         assert o_g <= max(10 * o_o, 1e-6), what
 
 
+@pytest.mark.parametrize("panel", PANELS)
 @pytest.mark.parametrize("variant", VARIANTS)
-def test_panel_many_workgroups_deterministic(variant):
+def test_panel_many_workgroups_deterministic(variant, panel):
     """m = 64000, n = 40: the sweeps after each panel run hundreds of row
     chunks and several column groups; parity and bit-identical repeats."""
     p = inputs.laplacian_graded_problem(N=40, n=40, decades=2.0, seed=14)
-    Q, R, P, info, _ = gpu_run(p, variant)
-    Q2, R2, _, _, _ = gpu_run(p, variant)
+    Q, R, P, info, _ = gpu_run(p, variant, panel=panel)
+    Q2, R2, _, _, _ = gpu_run(p, variant, panel=panel)
     assert info == 0
     assert np.array_equal(R, R2) and np.array_equal(Q, Q2)
     print(f"  orth {orth(p, Q):.2e}")
     close_1e10(R, Q, P, oracle_col(p, variant), "column algorithm")
-    close_1e10(R, Q, P, oracle(p, variant), "panel orientation")
+    close_1e10(R, Q, P, oracle(p, variant, panel=panel), "panel orientation")
 
 
-def test_panel_edges():
+@pytest.mark.parametrize("panel", PANELS)
+def test_panel_edges(panel):
     """Panel boundaries: n = 1, 4 (one full panel), 5 (a one-column last
-    panel), 8; square and tiny m; dense and CSR."""
+    panel), 8 (one outer panel), 9 (an outer panel and one column), 12, 17;
+    square and tiny m; dense and CSR."""
     g = inputs.rng(15)
-    for m, n in ((700, 1), (300, 4), (300, 5), (200, 8), (40, 40), (5, 3)):
+    for m, n in ((700, 1), (300, 4), (300, 5), (200, 8), (300, 9), (300, 12), (300, 17),
+                 (40, 40), (5, 3)):
         A = inputs.gram_spd(g, m)
         Z = np.asfortranarray(g.standard_normal((m, n)))
         for prob in (inputs.Problem(f"edge{m}x{n}", Z, dense=A),
                      inputs.Problem(f"edgecsr{m}x{n}", Z, csr=inputs.csr_from_dense(A))):
             for v in VARIANTS:
-                Q, R, P, info, _ = gpu_run(prob, v)
+                Q, R, P, info, _ = gpu_run(prob, v, panel=panel)
                 assert info == 0
-                for what, want in (("column", oracle_col(prob, v)), ("panel", oracle(prob, v))):
+                for what, want in (("column", oracle_col(prob, v)),
+                                   ("panel", oracle(prob, v, panel=panel))):
                     assert _rel(R, want.R) <= 1e-10, (prob.name, v, what, _rel(R, want.R))
                     assert _rel(Q, want.Q) <= 1e-10, (prob.name, v, what, _rel(Q, want.Q))
 
 
-def test_panel_breakdown_reports_column():
+@pytest.mark.parametrize("panel", PANELS)
+def test_panel_breakdown_reports_column(panel):
     """A zero column in the second panel (column 6) and a NaN in the third
     (column 10) stop at the right index; earlier columns stay valid."""
     g = inputs.rng(16)
@@ -196,13 +211,14 @@ def test_panel_breakdown_reports_column():
     Zn = Z.copy(order="F")
     Zn[7, 9] = np.nan
     for v in VARIANTS:
-        _, R, _, info, _ = gpu_run(inputs.Problem("zero", Zc, dense=A), v)
-        want = oracle(inputs.Problem("zero", Zc, dense=A), v)
+        _, R, _, info, _ = gpu_run(inputs.Problem("zero", Zc, dense=A), v, panel=panel)
+        want = oracle(inputs.Problem("zero", Zc, dense=A), v, panel=panel)
         col = oracle_col(inputs.Problem("zero", Zc, dense=A), v)
         assert info == 6 and want.info == 6 and col.info == 6
         assert _rel(R[:5, :5], want.R[:5, :5]) <= 1e-10
         assert _rel(R[:5, :5], col.R[:5, :5]) <= 1e-10
-        _, _, _, info, _ = gpu_run(inputs.Problem("nan", Zn, csr=inputs.csr_from_dense(A)), v)
+        _, _, _, info, _ = gpu_run(inputs.Problem("nan", Zn, csr=inputs.csr_from_dense(A)), v,
+                                   panel=panel)
         assert info == 10
 
 
@@ -212,9 +228,9 @@ def test_panel_argument_errors():
     info = torch.zeros(1, dtype=torch.int32, device=DEV)
     Z = torch.zeros(10, 4, dtype=torch.float64, device=DEV)
     work = torch.empty(1 << 20, dtype=torch.uint8, device=DEV)
-    # panel widths other than 4 are invalid; the panel schedule with classical
-    # Gram-Schmidt is not supported (with the second pass it is)
-    for panel, cgs, want in ((3, 0, -1), (8, 0, -1), (4, 1, -4)):
+    # panel values other than 4 and 8 are invalid; the panel schedules with
+    # classical Gram-Schmidt are not supported (with the second pass they are)
+    for panel, cgs, want in ((3, 0, -1), (16, 0, -1), (4, 1, -4), (8, 1, -4)):
         opts = amgs.Opts(0, panel, cgs, 0)
         st = amgs.amgs_qr_dense(h, 10, Z.data_ptr(), 10, 4, Z.data_ptr(), 10, Z.data_ptr(), 10,
                                 Z.data_ptr(), 4, None, 0, 1, 0, C.byref(opts), work.data_ptr(),
@@ -222,3 +238,4 @@ def test_panel_argument_errors():
         assert st == want, (panel, cgs, st)
     assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(0, 3, 0, 0)) == 0
     assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(0, 4, 0, 0)) > 0
+    assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(0, 8, 0, 0)) > 0
