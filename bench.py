@@ -7,11 +7,12 @@ memory.  The headline line is the default workload:
 
   lap128_n128    7-point 3-D Laplacian on a 128^3 grid + 1e-2 I (CSR,
                  m = 2,097,152, nnz = 14,581,760), Z 2097152 x 128 with
-                 kappa(Z) ~ 1e4, HA form in binary64 in the panel schedule
-                 (value: the fastest n-MV configuration, gated against the
-                 column algorithm at this size in the GPU tests), plus naive /
-                 HA / HP in binary64 and in the binary32-storage form, with
-                 and without the binary64 second pass, in both schedules.
+                 kappa(Z) ~ 1e4, HA form in binary64 in the two-level panel
+                 schedule (value: the fastest n-MV configuration, gated
+                 against the column algorithm at this size in the GPU
+                 tests), plus naive / HA / HP in binary64 and in the
+                 binary32-storage form, with and without the binary64 second
+                 pass, in the column schedule and both panel schedules.
 
 Other workloads (same JSON shape, reported in the design notes):
   lap64_n64      Laplacian 64^3 + 1e-2 I, Z 262144 x 64, kappa(Z) ~ 1e6.
@@ -617,7 +618,7 @@ def main():
     ap.add_argument("--variant", default="ha", choices=["naive", "ha", "hp"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
     ap.add_argument("--reorth", action="store_true", help="second pass in the headline run")
-    ap.add_argument("--panel", type=int, default=4, choices=[0, 4, 8],
+    ap.add_argument("--panel", type=int, default=8, choices=[0, 4, 8],
                     help="schedule of the headline run: 0 column order, 4 panels of four, "
                          "8 panels of eight taken apart as panels of four")
     args = ap.parse_args()

@@ -78,7 +78,8 @@ struct ProfScope {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t part, s_part, rr_part, S, zt, xv, X, P, wpart, lpart, lred, ell_col, ell_val, tile_long;
+    size_t part, s_part, rr_part, S, zt, xv, X, P, wpart, lpart, lpart8, lred, ell_col, ell_val,
+        tile_long;
     size_t base;    // bytes without the padded copy of A
     size_t total;   // bytes with it (the size the query reports)
 };
@@ -113,12 +114,15 @@ Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_g
     L.xv = variant != VAR_HP ? take((size_t)m * w) : off;
     L.X = variant == VAR_HP ? take((size_t)m * n * w) : off;
     L.P = P_given ? off : take((size_t)m * n * w);
-    const size_t pb = panel == PANEL_B1 ? PANEL_B1 : PANEL_B;
+    const bool two = panel == PANEL_B1;
+    const size_t pb = two ? PANEL_B1 : PANEL_B;
     // the outer block sweep may use more row chunks than the panel sweeps
-    const int64_t g_w = panel == PANEL_B1 && bsweep_chunks(m, w) > g_p ? bsweep_chunks(m, w) : g_p;
+    const int64_t g_b = two ? bsweep_chunks(m, w) : 0;
+    const int64_t g_w = g_b > g_p ? g_b : g_p;
     L.wpart = panel ? take((size_t)n * pb * g_w * 8) : off;
-    L.lpart = panel ? take(pb * pb * g_p * 8) : off;
-    L.lred = panel == PANEL_B1 ? take((size_t)PANEL_B1 * PANEL_B1 * 8) : off;
+    L.lpart = panel ? take((size_t)PANEL_B * PANEL_B * g_p * 8) : off;
+    L.lpart8 = two ? take((size_t)PANEL_B1 * PANEL_B1 * g_b * 8) : off;
+    L.lred = two ? take((size_t)PANEL_B1 * PANEL_B1 * 8) : off;
     L.base = off;
     // padded copy of a CSR A for the column MV (naive and HA), last, so that
     // a smaller workspace can leave it out; the size does not depend on nnz,
@@ -440,7 +444,7 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
                     d0 = j; c0 = j + 1; c1 = e;
                 }
                 const bool block1 = outer_end && !two;
-                profiled(block1, [&] { launch_psweep<T>(c, variant, j, k0, k1, d0, S, c0, c1, n_rr); });
+                profiled(block1, [&] { launch_psweep<T>(c, variant, j, k0, k1, d0, s, c0, c1, n_rr); });
                 st.kernel_launches++;
                 st.sweep_launches++;
                 const double pb = psweep_bytes(c.m, w, c1 > c0 ? c1 - c0 : 0, k1 - k0, j - d0 + 1, variant);
@@ -450,9 +454,8 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
                     st.block_sweep_bytes += pb;
                 }
                 if (inner_end) {
-                    launch_lfin<T>(c, S, s, e);
-                    launch_pfin2<T>(c, s, e, e, E, c.g_p);
-                    st.kernel_launches += 2;
+                    launch_pfin<T>(c, s, e, E);
+                    st.kernel_launches++;
                 }
                 if (outer_end) {
                     if (two) {
@@ -465,11 +468,11 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
                         st.sweep_bytes += bb;
                         st.block_sweep_launches++;
                         st.block_sweep_bytes += bb;
-                        launch_lfin<T>(c, S, S, E);
-                        launch_pfin2<T>(c, S, E, E, c.n, c.g_b);
+                        launch_lfin<T>(c, S, E);
+                        launch_pfin2<T>(c, S, E, E, c.n);
                         st.kernel_launches += 2;
                     } else {
-                        launch_pfin<T>(c, s, e);
+                        launch_pfin<T>(c, s, e, c.n);
                         st.kernel_launches++;
                     }
                     // HP: once r_{i,c} of the last HP_XB columns are final,
@@ -591,6 +594,7 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
         c.sp.g = c.g_p;
         c.wpart = base + L.wpart;
         c.lpart = base + L.lpart;
+        c.lpart8 = base + L.lpart8;
         c.lred = (double *)(base + L.lred);
         c.g_b = bsweep_chunks(c.m, w);
     }

@@ -26,7 +26,7 @@ constexpr int PANEL_B1 = 8;    // columns per outer panel of the two-level panel
 #define AMGS_BS_ST 4
 #endif
 constexpr int BS_ST = AMGS_BS_ST; // 16-row tiles per wave of the outer block sweep
-constexpr int BS_MAXC = 64;    // later columns per outer-block-sweep workgroup (max, a multiple of 16)
+constexpr int BS_MAXC = 256;   // later columns per outer-block-sweep workgroup (max, a multiple of 16)
 constexpr int PS_CB = 2;       // later columns streamed together by a panel-sweep thread
 constexpr int PS_MAXC = 64;    // later columns per panel-sweep workgroup (max)
 
@@ -149,7 +149,7 @@ struct PSweepArgs {
     int64_t pstride;
     int64_t g;
     void *lpart;      // lpart[((j - l0) * lstride + k - l0) * g + w]
-    int64_t lstride;  // PANEL_B (one level) or PANEL_B1 (two levels)
+    int64_t lstride;  // PANEL_B
 };
 
 // Outer block sweep of the two-level panel schedule (see k_bsweep): apply the
@@ -168,6 +168,7 @@ struct BSweepArgs {
     int64_t d0, nd;   // dot columns, nd <= PANEL_B1
     int64_t c0, c1, cpw;
     void *part;       // part[(c * PANEL_B1 + d - d0) * g + w]
+    void *lpart;      // partials of P_I^T Q_I: lpart[(i * PANEL_B1 + k) * g + w]
     int64_t g;
 };
 
@@ -205,9 +206,12 @@ struct Ctx {
     int Up;           // rows per thread of the panel sweeps
     int64_t g_p;      // their row chunks
     void *wpart;      // panel-sweep dot partials [n][PANEL_B or PANEL_B1][g_p]
-    void *lpart;      // partials of strict_lower(P_I^T Q_I) [lb][lb][g_p], lb = PANEL_B or PANEL_B1
-    double *lred;     // a reduced block of L [PANEL_B1][PANEL_B1] (two-level schedule)
-    int64_t g_b;      // row chunks of the outer block sweep (two-level schedule)
+    void *lpart;      // partials of strict_lower(P_I^T Q_I) [PANEL_B][PANEL_B][g_p] (inner panels)
+    // two-level schedule: the outer block sweep's row chunks, its partials of
+    // P_I^T Q_I [PANEL_B1][PANEL_B1][g_b], and the reduced L [PANEL_B1][PANEL_B1]
+    int64_t g_b;
+    void *lpart8;
+    double *lred;
     int64_t x_from;   // HP column kernel: first recurrence term it applies (-1: column schedule)
     int64_t n_pub;    // column kernels publish r_{j-1,c} for c < n_pub
     int cgs;          // classical Gram-Schmidt (no pending MGS update in k_reorth_a)
@@ -241,12 +245,11 @@ template <typename T> void launch_csr_spmm(const Ctx &c);
 template <typename T> void launch_dense_gemm(const Ctx &c);
 template <typename T> void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
                                          int64_t d0, int64_t l0, int64_t c0, int64_t c1, int64_t n_rr);
-template <typename T> void launch_pfin(const Ctx &c, int64_t s, int64_t e);
+template <typename T> void launch_pfin(const Ctx &c, int64_t s, int64_t e, int64_t c1);
 template <typename T> void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0,
                                          int64_t d1, int64_t c0, int64_t c1);
-template <typename T> void launch_lfin(const Ctx &c, int64_t l0, int64_t s, int64_t e);
-template <typename T> void launch_pfin2(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1,
-                                        int64_t g);
+template <typename T> void launch_lfin(const Ctx &c, int64_t s, int64_t e);
+template <typename T> void launch_pfin2(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1);
 int64_t bsweep_chunks(int64_t m, size_t w);
 template <typename T> void launch_pcol_blk(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
                                             int64_t xk0);

@@ -336,8 +336,27 @@ __device__ __forceinline__ int bs_act(int i)
     return sizeof(T) == 8 ? 4 * (i & 3) + (i >> 2) : i;
 }
 
+// The W partials of one 16-column tile starting at ct (nc columns): the
+// waves' entries added in wave order.
+template <typename T>
+__device__ __forceinline__ void bs_wpart(const T (*red)[16 * PANEL_B1], int64_t ct, int nc,
+                                         int nd, const BSweepArgs &a)
+{
+    constexpr int BB = PANEL_B1;
+    const int tid = threadIdx.x;
+    if (tid < nc * BB) {
+        const int cl = tid / BB, d = tid - cl * BB;
+        if (d < nd) {
+            T s = red[0][tid];
+#pragma unroll
+            for (int w = 1; w < 256 / WAVE; ++w) s += red[w][tid];
+            ((T *)a.part)[((ct + cl) * BB + d) * a.g + blockIdx.x] = s;
+        }
+    }
+}
+
 template <typename T, bool NTS>
-__global__ __launch_bounds__(256) void k_bsweep(BSweepArgs a)
+__global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
 {
     typedef typename Mfma<T>::acc_t acc_t;
     constexpr int ST = BS_ST;
@@ -345,7 +364,7 @@ __global__ __launch_bounds__(256) void k_bsweep(BSweepArgs a)
     constexpr int LD = WR + 4;          // padded LDS column (16-byte aligned)
     constexpr int BB = PANEL_B1;
     static_assert(WR == WAVE, "one row per lane in the contiguous accesses");
-    __shared__ T red[256 / WAVE][BS_MAXC * BB];
+    __shared__ T red[256 / WAVE][16 * BB];   // the waves' W of one 16-column tile
     __shared__ __attribute__((aligned(16))) T tile[256 / WAVE][16][LD];
     if (*a.info) return;
     const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
@@ -358,24 +377,39 @@ __global__ __launch_bounds__(256) void k_bsweep(BSweepArgs a)
     const bool rin = myrow < m;
     const int kw = (int)(a.k1 - a.k0), nd = (int)a.nd;
     T(*tl)[LD] = tile[wave];
-    // A operands of the wave's tiles: q_{k0+4s+l/16} at tile row l%16
-    // (update) and p_{d0+l%16} at matrix row 4 (l/16) + v (dots, step v)
+    // Operands that stay for every column: p_{d0+l%16} at matrix row
+    // 4 (l/16) + v (A of the dots, step v) and q_{k0+4s+l/16} at tile row
+    // l%16 (A of the update), both brought in with contiguous column reads
+    // through the LDS tile.  Grid row 0 also forms P_I^T Q_I over the wave's
+    // rows (entry [i, k] = p_{d0+i}^T q_{d0+k}, B operand q_{d0+l%16} at
+    // matrix row 4 (l/16) + v), added over the waves after the columns; its
+    // strictly lower part is the L of the block solve.
+    const bool own_l = blockIdx.y == 0 && nd > 1;
     T qa[ST][2], pa[ST][4];
+    acc_t lw = {0, 0, 0, 0};
 #pragma unroll
-    for (int st = 0; st < ST; ++st) {
-        const int64_t r0 = wrow0 + st * 16;
-        const int64_t ra = r0 + bs_act<T>(jl);
+    for (int c = 0; c < BB; ++c) {
+        tl[c][lane] = (rin && c < nd) ? P[myrow + (a.d0 + c) * a.ldp] : (T)0;
+        tl[BB + c][lane] = (own_l && rin && c < nd) ? Q[myrow + (a.d0 + c) * ldq] : (T)0;
+    }
+    __syncthreads();
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int kk = 4 * s + g4;
-            qa[st][s] = (ra < m && kk < kw) ? Q[ra + (a.k0 + kk) * ldq] : (T)0;
-        }
+    for (int st = 0; st < ST; ++st)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-            const int64_t rr = r0 + 4 * g4 + v;
-            pa[st][v] = (rr < m && jl < nd) ? P[rr + (a.d0 + jl) * a.ldp] : (T)0;
+            const int r = st * 16 + 4 * g4 + v;
+            pa[st][v] = jl < BB ? tl[jl][r] : (T)0;
+            if (own_l) lw = Mfma<T>::op(pa[st][v], jl < BB ? tl[BB + jl][r] : (T)0, lw);
         }
-    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < BB; ++c)
+        tl[c][lane] = (rin && c < kw) ? Q[myrow + (a.k0 + c) * ldq] : (T)0;
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < ST; ++st)
+#pragma unroll
+        for (int s2 = 0; s2 < 2; ++s2) qa[st][s2] = tl[4 * s2 + g4][st * 16 + bs_act<T>(jl)];
     const int64_t cA = a.c0 + (int64_t)blockIdx.y * a.cpw;
     const int64_t cB = (cA + a.cpw < a.c1) ? cA + a.cpw : a.c1;
     for (int64_t ct = cA; ct < cB; ct += 16) {
@@ -385,7 +419,8 @@ __global__ __launch_bounds__(256) void k_bsweep(BSweepArgs a)
 #pragma unroll
         for (int c = 0; c < 16; ++c)
             zl[c] = (c < nc && rin) ? ld_stream<NTS>(Q + (ct + c) * ldq + myrow) : (T)0;
-        __syncthreads();   // the previous block's LDS reads are done
+        __syncthreads();   // the previous block's LDS reads and W entries are done
+        if (ct > cA) bs_wpart<T>(red, ct - 16, 16, nd, a);
 #pragma unroll
         for (int c = 0; c < 16; ++c) tl[c][lane] = zl[c];
         __syncthreads();
@@ -419,45 +454,54 @@ __global__ __launch_bounds__(256) void k_bsweep(BSweepArgs a)
             for (int c = 0; c < 16; ++c)
                 if (c < nc && rin) st_stream<NTS>(Q + (ct + c) * ldq + myrow, tl[c][lane]);
         }
-        // W[i, col] for i = Mfma<T>::row(lane, v) < PANEL_B1
+        // W[i, col] for i = Mfma<T>::row(lane, v) < PANEL_B1, added over the
+        // waves at the next tile (or below)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int i = Mfma<T>::row(lane, v);
-            if (i < BB && cin) red[wave][(col - cA) * BB + i] = (T)w[v];
+            if (i < BB) red[wave][jl * BB + i] = (T)w[v];
         }
     }
     __syncthreads();
-    const int ncols = cA < cB ? (int)(cB - cA) : 0;
-    for (int idx = tid; idx < ncols * BB; idx += 256) {
-        const int cl = idx / BB, d = idx - cl * BB;
-        if (d >= nd) continue;
-        T s = red[0][idx];
+    if (cA < cB) {
+        const int64_t last = cA + (cB - 1 - cA) / 16 * 16;
+        bs_wpart<T>(red, last, (int)(cB - last), nd, a);
+    }
+    if (own_l) {
+        __syncthreads();   // the W entries have been read
 #pragma unroll
-        for (int w = 1; w < 256 / WAVE; ++w) s += red[w][idx];
-        ((T *)a.part)[((cA + cl) * BB + d) * a.g + blockIdx.x] = s;
+        for (int v = 0; v < 4; ++v) {
+            const int i = Mfma<T>::row(lane, v);
+            if (i < BB && jl < BB) red[wave][i * BB + jl] = (T)lw[v];
+        }
+        __syncthreads();
+        for (int idx = tid; idx < BB * BB; idx += 256) {
+            const int i = idx / BB, k = idx - i * BB;
+            if (!(k < i && i < nd)) continue;
+            T s = red[0][idx];
+#pragma unroll
+            for (int w = 1; w < 256 / WAVE; ++w) s += red[w][idx];
+            ((T *)a.lpart)[(int64_t)idx * a.g + blockIdx.x] = s;
+        }
     }
 }
 
-// The strictly lower block of L = strict_lower(P_I^T Q_I) for the columns
-// [s, s + b) of an outer panel starting at l0: each entry re-reduced from
-// its partials (fixed order) into lred[i * PANEL_B1 + k], binary64.
+// L = strict_lower(P_I^T Q_I) of an outer panel of b columns, each entry
+// re-reduced from the partials k_bsweep wrote (fixed order), one wave per
+// entry, into lred[i * PANEL_B1 + k] in binary64.
 template <typename T>
-__global__ __launch_bounds__(256) void k_lfin(const T *__restrict__ lpart, int64_t g, int off,
-                                              int b, double *__restrict__ lred,
-                                              const int32_t *info)
+__global__ __launch_bounds__(WAVE) void k_lfin(const T *__restrict__ lpart, int64_t g, int b,
+                                               double *__restrict__ lred, const int32_t *info)
 {
     if (*info) return;
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-    const int nitems = b * (b - 1) / 2;
-    for (int it = wave; it < nitems; it += 256 / WAVE) {
-        int q = it, i = 1;
-        while (q >= i) {
-            q -= i;
-            ++i;
-        }
-        const T v = wave_reduce_seq(lpart + ((int64_t)(off + i) * PANEL_B1 + off + q) * g, g);
-        if (lane == 0) lred[i * PANEL_B1 + q] = (double)v;
+    int q = blockIdx.x, i = 1;
+    while (q >= i) {
+        q -= i;
+        ++i;
     }
+    if (i >= b) return;
+    const T v = wave_reduce_seq(lpart + (int64_t)(i * PANEL_B1 + q) * g, g);
+    if (threadIdx.x == 0) lred[i * PANEL_B1 + q] = (double)v;
 }
 
 // r_{[s, s+b), c} for every later column c = c0 + blockIdx.x: the block dots
@@ -465,7 +509,7 @@ __global__ __launch_bounds__(256) void k_lfin(const T *__restrict__ lpart, int64
 // (I + L) r = W solved by forward substitution in binary64 with the reduced
 // L of k_lfin, and written to R.
 template <typename T, int B>
-__global__ __launch_bounds__(256) void k_pfin2(int64_t s, int b, int64_t c0,
+__global__ __launch_bounds__(B * WAVE) void k_pfin2(int64_t s, int b, int64_t c0,
                                                const T *__restrict__ wpart, int64_t g,
                                                const double *__restrict__ lred,
                                                double *__restrict__ R, int64_t ldr,
@@ -475,9 +519,9 @@ __global__ __launch_bounds__(256) void k_pfin2(int64_t s, int b, int64_t c0,
     if (*info) return;
     const int64_t c = c0 + blockIdx.x;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-    for (int it = wave; it < b; it += 256 / WAVE) {
-        const T v = wave_reduce_seq(wpart + (c * B + it) * g, g);
-        if (lane == 0) wv[it] = (double)v;
+    if (wave < b) {
+        const T v = wave_reduce_seq(wpart + (c * B + wave) * g, g);
+        if (lane == 0) wv[wave] = (double)v;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -513,7 +557,7 @@ void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
     a.g = c.g_p;
     a.lpart = c.lpart;
     const bool two = c.panel == PANEL_B1;
-    a.lstride = two ? PANEL_B1 : PANEL_B;
+    a.lstride = PANEL_B;
     const int64_t ncols = a.c1 - a.c0;
     int64_t gy = 1, cpw = PS_CB;
     if (ncols > 0) {
@@ -532,10 +576,10 @@ void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
 #define AMGS_PS_LAUNCH2(V_, NT_, DB_, KB_)                                                       \
     do {                                                                                          \
         if (c.ev_start)                                                                           \
-            hipExtLaunchKernelGGL((k_psweep<T, U, V_, NT_, DB_, KB_, KB_>), grid, block, 0,       \
+            hipExtLaunchKernelGGL((k_psweep<T, U, V_, NT_, DB_, KB_, PANEL_B>), grid, block, 0,   \
                                   c.stream, c.ev_start, c.ev_stop, 0, a);                         \
         else                                                                                      \
-            hipLaunchKernelGGL((k_psweep<T, U, V_, NT_, DB_, KB_, KB_>), grid, block, 0,          \
+            hipLaunchKernelGGL((k_psweep<T, U, V_, NT_, DB_, KB_, PANEL_B>), grid, block, 0,      \
                                c.stream, a);                                                      \
     } while (0)
 #define AMGS_PS_LAUNCH(V_, NT_, DB_)                                                              \
@@ -563,10 +607,10 @@ void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
 }
 
 template <typename T>
-void launch_pfin(const Ctx &c, int64_t s, int64_t e)
+void launch_pfin(const Ctx &c, int64_t s, int64_t e, int64_t c1)
 {
-    if (e >= c.n) return;
-    hipLaunchKernelGGL(k_pfin<T>, dim3((unsigned)(c.n - e)), dim3(256), 0, c.stream, s, e,
+    if (e >= c1) return;
+    hipLaunchKernelGGL(k_pfin<T>, dim3((unsigned)(c1 - e)), dim3(256), 0, c.stream, s, e,
                        (const T *)c.wpart, (const T *)c.lpart, c.g_p, c.R, c.ldr, c.info);
 }
 
@@ -585,7 +629,7 @@ void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0, int64_t d1,
     BSweepArgs a{};
     a.m = c.m; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp; a.R = c.R; a.ldr = c.ldr;
     a.info = c.info; a.k0 = k0; a.k1 = k1; a.d0 = d0; a.nd = d1 - d0;
-    a.c0 = c0; a.c1 = c1 > c0 ? c1 : c0; a.part = c.wpart; a.g = c.g_b;
+    a.c0 = c0; a.c1 = c1 > c0 ? c1 : c0; a.part = c.wpart; a.lpart = c.lpart8; a.g = c.g_b;
     const int64_t ncols = a.c1 - a.c0;
     // column groups: multiples of 16, at most BS_MAXC, enough workgroups
     int64_t gy = 1, cpw = 16;
@@ -616,26 +660,22 @@ void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0, int64_t d1,
 }
 
 template <typename T>
-void launch_lfin(const Ctx &c, int64_t l0, int64_t s, int64_t e)
+void launch_lfin(const Ctx &c, int64_t s, int64_t e)
 {
-    if (e - s < 2) return;
-    hipLaunchKernelGGL(k_lfin<T>, dim3(1), dim3(256), 0, c.stream, (const T *)c.lpart, c.g_p,
-                       (int)(s - l0), (int)(e - s), c.lred, c.info);
+    const int b = (int)(e - s);
+    if (b < 2) return;
+    hipLaunchKernelGGL(k_lfin<T>, dim3((unsigned)(b * (b - 1) / 2)), dim3(WAVE), 0, c.stream,
+                       (const T *)c.lpart8, c.g_b, b, c.lred, c.info);
 }
 
-// g: partials per dot (row chunks of the sweep that wrote them)
+// The outer block's coefficients for the later columns [c0, c1).
 template <typename T>
-void launch_pfin2(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1, int64_t g)
+void launch_pfin2(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1)
 {
     if (c1 <= c0) return;
-    const int b = (int)(e - s);
-    const dim3 grid((unsigned)(c1 - c0)), block(256);
-    if (b > PANEL_B)
-        hipLaunchKernelGGL((k_pfin2<T, PANEL_B1>), grid, block, 0, c.stream, s, b, c0,
-                           (const T *)c.wpart, g, (const double *)c.lred, c.R, c.ldr, c.info);
-    else
-        hipLaunchKernelGGL((k_pfin2<T, PANEL_B>), grid, block, 0, c.stream, s, b, c0,
-                           (const T *)c.wpart, g, (const double *)c.lred, c.R, c.ldr, c.info);
+    hipLaunchKernelGGL((k_pfin2<T, PANEL_B1>), dim3((unsigned)(c1 - c0)), dim3(PANEL_B1 * WAVE), 0,
+                       c.stream, s, (int)(e - s), c0, (const T *)c.wpart, c.g_b,
+                       (const double *)c.lred, c.R, c.ldr, c.info);
 }
 
 int64_t pcol_blk_partials(const Ctx &c) { return c.geo.g_rows2; }
@@ -669,14 +709,14 @@ template void launch_psweep<double>(const Ctx &, int, int64_t, int64_t, int64_t,
                                     int64_t, int64_t, int64_t);
 template void launch_psweep<float>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t, int64_t,
                                    int64_t, int64_t, int64_t);
-template void launch_pfin<double>(const Ctx &, int64_t, int64_t);
+template void launch_pfin<double>(const Ctx &, int64_t, int64_t, int64_t);
 template void launch_bsweep<double>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t);
 template void launch_bsweep<float>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t);
-template void launch_lfin<double>(const Ctx &, int64_t, int64_t, int64_t);
-template void launch_lfin<float>(const Ctx &, int64_t, int64_t, int64_t);
-template void launch_pfin2<double>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t);
-template void launch_pfin2<float>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t);
-template void launch_pfin<float>(const Ctx &, int64_t, int64_t);
+template void launch_lfin<double>(const Ctx &, int64_t, int64_t);
+template void launch_lfin<float>(const Ctx &, int64_t, int64_t);
+template void launch_pfin2<double>(const Ctx &, int64_t, int64_t, int64_t, int64_t);
+template void launch_pfin2<float>(const Ctx &, int64_t, int64_t, int64_t, int64_t);
+template void launch_pfin<float>(const Ctx &, int64_t, int64_t, int64_t);
 template void launch_pcol_blk<double>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t);
 template void launch_pcol_blk<float>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t);
 

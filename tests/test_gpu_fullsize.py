@@ -9,18 +9,21 @@ orientation as an extra check.
 
 * Laplacian 64^3 + 1e-2 I, Z 262144 x 64, kappa(Z) ~ 1e6 (no R bound
   applies): residual and ||Q^T A Q - I||_2 within max(floor, 10x) the
-  oracle's -- naive, HA, HP in binary64 in both schedules; the second pass in
-  binary64 and in the binary32 form, both schedules; CGS and CGS2.  At this m
+  oracle's -- naive, HA, HP in binary64; the second pass in binary64 and in
+  the binary32 form; CGS and CGS2 (column schedule only).  At this m
   the column and second-pass kernels hold four rows per thread, the
   configuration the measured second-pass and CGS figures run.
 * dense 16384 x 16384, Z 16384 x 256, kappa(Z) ~ 1.3: HP in binary64 (R, Q
   within 1e-10) and in the binary32 form (R within 64 u_32 kappa(R) sqrt(n)
   of the oracle's binary32 emulation, the 128 x 128 binary32 matrix-core
-  tiles), both schedules.
+  tiles).
 * Laplacian 128^3 + 1e-2 I, Z 2097152 x 128, kappa(Z) ~ 1e4: HA and HP in
   the binary32 form against the oracle's binary32 emulation on the same
   binary32 inputs (residual and orthogonality within 10x), and in binary64
-  (residual and orthogonality within max(floor, 10x)), both schedules.
+  (residual and orthogonality within max(floor, 10x)).
+
+Every case but CGS runs in the column schedule and in both panel schedules
+(panels of four; panels of eight taken apart as panels of four).
 """
 import numpy as np
 import pytest
@@ -69,7 +72,8 @@ def _oracles(prob, variant, precision, panel, reorth=False, cgs=False):
     outs = [("column algorithm",
              ref.qr_problem(prob, orientation="cgs" if cgs else "col", **kw))]
     if panel:
-        outs.append(("panel orientation", ref.qr_problem(prob, orientation="panel", **kw)))
+        outs.append(("panel orientation",
+                     ref.qr_problem(prob, orientation={4: "panel", 8: "panel8"}[panel], **kw)))
     return outs
 
 
@@ -110,7 +114,7 @@ def lap64_fp32(lap64):
     return _fp32_problem(lap64)
 
 
-@pytest.mark.parametrize("panel", [0, 4])
+@pytest.mark.parametrize("panel", [0, 4, 8])
 @pytest.mark.parametrize("variant", ["hp", "ha", "naive"])
 def test_lap64_full(lap64, variant, panel):
     p = lap64
@@ -119,7 +123,7 @@ def test_lap64_full(lap64, variant, panel):
     _at_oracle_level(p, Q, R, _oracles(p, variant, "fp64", panel))
 
 
-@pytest.mark.parametrize("panel", [0, 4])
+@pytest.mark.parametrize("panel", [0, 4, 8])
 @pytest.mark.parametrize("variant", ["hp", "ha", "naive"])
 def test_lap64_second_pass_fp64(lap64, variant, panel):
     p = lap64
@@ -128,7 +132,7 @@ def test_lap64_second_pass_fp64(lap64, variant, panel):
     _at_oracle_level(p, Q, R, _oracles(p, variant, "fp64", panel, reorth=True))
 
 
-@pytest.mark.parametrize("panel", [0, 4])
+@pytest.mark.parametrize("panel", [0, 4, 8])
 @pytest.mark.parametrize("variant", ["hp", "ha", "naive"])
 def test_lap64_second_pass_fp32(lap64_fp32, variant, panel):
     p = lap64_fp32
@@ -160,7 +164,7 @@ def dense16k():
     return inputs.dense16k_problem(device="cuda:0")
 
 
-@pytest.mark.parametrize("panel", [0, 4])
+@pytest.mark.parametrize("panel", [0, 4, 8])
 def test_dense16k_full(dense16k, panel):
     p = dense16k
     Q, R, info = _run(p, "hp", "fp64", panel)
@@ -172,7 +176,7 @@ def test_dense16k_full(dense16k, panel):
         assert eR <= 1e-10 and eQ <= 1e-10, what
 
 
-@pytest.mark.parametrize("panel", [0, 4])
+@pytest.mark.parametrize("panel", [0, 4, 8])
 def test_dense16k_fp32_full(dense16k, panel):
     p = _fp32_problem(dense16k)
     Q, R, info = _run(p, "hp", "fp32", panel)
@@ -201,7 +205,7 @@ def lap128_fp32(lap128_fp64):
     return _fp32_problem(lap128_fp64)
 
 
-@pytest.mark.parametrize("panel", [0, 4])
+@pytest.mark.parametrize("panel", [0, 4, 8])
 @pytest.mark.parametrize("variant", ["hp", "ha"])
 def test_lap128_fp32_full(lap128_fp32, variant, panel):
     p = lap128_fp32
@@ -210,7 +214,7 @@ def test_lap128_fp32_full(lap128_fp32, variant, panel):
     _at_oracle_level(p, Q, R, _oracles(p, variant, "fp32", panel), floors=(0.0, 0.0))
 
 
-@pytest.mark.parametrize("panel", [0, 4])
+@pytest.mark.parametrize("panel", [0, 4, 8])
 @pytest.mark.parametrize("variant", ["hp", "ha"])
 def test_lap128_fp64_full(lap128_fp64, variant, panel):
     p = lap128_fp64
