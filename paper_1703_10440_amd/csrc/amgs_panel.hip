@@ -556,7 +556,9 @@ void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
     a.pstride = block_dots ? PANEL_B : 1;
     a.g = c.g_p;
     a.lpart = c.lpart;
-    const bool two = c.panel == PANEL_B1;
+    // a pending block wider than PANEL_B (the previous outer panel) needs the
+    // wider kernel; every other step uses the one-level kernels
+    const bool two = k1 - k0 > PANEL_B;
     a.lstride = PANEL_B;
     const int64_t ncols = a.c1 - a.c0;
     int64_t gy = 1, cpw = PS_CB;
