@@ -15,6 +15,9 @@ constexpr int BT_RED = 8;           // values per workgroup reduction
 constexpr int BT_NCLASS = 8;        // size classes: 4 ranges of m x (n <= 16, n > 16)
 constexpr int BT_TILE_HA = 8;       // widest column block (registers): naive / HA
 constexpr int BT_TILE_HP = 4;       // HP keeps z and x blocks
+constexpr int BT_TUNE_MAX = 1024;   // instances in the autotuner's sample of the batch
+constexpr int BT_TUNE_REPS = 5;     // timed passes per candidate (best taken)
+constexpr float BT_TUNE_GAIN = 0.02f; // a width is taken only if the pass gets this much faster
 
 // One entry of the device work list, in largest-first order.
 struct BatchItem {

@@ -599,19 +599,23 @@ bool make_tune_set(TuneSet &ts, const std::vector<int32_t> &ks, const amgs_batch
                      hipMemcpyHostToDevice) == hipSuccess;
 }
 
-// Time the persistent kernel on a tune set with tile B for every instance.
-float time_tile(amgs_batch_plan *pl, TuneSet &ts, int B, hipStream_t s, hipEvent_t e0, hipEvent_t e1)
+// Time one pass of the persistent kernel over a tune set with the tiles its
+// items hold (the widest decides the kernel and its resident grid): the best
+// of `reps` launches.
+float time_mix(amgs_batch_plan *pl, TuneSet &ts, int reps, hipStream_t s, hipEvent_t e0,
+               hipEvent_t e1)
 {
-    for (auto &it : ts.items) it.B = B;
+    int bmax = 1;
+    for (const auto &it : ts.items) bmax = std::max(bmax, it.B);
     if (hipMemcpy(ts.d_items, ts.items.data(), ts.items.size() * sizeof(BatchItem),
                   hipMemcpyHostToDevice) != hipSuccess)
         return -1.f;
-    const int grid = std::min(batched_resident_wgs(pl->h->device, pl->precision, pl->variant, B),
+    const int grid = std::min(batched_resident_wgs(pl->h->device, pl->precision, pl->variant, bmax),
                               std::max(ts.count, 1));
     float best = -1.f;
-    for (int rep = 0; rep < 3; ++rep) {
+    for (int rep = 0; rep < reps; ++rep) {
         (void)hipEventRecord(e0, s);
-        launch_batched(pl->precision, pl->variant, B, pl->reorth, grid, ts.d_desc, ts.d_items,
+        launch_batched(pl->precision, pl->variant, bmax, pl->reorth, grid, ts.d_desc, ts.d_items,
                        ts.count, ts.d_work, ts.d_info, ts.d_counter, s);
         (void)hipEventRecord(e1, s);
         if (hipEventSynchronize(e1) != hipSuccess) return -1.f;
@@ -622,40 +626,87 @@ float time_tile(amgs_batch_plan *pl, TuneSet &ts, int B, hipStream_t s, hipEvent
     return best;
 }
 
-// Autotuner: for every size class present, time B in {1, 2, 4, 8} (up to the
-// variant's register limit) on up to 64
-// synthetic instances with the class's largest shapes and keep the fastest.
+// Autotuner on the batch's own mix: a stratified sample of the instances
+// (every s-th in largest-first order, at most BT_TUNE_MAX, so every size
+// class keeps its share of the work) is run as one persistent pass, as the
+// real batch is.  Starting from the built-in widths, one width for every
+// class is tried first (the widest tile decides the kernel and its resident
+// grid for all classes); then each size class in turn (largest total work
+// first) tries the other widths {1, 2, 4, 8} (up to the variant's register
+// limit) with every other class fixed.  A change is taken only if the whole
+// pass gets faster by more than BT_TUNE_GAIN, so that timing noise does not
+// flip near-equal choices.  Two sweeps over the classes at most.
 template <typename T>
 void autotune(amgs_batch_plan *pl)
 {
+    std::vector<int32_t> order(pl->batch);
+    for (int32_t k = 0; k < pl->batch; ++k) order[k] = k;
+    auto work = [&](int32_t k) { return (double)pl->m[k] * pl->n[k] * pl->n[k]; };
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int32_t a, int32_t b) { return work(a) > work(b); });
+    const int32_t stride = (pl->batch + BT_TUNE_MAX - 1) / BT_TUNE_MAX;
+    std::vector<int32_t> ks;
+    for (int32_t t = 0; t < pl->batch; t += stride) ks.push_back(order[t]);
+    TuneSet ts;
+    if (!make_tune_set<T>(ts, ks, pl)) return;
+    std::vector<int> cls_of(ks.size());
+    double share[BT_NCLASS] = {0};
+    for (size_t t = 0; t < ks.size(); ++t) {
+        cls_of[t] = size_class(pl->m[ks[t]], pl->n[ks[t]]);
+        share[cls_of[t]] += work(ks[t]);
+    }
+    std::vector<int> classes;
+    for (int c = 0; c < BT_NCLASS; ++c)
+        if (share[c] > 0) classes.push_back(c);
+    std::stable_sort(classes.begin(), classes.end(),
+                     [&](int a, int b) { return share[a] > share[b]; });
     hipStream_t s = nullptr;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return;
     (void)hipEventCreate(&e0);
     (void)hipEventCreate(&e1);
-    for (int cls = 0; cls < BT_NCLASS; ++cls) {
-        std::vector<int32_t> ks;
-        for (int32_t k = 0; k < pl->batch; ++k)
-            if (size_class(pl->m[k], pl->n[k]) == cls) ks.push_back(k);
-        if (ks.empty()) continue;
-        std::stable_sort(ks.begin(), ks.end(), [&](int32_t a, int32_t b) {
-            return (double)pl->m[a] * pl->n[a] * pl->n[a] > (double)pl->m[b] * pl->n[b] * pl->n[b];
-        });
-        if (ks.size() > 64) ks.resize(64);
-        TuneSet ts;
-        if (!make_tune_set<T>(ts, ks, pl)) continue;
-        int bestB = pl->class_B[cls];
-        float bestT = -1.f;
-        for (int B : {1, 2, 4, 8}) {
-            if (B > max_tile(pl->variant)) continue;
-            const float t = time_tile(pl, ts, B, s, e0, e1);
-            if (t > 0.f && (bestT < 0.f || t < bestT)) {
-                bestT = t;
-                bestB = B;
+    int B[BT_NCLASS];
+    for (int c = 0; c < BT_NCLASS; ++c) B[c] = std::min(pl->class_B[c], max_tile(pl->variant));
+    auto run = [&]() {
+        for (size_t t = 0; t < ts.items.size(); ++t) ts.items[t].B = B[cls_of[t]];
+        return time_mix(pl, ts, BT_TUNE_REPS, s, e0, e1);
+    };
+    // one untimed pass first (code loading, caches)
+    (void)run();
+    float base = run();
+    // the widest tile decides the kernel every class runs in, so start from
+    // the best single width for all classes
+    for (int cand : {1, 2, 4, 8}) {
+        if (cand > max_tile(pl->variant) || base <= 0.f) continue;
+        int keep[BT_NCLASS];
+        for (int c = 0; c < BT_NCLASS; ++c) {
+            keep[c] = B[c];
+            B[c] = cand;
+        }
+        const float t = run();
+        if (t > 0.f && t < base * (1.f - BT_TUNE_GAIN)) base = t;
+        else
+            for (int c = 0; c < BT_NCLASS; ++c) B[c] = keep[c];
+    }
+    for (int sweep = 0; sweep < 2 && base > 0.f; ++sweep) {
+        bool changed = false;
+        for (int c : classes) {
+            for (int cand : {1, 2, 4, 8}) {
+                if (cand > max_tile(pl->variant) || cand == B[c]) continue;
+                const int old = B[c];
+                B[c] = cand;
+                const float t = run();
+                if (t > 0.f && t < base * (1.f - BT_TUNE_GAIN)) {
+                    base = t;
+                    changed = true;
+                } else {
+                    B[c] = old;
+                }
             }
         }
-        pl->class_B[cls] = bestB;
+        if (!changed) break;
     }
+    for (int c = 0; c < BT_NCLASS; ++c) pl->class_B[c] = B[c];
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     (void)hipStreamDestroy(s);

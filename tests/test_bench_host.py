@@ -51,3 +51,23 @@ def test_batch_requested_bytes_counts_each_pass():
     # wider blocks read the earlier columns fewer times
     assert (bench.batch_requested_bytes([p], [8] * 8, "ha", w)
             < bench.batch_requested_bytes([p], [1] * 8, "ha", w))
+
+
+def test_batch_model_bytes_by_hand():
+    """The method's byte model and compulsory floor for one instance, counted
+    by hand: m = 100, n = 8, tridiagonal A, binary64 and binary32."""
+    m, n = 100, 8
+    D = np.diag(np.full(m, 4.0)) + np.diag(np.full(m - 1, -1.0), 1) + np.diag(np.full(m - 1, -1.0), -1)
+    p = inputs.Problem("tri", np.asfortranarray(np.ones((m, n))), csr=inputs.csr_from_dense(D))
+    nnz = 3 * m - 2
+    for w in (8, 4):
+        A = 4 * (m + 1) + nnz * (4 + w)
+        io = 2 * m * n * w + 8 * n * n
+        proj = m * n * (n - 1) * w
+        S1 = A + 2 * m * w
+        want = {"naive": 2 * n * S1 + proj + io, "ha": n * S1 + proj + io,
+                "hp": A + 2 * m * n * w + proj + io}
+        for v, b in want.items():
+            alg, floor = bench.batch_model_bytes([p], v, w)
+            assert alg == b, (v, w)
+            assert floor == A + io
