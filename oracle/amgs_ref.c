@@ -75,6 +75,15 @@
  * r_ij += s_i.  For HP the same s_i also correct x_j: x_j <- x_j -
  * sum_i s_i p_i (binary64, rounded once), applied after the first-pass
  * recurrence.
+ *
+ * reorth = 2, blocked second pass (orientation 4 only): when an outer panel
+ * [S, E) starts, its columns have received every first-pass projection onto
+ * the columns before S; each of them then gets the classical pass above
+ * against all i < S at once (same arithmetic), and later, at its own step,
+ * the pass against the earlier columns of its outer panel only, i in
+ * [S, j).  The two parts together cover every i < j, as the per-column pass
+ * does, with the earlier outer panels streamed once per outer panel instead
+ * of once per column.
  */
 #include <math.h>
 #include <stdint.h>
@@ -229,31 +238,39 @@ static void scale(double *y, const double *v, double r, int64_t m, int prec)
 /* ------------------------------------------------- second (reorth) pass */
 /* s_i = p_i^T z for i < j (binary64), z <- z - sum_i s_i q_i, r_ij += s_i.
  * For HP, also x <- x - sum_i s_i p_i. */
-static void reorth_pass(double *z, double *x_or_null, int64_t j, const double *Q, int64_t ldq,
-                        const double *P, int64_t ldp, double *Rcol, int64_t m, int prec)
+static void reorth_range(double *z, double *x_or_null, int64_t i0, int64_t j, const double *Q,
+                         int64_t ldq, const double *P, int64_t ldp, double *Rcol, int64_t m,
+                         int prec)
 {
-    if (j == 0) return;
-    double *s = (double *)malloc((size_t)j * sizeof(double));
-    for (int64_t i = 0; i < j; ++i) s[i] = dot_hi(P + i * ldp, z, m);
+    if (j <= i0) return;
+    double *s = (double *)malloc((size_t)(j - i0) * sizeof(double));
+    for (int64_t i = i0; i < j; ++i) s[i - i0] = dot_hi(P + i * ldp, z, m);
 #pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < m; ++k) {
         double zk = z[k];
-        for (int64_t i = 0; i < j; ++i) {
-            double prod = s[i] * Q[i * ldq + k];
+        for (int64_t i = i0; i < j; ++i) {
+            double prod = s[i - i0] * Q[i * ldq + k];
             zk = zk - prod;
         }
         z[k] = st(zk, prec);
         if (x_or_null) {
             double xk = x_or_null[k];
-            for (int64_t i = 0; i < j; ++i) {
-                double prod = s[i] * P[i * ldp + k];
+            for (int64_t i = i0; i < j; ++i) {
+                double prod = s[i - i0] * P[i * ldp + k];
                 xk = xk - prod;
             }
             x_or_null[k] = st(xk, prec);
         }
     }
-    for (int64_t i = 0; i < j; ++i) Rcol[i] = Rcol[i] + s[i];
+    for (int64_t i = i0; i < j; ++i) Rcol[i] = Rcol[i] + s[i - i0];
     free(s);
+}
+
+/* The second pass of column j against every earlier column. */
+static void reorth_pass(double *z, double *x_or_null, int64_t j, const double *Q, int64_t ldq,
+                        const double *P, int64_t ldp, double *Rcol, int64_t m, int prec)
+{
+    reorth_range(z, x_or_null, 0, j, Q, ldq, P, ldp, Rcol, m, prec);
 }
 
 /* r_jj = sqrt(z^T x) with binary64 accumulation; returns 0 on breakdown. */
@@ -369,6 +386,7 @@ typedef struct {
     int64_t *mv_calls, *mv_cols;
     int nlev;
     const int *width;   /* panel widths, outermost first; each divides the one before */
+    int64_t re_lo;      /* reorth == 2: the in-panel second pass starts at this column */
 } panel_ctx;
 
 /* The column algorithm on the columns [s, e) of a finished-below panel: each
@@ -393,8 +411,11 @@ static int panel_columns(const panel_ctx *c, int64_t s, int64_t e)
                 axpy_st(c->x, st(Rc[i], c->prec), c->P + i * c->ldp, m, c->prec);
             xr = c->x;
         }
-        /* the optional second pass, at the same point as in the column form */
-        if (c->reorth) reorth_pass(z, xr, j, c->Q, c->ldq, c->P, c->ldp, Rc, m, c->prec);
+        /* the optional second pass, at the same point as in the column form;
+         * in the blocked form only against the columns of its outer panel */
+        if (c->reorth)
+            reorth_range(z, xr, c->reorth == 2 ? c->re_lo : 0, j, c->Q, c->ldq, c->P, c->ldp, Rc,
+                         m, c->prec);
         if (c->variant != REF_HP) {
             mv_st(c->A, z, c->x, c->prec);
             *c->mv_calls += 1; *c->mv_cols += 1;
@@ -447,11 +468,20 @@ static void panel_block(const panel_ctx *c, int64_t s, int64_t e, int64_t c0, in
 /* Columns [S, E) at level lev: panels of width[lev] in order; each is taken
  * apart at the next level (the column algorithm below the last one), and
  * once finished acts as one block on the remaining columns of [S, E). */
-static int panel_range(const panel_ctx *c, int64_t S, int64_t E, int lev)
+static int panel_range(panel_ctx *c, int64_t S, int64_t E, int lev)
 {
     const int64_t B = c->width[lev];
     for (int64_t s = S; s < E; s += B) {
         const int64_t e = s + B < E ? s + B : E;
+        if (c->reorth == 2 && lev == 0) {
+            /* blocked second pass: every column of this outer panel against
+             * all earlier columns at once (their first pass against those
+             * is complete), then in-panel passes from s on */
+            for (int64_t col = s; col < e; ++col)
+                reorth_range(c->Q + col * c->ldq, c->variant == REF_HP ? c->X + col * c->m : NULL,
+                             0, s, c->Q, c->ldq, c->P, c->ldp, c->R + col * c->ldr, c->m, c->prec);
+            c->re_lo = s;
+        }
         const int info = lev + 1 < c->nlev ? panel_range(c, s, e, lev + 1) : panel_columns(c, s, e);
         if (info) return info;
         if (e < E) panel_block(c, s, e, e, E);
@@ -469,7 +499,7 @@ static int qr_panel(const ref_op *A, int64_t m, int64_t n, double *Q, int64_t ld
         *mv_calls += 1; *mv_cols += n;
     }
     panel_ctx c = {A, m, n, Q, R, P, X, x, ldq, ldr, ldp, variant, reorth, prec,
-                   mv_calls, mv_cols, nlev, width};
+                   mv_calls, mv_cols, nlev, width, 0};
     const int info = panel_range(&c, 0, n, 0);
     free(x);
     return info;
@@ -524,6 +554,7 @@ static int run(const ref_op *A, int64_t n, int64_t first, const double *Z, int64
     if (m < 0 || n < 0 || n > m || ldz < m || ldq < m || ldr < n) return -1;
     if (variant < 0 || variant > 2 || orientation < 0 || orientation > 4) return -1;
     if (prec < 0 || prec > 1) return -1;
+    if (reorth < 0 || reorth > 2 || (reorth == 2 && orientation != REF_PANEL2)) return -1;
     /* successive orthogonalisation: columns before first are final in Q, P
      * and R (column and classical forms only) */
     if (first < 0 || first > n) return -1;

@@ -71,12 +71,13 @@ class Result:
 
 
 def qr(Z: np.ndarray, dense: Optional[np.ndarray] = None, csr=None, variant: str = "ha",
-       orientation: str = "col", reorth: bool = False, precision: str = "fp64",
+       orientation: str = "col", reorth=False, precision: str = "fp64",
        lib=None, first: int = 0, Q0=None, P0=None, R0=None) -> Result:
     """Run the oracle.  ``dense`` is an m x m symmetric matrix; ``csr`` is an
     object with ``m, row_ptr, col_idx, vals``.  Returns Q, R, P = AQ, info.
     first > 0: Q0, P0, R0 hold the final leading columns (successive
-    orthogonalisation)."""
+    orthogonalisation).  reorth: False / True (the second pass per column) or
+    2 (the blocked second pass of the "panel8" orientation)."""
     lib = lib or load()
     Z = np.asfortranarray(Z, dtype=np.float64)
     m, n = Z.shape
@@ -90,7 +91,7 @@ def qr(Z: np.ndarray, dense: Optional[np.ndarray] = None, csr=None, variant: str
     stats = (C.c_int64 * 2)()
     ld = max(m, 1)
     args = (n, _d(Z), ld, _d(Q), ld, _d(R), max(n, 1), _d(P), ld, VARIANTS[variant],
-            ORIENT[orientation], int(bool(reorth)), PRECISION[precision], stats, int(first))
+            ORIENT[orientation], int(reorth), PRECISION[precision], stats, int(first))
     if dense is not None:
         A = np.asfortranarray(dense, dtype=np.float64)
         info = lib.amgs_ref_qr_dense(m, _d(A), max(m, 1), *args)

@@ -557,6 +557,63 @@ def pin_panel8(lib) -> list:
     return fails
 
 
+def pin_blocked_second_pass(lib) -> list:
+    """Blocked second pass (reorth = 2, orientation "panel8"): each outer
+    panel's columns get the classical pass against all earlier outer panels
+    at once, then the in-panel pass.  Every pass only removes components
+    along earlier columns and adds the same coefficients into R, so the
+    closed forms hold (n = 21: two full outer panels and a ragged one); with
+    n <= 8 there is no earlier outer panel and it is the per-column pass bit
+    for bit; on an experiment-II case-2 problem (the first pass loses
+    orthogonality, so the pass's coefficients matter) the residual stays at
+    rounding level and the loss drops below a tenth of the first pass's, to
+    within 10x that of the per-column pass; in the binary32 form it restores
+    orthogonality by orders of magnitude."""
+    fails = []
+    for p in (inputs.random_dense_problem(60, 21, 33), inputs.random_csr_problem(300, 21, 9, 33)):
+        Ad = p.dense if p.dense is not None else p.csr.to_dense()
+        Rc = _chol_R(p.Z, Ad)
+        for v in VARIANTS:
+            r = ref.qr(p.Z, dense=p.dense, csr=p.csr, variant=v, orientation="panel8", reorth=2,
+                       lib=lib)
+            e, eq, ep = (_rel(np.triu(r.R), Rc), _rel(r.Q, np.linalg.solve(Rc.T, p.Z.T).T),
+                         _rel(r.P, Ad @ r.Q))
+            if r.info != 0 or not (e <= 1e-13 and eq <= 1e-12 and ep <= 1e-12):
+                fails.append(f"blocked pass chol {p.name} {v}: R {e} Q {eq} P {ep} info {r.info}")
+    for nn in (5, 8):
+        p = inputs.random_dense_problem(40, nn, 6)
+        for v in VARIANTS:
+            a = ref.qr(p.Z, dense=p.dense, variant=v, orientation="panel8", reorth=True, lib=lib)
+            b = ref.qr(p.Z, dense=p.dense, variant=v, orientation="panel8", reorth=2, lib=lib)
+            if not (np.array_equal(a.R, b.R) and np.array_equal(a.Q, b.Q)):
+                fails.append(f"blocked pass n={nn} {v}: differs from the per-column pass")
+    p = inputs.exp2_problem(100, 20, 1e8, 1e8, 2, 7)
+    for v in ("naive", "ha"):
+        r0 = ref.qr_problem(p, variant=v, orientation="panel8", lib=lib)
+        r1 = ref.qr_problem(p, variant=v, orientation="panel8", reorth=True, lib=lib)
+        r2 = ref.qr_problem(p, variant=v, orientation="panel8", reorth=2, lib=lib)
+        res = ref.residual(p.Z, r2.Q, r2.R)
+        o0, o1, o2 = (ref.orth_loss(r.Q, dense=p.dense) for r in (r0, r1, r2))
+        if r2.info != 0 or res > 1e-14 or not (o2 <= 10 * o1 + 1e-15 and o2 < 0.1 * o0):
+            fails.append(f"blocked pass exp2 {v}: residual {res} loss {o2} (per-column {o1}, "
+                         f"no pass {o0})")
+    q = inputs.laplacian_graded_problem(N=10, n=20, decades=4.0, seed=3)
+    for v in ("naive", "ha"):
+        o0 = ref.orth_loss(ref.qr_problem(q, variant=v, orientation="panel8", precision="fp32",
+                                          lib=lib).Q, csr=q.csr)
+        o2 = ref.orth_loss(ref.qr_problem(q, variant=v, orientation="panel8", precision="fp32",
+                                          reorth=2, lib=lib).Q, csr=q.csr)
+        if not o2 < 1e-2 * o0:
+            fails.append(f"blocked pass binary32 orthogonality {v}: {o0} -> {o2}")
+    # only with the two-level panel orientation
+    try:
+        ref.qr(q.Z, csr=q.csr, variant="ha", orientation="panel", reorth=2, lib=lib)
+        fails.append("blocked pass accepted outside the two-level orientation")
+    except ValueError:
+        pass
+    return fails
+
+
 def pin_cgs(lib) -> list:
     """Classical Gram-Schmidt (orientation "cgs"): the closed forms on
     well-conditioned problems (with and without the second pass), Householder
@@ -657,4 +714,4 @@ ALL_PINS = [pin_hand_example, pin_cholesky, pin_identity_householder, pin_choles
             pin_col_row_bitwise, pin_mv_counts, pin_scaling, pin_first_column,
             pin_residual_and_reorth, pin_exp2_accuracy, pin_fp32_accumulation,
             pin_fp32_mv_axpy_rounding, pin_fp32_vs_fp64, pin_breakdown,
-            pin_panel, pin_panel8, pin_cgs, pin_successive]
+            pin_panel, pin_panel8, pin_blocked_second_pass, pin_cgs, pin_successive]

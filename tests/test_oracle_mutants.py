@@ -32,7 +32,7 @@ MUTANTS = [
     ("row HP recurrence uses the wrong column of X",
      "axpy_st(X + j * m, st(R[j * ldr + i], prec)", "axpy_st(X + i * m, st(R[j * ldr + i], prec)"),
     ("second pass does not add s_i into R",
-     "Rcol[i] = Rcol[i] + s[i];", "Rcol[i] = Rcol[i];"),
+     "Rcol[i] = Rcol[i] + s[i - i0];", "Rcol[i] = Rcol[i];"),
     ("A-norm accumulated in binary32 in the binary32 form",
      "double rr = dot_hi(z, x, m);", "double rr = dot_st(z, x, m, REF_FP32);"),
     ("binary32 projections accumulated in binary64",
@@ -92,6 +92,12 @@ MUTANTS = [
     ("two-level panels: a 4-panel block also acts beyond its own 8-panel",
      "if (e < E) panel_block(c, s, e, e, E);",
      "if (e < E) panel_block(c, s, e, e, lev > 0 ? c->n : E);"),
+    ("blocked second pass leaves the last earlier column out",
+     "                             0, s, c->Q, c->ldq, c->P, c->ldp, c->R + col * c->ldr, c->m, c->prec);",
+     "                             0, s - 1, c->Q, c->ldq, c->P, c->ldp, c->R + col * c->ldr, c->m, c->prec);"),
+    ("blocked second pass skips the last column of each outer panel",
+     "            for (int64_t col = s; col < e; ++col)\n                reorth_range(",
+     "            for (int64_t col = s; col + 1 < e; ++col)\n                reorth_range("),
     ("two-level panels: a finished 8-panel never acts on the later columns",
      "if (e < E) panel_block(c, s, e, e, E);",
      "if (e < E && lev > 0) panel_block(c, s, e, e, E);"),
