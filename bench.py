@@ -315,6 +315,8 @@ def bench_single(args, torch, amgs):
         combos = [(v, p, False, 0, False) for p in ("fp64", "fp32") for v in ("naive", "ha", "hp")]
         combos += [(v, p, True, pan, False) for p in ("fp32", "fp64") for pan in (0, 4, 8)
                    for v in ("ha", "hp")]
+        # the blocked second pass (two-level schedule only)
+        combos += [(v, p, 2, 8, False) for p in ("fp32", "fp64") for v in ("ha", "hp")]
         combos += [(v, p, False, pan, False) for pan in (4, 8) for p in ("fp64", "fp32")
                    for v in ("naive", "ha", "hp")]
         combos += [(v, "fp64", ro, 0, True) for ro in (False, True) for v in ("naive", "ha", "hp")]
@@ -324,7 +326,8 @@ def bench_single(args, torch, amgs):
             steps = 1 if heavy else (max(2, args.steps // 4) if v == "naive" else max(3, args.steps // 2))
             tv, o = time_steps(r, steps, 1, torch)
             orth, res = accuracy(data, o, torch)
-            key = (("cgs_" if cgs else "") + f"{v}_{p}" + ("_reorth" if ro else "")
+            key = (("cgs_" if cgs else "") + f"{v}_{p}"
+                   + ("_reorthblk" if ro == 2 else "_reorth" if ro else "")
                    + (f"_panel{pan}" if pan else ""))
             variants[key] = {"cols_per_s": round(prob.n / tv, 1), "ms": round(tv * 1e3, 4),
                              "orth_loss": orth, "residual": res, "info": int(o.info.item())}
@@ -342,10 +345,11 @@ def bench_single(args, torch, amgs):
             # the binary32 form with the binary64 second pass against plain
             # binary64 in the same schedule
             for v in ("ha", "hp"):
-                k = f"{v}_fp32_reorth{sfx}"
-                if k in variants:
-                    variants[k]["speedup_vs_fp64"] = round(
-                        variants[f"{v}_fp64{sfx}"]["ms"] / variants[k]["ms"], 3)
+                for kind in ("reorth", "reorthblk"):
+                    k = f"{v}_fp32_{kind}{sfx}"
+                    if k in variants:
+                        variants[k]["speedup_vs_fp64"] = round(
+                            variants[f"{v}_fp64{sfx}"]["ms"] / variants[k]["ms"], 3)
         # fastest modified Gram-Schmidt configuration per precision (either
         # schedule, no second pass)
         best = {}
@@ -368,7 +372,7 @@ def bench_single(args, torch, amgs):
         log(f"[bench] cpu, one thread {cpu1}")
     cfg = {"workload": args.workload, "m": prob.m, "n": prob.n,
            "A": "csr" if prob.csr is not None else "dense", "nnz": int(big),
-           "variant": head_v, "precision": head_p, "reorth": bool(args.reorth),
+           "variant": head_v, "precision": head_p, "reorth": int(args.reorth),
            "schedule": f"panel{args.panel}" if args.panel else "column"}
     line = {"metric": METRIC, "value": round(prob.n / t, 2), "unit": "cols/s", "n_gpus": 1,
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t * 1e3, 4),
@@ -652,7 +656,9 @@ def main():
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--variant", default="ha", choices=["naive", "ha", "hp"])
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--reorth", action="store_true", help="second pass in the headline run")
+    ap.add_argument("--reorth", type=int, nargs="?", const=1, default=0, choices=[0, 1, 2],
+                    help="second pass in the headline run: 1 per column, 2 blocked "
+                         "(two-level schedule only)")
     ap.add_argument("--panel", type=int, default=8, choices=[0, 4, 8],
                     help="schedule of the headline run: 0 column order, 4 panels of four, "
                          "8 panels of eight taken apart as panels of four")

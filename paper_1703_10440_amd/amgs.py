@@ -281,7 +281,9 @@ def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=Fal
            panel=0, cgs=False, first=0, R=None) -> QRResult:
     """A-orthonormalise the columns of Z (device tensors; A in CSR).
     panel: 0 for the column schedule, 4 for the panel schedule, 8 for the
-    two-level panel schedule (panels of eight, each as two of four); cgs: classical
+    two-level panel schedule (panels of eight, each as two of four); reorth:
+    False, True (second pass per column) or 2 (blocked second pass, panel=8
+    only); cgs: classical
     instead of modified Gram-Schmidt; first > 0: columns before it are final
     in the Q, P and R passed in (successive orthogonalisation).  stream: a
     torch stream or raw hipStream_t to run on (default: torch's current
@@ -295,7 +297,7 @@ def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=Fal
         row_ptr = row_ptr.to(device=device, dtype=torch.int32).contiguous()
         col_idx = col_idx.to(device=device, dtype=torch.int32).contiguous()
         h = handle(device.index or 0)
-        opts = Opts(int(bool(reorth)), int(panel), int(bool(cgs)), int(first))
+        opts = Opts(int(reorth), int(panel), int(bool(cgs)), int(first))
         v, p = VARIANTS[variant], PRECISIONS[precision]
         wb = amgs_workspace_bytes(h, m, n, 0, v, p, int(Pc is not None), opts)
         work = _workspace(work, wb, device)
@@ -314,7 +316,9 @@ def qr_dense(A, Z, variant="ha", precision="fp64", reorth=False, return_p=False,
              R=None) -> QRResult:
     """A-orthonormalise the columns of Z (device tensors; A dense symmetric).
     panel: 0 for the column schedule, 4 for the panel schedule, 8 for the
-    two-level panel schedule (panels of eight, each as two of four); cgs: classical
+    two-level panel schedule (panels of eight, each as two of four); reorth:
+    False, True (second pass per column) or 2 (blocked second pass, panel=8
+    only); cgs: classical
     instead of modified Gram-Schmidt; first > 0: columns before it are final
     in the Q, P and R passed in (successive orthogonalisation).  stream: as
     for qr_csr."""
@@ -324,7 +328,7 @@ def qr_dense(A, Z, variant="ha", precision="fp64", reorth=False, return_p=False,
         device = Zc.device
         Ac = colmajor(A.to(device), dt)
         h = handle(device.index or 0)
-        opts = Opts(int(bool(reorth)), int(panel), int(bool(cgs)), int(first))
+        opts = Opts(int(reorth), int(panel), int(bool(cgs)), int(first))
         v, p = VARIANTS[variant], PRECISIONS[precision]
         wb = amgs_workspace_bytes(h, m, n, 1, v, p, int(Pc is not None), opts)
         work = _workspace(work, wb, device)

@@ -78,8 +78,8 @@ struct ProfScope {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t part, s_part, rr_part, S, zt, xv, X, P, wpart, lpart, lpart8, lred, ell_col, ell_val,
-        tile_long;
+    size_t part, s_part, rr_part, S, zt, xv, X, P, wpart, lpart, lpart8, lred, rb_part, rb_s,
+        ell_col, ell_val, tile_long;
     size_t base;    // bytes without the padded copy of A
     size_t total;   // bytes with it (the size the query reports)
 };
@@ -123,6 +123,10 @@ Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_g
     L.lpart = panel ? take((size_t)PANEL_B * PANEL_B * g_p * 8) : off;
     L.lpart8 = two ? take((size_t)PANEL_B1 * PANEL_B1 * g_b * 8) : off;
     L.lred = two ? take((size_t)PANEL_B1 * PANEL_B1 * 8) : off;
+    // blocked second pass: coefficient partials and coefficients of an outer panel
+    const bool rb = two && reorth == 2;
+    L.rb_part = rb ? take((size_t)n * PANEL_B1 * g_b * 8) : off;
+    L.rb_s = rb ? take((size_t)n * PANEL_B1 * 8) : off;
     L.base = off;
     // padded copy of a CSR A for the column MV (naive and HA), last, so that
     // a smaller workspace can leave it out; the size does not depend on nnz,
@@ -342,16 +346,33 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
             launch();
         }
     };
+    // blocked second pass (reorth = 2, two levels only): each outer panel's
+    // columns first get the previous outer panel's block, then the second
+    // pass against every earlier column at once; the per-column pass then
+    // covers only the earlier columns of the outer panel
+    const bool blk = two && c.reorth_blk;
     for (int64_t S = 0; S < c.n; S += B1) {
         const int64_t E = S + B1 < c.n ? S + B1 : c.n;
         const int64_t bp0 = S > 0 ? S - B1 : S;   // the previous outer panel [bp0, S)
+        if (blk && S > 0) {
+            profiled(false, [&] { launch_bsweep<T>(c, bp0, S, S, S, S, E); });
+            launch_rb<T>(c, S, E, variant);
+            st.kernel_launches += 4;
+            st.sweep_launches++;
+            st.sweep_bytes += (double)(E - S) * 2.0 * (double)c.m * w + (double)(S - bp0) * (double)c.m * w;
+        }
+        c.re_lo = blk ? S : 0;
+        // the outer block still pending for this panel's columns
+        const int64_t ob0 = blk ? S : bp0;
         for (int64_t s = S; s < E; s += B) {
             const int64_t e = s + B < E ? s + B : E;
             // the block still pending for this panel's columns: the previous
             // outer panel for the first inner panel, else the previous inner one
-            const int64_t pk0 = s == S ? bp0 : s - B, pk1 = s;
+            const int64_t pk0 = s == S ? ob0 : s - B, pk1 = s;
             for (int64_t j = s; j < e; ++j) {
-                const bool first_blk = j == s && pk1 > pk0;
+                // (with the blocked pass the first column of an outer panel has
+                // no pending term either: it takes the same block-step path)
+                const bool first_blk = j == s && (pk1 > pk0 || (blk && j == S && S > 0));
                 int64_t n_rr = 0;
                 // column kernels publish r_{j-1,c} only inside the panel
                 c.n_pub = e;
@@ -359,7 +380,7 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
                     ProfScope ps(h, variant == VAR_HP ? 1 : -1, c.stream);
                     // the optional second pass runs on column j after its
                     // projections, before its MV, as in the column schedule
-                    const bool ro = reorth && j > 0;
+                    const bool ro = reorth && j > c.re_lo;
                     if (first_blk) {
                         // HP: the x terms of the pending block unless an
                         // x-block pass at s has applied them
@@ -459,7 +480,7 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
                 }
                 if (outer_end) {
                     if (two) {
-                        profiled(true, [&] { launch_bsweep<T>(c, bp0, S, S, E, E, c.n); });
+                        profiled(true, [&] { launch_bsweep<T>(c, bp0, S, S, E, E, c.n); });   // [E, n) lacks the block [bp0, S) also with blk
                         const double col = (double)c.m * (double)w;
                         const double bb = (double)(c.n - E) * (S > bp0 ? 2.0 : 1.0) * col
                                           + (double)((S - bp0) + (E - S)) * col;
@@ -482,6 +503,7 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
             }
         }
     }
+    c.re_lo = 0;
     if (hipGetLastError() != hipSuccess) return AMGS_ERR_HIP;
     return AMGS_OK;
 }
@@ -565,8 +587,11 @@ amgs_status_t run_cgs(amgs_handle *h, Ctx &c, int variant, int reorth)
 amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision_t p,
                         const amgs_opts_t *o, void *work, size_t work_bytes, int P_given)
 {
-    const int reorth = o ? (o->reorth != 0) : 0;
+    const int reorth_mode = o ? o->reorth : 0;
+    const int reorth = reorth_mode != 0;
     const int panel = o ? o->panel : 0;
+    if (reorth_mode < 0 || reorth_mode > 2) return AMGS_ERR_ARG;
+    if (reorth_mode == 2 && panel != PANEL_B1) return AMGS_ERR_UNSUPPORTED;
     const int cgs = o ? o->cgs : 0;
     const int64_t first = o ? o->first : 0;
     if (panel != 0 && panel != PANEL_B && panel != PANEL_B1) return AMGS_ERR_ARG;
@@ -577,7 +602,8 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
     if (first == c.n) return AMGS_OK;
     const size_t w = p == AMGS_FP64 ? 8 : 4;
     c.geo = make_geo(c.m, c.nnz, c.is_dense);
-    Layout L = layout(c.m, c.n, c.geo, (int)v, w, P_given, reorth || cgs, panel, c.is_dense);
+    Layout L = layout(c.m, c.n, c.geo, (int)v, w, P_given, cgs ? 1 : reorth_mode, panel,
+                      c.is_dense);
     if (!work || work_bytes < L.base) return AMGS_ERR_WORKSPACE;
     char *base = (char *)work;
     c.sp.part = base + L.part;
@@ -597,6 +623,9 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
         c.lpart8 = base + L.lpart8;
         c.lred = (double *)(base + L.lred);
         c.g_b = bsweep_chunks(c.m, w);
+        c.reorth_blk = reorth_mode == 2;
+        c.rb_part = base + L.rb_part;
+        c.rb_s = (double *)(base + L.rb_s);
     }
     c.s_part = (double *)(base + L.s_part);
     c.rr_part = (double *)(base + L.rr_part);
@@ -735,8 +764,11 @@ size_t amgs_workspace_bytes(amgs_handle_t h, int64_t m, int64_t n, int32_t is_de
     const int cgs = o ? o->cgs : 0;
     if (panel != 0 && panel != PANEL_B && panel != PANEL_B1) return 0;
     if (cgs != 0 && cgs != 1) return 0;
+    const int reorth_mode = o ? o->reorth : 0;
+    if (reorth_mode < 0 || reorth_mode > 2) return 0;
+    if (reorth_mode == 2 && panel != PANEL_B1) return 0;
     Layout L = layout(m, n, g, (int)v, p == AMGS_FP64 ? 8 : 4, P_given,
-                      (o ? o->reorth != 0 : 0) || cgs, panel, is_dense);
+                      cgs ? 1 : reorth_mode, panel, is_dense);
     return L.total;
 }
 

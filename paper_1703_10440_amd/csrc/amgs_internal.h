@@ -102,6 +102,7 @@ struct RowArgs {
     int64_t x_from;   // HP column kernel: first recurrence term (-1: column schedule)
     int32_t pend;     // k_reorth_a: apply the pending update r_{j-1,j} q_{j-1} and publish R
     int32_t z_in_zt;  // k_reorth_a: z_j is read from zt instead of Q
+    int64_t re_lo;    // second pass: against the earlier columns [re_lo, j)
 };
 
 struct SweepArgs {
@@ -172,6 +173,22 @@ struct BSweepArgs {
     int64_t g;
 };
 
+// Blocked second pass of an outer panel [s, s + nz) (see k_rb_dots).
+struct RbArgs {
+    int64_t m;
+    const void *Q;    // q_i for i < s; the panel's z columns (updated in place)
+    int64_t ldq;
+    const void *P;
+    int64_t ldp;
+    void *X;          // HP: the panel's x columns (updated in place)
+    int64_t ldx;
+    int64_t s, nz;
+    void *part;       // binary64 partials part[(i * PANEL_B1 + c) * g + w]
+    int64_t g;
+    const double *S;  // the coefficients s_ic at [i * PANEL_B1 + c]
+    const int32_t *info;
+};
+
 // Everything one amgs_qr_* call needs on the host side.
 struct Ctx {
     int64_t m, n;
@@ -218,6 +235,13 @@ struct Ctx {
     int64_t first;    // columns [0, first) are already final (successive orthogonalisation)
     int z_in_zt;      // k_reorth_a reads z_j from zt
     int no_pend;      // k_reorth_a: column j has no single pending update (first column of a panel)
+    // blocked second pass (two-level schedule): the per-column pass covers
+    // [re_lo, j); the outer panel's block pass keeps its coefficient
+    // partials [n][PANEL_B1][g_b] and the reduced coefficients [n][PANEL_B1]
+    int reorth_blk;
+    int64_t re_lo;
+    void *rb_part;
+    double *rb_s;
     // padded copy of a CSR A for the column MV (ell_k = 0: not used)
     int32_t *ell_col;
     void *ell_val;
@@ -237,6 +261,7 @@ template <typename T> void launch_mv(const Ctx &c, int64_t j, int src_mode);
 template <typename T> void launch_col_hp(const Ctx &c, int64_t j, bool reorth_a);
 template <typename T> void launch_reorth_a(const Ctx &c, int64_t j);
 void launch_reorth_fin(const Ctx &c, int64_t j);
+template <typename T> void launch_rb(const Ctx &c, int64_t s, int64_t e, int variant);
 template <typename T> void launch_reorth_b(const Ctx &c, int64_t j, bool hp);
 template <typename T> void launch_sweep(const Ctx &c, int64_t j, int variant, int64_t n_rr);
 template <typename T> bool launch_hp_xblock(const Ctx &c, int64_t s, int64_t c_from);

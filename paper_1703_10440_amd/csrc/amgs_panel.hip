@@ -540,6 +540,162 @@ __global__ __launch_bounds__(B * WAVE) void k_pfin2(int64_t s, int b, int64_t c0
     }
 }
 
+// ------------------------------------------ blocked second pass (reorth = 2)
+// When an outer panel [s, s + nz) of the two-level schedule starts, its
+// columns have every first-pass projection onto the columns before s.  Each
+// of them gets the classical second pass against all i < s at once:
+// s_ic = p_i^T z_c accumulated in binary64, z_c -= sum_i s_ic q_i in binary64
+// rounded once to storage, r_ic += s_ic, and for HP x_c -= sum_i s_ic p_i.
+// Both contractions run on the binary64 matrix cores (binary32 data is
+// widened on the way in, so the products are exact and the sums binary64),
+// on the tiles and LDS staging of k_bsweep: a wave owns 64 rows of the
+// panel's columns and streams the earlier columns 16 at a time.
+template <typename T>
+__global__ __launch_bounds__(256, 4) void k_rb_dots(RbArgs a)
+{
+    typedef Mfma<double>::acc_t acc_t;
+    constexpr int WR = 64, LD = WR + 4, BB = PANEL_B1;
+    __shared__ double red[256 / WAVE][16 * BB];
+    __shared__ __attribute__((aligned(16))) T tile[256 / WAVE][16][LD];
+    if (*a.info) return;
+    const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
+    const int g4 = lane >> 4, jl = lane & 15;
+    const T *__restrict__ Q = (const T *)a.Q;
+    const T *__restrict__ P = (const T *)a.P;
+    const int64_t myrow = ((int64_t)blockIdx.x * (256 / WAVE) + wave) * WR + lane;
+    const bool rin = myrow < a.m;
+    const int nz = (int)a.nz;
+    T(*tl)[LD] = tile[wave];
+    // B operands: z_{s+l%16} at matrix row 4 (l/16) + v of each 16-row tile
+#pragma unroll
+    for (int c = 0; c < BB; ++c) tl[c][lane] = (rin && c < nz) ? Q[myrow + (a.s + c) * a.ldq] : (T)0;
+    __syncthreads();
+    double zb[4][4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) zb[st][v] = jl < BB ? (double)tl[jl][st * 16 + 4 * g4 + v] : 0.0;
+    for (int64_t ig = 0; ig < a.s; ig += 16) {
+        __syncthreads();   // the previous tile's reads and sums are done
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            tl[c][lane] = (rin && ig + c < a.s) ? P[myrow + (ig + c) * a.ldp] : (T)0;
+        __syncthreads();
+        acc_t w = {0, 0, 0, 0};
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                w = Mfma<double>::op((double)tl[jl][st * 16 + 4 * g4 + v], zb[st][v], w);
+        // W[i, c] for i = ig + Mfma<double>::row(lane, v), c = l%16 < PANEL_B1
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (jl < BB) red[wave][Mfma<double>::row(lane, v) * BB + jl] = w[v];
+        __syncthreads();
+        if (tid < 16 * BB) {
+            const int il = tid / BB, c = tid - il * BB;
+            if (ig + il < a.s && c < nz) {
+                double sum = red[0][tid];
+#pragma unroll
+                for (int wv = 1; wv < 256 / WAVE; ++wv) sum += red[wv][tid];
+                ((double *)a.part)[((ig + il) * BB + c) * a.g + blockIdx.x] = sum;
+            }
+        }
+    }
+}
+
+// s_ic from its partials (one wave each, fixed order), kept for the update
+// and added into R.
+__global__ __launch_bounds__(256) void k_rb_fin(RbArgs a, double *__restrict__ R, int64_t ldr)
+{
+    if (*a.info) return;
+    const int64_t idx = (int64_t)blockIdx.x * (256 / WAVE) + threadIdx.x / WAVE;
+    const int nz = (int)a.nz;
+    if (idx >= a.s * nz) return;
+    const int64_t i = idx / nz, c = idx - i * nz;
+    const double v = wave_reduce_seq((const double *)a.part + (i * PANEL_B1 + c) * a.g, a.g);
+    if ((threadIdx.x & (WAVE - 1)) == 0) {
+        ((double *)a.S)[i * PANEL_B1 + c] = v;
+        R[i + (a.s + c) * ldr] += v;
+    }
+}
+
+// z_c (HP: and x_c) -= sum_{i < s} s_ic q_i (p_i): D = Z + Q_tile (-S), the
+// panel's columns entering as the binary64 accumulator (register v of lane l
+// = matrix row 4 (l/16) + v of the 16-row tile, so tile row i of the A
+// operand is matrix row bs_act<double>(i)), rounded once to storage.
+template <typename T, bool HP>
+__global__ __launch_bounds__(256, 4) void k_rb_upd(RbArgs a)
+{
+    typedef Mfma<double>::acc_t acc_t;
+    constexpr int WR = 64, LD = WR + 4, BB = PANEL_B1;
+    __shared__ __attribute__((aligned(16))) T tile[256 / WAVE][16][LD];
+    if (*a.info) return;
+    const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
+    const int g4 = lane >> 4, jl = lane & 15;
+    T *__restrict__ Q = (T *)a.Q;
+    const T *__restrict__ P = (const T *)a.P;
+    T *__restrict__ X = (T *)a.X;
+    const int64_t myrow = ((int64_t)blockIdx.x * (256 / WAVE) + wave) * WR + lane;
+    const bool rin = myrow < a.m;
+    const int nz = (int)a.nz;
+    T(*tl)[LD] = tile[wave];
+    (void)tid;
+#pragma unroll
+    for (int c = 0; c < BB; ++c) {
+        tl[c][lane] = (rin && c < nz) ? Q[myrow + (a.s + c) * a.ldq] : (T)0;
+        tl[BB + c][lane] = (HP && rin && c < nz) ? X[myrow + (a.s + c) * a.ldx] : (T)0;
+    }
+    __syncthreads();
+    acc_t z[4], x[4];
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            z[st][v] = jl < BB ? (double)tl[jl][st * 16 + 4 * g4 + v] : 0.0;
+            x[st][v] = (HP && jl < BB) ? (double)tl[BB + jl][st * 16 + 4 * g4 + v] : 0.0;
+        }
+    const double *__restrict__ S = a.S;
+    // acc -= V_{<s} S over the earlier columns, 16 at a time through the tile
+    auto apply = [&](const T *__restrict__ V, int64_t ldv, acc_t(&acc)[4]) {
+        for (int64_t ig = 0; ig < a.s; ig += 16) {
+            __syncthreads();
+#pragma unroll
+            for (int c = 0; c < 16; ++c)
+                tl[c][lane] = (rin && ig + c < a.s) ? V[myrow + (ig + c) * ldv] : (T)0;
+            __syncthreads();
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const int64_t i = ig + 4 * s4 + g4;
+                const double b = (i < a.s && jl < nz) ? -S[i * BB + jl] : 0.0;
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const double av = (double)tl[4 * s4 + g4][st * 16 + bs_act<double>(jl)];
+                    acc[st] = Mfma<double>::op(av, b, acc[st]);
+                }
+            }
+        }
+    };
+    apply((const T *)Q, a.ldq, z);
+    if (HP) apply(P, a.ldp, x);
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+            if (jl < BB) {
+                tl[jl][st * 16 + 4 * g4 + v] = (T)z[st][v];
+                if (HP) tl[BB + jl][st * 16 + 4 * g4 + v] = (T)x[st][v];
+            }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < BB; ++c)
+        if (rin && c < nz) {
+            Q[myrow + (a.s + c) * a.ldq] = tl[c][lane];
+            if (HP) X[myrow + (a.s + c) * a.ldx] = tl[BB + c][lane];
+        }
+}
+
 // ------------------------------------------------------------- launchers
 template <typename T>
 void launch_psweep(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1, int64_t d0,
@@ -680,6 +836,24 @@ void launch_pfin2(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1)
                        (const double *)c.lred, c.R, c.ldr, c.info);
 }
 
+// The blocked second pass of the outer panel [s, e) against the columns
+// before s (reorth = 2).
+template <typename T>
+void launch_rb(const Ctx &c, int64_t s, int64_t e, int variant)
+{
+    if (s <= 0 || e <= s) return;
+    RbArgs a{};
+    a.m = c.m; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp; a.X = c.X; a.ldx = c.m;
+    a.s = s; a.nz = e - s; a.part = c.rb_part; a.g = c.g_b; a.S = c.rb_s; a.info = c.info;
+    const dim3 grid((unsigned)c.g_b), block(256);
+    hipLaunchKernelGGL(k_rb_dots<T>, grid, block, 0, c.stream, a);
+    const int64_t waves = s * (e - s);
+    hipLaunchKernelGGL(k_rb_fin, dim3((unsigned)((waves + 3) / 4)), block, 0, c.stream, a, c.R,
+                       c.ldr);
+    if (variant == VAR_HP) hipLaunchKernelGGL((k_rb_upd<T, true>), grid, block, 0, c.stream, a);
+    else hipLaunchKernelGGL((k_rb_upd<T, false>), grid, block, 0, c.stream, a);
+}
+
 int64_t pcol_blk_partials(const Ctx &c) { return c.geo.g_rows2; }
 
 template <typename T>
@@ -718,6 +892,8 @@ template void launch_lfin<double>(const Ctx &, int64_t, int64_t);
 template void launch_lfin<float>(const Ctx &, int64_t, int64_t);
 template void launch_pfin2<double>(const Ctx &, int64_t, int64_t, int64_t, int64_t);
 template void launch_pfin2<float>(const Ctx &, int64_t, int64_t, int64_t, int64_t);
+template void launch_rb<double>(const Ctx &, int64_t, int64_t, int);
+template void launch_rb<float>(const Ctx &, int64_t, int64_t, int);
 template void launch_pfin<float>(const Ctx &, int64_t, int64_t, int64_t);
 template void launch_pcol_blk<double>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t);
 template void launch_pcol_blk<float>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t);

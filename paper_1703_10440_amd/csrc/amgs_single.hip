@@ -545,7 +545,7 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
         double t = block_sum<double, 256>(acc, lds);
         if (tid == 0) a.rr_out[blockIdx.x] = t;
     } else {
-        const int64_t i_lo = (int64_t)blockIdx.y * RE_GROUP;
+        const int64_t i_lo = a.re_lo + (int64_t)blockIdx.y * RE_GROUP;
         reorth_partials<T, U>(P, a.ldp, j, zr, row0, a.m, a.s_part, red, i_lo, i_lo + RE_GROUP);
     }
     // R[j-1, c] for c >= j (read by later kernels only) is published last
@@ -591,7 +591,7 @@ __global__ __launch_bounds__(256) void k_reorth_a(RowArgs a)
         }
     }
     // this grid row's group of coefficients
-    const int64_t i_lo = (int64_t)blockIdx.y * RE_GROUP;
+    const int64_t i_lo = a.re_lo + (int64_t)blockIdx.y * RE_GROUP;
     reorth_partials<T, U>(P, a.ldp, j, zr, row0, a.m, a.s_part, red, i_lo, i_lo + RE_GROUP);
     // R[j-1, c] for c >= j (read by later kernels only) is published last
     if (pend && blockIdx.y == 0) publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
@@ -601,12 +601,13 @@ __global__ __launch_bounds__(256) void k_reorth_a(RowArgs a)
 // Wave w of the grid handles coefficient i = w: S[i] = sum of its partials,
 // and r_ij += S[i].
 __global__ __launch_bounds__(256) void k_reorth_fin(const double *__restrict__ s_part,
-                                                    int64_t g, int64_t j, double *__restrict__ S,
+                                                    int64_t g, int64_t i0, int64_t j,
+                                                    double *__restrict__ S,
                                                     double *__restrict__ R, int64_t ldr,
                                                     const int32_t *info)
 {
     if (*info) return;
-    const int64_t i = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+    const int64_t i = i0 + (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     if (i >= j) return;
     double s = wave_reduce_seq(s_part + i * g, g);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
@@ -640,7 +641,7 @@ __global__ __launch_bounds__(256) void k_reorth_b(RowArgs a)
         zd[u] = k < a.m ? (double)zv[k] : 0.0;
         xd[u] = (HP && k < a.m) ? (double)xv[k] : 0.0;
     }
-    for (int64_t ib = 0; ib < j; ib += 4) {
+    for (int64_t ib = a.re_lo; ib < j; ib += 4) {
         T qv[4][U], pv[HP ? 4 : 1][U];
 #pragma unroll
         for (int t = 0; t < 4; ++t)
@@ -928,9 +929,11 @@ __global__ __launch_bounds__(256) void k_csr_spmm(int64_t m, int64_t n, int64_t 
                 spmm_group<T>(Zc, ldz, nc, l, v, in, acc);
             }
         }
+        // X is not read again by this kernel: streamed past the caches, which
+        // keep the gathered rows of Z
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            if (c < nc) X[row + (c0 + c) * ldx] = acc[c];
+            if (c < nc) __builtin_nontemporal_store(acc[c], X + row + (c0 + c) * ldx);
     }
 }
 
@@ -987,9 +990,11 @@ __global__ __launch_bounds__(256) void k_csr_spmm_lanes(int64_t m, int64_t n,
 #pragma unroll
         for (int off = L / 2; off >= 1; off >>= 1) acc[c] += __shfl_xor(acc[c], off, L);
     if (live && lig == 0) {
+        // X is not read again by this kernel: streamed past the caches, which
+        // keep the gathered rows of Z
 #pragma unroll
         for (int c = 0; c < C; ++c)
-            if (c < nc) X[row + (c0 + c) * ldx] = acc[c];
+            if (c < nc) __builtin_nontemporal_store(acc[c], X + row + (c0 + c) * ldx);
     }
 }
 
@@ -1126,7 +1131,7 @@ static RowArgs row_args(const Ctx &c, int64_t j)
     a.pend = (c.cgs || c.no_pend) ? 0 : 1;
     a.z_in_zt = c.z_in_zt; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp;
     a.X = c.X; a.ldx = c.m; a.zt = c.zt; a.R = c.R; a.ldr = c.ldr; a.info = c.info;
-    a.sp = c.sp; a.rr_out = c.rr_part; a.s_part = c.s_part; a.S = c.S;
+    a.sp = c.sp; a.rr_out = c.rr_part; a.s_part = c.s_part; a.S = c.S; a.re_lo = c.re_lo;
     return a;
 }
 
@@ -1151,7 +1156,7 @@ void launch_col_hp(const Ctx &c, int64_t j, bool reorth_a)
     RowArgs a = row_args(c, j);
     const dim3 grid((unsigned)c.geo.g_rows2), block(256);
     if (reorth_a) {
-        const dim3 grid2((unsigned)c.geo.g_rows2, (unsigned)((j + RE_GROUP - 1) / RE_GROUP));
+        const dim3 grid2((unsigned)c.geo.g_rows2, (unsigned)((j - c.re_lo + RE_GROUP - 1) / RE_GROUP));
         AMGS_DISPATCH_U2(c.geo.U2, hipLaunchKernelGGL((k_col_hp<T, UU, true>), grid2, block, 0, c.stream, a));
     } else {
         AMGS_DISPATCH_U2(c.geo.U2, hipLaunchKernelGGL((k_col_hp<T, UU, false>), grid, block, 0, c.stream, a));
@@ -1162,15 +1167,17 @@ template <typename T>
 void launch_reorth_a(const Ctx &c, int64_t j)
 {
     RowArgs a = row_args(c, j);
-    const dim3 grid((unsigned)c.geo.g_rows2, (unsigned)((j + RE_GROUP - 1) / RE_GROUP)), block(256);
+    const dim3 grid((unsigned)c.geo.g_rows2, (unsigned)((j - c.re_lo + RE_GROUP - 1) / RE_GROUP)),
+        block(256);
     AMGS_DISPATCH_U2(c.geo.U2, hipLaunchKernelGGL((k_reorth_a<T, UU>), grid, block, 0, c.stream, a));
 }
 
 void launch_reorth_fin(const Ctx &c, int64_t j)
 {
-    const int64_t blocks = (j + 3) / 4;
+    const int64_t blocks = (j - c.re_lo + 3) / 4;
     hipLaunchKernelGGL(k_reorth_fin, dim3((unsigned)blocks), dim3(256), 0, c.stream,
-                       (const double *)c.s_part, c.geo.g_rows2, j, c.S, c.R, c.ldr, c.info);
+                       (const double *)c.s_part, c.geo.g_rows2, c.re_lo, j, c.S, c.R, c.ldr,
+                       c.info);
 }
 
 // One row per thread: the pass reads j earlier columns per row, so the

@@ -221,3 +221,27 @@ def test_lap128_fp64_full(lap128_fp64, variant, panel):
     Q, R, info = _run(p, variant, "fp64", panel)
     assert info == 0
     _at_oracle_level(p, Q, R, _oracles(p, variant, "fp64", panel))
+
+
+@pytest.mark.parametrize("variant", ["hp", "ha"])
+def test_lap128_fp32_blocked_second_pass(lap128_fp32, variant):
+    """The binary32 form with the blocked second pass (reorth = 2, two-level
+    schedule): residual and orthogonality at the level of the oracle's
+    blocked pass on the same binary32 inputs."""
+    p = lap128_fp32
+    Q, R, info = _run(p, variant, "fp32", 8, reorth=2)
+    assert info == 0
+    want = ref.qr_problem(p, variant=variant, orientation="panel8", precision="fp32", reorth=2)
+    _at_oracle_level(p, Q, R, [("panel8 orientation, blocked pass", want)], floors=(0.0, 0.0))
+
+
+@pytest.mark.parametrize("variant", ["hp", "ha", "naive"])
+def test_lap64_blocked_second_pass_fp64(lap64, variant):
+    p = lap64
+    Q, R, info = _run(p, variant, "fp64", 8, reorth=2)
+    assert info == 0
+    outs = [("column algorithm, per-column pass",
+             ref.qr_problem(p, variant=variant, orientation="col", reorth=True)),
+            ("panel8 orientation, blocked pass",
+             ref.qr_problem(p, variant=variant, orientation="panel8", reorth=2))]
+    _at_oracle_level(p, Q, R, outs)

@@ -239,3 +239,75 @@ def test_panel_argument_errors():
     assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(0, 3, 0, 0)) == 0
     assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(0, 4, 0, 0)) > 0
     assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(0, 8, 0, 0)) > 0
+
+
+# ----------------------------------------------- blocked second pass (reorth=2)
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("pi", [0, 1, 3, 4], ids=[SMALL[i].name for i in (0, 1, 3, 4)])
+def test_blocked_second_pass(pi, variant, precision):
+    """opts.reorth = 2 in the two-level schedule against the oracle's blocked
+    pass and against the per-column pass of the column algorithm: binary64
+    within 1e-10 (kappa(Z) <= 1e3 here), the binary32 form within the
+    binary32 bound and at the oracle's orthogonality."""
+    p = SMALL[pi]
+    if precision == "fp32":
+        Z32 = np.asfortranarray(p.Z.astype(np.float32).astype(np.float64))
+        if p.csr is not None:
+            p = inputs.Problem(p.name, Z32, csr=inputs.CSR(
+                p.m, p.csr.row_ptr, p.csr.col_idx, p.csr.vals.astype(np.float32).astype(np.float64)))
+        else:
+            p = inputs.Problem(p.name, Z32, dense=np.asfortranarray(
+                p.dense.astype(np.float32).astype(np.float64)))
+    Q, R, P, info, _ = gpu_run(p, variant, precision=precision, panel=8, reorth=2)
+    assert info == 0
+    blk = ref.qr_problem(p, variant=variant, orientation="panel8", precision=precision, reorth=2)
+    col = ref.qr_problem(p, variant=variant, orientation="col", precision=precision, reorth=True)
+    assert blk.info == 0 and col.info == 0
+    if precision == "fp64":
+        close_1e10(R, Q, P, col, "column algorithm, per-column pass")
+        close_1e10(R, Q, P, blk, "panel8 orientation, blocked pass")
+    else:
+        kappa = np.linalg.cond(oracle_col(p, variant).R)
+        tol = 64 * U32 * kappa * np.sqrt(p.n)
+        o_g = orth(p, Q)
+        for what, want in (("column algorithm, per-column pass", col),
+                           ("panel8 orientation, blocked pass", blk)):
+            e32, o_o = _rel(R, want.R), orth(p, want.Q)
+            print(f"  R vs fp32 {what} {e32:.2e} tol {tol:.2e} orth {o_g:.2e} (oracle {o_o:.2e})")
+            assert e32 <= tol, what
+            assert o_g <= max(10 * o_o, 1e-6), what
+
+
+@pytest.mark.parametrize("variant", ["naive", "ha"])
+def test_blocked_second_pass_ill_conditioned(variant):
+    """kappa(Z) ~ 1e6, three outer panels, binary32 form: the blocked pass
+    restores A-orthogonality to the per-column pass's level."""
+    p0 = inputs.laplacian_graded_problem(N=16, n=24, decades=6.0, seed=11)
+    Z32 = np.asfortranarray(p0.Z.astype(np.float32).astype(np.float64))
+    p = inputs.Problem(p0.name, Z32, csr=inputs.CSR(
+        p0.m, p0.csr.row_ptr, p0.csr.col_idx, p0.csr.vals.astype(np.float32).astype(np.float64)))
+    Q0, _, _, _, _ = gpu_run(p, variant, precision="fp32", panel=8)
+    Q, R, _, info, _ = gpu_run(p, variant, precision="fp32", panel=8, reorth=2)
+    assert info == 0
+    blk = ref.qr_problem(p, variant=variant, orientation="panel8", precision="fp32", reorth=2)
+    o0, o_g, o_o = orth(p, Q0), orth(p, Q), orth(p, blk.Q)
+    print(f"  orth without pass {o0:.2e}, blocked pass {o_g:.2e} (oracle {o_o:.2e})")
+    assert o_g <= max(10 * o_o, 1e-6) and o_g < 1e-2 * o0
+    assert ref.residual(p.Z, Q, R) <= 10 * ref.residual(p.Z, blk.Q, blk.R) + 1e-7
+
+
+def test_blocked_second_pass_needs_two_levels():
+    h = amgs.handle(0)
+    import ctypes as C
+    info = torch.zeros(1, dtype=torch.int32, device=DEV)
+    Z = torch.zeros(10, 4, dtype=torch.float64, device=DEV)
+    work = torch.empty(1 << 20, dtype=torch.uint8, device=DEV)
+    for reorth, panel, want in ((2, 0, -4), (2, 4, -4), (3, 8, -1)):
+        opts = amgs.Opts(reorth, panel, 0, 0)
+        st = amgs.amgs_qr_dense(h, 10, Z.data_ptr(), 10, 4, Z.data_ptr(), 10, Z.data_ptr(), 10,
+                                Z.data_ptr(), 4, None, 0, 1, 0, C.byref(opts), work.data_ptr(),
+                                work.numel(), info.data_ptr(), None)
+        assert st == want, (reorth, panel, st)
+    assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(2, 8, 0, 0)) > 0
+    assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(2, 4, 0, 0)) == 0
