@@ -26,6 +26,7 @@ constexpr int PANEL_B1 = 8;    // columns per outer panel of the two-level panel
 #define AMGS_BS_ST 4
 #endif
 constexpr int BS_ST = AMGS_BS_ST; // 16-row tiles per wave of the outer block sweep
+constexpr int RB_GROUPS = 2;   // 16-column groups whose blocked-pass products a wave holds at once
 constexpr int BS_MAXC = 256;   // later columns per outer-block-sweep workgroup (max, a multiple of 16)
 constexpr int PS_CB = 2;       // later columns streamed together by a panel-sweep thread
 constexpr int PS_MAXC = 64;    // later columns per panel-sweep workgroup (max)

@@ -551,10 +551,10 @@ __global__ __launch_bounds__(B * WAVE) void k_pfin2(int64_t s, int b, int64_t c0
 // on the tiles and LDS staging of k_bsweep: a wave owns 64 rows of the
 // panel's columns and streams the earlier columns 16 at a time.
 template <typename T>
-__global__ __launch_bounds__(256, 4) void k_rb_dots(RbArgs a)
+__global__ __launch_bounds__(256) void k_rb_dots(RbArgs a)
 {
     typedef Mfma<double>::acc_t acc_t;
-    constexpr int WR = 64, LD = WR + 4, BB = PANEL_B1;
+    constexpr int WR = 64, LD = WR + 4, BB = PANEL_B1, NG = RB_GROUPS;
     __shared__ double red[256 / WAVE][16 * BB];
     __shared__ __attribute__((aligned(16))) T tile[256 / WAVE][16][LD];
     if (*a.info) return;
@@ -575,30 +575,52 @@ __global__ __launch_bounds__(256, 4) void k_rb_dots(RbArgs a)
     for (int st = 0; st < 4; ++st)
 #pragma unroll
         for (int v = 0; v < 4; ++v) zb[st][v] = jl < BB ? (double)tl[jl][st * 16 + 4 * g4 + v] : 0.0;
-    for (int64_t ig = 0; ig < a.s; ig += 16) {
-        __syncthreads();   // the previous tile's reads and sums are done
+    // the earlier columns 16 at a time, NG groups per round: the next group's
+    // columns are loaded while the current one's products run, and the
+    // round's products stay in registers until its sums are written
+    T nxt[16];
+    auto load = [&](int64_t ig) {
 #pragma unroll
         for (int c = 0; c < 16; ++c)
-            tl[c][lane] = (rin && ig + c < a.s) ? P[myrow + (ig + c) * a.ldp] : (T)0;
-        __syncthreads();
-        acc_t w = {0, 0, 0, 0};
+            nxt[c] = (rin && ig + c < a.s) ? P[myrow + (ig + c) * a.ldp] : (T)0;
+    };
+    load(0);
+    for (int64_t ig0 = 0; ig0 < a.s; ig0 += 16 * NG) {
+        acc_t w[NG];
 #pragma unroll
-        for (int st = 0; st < 4; ++st)
+        for (int q = 0; q < NG; ++q) {
+            w[q] = acc_t{0, 0, 0, 0};
+            const int64_t ig = ig0 + 16 * q;
+            if (ig >= a.s) continue;
+            __syncthreads();   // the previous group's LDS reads are done
 #pragma unroll
-            for (int v = 0; v < 4; ++v)
-                w = Mfma<double>::op((double)tl[jl][st * 16 + 4 * g4 + v], zb[st][v], w);
+            for (int c = 0; c < 16; ++c) tl[c][lane] = nxt[c];
+            __syncthreads();
+            if (ig + 16 < a.s) load(ig + 16);
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    w[q] = Mfma<double>::op((double)tl[jl][st * 16 + 4 * g4 + v], zb[st][v], w[q]);
+        }
         // W[i, c] for i = ig + Mfma<double>::row(lane, v), c = l%16 < PANEL_B1
 #pragma unroll
-        for (int v = 0; v < 4; ++v)
-            if (jl < BB) red[wave][Mfma<double>::row(lane, v) * BB + jl] = w[v];
-        __syncthreads();
-        if (tid < 16 * BB) {
-            const int il = tid / BB, c = tid - il * BB;
-            if (ig + il < a.s && c < nz) {
-                double sum = red[0][tid];
+        for (int q = 0; q < NG; ++q) {
+            const int64_t ig = ig0 + 16 * q;
+            if (ig >= a.s) continue;
+            __syncthreads();
 #pragma unroll
-                for (int wv = 1; wv < 256 / WAVE; ++wv) sum += red[wv][tid];
-                ((double *)a.part)[((ig + il) * BB + c) * a.g + blockIdx.x] = sum;
+            for (int v = 0; v < 4; ++v)
+                if (jl < BB) red[wave][Mfma<double>::row(lane, v) * BB + jl] = w[q][v];
+            __syncthreads();
+            if (tid < 16 * BB) {
+                const int il = tid / BB, c = tid - il * BB;
+                if (ig + il < a.s && c < nz) {
+                    double sum = red[0][tid];
+#pragma unroll
+                    for (int wv = 1; wv < 256 / WAVE; ++wv) sum += red[wv][tid];
+                    ((double *)a.part)[((ig + il) * BB + c) * a.g + blockIdx.x] = sum;
+                }
             }
         }
     }
@@ -625,7 +647,7 @@ __global__ __launch_bounds__(256) void k_rb_fin(RbArgs a, double *__restrict__ R
 // = matrix row 4 (l/16) + v of the 16-row tile, so tile row i of the A
 // operand is matrix row bs_act<double>(i)), rounded once to storage.
 template <typename T, bool HP>
-__global__ __launch_bounds__(256, 4) void k_rb_upd(RbArgs a)
+__global__ __launch_bounds__(256) void k_rb_upd(RbArgs a)
 {
     typedef Mfma<double>::acc_t acc_t;
     constexpr int WR = 64, LD = WR + 4, BB = PANEL_B1;
@@ -656,14 +678,21 @@ __global__ __launch_bounds__(256, 4) void k_rb_upd(RbArgs a)
             x[st][v] = (HP && jl < BB) ? (double)tl[BB + jl][st * 16 + 4 * g4 + v] : 0.0;
         }
     const double *__restrict__ S = a.S;
-    // acc -= V_{<s} S over the earlier columns, 16 at a time through the tile
+    // acc -= V_{<s} S over the earlier columns, 16 at a time through the
+    // tile, the next group's columns loaded while the current one's products run
     auto apply = [&](const T *__restrict__ V, int64_t ldv, acc_t(&acc)[4]) {
+        T nxt[16];
+#pragma unroll
+        for (int c = 0; c < 16; ++c) nxt[c] = (rin && c < a.s) ? V[myrow + c * ldv] : (T)0;
         for (int64_t ig = 0; ig < a.s; ig += 16) {
             __syncthreads();
 #pragma unroll
-            for (int c = 0; c < 16; ++c)
-                tl[c][lane] = (rin && ig + c < a.s) ? V[myrow + (ig + c) * ldv] : (T)0;
+            for (int c = 0; c < 16; ++c) tl[c][lane] = nxt[c];
             __syncthreads();
+            if (ig + 16 < a.s)
+#pragma unroll
+                for (int c = 0; c < 16; ++c)
+                    nxt[c] = (rin && ig + 16 + c < a.s) ? V[myrow + (ig + 16 + c) * ldv] : (T)0;
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) {
                 const int64_t i = ig + 4 * s4 + g4;
