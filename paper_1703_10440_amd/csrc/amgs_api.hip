@@ -303,7 +303,7 @@ double psweep_bytes(int64_t m, size_t w, int64_t ncols, int64_t kw, int64_t bd, 
 // vectors, and k_lfin + k_pfin2 solve for the coefficients.  A column thus
 // receives the blocks of the earlier outer panels, then the block of the
 // earlier inner panel of its own outer panel, then the column steps of its
-// inner panel: the order of the oracle's panel orientations.
+// inner panel (the order of the two-level panel reading of the method).
 template <typename T>
 amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
 {

@@ -149,6 +149,21 @@ __device__ __forceinline__ T ld_stream(const T *p)
     if constexpr (NT) return __builtin_nontemporal_load(p);
     else return *p;
 }
+// Guarded loads that stay in flight together.  A load under a test that is
+// the same in every lane (a column count) is otherwise compiled as a branch
+// that waits for the load at its join.  ld_fix issues the load from an
+// index that is always valid (f when !ok), pin() keeps the compiler from
+// moving the issued loads below it, and pick() then drops the values of the
+// failed tests: v = ld_fix(p, i, f, ok); ...; pin(); v = pick(v, ok).
+template <bool NT = false, typename T>
+__device__ __forceinline__ T ld_fix(const T *__restrict__ p, int64_t i, int64_t f, bool ok)
+{
+    return ld_stream<NT>(p + (ok ? i : f));
+}
+__device__ __forceinline__ void pin() { asm volatile("" ::: "memory"); }
+template <typename T>
+__device__ __forceinline__ T pick(T v, bool ok) { return ok ? v : (T)0; }
+
 template <bool NT, typename T>
 __device__ __forceinline__ void st_stream(T *p, T v)
 {

@@ -122,6 +122,19 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
     }
     for (int64_t cb = c0; cb < c1; cb += PS_CB) {
         if (cb > c0) load_group(cb);
+        // the group's pending coefficients; in binary32 they are requested
+        // together (the compiler would otherwise wait for each one where it
+        // is converted; a coefficient past the group or the block reads R[0],
+        // unused)
+        double rcd[PS_CB][KB];
+        if constexpr (sizeof(T) == 4) {
+#pragma unroll
+            for (int t = 0; t < PS_CB; ++t)
+#pragma unroll
+                for (int i = 0; i < KB; ++i)
+                    rcd[t][i] = ld_fix(a.R, (a.k0 + i) + (cb + t) * a.ldr, 0, cb + t < c1 && i < kw);
+            pin();
+        }
         T acc[PS_CB][DB];
 #pragma unroll
         for (int t = 0; t < PS_CB; ++t) {
@@ -129,7 +142,8 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
             T rc[KB];
 #pragma unroll
             for (int i = 0; i < KB; ++i)
-                rc[i] = (cin && i < kw) ? (T)a.R[(a.k0 + i) + (cb + t) * a.ldr] : (T)0;
+                rc[i] = sizeof(T) == 4 ? (T)rcd[t][i]
+                                       : ((cin && i < kw) ? (T)a.R[(a.k0 + i) + (cb + t) * a.ldr] : (T)0);
 #pragma unroll
             for (int d = 0; d < DB; ++d) acc[t][d] = 0;
 #pragma unroll
@@ -546,10 +560,11 @@ __global__ __launch_bounds__(B * WAVE) void k_pfin2(int64_t s, int b, int64_t c0
 // of them gets the classical second pass against all i < s at once:
 // s_ic = p_i^T z_c accumulated in binary64, z_c -= sum_i s_ic q_i in binary64
 // rounded once to storage, r_ic += s_ic, and for HP x_c -= sum_i s_ic p_i.
-// Both contractions run on the binary64 matrix cores (binary32 data is
-// widened on the way in, so the products are exact and the sums binary64),
-// on the tiles and LDS staging of k_bsweep: a wave owns 64 rows of the
-// panel's columns and streams the earlier columns 16 at a time.
+// The dots run on the binary64 matrix cores (binary32 data is widened on
+// the way in, so the products are exact and the sums binary64), on the
+// tiles and LDS staging of k_bsweep: a wave owns 64 rows of the panel's
+// columns and streams the earlier columns 16 at a time.  The update runs
+// on the vector units (k_rb_updv).
 template <typename T>
 __global__ __launch_bounds__(256) void k_rb_dots(RbArgs a)
 {
@@ -642,86 +657,76 @@ __global__ __launch_bounds__(256) void k_rb_fin(RbArgs a, double *__restrict__ R
     }
 }
 
-// z_c (HP: and x_c) -= sum_{i < s} s_ic q_i (p_i): D = Z + Q_tile (-S), the
-// panel's columns entering as the binary64 accumulator (register v of lane l
-// = matrix row 4 (l/16) + v of the 16-row tile, so tile row i of the A
-// operand is matrix row bs_act<double>(i)), rounded once to storage.
-template <typename T, bool HP>
-__global__ __launch_bounds__(256) void k_rb_upd(RbArgs a)
+// z_c (HP: and x_c) -= sum_{i < s} s_ic q_i (p_i), binary64 accumulation
+// rounded once to storage, on the vector units: one row per thread, the
+// panel's columns in binary64 registers, the earlier columns streamed
+// sixteen at a time with every coefficient s_ic a wave-uniform operand.
+// Each earlier element is used by eight fused multiply-adds (one per panel
+// column), so no product is wasted (on the 16x16x4 matrix cores half of
+// them would be), and the kernel needs neither LDS nor barriers.  The
+// loads are unconditional (a column index past the end is clamped, its
+// value dropped by a select or a uniform test) so that they are all in
+// flight together.
+template <typename T, bool HP, bool FULL>
+__device__ __forceinline__ void rb_updv_group(const T *__restrict__ Q, int64_t ldq,
+                                              const T *__restrict__ P, int64_t ldp,
+                                              const double *__restrict__ S, int64_t row,
+                                              int64_t ib, int64_t s, double (&z)[PANEL_B1],
+                                              double (&x)[PANEL_B1])
 {
-    typedef Mfma<double>::acc_t acc_t;
-    constexpr int WR = 64, LD = WR + 4, BB = PANEL_B1;
-    __shared__ __attribute__((aligned(16))) T tile[256 / WAVE][16][LD];
+    constexpr int BB = PANEL_B1, G = 16;
+    T qv[G], pv[HP ? G : 1];
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+        const int64_t i = FULL ? ib + t : (ib + t < s ? ib + t : s - 1);
+        qv[t] = Q[row + i * ldq];
+        if (HP) pv[HP ? t : 0] = P[row + i * ldp];
+    }
+#pragma unroll
+    for (int t = 0; t < G; ++t) {
+        if (FULL || ib + t < s) {
+            const double qd = (double)qv[t];
+            const double pd = HP ? (double)pv[HP ? t : 0] : 0.0;
+#pragma unroll
+            for (int c = 0; c < BB; ++c) {
+                const double sc = S[(ib + t) * BB + c];
+                z[c] = __builtin_fma(-sc, qd, z[c]);
+                if (HP) x[c] = __builtin_fma(-sc, pd, x[c]);
+            }
+        }
+    }
+}
+
+template <typename T, bool HP>
+__global__ __launch_bounds__(256) void k_rb_updv(RbArgs a)
+{
+    constexpr int BB = PANEL_B1, G = 16;
     if (*a.info) return;
-    const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
-    const int g4 = lane >> 4, jl = lane & 15;
+    const int64_t row = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (row >= a.m) return;
     T *__restrict__ Q = (T *)a.Q;
     const T *__restrict__ P = (const T *)a.P;
     T *__restrict__ X = (T *)a.X;
-    const int64_t myrow = ((int64_t)blockIdx.x * (256 / WAVE) + wave) * WR + lane;
-    const bool rin = myrow < a.m;
     const int nz = (int)a.nz;
-    T(*tl)[LD] = tile[wave];
-    (void)tid;
+    const int64_t s = a.s;
+    double z[BB], x[BB];
 #pragma unroll
     for (int c = 0; c < BB; ++c) {
-        tl[c][lane] = (rin && c < nz) ? Q[myrow + (a.s + c) * a.ldq] : (T)0;
-        tl[BB + c][lane] = (HP && rin && c < nz) ? X[myrow + (a.s + c) * a.ldx] : (T)0;
+        const int64_t cc = s + (c < nz ? c : nz - 1);
+        const T zv = Q[row + cc * a.ldq];
+        const T xv = HP ? X[row + cc * a.ldx] : (T)0;
+        z[c] = c < nz ? (double)zv : 0.0;
+        x[c] = (HP && c < nz) ? (double)xv : 0.0;
     }
-    __syncthreads();
-    acc_t z[4], x[4];
-#pragma unroll
-    for (int st = 0; st < 4; ++st)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            z[st][v] = jl < BB ? (double)tl[jl][st * 16 + 4 * g4 + v] : 0.0;
-            x[st][v] = (HP && jl < BB) ? (double)tl[BB + jl][st * 16 + 4 * g4 + v] : 0.0;
-        }
-    const double *__restrict__ S = a.S;
-    // acc -= V_{<s} S over the earlier columns, 16 at a time through the
-    // tile, the next group's columns loaded while the current one's products run
-    auto apply = [&](const T *__restrict__ V, int64_t ldv, acc_t(&acc)[4]) {
-        T nxt[16];
-#pragma unroll
-        for (int c = 0; c < 16; ++c) nxt[c] = (rin && c < a.s) ? V[myrow + c * ldv] : (T)0;
-        for (int64_t ig = 0; ig < a.s; ig += 16) {
-            __syncthreads();
-#pragma unroll
-            for (int c = 0; c < 16; ++c) tl[c][lane] = nxt[c];
-            __syncthreads();
-            if (ig + 16 < a.s)
-#pragma unroll
-                for (int c = 0; c < 16; ++c)
-                    nxt[c] = (rin && ig + 16 + c < a.s) ? V[myrow + (ig + 16 + c) * ldv] : (T)0;
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-                const int64_t i = ig + 4 * s4 + g4;
-                const double b = (i < a.s && jl < nz) ? -S[i * BB + jl] : 0.0;
-#pragma unroll
-                for (int st = 0; st < 4; ++st) {
-                    const double av = (double)tl[4 * s4 + g4][st * 16 + bs_act<double>(jl)];
-                    acc[st] = Mfma<double>::op(av, b, acc[st]);
-                }
-            }
-        }
-    };
-    apply((const T *)Q, a.ldq, z);
-    if (HP) apply(P, a.ldp, x);
-    __syncthreads();
-#pragma unroll
-    for (int st = 0; st < 4; ++st)
-#pragma unroll
-        for (int v = 0; v < 4; ++v)
-            if (jl < BB) {
-                tl[jl][st * 16 + 4 * g4 + v] = (T)z[st][v];
-                if (HP) tl[BB + jl][st * 16 + 4 * g4 + v] = (T)x[st][v];
-            }
-    __syncthreads();
+    int64_t ib = 0;
+    for (; ib + G <= s; ib += G)
+        rb_updv_group<T, HP, true>(Q, a.ldq, P, a.ldp, a.S, row, ib, s, z, x);
+    if (ib < s) rb_updv_group<T, HP, false>(Q, a.ldq, P, a.ldp, a.S, row, ib, s, z, x);
 #pragma unroll
     for (int c = 0; c < BB; ++c)
-        if (rin && c < nz) {
-            Q[myrow + (a.s + c) * a.ldq] = tl[c][lane];
-            if (HP) X[myrow + (a.s + c) * a.ldx] = tl[BB + c][lane];
+        if (c < nz) {
+            Q[row + (s + c) * a.ldq] = (T)z[c];
+            if (HP) X[row + (s + c) * a.ldx] = (T)x[c];
         }
 }
 
@@ -879,8 +884,9 @@ void launch_rb(const Ctx &c, int64_t s, int64_t e, int variant)
     const int64_t waves = s * (e - s);
     hipLaunchKernelGGL(k_rb_fin, dim3((unsigned)((waves + 3) / 4)), block, 0, c.stream, a, c.R,
                        c.ldr);
-    if (variant == VAR_HP) hipLaunchKernelGGL((k_rb_upd<T, true>), grid, block, 0, c.stream, a);
-    else hipLaunchKernelGGL((k_rb_upd<T, false>), grid, block, 0, c.stream, a);
+    const dim3 gv((unsigned)((c.m + 255) / 256));
+    if (variant == VAR_HP) hipLaunchKernelGGL((k_rb_updv<T, true>), gv, block, 0, c.stream, a);
+    else hipLaunchKernelGGL((k_rb_updv<T, false>), gv, block, 0, c.stream, a);
 }
 
 int64_t pcol_blk_partials(const Ctx &c) { return c.geo.g_rows2; }

@@ -218,6 +218,13 @@ __global__ __launch_bounds__(MV_TILE) void k_csr_mv_ell(CsrMvArgs a)
     const int K = a.ell_k;
     const int64_t m = a.m;
     const int64_t stride = (int64_t)gridDim.x * MV_TILE;
+    // Every load is unconditional and pinned (see ld_fix) before its value
+    // is tested, so that all entries, and then all gathers, are in flight
+    // together.  A row past the end reads row m - 1 (its results are not
+    // stored), a slot from K on repeats slot K - 1 and a padding entry
+    // gathers the row's own element; both are then skipped.  Without a
+    // pending term q_{j-1} is read from src and not used.
+    const T *__restrict__ qsrc = with_upd ? qprev : src;
     T r = 0;
     double rjj = 1.0;
     double acc = 0.0;
@@ -229,28 +236,27 @@ __global__ __launch_bounds__(MV_TILE) void k_csr_mv_ell(CsrMvArgs a)
         T av[RPT][ELL_K];
         T own_s[RPT], own_q[RPT];
         int lng[RPT];
+        int64_t rowc[RPT];
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
             const int64_t t0 = row0 + u * stride;
             const int64_t row = t0 + tid;
-            const bool live = row < m;
-            lng[u] = t0 < m ? a.tile_long[t0 / MV_TILE] : 0;
-            own_s[u] = 0;
-            own_q[u] = 0;
+            rowc[u] = row < m ? row : m - 1;
+            lng[u] = a.tile_long[(t0 < m ? t0 : m - 1) / MV_TILE] & -(int)(t0 < m);
 #pragma unroll
             for (int k = 0; k < ELL_K; ++k) {
-                col[u][k] = -1;
-                av[u][k] = 0;
-                if (live && k < K) {
-                    col[u][k] = ecol[(int64_t)k * m + row];
-                    av[u][k] = eval[(int64_t)k * m + row];
-                }
+                const int64_t kc = k < K ? k : K - 1;
+                col[u][k] = ecol[kc * m + rowc[u]] | -(int32_t)(k >= K);
+                av[u][k] = eval[kc * m + rowc[u]];
             }
-            if (live && (SRC == SRC_UPD || RR)) {
-                own_s[u] = src[row];
-                if (with_upd) own_q[u] = qprev[row];
+            own_s[u] = 0;
+            own_q[u] = 0;
+            if (SRC == SRC_UPD || RR) {
+                own_s[u] = src[rowc[u]];
+                if (SRC == SRC_UPD) own_q[u] = qsrc[rowc[u]];
             }
         }
+        pin();
         // the coefficient r_{j-1,j} (or r_jj for the naive second MV) is
         // re-reduced by wave 0 while those loads are in flight
         if (first && (with_upd || SRC == SRC_DIV)) {
@@ -278,11 +284,27 @@ __global__ __launch_bounds__(MV_TILE) void k_csr_mv_ell(CsrMvArgs a)
             if (SRC == SRC_DIV) v = scale_div(v, rjj);
             return v;
         };
-        T xv[RPT][ELL_K];
+        // every gather (with q_{j-1} at the same rows) is issued before any
+        // is used
+        T xv[RPT][ELL_K], xq[SRC == SRC_UPD ? RPT : 1][ELL_K];
 #pragma unroll
         for (int u = 0; u < RPT; ++u)
 #pragma unroll
-            for (int k = 0; k < ELL_K; ++k) xv[u][k] = col[u][k] >= 0 ? load(col[u][k]) : (T)0;
+            for (int k = 0; k < ELL_K; ++k) {
+                const int32_t c = col[u][k];
+                const int64_t l = c >= 0 ? (int64_t)c : rowc[u];
+                xv[u][k] = src[l];
+                if (SRC == SRC_UPD) xq[SRC == SRC_UPD ? u : 0][k] = qsrc[l];
+            }
+        pin();
+#pragma unroll
+        for (int u = 0; u < RPT; ++u)
+#pragma unroll
+            for (int k = 0; k < ELL_K; ++k) {
+                if (SRC == SRC_UPD)
+                    xv[u][k] = with_upd ? upd(xv[u][k], r, xq[SRC == SRC_UPD ? u : 0][k]) : xv[u][k];
+                if (SRC == SRC_DIV) xv[u][k] = scale_div(xv[u][k], rjj);
+            }
 #pragma unroll
         for (int u = 0; u < RPT; ++u) {
             const int64_t row = row0 + u * stride + tid;
@@ -291,8 +313,10 @@ __global__ __launch_bounds__(MV_TILE) void k_csr_mv_ell(CsrMvArgs a)
             // multiplied by zero
             T s = 0;
 #pragma unroll
-            for (int k = 0; k < ELL_K; ++k)
-                if (col[u][k] >= 0) s += av[u][k] * xv[u][k];
+            for (int k = 0; k < ELL_K; ++k) {
+                const T t = s + av[u][k] * xv[u][k];
+                s = col[u][k] >= 0 ? t : s;
+            }
             if (lng[u]) {
                 // the row's entries past the first K, eight at a time
                 const int32_t e1 = a.row_ptr[row + 1];
@@ -315,7 +339,7 @@ __global__ __launch_bounds__(MV_TILE) void k_csr_mv_ell(CsrMvArgs a)
             y[row] = s;
             if (SRC == SRC_UPD || RR) {
                 T zs = own_s[u];
-                if (with_upd) zs = upd(zs, r, own_q[u]);
+                if (SRC == SRC_UPD) zs = with_upd ? upd(zs, r, own_q[u]) : zs;
                 if (SRC == SRC_DIV) zs = scale_div(zs, rjj);
                 if (SRC == SRC_UPD) zt[row] = zs;
                 if (RR) acc += (double)zs * (double)s;
@@ -421,50 +445,49 @@ __global__ __launch_bounds__(256) void k_dense_mv(DenseMvArgs a)
     if (SRC == SRC_UPD && qprev) publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
 }
 
-// Partials of the second-pass coefficients s_i = p_i^T z_j, i < j, for the
-// rows this workgroup owns (binary64 accumulation): eight p_i are streamed
-// together, each wave reduces its part, and the four wave sums are combined
-// in wave order once per 64 coefficients.
+// The p_i of one workgroup's group of second-pass coefficients,
+// i in [i_lo, min(i_lo + RE_GROUP, j)), at its rows (zero elsewhere).
 template <typename T, int U>
-__device__ __forceinline__ void reorth_partials(const T *__restrict__ P, int64_t ldp, int64_t j,
-                                                const T (&zr)[U], int64_t row0, int64_t m,
-                                                double *__restrict__ s_part, double (*red)[64],
-                                                int64_t i_lo, int64_t i_hi)
+__device__ __forceinline__ void reorth_load(const T *__restrict__ P, int64_t ldp, int64_t j,
+                                            int64_t i_lo, int64_t row0, int64_t m,
+                                            T (&pv)[RE_GROUP][U])
+{
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int t = 0; t < RE_GROUP; ++t)
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = row0 + u * 256 + tid;
+            const int64_t kc = k < m ? k : m - 1;
+            pv[t][u] = ld_fix(P, k + (i_lo + t) * ldp, kc, i_lo + t < j && k < m);
+        }
+}
+
+// Partials of the second-pass coefficients s_i = p_i^T z_j of that group
+// over the workgroup's rows (binary64 accumulation): each wave reduces its
+// part, and the four wave sums are combined in wave order.
+template <typename T, int U>
+__device__ __forceinline__ void reorth_partials(const T (&pv)[RE_GROUP][U], const T (&zr)[U],
+                                                int64_t j, int64_t i_lo,
+                                                double *__restrict__ s_part,
+                                                double (*red)[RE_GROUP])
 {
     const int tid = threadIdx.x, wave = tid / WAVE;
-    if (i_hi > j) i_hi = j;
-    for (int64_t ib0 = i_lo; ib0 < i_hi; ib0 += 64) {
-        const int64_t nb = (i_hi - ib0 < 64) ? i_hi - ib0 : 64;
-        for (int64_t ib = ib0; ib < ib0 + nb; ib += 8) {
-            double sacc[8];
-            T pv[8][U];
+    const int64_t nb = j - i_lo < RE_GROUP ? j - i_lo : RE_GROUP;
 #pragma unroll
-            for (int t = 0; t < 8; ++t)
+    for (int t = 0; t < RE_GROUP; ++t) {
+        double sacc = 0.0;
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int64_t k = row0 + u * 256 + tid;
-                    pv[t][u] = (ib + t < ib0 + nb && k < m) ? P[k + (ib + t) * ldp] : (T)0;
-                }
+        for (int u = 0; u < U; ++u) sacc += (double)pv[t][u] * (double)zr[u];
+        const double v = wave_sum(sacc);
+        if ((tid & (WAVE - 1)) == 0) red[wave][t] = v;
+    }
+    __syncthreads();
+    if (tid < nb) {
+        double v = red[0][tid];
 #pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                sacc[t] = 0.0;
-#pragma unroll
-                for (int u = 0; u < U; ++u) sacc[t] += (double)pv[t][u] * (double)zr[u];
-            }
-#pragma unroll
-            for (int t = 0; t < 8; ++t) {
-                const double v = wave_sum(sacc[t]);
-                if ((tid & (WAVE - 1)) == 0 && ib + t < ib0 + nb) red[wave][ib - ib0 + t] = v;
-            }
-        }
-        __syncthreads();
-        if (tid < nb) {
-            double v = red[0][tid];
-#pragma unroll
-            for (int w = 1; w < 256 / WAVE; ++w) v += red[w][tid];
-            s_part[(ib0 + tid) * gridDim.x + blockIdx.x] = v;
-        }
-        __syncthreads();
+        for (int w = 1; w < 256 / WAVE; ++w) v += red[w][tid];
+        s_part[(i_lo + tid) * gridDim.x + blockIdx.x] = v;
     }
 }
 
@@ -478,7 +501,7 @@ template <typename T, int U, bool REORTH_A>
 __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
 {
     __shared__ double lds[256 / WAVE];
-    __shared__ double red[256 / WAVE][64];
+    __shared__ double red[256 / WAVE][RE_GROUP];
     __shared__ T s_r;
     if (*a.info) return;
     const int64_t j = a.j;
@@ -497,12 +520,29 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
         const bool in = k < a.m;
+        const int64_t kc = in ? k : a.m - 1;
         const bool xin = in && blockIdx.y == 0;   // only grid row 0 needs x_j
-        zr[u] = in ? Q[k + j * a.ldq] : (T)0;
-        qp[u] = (in && j > 0) ? Q[k + (j - 1) * a.ldq] : (T)0;
-        x[u] = xin ? X[k + j * a.ldx] : (T)0;
+        zr[u] = ld_fix(Q, k + j * a.ldq, kc, in);
+        qp[u] = ld_fix(Q, k + (j - 1) * a.ldq, kc, in && j > 0);
+        x[u] = ld_fix(X, k + j * a.ldx, kc, xin);
 #pragma unroll
-        for (int t = 0; t < HP_XB; ++t) pv[t][u] = (xin && i0 + t < j) ? P[k + (i0 + t) * a.ldp] : (T)0;
+        for (int t = 0; t < HP_XB; ++t)
+            pv[t][u] = ld_fix(P, k + (i0 + t) * a.ldp, kc, xin && i0 + t < j);
+    }
+    // the published r_ij of the recurrence (i < j - 1), requested with them
+    double rv[HP_XB];
+#pragma unroll
+    for (int t = 0; t < HP_XB; ++t) rv[t] = ld_fix(a.R, (i0 + t) + j * a.ldr, 0, i0 + t < j - 1);
+    pin();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = row0 + u * 256 + tid;
+        const bool in = k < a.m, xin = in && blockIdx.y == 0;
+        zr[u] = pick(zr[u], in);
+        qp[u] = pick(qp[u], in && j > 0);
+        x[u] = pick(x[u], xin);
+#pragma unroll
+        for (int t = 0; t < HP_XB; ++t) pv[t][u] = pick(pv[t][u], xin && i0 + t < j);
     }
     // with REORTH_A the grid has one row per group of second-pass
     // coefficients; grid row 0 alone writes z_j (to zt, so that the other
@@ -526,7 +566,7 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
         for (int t = 0; t < HP_XB; ++t) {
             const int64_t i = i0 + t;
             if (i < j) {
-                const T ri = (i == j - 1) ? r : (T)a.R[i + j * a.ldr];
+                const T ri = (i == j - 1) ? r : (T)rv[t];
 #pragma unroll
                 for (int u = 0; u < U; ++u) x[u] = upd(x[u], ri, pv[t][u]);
             }
@@ -546,7 +586,9 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
         if (tid == 0) a.rr_out[blockIdx.x] = t;
     } else {
         const int64_t i_lo = a.re_lo + (int64_t)blockIdx.y * RE_GROUP;
-        reorth_partials<T, U>(P, a.ldp, j, zr, row0, a.m, a.s_part, red, i_lo, i_lo + RE_GROUP);
+        T pr[RE_GROUP][U];
+        reorth_load<T, U>(P, a.ldp, j, i_lo, row0, a.m, pr);
+        reorth_partials<T, U>(pr, zr, j, i_lo, a.s_part, red);
     }
     // R[j-1, c] for c >= j (read by later kernels only) is published last
     if (j > 0 && own) publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
@@ -559,7 +601,7 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
 template <typename T, int U>
 __global__ __launch_bounds__(256) void k_reorth_a(RowArgs a)
 {
-    __shared__ double red[256 / WAVE][64];
+    __shared__ double red[256 / WAVE][RE_GROUP];
     __shared__ T s_r;
     if (*a.info) return;
     const int64_t j = a.j;
@@ -570,15 +612,29 @@ __global__ __launch_bounds__(256) void k_reorth_a(RowArgs a)
     const int64_t row0 = (int64_t)blockIdx.x * 256 * U;
     // z_j from Q (or, for a second classical pass of naive / HA, from zt);
     // with pend, the pending update r_{j-1,j} q_{j-1} of the column
-    // schedule is applied first (classical Gram-Schmidt has none)
+    // schedule is applied first (classical Gram-Schmidt has none).  All row
+    // loads, this grid row's p_i included, are issued before the wait for
+    // r_{j-1,j}.
     const bool pend = a.pend && j > 0;
     const T *__restrict__ zsrc = a.z_in_zt ? (const T *)zt : Q + j * a.ldq;
-    T zr[U], qp[U];
+    const int64_t i_lo = a.re_lo + (int64_t)blockIdx.y * RE_GROUP;
+    T zr[U], qp[U], pv[RE_GROUP][U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
-        zr[u] = k < a.m ? zsrc[k] : (T)0;
-        qp[u] = (k < a.m && pend) ? Q[k + (j - 1) * a.ldq] : (T)0;
+        const int64_t kc = k < a.m ? k : a.m - 1;
+        zr[u] = ld_fix(zsrc, k, kc, k < a.m);
+        qp[u] = ld_fix(Q, k + (j - 1) * a.ldq, kc, k < a.m && pend);
+    }
+    reorth_load<T, U>(P, a.ldp, j, i_lo, row0, a.m, pv);
+    pin();
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const int64_t k = row0 + u * 256 + tid;
+        zr[u] = pick(zr[u], k < a.m);
+        qp[u] = pick(qp[u], k < a.m && pend);
+#pragma unroll
+        for (int t = 0; t < RE_GROUP; ++t) pv[t][u] = pick(pv[t][u], i_lo + t < j && k < a.m);
     }
     T r = 0;
     if (pend) r = block_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
@@ -590,9 +646,7 @@ __global__ __launch_bounds__(256) void k_reorth_a(RowArgs a)
             if (blockIdx.y == 0 && !a.z_in_zt) zt[k] = zr[u];
         }
     }
-    // this grid row's group of coefficients
-    const int64_t i_lo = a.re_lo + (int64_t)blockIdx.y * RE_GROUP;
-    reorth_partials<T, U>(P, a.ldp, j, zr, row0, a.m, a.s_part, red, i_lo, i_lo + RE_GROUP);
+    reorth_partials<T, U>(pv, zr, j, i_lo, a.s_part, red);
     // R[j-1, c] for c >= j (read by later kernels only) is published last
     if (pend && blockIdx.y == 0) publish_row<T>(a.sp, j - 1, j, a.n, a.R, a.ldr);
 }
@@ -638,24 +692,32 @@ __global__ __launch_bounds__(256) void k_reorth_b(RowArgs a)
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
-        zd[u] = k < a.m ? (double)zv[k] : 0.0;
-        xd[u] = (HP && k < a.m) ? (double)xv[k] : 0.0;
+        const int64_t kc = k < a.m ? k : a.m - 1;
+        zd[u] = (double)ld_fix(zv, k, kc, k < a.m);
+        xd[u] = HP ? (double)ld_fix(xv, k, kc, k < a.m) : 0.0;
     }
-    for (int64_t ib = a.re_lo; ib < j; ib += 4) {
-        T qv[4][U], pv[HP ? 4 : 1][U];
+    // the earlier columns eight at a time (one group for the columns of a
+    // panel of eight), all of a group's loads in flight together
+    for (int64_t ib = a.re_lo; ib < j; ib += 8) {
+        T qv[8][U], pv[HP ? 8 : 1][U];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
+        for (int t = 0; t < 8; ++t)
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const int64_t k = row0 + u * 256 + tid;
+                const int64_t kc = k < a.m ? k : a.m - 1;
                 const bool in = ib + t < j && k < a.m;
-                qv[t][u] = in ? Q[k + (ib + t) * a.ldq] : (T)0;
-                if (HP) pv[HP ? t : 0][u] = in ? P[k + (ib + t) * a.ldp] : (T)0;
+                qv[t][u] = ld_fix(Q, k + (ib + t) * a.ldq, kc, in);
+                if (HP) pv[HP ? t : 0][u] = ld_fix(P, k + (ib + t) * a.ldp, kc, in);
             }
+        double sv[8];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
+        for (int t = 0; t < 8; ++t) sv[t] = ld_fix(a.S, ib + t, ib, ib + t < j);
+        pin();
+#pragma unroll
+        for (int t = 0; t < 8; ++t) {
             if (ib + t < j) {
-                const double s = a.S[ib + t];
+                const double s = sv[t];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     zd[u] -= s * (double)qv[t][u];
