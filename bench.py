@@ -51,7 +51,7 @@ TRAFFIC_FILES = {
 KERNEL_SOURCES = {
     "sweep": ("amgs_single.hip", "amgs_device.h", "amgs_internal.h"),
     "block_sweep": ("amgs_panel.hip", "amgs_device.h", "amgs_internal.h"),
-    "block_sweep8": ("amgs_panel.hip", "amgs_device.h", "amgs_internal.h"),
+    "block_sweep8": ("amgs_bsweep.hip", "amgs_device.h", "amgs_internal.h"),
 }
 
 

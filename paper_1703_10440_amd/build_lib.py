@@ -15,7 +15,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libamgs.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["amgs_api.hip", "amgs_single.hip", "amgs_gemm.hip", "amgs_batched.hip", "amgs_panel.hip"]
+SOURCES = ["amgs_api.hip", "amgs_single.hip", "amgs_gemm.hip", "amgs_batched.hip", "amgs_panel.hip",
+           "amgs_bsweep.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -325,181 +325,6 @@ __global__ __launch_bounds__(256) void k_pcol_blk(RowArgs a, int64_t k0, int64_t
     }
 }
 
-// ------------------------------------- outer block of the two-level schedule
-// After an outer panel I = [d0, d0 + nd) is finished, one pass over every
-// later column c (the columns of grid row y) applies the pending outer panel
-// I-1 = [k0, k1) as a block, z_c -= Q_{I-1} r_{I-1,c} (coefficients final in
-// R), and forms the partials of W_c = P_I^T z_c.  Both are small dense
-// contractions and run on the matrix cores, on tiles of 16 rows x 16 later
-// columns: the update is D = Z + Q_{I-1} (-R_{I-1,tile}) (two 16x16x4 steps
-// over the eight pending columns, Z entering as the accumulator), and the
-// dots W += P_I^T D take D's registers directly as the B operand (four
-// 16x16x4 steps over the tile's rows, rows 8..15 of W unused).  For that the
-// tile's rows are permuted so that register v of lane l holds matrix row
-// 4 (l/16) + v of the tile: tile row i of the update's A operand is matrix
-// row bs_act(i).  A wave owns BS_ST consecutive 16-row tiles (64 rows) and
-// walks the workgroup's later columns 16 at a time.  Each column of such a
-// 64 x 16 block is read and written with whole-wave contiguous accesses and
-// moved between that layout and the matrix-core layout through the wave's
-// own LDS tile.  Each later column is read and written once per outer
-// panel.  The per-wave W tiles are added in wave order through LDS.
-template <typename T>
-__device__ __forceinline__ int bs_act(int i)
-{
-    // binary64 results: register v of lane l is tile row 4 v + l/16
-    return sizeof(T) == 8 ? 4 * (i & 3) + (i >> 2) : i;
-}
-
-// The W partials of one 16-column tile starting at ct (nc columns): the
-// waves' entries added in wave order.
-template <typename T>
-__device__ __forceinline__ void bs_wpart(const T (*red)[16 * PANEL_B1], int64_t ct, int nc,
-                                         int nd, const BSweepArgs &a)
-{
-    constexpr int BB = PANEL_B1;
-    const int tid = threadIdx.x;
-    if (tid < nc * BB) {
-        const int cl = tid / BB, d = tid - cl * BB;
-        if (d < nd) {
-            T s = red[0][tid];
-#pragma unroll
-            for (int w = 1; w < 256 / WAVE; ++w) s += red[w][tid];
-            ((T *)a.part)[((ct + cl) * BB + d) * a.g + blockIdx.x] = s;
-        }
-    }
-}
-
-template <typename T, bool NTS>
-__global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
-{
-    typedef typename Mfma<T>::acc_t acc_t;
-    constexpr int ST = BS_ST;
-    constexpr int WR = ST * 16;         // rows per wave
-    constexpr int LD = WR + 4;          // padded LDS column (16-byte aligned)
-    constexpr int BB = PANEL_B1;
-    static_assert(WR == WAVE, "one row per lane in the contiguous accesses");
-    __shared__ T red[256 / WAVE][16 * BB];   // the waves' W of one 16-column tile
-    __shared__ __attribute__((aligned(16))) T tile[256 / WAVE][16][LD];
-    if (*a.info) return;
-    const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
-    const int g4 = lane >> 4, jl = lane & 15;
-    T *__restrict__ Q = (T *)a.Q;
-    const T *__restrict__ P = (const T *)a.P;
-    const int64_t m = a.m, ldq = a.ldq;
-    const int64_t wrow0 = ((int64_t)blockIdx.x * (256 / WAVE) + wave) * WR;
-    const int64_t myrow = wrow0 + lane;
-    const bool rin = myrow < m;
-    const int kw = (int)(a.k1 - a.k0), nd = (int)a.nd;
-    T(*tl)[LD] = tile[wave];
-    // Operands that stay for every column: p_{d0+l%16} at matrix row
-    // 4 (l/16) + v (A of the dots, step v) and q_{k0+4s+l/16} at tile row
-    // l%16 (A of the update), both brought in with contiguous column reads
-    // through the LDS tile.  Grid row 0 also forms P_I^T Q_I over the wave's
-    // rows (entry [i, k] = p_{d0+i}^T q_{d0+k}, B operand q_{d0+l%16} at
-    // matrix row 4 (l/16) + v), added over the waves after the columns; its
-    // strictly lower part is the L of the block solve.
-    const bool own_l = blockIdx.y == 0 && nd > 1;
-    T qa[ST][2], pa[ST][4];
-    acc_t lw = {0, 0, 0, 0};
-#pragma unroll
-    for (int c = 0; c < BB; ++c) {
-        tl[c][lane] = (rin && c < nd) ? P[myrow + (a.d0 + c) * a.ldp] : (T)0;
-        tl[BB + c][lane] = (own_l && rin && c < nd) ? Q[myrow + (a.d0 + c) * ldq] : (T)0;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int st = 0; st < ST; ++st)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = st * 16 + 4 * g4 + v;
-            pa[st][v] = jl < BB ? tl[jl][r] : (T)0;
-            if (own_l) lw = Mfma<T>::op(pa[st][v], jl < BB ? tl[BB + jl][r] : (T)0, lw);
-        }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < BB; ++c)
-        tl[c][lane] = (rin && c < kw) ? Q[myrow + (a.k0 + c) * ldq] : (T)0;
-    __syncthreads();
-#pragma unroll
-    for (int st = 0; st < ST; ++st)
-#pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2) qa[st][s2] = tl[4 * s2 + g4][st * 16 + bs_act<T>(jl)];
-    const int64_t cA = a.c0 + (int64_t)blockIdx.y * a.cpw;
-    const int64_t cB = (cA + a.cpw < a.c1) ? cA + a.cpw : a.c1;
-    for (int64_t ct = cA; ct < cB; ct += 16) {
-        const int nc = (int)(cB - ct < 16 ? cB - ct : 16);
-        // the wave's 64 x 16 block, one contiguous column access per column
-        T zl[16];
-#pragma unroll
-        for (int c = 0; c < 16; ++c)
-            zl[c] = (c < nc && rin) ? ld_stream<NTS>(Q + (ct + c) * ldq + myrow) : (T)0;
-        __syncthreads();   // the previous block's LDS reads and W entries are done
-        if (ct > cA) bs_wpart<T>(red, ct - 16, 16, nd, a);
-#pragma unroll
-        for (int c = 0; c < 16; ++c) tl[c][lane] = zl[c];
-        __syncthreads();
-        const int64_t col = ct + jl;
-        const bool cin = jl < nc;
-        // B operand of the update: -r_{k0+4s+l/16, col}
-        T rb[2];
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int kk = 4 * s + g4;
-            rb[s] = (cin && kk < kw) ? -(T)a.R[(a.k0 + kk) + col * a.ldr] : (T)0;
-        }
-        acc_t w = {0, 0, 0, 0};
-#pragma unroll
-        for (int st = 0; st < ST; ++st) {
-            acc_t z;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) z[v] = tl[jl][st * 16 + 4 * g4 + v];
-            if (kw > 0) {
-                z = Mfma<T>::op(qa[st][0], rb[0], z);
-                if (kw > 4) z = Mfma<T>::op(qa[st][1], rb[1], z);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) tl[jl][st * 16 + 4 * g4 + v] = (T)z[v];
-            }
-#pragma unroll
-            for (int v = 0; v < 4; ++v) w = Mfma<T>::op(pa[st][v], (T)z[v], w);
-        }
-        if (kw > 0) {
-            __syncthreads();
-#pragma unroll
-            for (int c = 0; c < 16; ++c)
-                if (c < nc && rin) st_stream<NTS>(Q + (ct + c) * ldq + myrow, tl[c][lane]);
-        }
-        // W[i, col] for i = Mfma<T>::row(lane, v) < PANEL_B1, added over the
-        // waves at the next tile (or below)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = Mfma<T>::row(lane, v);
-            if (i < BB) red[wave][jl * BB + i] = (T)w[v];
-        }
-    }
-    __syncthreads();
-    if (cA < cB) {
-        const int64_t last = cA + (cB - 1 - cA) / 16 * 16;
-        bs_wpart<T>(red, last, (int)(cB - last), nd, a);
-    }
-    if (own_l) {
-        __syncthreads();   // the W entries have been read
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = Mfma<T>::row(lane, v);
-            if (i < BB && jl < BB) red[wave][i * BB + jl] = (T)lw[v];
-        }
-        __syncthreads();
-        for (int idx = tid; idx < BB * BB; idx += 256) {
-            const int i = idx / BB, k = idx - i * BB;
-            if (!(k < i && i < nd)) continue;
-            T s = red[0][idx];
-#pragma unroll
-            for (int w = 1; w < 256 / WAVE; ++w) s += red[w][idx];
-            ((T *)a.lpart)[(int64_t)idx * a.g + blockIdx.x] = s;
-        }
-    }
-}
-
 // L = strict_lower(P_I^T Q_I) of an outer panel of b columns, each entry
 // re-reduced from the partials k_bsweep wrote (fixed order), one wave per
 // entry, into lred[i * PANEL_B1 + k] in binary64.
@@ -806,51 +631,6 @@ void launch_pfin(const Ctx &c, int64_t s, int64_t e, int64_t c1)
                        (const T *)c.wpart, (const T *)c.lpart, c.g_p, c.R, c.ldr, c.info);
 }
 
-int64_t bsweep_chunks(int64_t m, size_t w)
-{
-    (void)w;
-    const int64_t rows = (int64_t)(256 / WAVE) * BS_ST * 16;
-    const int64_t g = (m + rows - 1) / rows;
-    return g < 1 ? 1 : g;
-}
-
-template <typename T>
-void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0, int64_t d1, int64_t c0,
-                   int64_t c1)
-{
-    BSweepArgs a{};
-    a.m = c.m; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp; a.R = c.R; a.ldr = c.ldr;
-    a.info = c.info; a.k0 = k0; a.k1 = k1; a.d0 = d0; a.nd = d1 - d0;
-    a.c0 = c0; a.c1 = c1 > c0 ? c1 : c0; a.part = c.wpart; a.lpart = c.lpart8; a.g = c.g_b;
-    const int64_t ncols = a.c1 - a.c0;
-    // column groups: multiples of 16, at most BS_MAXC, enough workgroups
-    int64_t gy = 1, cpw = 16;
-    if (ncols > 0) {
-        gy = (SWEEP_TARGET_WG + c.g_b - 1) / c.g_b;
-        const int64_t max_gy = (ncols + 15) / 16;
-        if (gy > max_gy) gy = max_gy;
-        if (gy < 1) gy = 1;
-        cpw = (ncols + gy - 1) / gy;
-        cpw = (cpw + 15) / 16 * 16;
-        if (cpw > BS_MAXC) cpw = BS_MAXC;
-        gy = (ncols + cpw - 1) / cpw;
-    }
-    a.cpw = cpw;
-    const dim3 grid((unsigned)c.g_b, (unsigned)gy), block(256);
-    const bool nts = (double)ncols * (double)c.m * sizeof(T) > SWEEP_NT_BYTES;
-#define AMGS_BS(NT_)                                                                              \
-    do {                                                                                          \
-        if (c.ev_start)                                                                           \
-            hipExtLaunchKernelGGL((k_bsweep<T, NT_>), grid, block, 0, c.stream, c.ev_start,       \
-                                  c.ev_stop, 0, a);                                               \
-        else                                                                                      \
-            hipLaunchKernelGGL((k_bsweep<T, NT_>), grid, block, 0, c.stream, a);                  \
-    } while (0)
-    if (nts) AMGS_BS(true);
-    else AMGS_BS(false);
-#undef AMGS_BS
-}
-
 template <typename T>
 void launch_lfin(const Ctx &c, int64_t s, int64_t e)
 {
@@ -921,8 +701,6 @@ template void launch_psweep<double>(const Ctx &, int, int64_t, int64_t, int64_t,
 template void launch_psweep<float>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t, int64_t,
                                    int64_t, int64_t, int64_t);
 template void launch_pfin<double>(const Ctx &, int64_t, int64_t, int64_t);
-template void launch_bsweep<double>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t);
-template void launch_bsweep<float>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t);
 template void launch_lfin<double>(const Ctx &, int64_t, int64_t);
 template void launch_lfin<float>(const Ctx &, int64_t, int64_t);
 template void launch_pfin2<double>(const Ctx &, int64_t, int64_t, int64_t, int64_t);
