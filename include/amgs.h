@@ -85,6 +85,16 @@ typedef struct amgs_handle *amgs_handle_t;
  *   reorth  1: second (reorthogonalisation) pass per column (see above),
  *           in either schedule: it runs on column j after the column's
  *           projections and before its MV.
+ *           2: blocked second pass, two-level panel schedule only (panel =
+ *           8, else AMGS_ERR_UNSUPPORTED).  When an eight-panel [S, S + 8)
+ *           starts, its columns have all their first-pass projections onto
+ *           the columns before S; each of them then gets the second pass
+ *           against all i < S at once (s_ic = p_i^T z_c in binary64,
+ *           z_c -= sum_{i<S} s_ic q_i in binary64 rounded once, r_ic += s_ic,
+ *           HP also x_c -= sum_{i<S} s_ic p_i), and column j of the panel
+ *           gets the per-column pass above against [S, j) only.  The earlier
+ *           columns are streamed once per eight-panel instead of once per
+ *           column.  Other values are AMGS_ERR_ARG.
  *   panel   0: the column algorithm's own order of operations (default).
  *           4: panel schedule.  Columns are taken in panels of four; inside
  *           a panel every step is the column algorithm's.  The effect of a

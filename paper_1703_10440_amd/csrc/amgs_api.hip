@@ -169,7 +169,7 @@ amgs_status_t run_single(amgs_handle *h, Ctx &c, int variant, int reorth)
     const size_t w = sizeof(T);
     amgs_stats_t &st = h->stats;
     st = amgs_stats_t{};
-    launch_init<T>(c, c.Z != c.Q);
+    launch_init<T>(c, c.Z != c.Q ? c.n - c.first : 0);
     st.kernel_launches++;
     if (c.ell_k) {
         launch_csr_to_ell<T>(c);
@@ -310,7 +310,10 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
     const size_t w = sizeof(T);
     amgs_stats_t &st = h->stats;
     st = amgs_stats_t{};
-    launch_init<T>(c, c.Z != c.Q);
+    // two levels: the later columns' first read is in the block sweep after
+    // the second eight-panel, which takes them from Z (from_z below), so only
+    // the first two eight-panels are copied
+    launch_init<T>(c, c.Z == c.Q ? 0 : c.panel == PANEL_B1 && c.n > 2 * PANEL_B1 ? 2 * PANEL_B1 : c.n);
     st.kernel_launches++;
     if (c.ell_k) {
         launch_csr_to_ell<T>(c);
@@ -480,7 +483,10 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
                 }
                 if (outer_end) {
                     if (two) {
-                        profiled(true, [&] { launch_bsweep<T>(c, bp0, S, S, E, E, c.n); });   // [E, n) lacks the block [bp0, S) also with blk
+                        // [E, n) lacks the block [bp0, S) also with blk; after the
+                        // first two eight-panels the columns from E on have never
+                        // been written and are read from Z
+                        profiled(true, [&] { launch_bsweep<T>(c, bp0, S, S, E, E, c.n, S < 2 * B1); });
                         const double col = (double)c.m * (double)w;
                         const double bb = (double)(c.n - E) * (S > bp0 ? 2.0 : 1.0) * col
                                           + (double)((S - bp0) + (E - S)) * col;
@@ -518,7 +524,7 @@ amgs_status_t run_cgs(amgs_handle *h, Ctx &c, int variant, int reorth)
     const size_t w = sizeof(T);
     amgs_stats_t &st = h->stats;
     st = amgs_stats_t{};
-    launch_init<T>(c, c.Z != c.Q);
+    launch_init<T>(c, c.Z != c.Q ? c.n - c.first : 0);
     st.kernel_launches++;
     if (c.ell_k) {
         launch_csr_to_ell<T>(c);

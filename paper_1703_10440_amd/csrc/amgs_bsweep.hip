@@ -70,6 +70,7 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
     const int tid = threadIdx.x, wave = tid / WAVE, lane = tid & (WAVE - 1);
     const int g4 = lane >> 4, jl = lane & 15;
     T *__restrict__ Q = (T *)a.Q;
+    const T *__restrict__ Zs = (const T *)a.Zs;   // the later columns' current values
     const T *__restrict__ P = (const T *)a.P;
     const int64_t m = a.m, ldq = a.ldq;
     const int64_t wrow0 = ((int64_t)blockIdx.x * (256 / WAVE) + wave) * WR;
@@ -118,7 +119,7 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
         T zl[16];
 #pragma unroll
         for (int c = 0; c < 16; ++c)
-            zl[c] = (c < nc && rin) ? ld_stream<NTS>(Q + (ct + c) * ldq + myrow) : (T)0;
+            zl[c] = (c < nc && rin) ? ld_stream<NTS>(Zs + (ct + c) * a.ldzs + myrow) : (T)0;
         __syncthreads();   // the previous block's LDS reads and W entries are done
         if (ct > cA) bs_wpart<T>(red, ct - 16, 16, nd, a);
 #pragma unroll
@@ -197,10 +198,12 @@ int64_t bsweep_chunks(int64_t m, size_t w)
 
 template <typename T>
 void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0, int64_t d1, int64_t c0,
-                   int64_t c1)
+                   int64_t c1, bool from_z)
 {
     BSweepArgs a{};
     a.m = c.m; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp; a.R = c.R; a.ldr = c.ldr;
+    a.Zs = from_z ? c.Z : c.Q;
+    a.ldzs = from_z ? c.ldz : c.ldq;
     a.info = c.info; a.k0 = k0; a.k1 = k1; a.d0 = d0; a.nd = d1 - d0;
     a.c0 = c0; a.c1 = c1 > c0 ? c1 : c0; a.part = c.wpart; a.lpart = c.lpart8; a.g = c.g_b;
     const int64_t ncols = a.c1 - a.c0;
@@ -233,7 +236,9 @@ void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0, int64_t d1,
 }
 
 
-template void launch_bsweep<double>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t);
-template void launch_bsweep<float>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t);
+template void launch_bsweep<double>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t,
+                                    bool);
+template void launch_bsweep<float>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t,
+                                   bool);
 
 } // namespace amgs

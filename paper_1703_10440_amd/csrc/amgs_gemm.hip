@@ -158,17 +158,17 @@ void launch_dense_gemm(const Ctx &c)
     // the new columns [first, n) only
     constexpr int TN = sizeof(T) == 8 ? 64 : 128;
     const int64_t nn = c.n - c.first;
-    const T *Zn = (const T *)c.Q + c.first * c.ldq;
+    const T *Zn = (const T *)c.Z + c.first * c.ldz;   // read from Z (see launch_csr_spmm)
     T *Xn = (T *)c.X + c.first * c.m;
     const int64_t big = ((c.m + 127) / 128) * ((nn + TN - 1) / TN);
     if (big >= 256) {
         const dim3 grid((unsigned)((c.m + 127) / 128), (unsigned)((nn + TN - 1) / TN));
         hipLaunchKernelGGL((k_gemm_atb<T, 128, TN>), grid, dim3(256), 0, c.stream, c.m, nn,
-                           (const T *)c.A, c.lda, Zn, c.ldq, Xn, c.m);
+                           (const T *)c.A, c.lda, Zn, c.ldz, Xn, c.m);
     } else {
         const dim3 grid((unsigned)((c.m + 63) / 64), (unsigned)((nn + 63) / 64));
         hipLaunchKernelGGL((k_gemm_atb<T, 64, 64>), grid, dim3(256), 0, c.stream, c.m, nn,
-                           (const T *)c.A, c.lda, Zn, c.ldq, Xn, c.m);
+                           (const T *)c.A, c.lda, Zn, c.ldz, Xn, c.m);
     }
 }
 

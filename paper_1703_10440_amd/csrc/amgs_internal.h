@@ -161,6 +161,8 @@ struct BSweepArgs {
     int64_t m;
     void *Q;
     int64_t ldq;
+    const void *Zs;   // where the later columns are read (Q, or Z before their first write)
+    int64_t ldzs;
     const void *P;
     int64_t ldp;
     const double *R;
@@ -256,7 +258,7 @@ struct Ctx {
 
 Geo make_geo(int64_t m, int64_t nnz, int is_dense);
 
-template <typename T> void launch_init(const Ctx &c, int copy);
+template <typename T> void launch_init(const Ctx &c, int64_t ncopy);
 template <typename T> void launch_csr_to_ell(const Ctx &c);
 template <typename T> void launch_mv(const Ctx &c, int64_t j, int src_mode);
 template <typename T> void launch_col_hp(const Ctx &c, int64_t j, bool reorth_a);
@@ -273,7 +275,7 @@ template <typename T> void launch_psweep(const Ctx &c, int variant, int64_t j, i
                                          int64_t d0, int64_t l0, int64_t c0, int64_t c1, int64_t n_rr);
 template <typename T> void launch_pfin(const Ctx &c, int64_t s, int64_t e, int64_t c1);
 template <typename T> void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0,
-                                         int64_t d1, int64_t c0, int64_t c1);
+                                         int64_t d1, int64_t c0, int64_t c1, bool from_z = false);
 template <typename T> void launch_lfin(const Ctx &c, int64_t s, int64_t e);
 template <typename T> void launch_pfin2(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1);
 int64_t bsweep_chunks(int64_t m, size_t w);

@@ -32,17 +32,27 @@ __global__ __launch_bounds__(256) void k_init(int64_t m, int64_t n, int64_t firs
                                               const T *__restrict__ Z, int64_t ldz,
                                               T *__restrict__ Q, int64_t ldq,
                                               double *__restrict__ R, int64_t ldr, int32_t *info,
-                                              int copy)
+                                              int64_t ncopy)
 {
-    // columns [0, first) are final already and left untouched
+    // columns [0, first) are final already and left untouched; columns
+    // [first, first + ncopy) are copied (element e = row k of column j, the
+    // position advanced by the grid stride without a division per element)
     const int64_t nn = n - first;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     const int64_t t0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (copy)
-        for (int64_t e = t0; e < m * nn; e += stride) {
-            int64_t j = first + e / m, k = e % m;
+    if (ncopy > 0) {
+        const int64_t sj = stride / m, sk = stride - sj * m;
+        int64_t j = first + t0 / m, k = t0 % m;
+        for (int64_t e = t0; e < m * ncopy; e += stride) {
             Q[k + j * ldq] = Z[k + j * ldz];
+            j += sj;
+            k += sk;
+            if (k >= m) {
+                k -= m;
+                ++j;
+            }
         }
+    }
     for (int64_t e = t0; e < n * nn; e += stride) {
         int64_t j = first + e / n, i = e % n;
         R[i + j * ldr] = 0.0;
@@ -1080,15 +1090,15 @@ __global__ void k_set_i32(int32_t *p, int32_t v) { *p = v; }
 // Host launchers
 // ====================================================================
 template <typename T>
-void launch_init(const Ctx &c, int copy)
+void launch_init(const Ctx &c, int64_t ncopy)
 {
     const int64_t nn = c.n - c.first;
-    int64_t work = copy ? c.m * nn : c.n * nn;
+    int64_t work = ncopy > 0 ? c.m * ncopy : c.n * nn;
     int64_t blocks = (work + 255) / 256;
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_init<T>, dim3((unsigned)blocks), dim3(256), 0, c.stream, c.m, c.n,
-                       c.first, (const T *)c.Z, c.ldz, (T *)c.Q, c.ldq, c.R, c.ldr, c.info, copy);
+                       c.first, (const T *)c.Z, c.ldz, (T *)c.Q, c.ldq, c.R, c.ldr, c.info, ncopy);
 }
 
 // The padded copy of A used by the short-row column MV: one workgroup per
@@ -1330,16 +1340,17 @@ bool launch_hp_xblock(const Ctx &c, int64_t s, int64_t c_from)
 template <typename T>
 void launch_csr_spmm(const Ctx &c)
 {
-    // the new columns [first, n) only
+    // the new columns [first, n) only, read from Z (the working copy in Q
+    // may not hold them yet)
     const int64_t nn = c.n - c.first;
-    const T *Zn = (const T *)c.Q + c.first * c.ldq;
+    const T *Zn = (const T *)c.Z + c.first * c.ldz;
     T *Xn = (T *)c.X + c.first * c.m;
     const int L = c.geo.lanes;
     if (L <= 1) {
         // short rows: a thread per row (entries in registers for <= 8)
         const dim3 grid((unsigned)((c.m + 255) / 256)), block(256);
         hipLaunchKernelGGL(k_csr_spmm<T>, grid, block, 0, c.stream, c.m, nn, c.nnz, c.row_ptr,
-                           c.col_idx, (const T *)c.vals, Zn, c.ldq, Xn, c.m);
+                           c.col_idx, (const T *)c.vals, Zn, c.ldz, Xn, c.m);
         return;
     }
     const int64_t rows = 256 / L;
@@ -1347,7 +1358,7 @@ void launch_csr_spmm(const Ctx &c)
     const dim3 block(256);
 #define AMGS_SPMM_L(LL)                                                                            \
     hipLaunchKernelGGL((k_csr_spmm_lanes<T, LL>), grid, block, 0, c.stream, c.m, nn, c.row_ptr,   \
-                       c.col_idx, (const T *)c.vals, Zn, c.ldq, Xn, c.m)
+                       c.col_idx, (const T *)c.vals, Zn, c.ldz, Xn, c.m)
     switch (L) {
     case 2: AMGS_SPMM_L(2); break;
     case 4: AMGS_SPMM_L(4); break;
@@ -1371,8 +1382,8 @@ void launch_csr_check(int64_t m, int64_t nnz, const int32_t *row_ptr, const int3
                        col_idx, flag);
 }
 
-template void launch_init<double>(const Ctx &, int);
-template void launch_init<float>(const Ctx &, int);
+template void launch_init<double>(const Ctx &, int64_t);
+template void launch_init<float>(const Ctx &, int64_t);
 template void launch_csr_to_ell<double>(const Ctx &);
 template void launch_csr_to_ell<float>(const Ctx &);
 template void launch_publish<double>(const Ctx &, int64_t);

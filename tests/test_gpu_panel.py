@@ -311,3 +311,42 @@ def test_blocked_second_pass_needs_two_levels():
         assert st == want, (reorth, panel, st)
     assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(2, 8, 0, 0)) > 0
     assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(2, 4, 0, 0)) == 0
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant", VARIANTS)
+@pytest.mark.parametrize("pi", [1, 3], ids=[SMALL[i].name for i in (1, 3)])
+def test_two_level_working_copy(pi, variant, precision):
+    """Two-level schedule: only the first two eight-panels are copied from Z
+    before the call's work, and the block sweep after the second eight-panel
+    reads the later columns from Z.  Out of place, Z must come back untouched;
+    in place (Q aliases Z) the result must equal the out-of-place one bit for
+    bit.  Both problems have n > 16, so columns from 16 on take the Z path."""
+    p = SMALL[pi]
+    assert p.n > 16
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    Z0 = amgs.colmajor(torch.from_numpy(np.ascontiguousarray(p.Z)).to(DEV).to(dt))
+    Zc = Z0.clone()
+
+    def run(Zt, Q=None):
+        print(f"[gpu] working copy {p.name} {variant} {precision} inplace={Q is not None}",
+              flush=True)
+        kw = dict(variant=variant, precision=precision, return_p=True, panel=8, Q=Q)
+        if p.csr is not None:
+            return amgs.qr_csr(torch.from_numpy(p.csr.row_ptr).to(DEV),
+                               torch.from_numpy(p.csr.col_idx).to(DEV),
+                               torch.from_numpy(p.csr.vals).to(DEV).to(dt), Zt, **kw)
+        return amgs.qr_dense(torch.from_numpy(np.ascontiguousarray(p.dense)).to(DEV).to(dt),
+                             Zt, **kw)
+
+    a = run(Z0)
+    torch.cuda.synchronize()
+    assert torch.equal(Z0, Zc), "Z modified by an out-of-place call"
+    b = run(Zc, Q=Zc)
+    torch.cuda.synchronize()
+    assert int(a.info.item()) == 0 and int(b.info.item()) == 0
+    assert torch.equal(a.Q, Zc) and torch.equal(a.R, b.R) and torch.equal(a.P, b.P)
+    want = oracle_col(p, variant, precision=precision)
+    if precision == "fp64":
+        close_1e10(a.R.cpu().numpy(), a.Q.cpu().numpy(), a.P.cpu().numpy(), want,
+                   "column algorithm")
