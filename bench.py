@@ -124,6 +124,29 @@ def time_steps(fn, steps, warmup, torch):
     return (time.perf_counter() - t0) / steps, out
 
 
+def time_graph(fn, steps, torch):
+    """The same call captured once in a HIP graph (torch.cuda.graph, after a
+    warm-up on the capturing stream) and replayed `steps` times: the library
+    only enqueues kernels, so the replay does the same work without the
+    host-side launch of each kernel."""
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        out = fn()
+    g.replay()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        g.replay()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, out, g
+
+
 def accuracy(data, out, torch):
     """||Q^T A Q - I||_2 and ||Z - QR||_F / ||Z||_F in binary64 (torch used
     only to evaluate the metrics)."""
@@ -300,6 +323,12 @@ def bench_single(args, torch, amgs):
     t, out = time_steps(run, args.steps, args.warmup, torch)
     info = int(out.info.item())
     log(f"[bench] {head_v}/{head_p}: {t * 1e3:.3f} ms/step info={info}")
+    tg, gout, graph = time_graph(run, args.steps, torch)
+    graph_line = {"ms_per_step": round(tg * 1e3, 4), "value": round(prob.n / tg, 2),
+                  "info": int(gout.info.item()),
+                  "same_result": bool(torch.equal(gout.R, out.R))}
+    del graph, gout
+    log(f"[bench] {head_v}/{head_p} graph replay: {tg * 1e3:.3f} ms/step {graph_line}")
     roof = sweep_roofline(run, amgs, torch, args.workload)
     log(f"[bench] sweep roofline {roof}")
     gemmroof = None
@@ -378,7 +407,8 @@ def bench_single(args, torch, amgs):
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t * 1e3, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64" if head_p == "fp64" else "f32", "data": "synthetic", "config": cfg,
-            "roofline": roof, "mv_roofline": mvroof, "cpu_baseline": cpu, "variants": variants}
+            "roofline": roof, "mv_roofline": mvroof, "cpu_baseline": cpu, "variants": variants,
+            "graph_replay": graph_line}
     if gemmroof is not None:
         line["gemm_roofline"] = gemmroof
     if cpu1 is not None:

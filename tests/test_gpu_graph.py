@@ -42,15 +42,23 @@ def _call(prob, A, Z, variant, panel, Q, R, P, work, precision="fp64", reorth=Fa
     return amgs.qr_dense(A, Z, **kw)
 
 
-@pytest.mark.parametrize("panel", [0, 4])
+@pytest.mark.parametrize("panel", [0, 4, 8])
 @pytest.mark.parametrize("variant", ["naive", "ha", "hp"])
 @pytest.mark.parametrize("kind", ["csr", "dense"])
 def test_captured_call_replays_bitwise(kind, variant, panel):
     _replay_check(kind, variant, panel, "fp64", False)
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant", ["naive", "ha", "hp"])
+@pytest.mark.parametrize("kind", ["csr", "dense"])
+def test_captured_blocked_second_pass_replays_bitwise(kind, variant, precision):
+    """The blocked second pass (two-level schedule) enqueues kernels only."""
+    _replay_check(kind, variant, 8, precision, 2)
+
+
 @pytest.mark.parametrize("form", ["fp32", "fp64_reorth", "fp32_reorth"])
-@pytest.mark.parametrize("panel", [0, 4])
+@pytest.mark.parametrize("panel", [0, 4, 8])
 @pytest.mark.parametrize("variant", ["naive", "ha", "hp"])
 @pytest.mark.parametrize("kind", ["csr", "dense"])
 def test_captured_call_replays_bitwise_other_forms(kind, variant, panel, form):
