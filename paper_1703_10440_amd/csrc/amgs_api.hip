@@ -79,7 +79,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
     size_t part, s_part, rr_part, S, zt, xv, X, P, wpart, lpart, lpart8, lred, rb_part, rb_s,
-        ell_col, ell_val, tile_long;
+        ell_col, ell_val, tile_long, ell_d16, ell_wide;
     size_t base;    // bytes without the padded copy of A
     size_t total;   // bytes with it (the size the query reports)
 };
@@ -135,6 +135,8 @@ Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_g
     L.ell_col = ell ? take((size_t)ELL_K * m * 4) : off;
     L.ell_val = ell ? take((size_t)ELL_K * m * w) : off;
     L.tile_long = ell ? take((size_t)((m + MV_TILE - 1) / MV_TILE) * 4) : off;
+    L.ell_d16 = ell ? take((size_t)ELL_K * m * 2) : off;
+    L.ell_wide = ell ? take(4) : off;
     L.total = off;
     return L;
 }
@@ -653,6 +655,8 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
         c.ell_col = (int32_t *)(base + L.ell_col);
         c.ell_val = base + L.ell_val;
         c.tile_long = (int32_t *)(base + L.tile_long);
+        c.ell_d16 = (int16_t *)(base + L.ell_d16);
+        c.ell_wide = (int32_t *)(base + L.ell_wide);
     }
     DeviceGuard dg(h->device);
     return p == AMGS_FP64 ? run_single<double>(h, c, (int)v, reorth)

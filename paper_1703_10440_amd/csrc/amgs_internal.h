@@ -20,6 +20,7 @@ constexpr int SPMM_LC = 8;     // columns per pass of the multi-lane CSR block p
 constexpr int MAX_G_MV = 512;  // partials of an MV column kernel
 constexpr int MV_TILE = 512;   // rows (= threads) per padded-copy MV workgroup
 constexpr int ELL_K = 8;       // most entries per row held in the padded copy of A
+constexpr int16_t ELL_PAD = -32768;   // 16-bit column offset of a padding entry
 constexpr int PANEL_B = 4;     // columns per panel of the panel schedule (inner panels of the two-level one)
 constexpr int PANEL_B1 = 8;    // columns per outer panel of the two-level panel schedule
 #ifndef AMGS_BS_ST
@@ -67,6 +68,10 @@ struct CsrMvArgs {
     const void *ell_val;
     const int32_t *tile_long;  // per MV_TILE rows: some row has more than ell_k entries
     int32_t ell_k;
+    // the same columns as 16-bit offsets from the row (ELL_PAD past the end),
+    // used when *ell_wide is 0: every offset fits
+    const int16_t *ell_d16;
+    const int32_t *ell_wide;
 };
 
 struct DenseMvArgs {
@@ -249,6 +254,8 @@ struct Ctx {
     int32_t *ell_col;
     void *ell_val;
     int32_t *tile_long;
+    int16_t *ell_d16;
+    int32_t *ell_wide;
     int32_t ell_k;
     hipStream_t stream;
     // when set, the sweep is launched with these events bound to its own

@@ -32,7 +32,7 @@ __global__ __launch_bounds__(256) void k_init(int64_t m, int64_t n, int64_t firs
                                               const T *__restrict__ Z, int64_t ldz,
                                               T *__restrict__ Q, int64_t ldq,
                                               double *__restrict__ R, int64_t ldr, int32_t *info,
-                                              int64_t ncopy)
+                                              int64_t ncopy, int32_t *zero_word)
 {
     // columns [0, first) are final already and left untouched; columns
     // [first, first + ncopy) are copied (element e = row k of column j, the
@@ -57,7 +57,10 @@ __global__ __launch_bounds__(256) void k_init(int64_t m, int64_t n, int64_t firs
         int64_t j = first + e / n, i = e % n;
         R[i + j * ldr] = 0.0;
     }
-    if (t0 == 0) *info = 0;
+    if (t0 == 0) {
+        *info = 0;
+        if (zero_word) *zero_word = 0;   // the padded copy's flag, set later in the call
+    }
 }
 
 // R[jrow, c] for c in [c0, n) from the sweep partials, when no column kernel
@@ -177,6 +180,10 @@ __global__ __launch_bounds__(512) void k_csr_mv(CsrMvArgs a)
 // row's own z are requested together, then every gather.  Entries past K
 // (rows longer than K, flagged per tile of MV_TILE rows) are read from the
 // CSR arrays.  Same contract as k_csr_mv; the sum runs in stored order.
+// The columns are also stored as 16-bit offsets from the row (ELL_PAD past
+// the row's end); when every offset fits (no workgroup sets *ell_wide,
+// which the call's k_init has cleared) the MV reads those, 2 bytes per
+// entry instead of 4.
 template <typename T>
 __global__ __launch_bounds__(MV_TILE) void k_csr_to_ell(int64_t m, int32_t K,
                                                         const int32_t *__restrict__ row_ptr,
@@ -184,40 +191,52 @@ __global__ __launch_bounds__(MV_TILE) void k_csr_to_ell(int64_t m, int32_t K,
                                                         const T *__restrict__ vals,
                                                         int32_t *__restrict__ ell_col,
                                                         T *__restrict__ ell_val,
-                                                        int32_t *__restrict__ tile_long)
+                                                        int32_t *__restrict__ tile_long,
+                                                        int16_t *__restrict__ ell_d16,
+                                                        int32_t *__restrict__ ell_wide)
 {
     const int64_t row = (int64_t)blockIdx.x * MV_TILE + threadIdx.x;
-    int lng = 0;
+    int lng = 0, wide = 0;
     if (row < m) {
         const int32_t e0 = row_ptr[row], e1 = row_ptr[row + 1];
         for (int k = 0; k < K; ++k) {
             const int32_t e = e0 + k;
             int32_t cv = -1;
             T v = 0;
+            int16_t d = ELL_PAD;
             if (e < e1) {
                 cv = col_idx[e];
                 v = vals[e];
+                const int64_t off = (int64_t)cv - row;
+                if (off > ELL_PAD && off <= 32767) d = (int16_t)off;
+                else wide = 1;
             }
             ell_col[(int64_t)k * m + row] = cv;
             ell_val[(int64_t)k * m + row] = v;
+            ell_d16[(int64_t)k * m + row] = d;
         }
         lng = e1 - e0 > K;
     }
     lng = __syncthreads_or(lng);
-    if (threadIdx.x == 0) tile_long[blockIdx.x] = lng;
+    wide = __syncthreads_or(wide);
+    if (threadIdx.x == 0) {
+        tile_long[blockIdx.x] = lng;
+        if (wide) atomicOr(ell_wide, 1);
+    }
 }
 
 // RPT rows per thread: the thread's rows in RPT consecutive grid-stride
-// tiles are requested together (more loads in flight per wave).
-template <typename T, int SRC, bool RR, int RPT>
-__global__ __launch_bounds__(MV_TILE) void k_csr_mv_ell(CsrMvArgs a)
+// tiles are requested together (more loads in flight per wave).  D16: the
+// columns come from the 16-bit offsets.
+template <typename T, int SRC, bool RR, int RPT, bool D16>
+__device__ __forceinline__ void csr_mv_ell_body(const CsrMvArgs &a)
 {
     __shared__ double lds[MV_TILE / WAVE];
     __shared__ T s_r;
     __shared__ double s_rr;
-    if (*a.info) return;
     const T *__restrict__ vals = (const T *)a.vals;
     const int32_t *__restrict__ ecol = a.ell_col;
+    const int16_t *__restrict__ ed16 = a.ell_d16;
     const T *__restrict__ eval = (const T *)a.ell_val;
     const T *__restrict__ src = (const T *)a.src;
     const T *__restrict__ qprev = (const T *)a.qprev;
@@ -256,7 +275,8 @@ __global__ __launch_bounds__(MV_TILE) void k_csr_mv_ell(CsrMvArgs a)
 #pragma unroll
             for (int k = 0; k < ELL_K; ++k) {
                 const int64_t kc = k < K ? k : K - 1;
-                col[u][k] = ecol[kc * m + rowc[u]] | -(int32_t)(k >= K);
+                // (a 16-bit offset is decoded after pin() below)
+                col[u][k] = D16 ? (int32_t)ed16[kc * m + rowc[u]] : ecol[kc * m + rowc[u]];
                 av[u][k] = eval[kc * m + rowc[u]];
             }
             own_s[u] = 0;
@@ -267,6 +287,14 @@ __global__ __launch_bounds__(MV_TILE) void k_csr_mv_ell(CsrMvArgs a)
             }
         }
         pin();
+#pragma unroll
+        for (int u = 0; u < RPT; ++u)
+#pragma unroll
+            for (int k = 0; k < ELL_K; ++k) {
+                int32_t cv = col[u][k];
+                if (D16) cv = cv == ELL_PAD ? -1 : (int32_t)rowc[u] + cv;
+                col[u][k] = cv | -(int32_t)(k >= K);
+            }
         // the coefficient r_{j-1,j} (or r_jj for the naive second MV) is
         // re-reduced by wave 0 while those loads are in flight
         if (first && (with_upd || SRC == SRC_DIV)) {
@@ -363,6 +391,16 @@ __global__ __launch_bounds__(MV_TILE) void k_csr_mv_ell(CsrMvArgs a)
     // R[j-1, c] for c >= j, read by the next sweep, is published last so
     // that it does not delay this kernel's own loads
     if (with_upd) publish_row<T>(a.sp, a.j - 1, a.j, a.n, a.R, a.ldr);
+}
+
+// The padded-copy MV with the column format of this call's copy: the
+// 16-bit offsets unless some offset did not fit (a wave-uniform test, once).
+template <typename T, int SRC, bool RR, int RPT>
+__global__ __launch_bounds__(MV_TILE) void k_csr_mv_ell(CsrMvArgs a)
+{
+    if (*a.info) return;
+    if (*a.ell_wide) csr_mv_ell_body<T, SRC, RR, RPT, false>(a);
+    else csr_mv_ell_body<T, SRC, RR, RPT, true>(a);
 }
 
 // ----------------------------------------------------- dense MV (column kernel)
@@ -1098,7 +1136,8 @@ void launch_init(const Ctx &c, int64_t ncopy)
     if (blocks > 4096) blocks = 4096;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_init<T>, dim3((unsigned)blocks), dim3(256), 0, c.stream, c.m, c.n,
-                       c.first, (const T *)c.Z, c.ldz, (T *)c.Q, c.ldq, c.R, c.ldr, c.info, ncopy);
+                       c.first, (const T *)c.Z, c.ldz, (T *)c.Q, c.ldq, c.R, c.ldr, c.info, ncopy,
+                       c.ell_k ? c.ell_wide : nullptr);
 }
 
 // The padded copy of A used by the short-row column MV: one workgroup per
@@ -1109,7 +1148,7 @@ void launch_csr_to_ell(const Ctx &c)
     const int64_t tiles = (c.m + MV_TILE - 1) / MV_TILE;
     hipLaunchKernelGGL(k_csr_to_ell<T>, dim3((unsigned)tiles), dim3(MV_TILE), 0, c.stream, c.m,
                        c.ell_k, c.row_ptr, c.col_idx, (const T *)c.vals, c.ell_col,
-                       (T *)c.ell_val, c.tile_long);
+                       (T *)c.ell_val, c.tile_long, c.ell_d16, c.ell_wide);
 }
 
 template <typename T>
@@ -1180,6 +1219,7 @@ void launch_mv(const Ctx &c, int64_t j, int src_mode)
         CsrMvArgs a{};
         a.m = c.m; a.n = c.n_pub; a.j = j; a.row_ptr = c.row_ptr; a.col_idx = c.col_idx; a.vals = c.vals;
         a.ell_col = c.ell_col; a.ell_val = c.ell_val; a.tile_long = c.tile_long; a.ell_k = c.ell_k;
+        a.ell_d16 = c.ell_d16; a.ell_wide = c.ell_wide;
         a.info = c.info; a.R = c.R; a.ldr = c.ldr; a.sp = c.sp;
         a.rr_part = c.rr_part; a.n_rr = c.n_rr_mv; a.rr_out = c.rr_part;
         if (src_mode == SRC_UPD) {

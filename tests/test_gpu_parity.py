@@ -351,7 +351,10 @@ def test_workspace_without_padded_copy(variant, panel):
         opts = amgs.Opts(0, panel, 0, 0)
         full = amgs.amgs_workspace_bytes(h, m, n, 0, amgs.VARIANTS[variant],
                                          amgs.PRECISIONS["fp64"], 1, opts)   # P passed
-        copy = _align256(8 * m * 4) + _align256(8 * m * 8) + _align256((m + 511) // 512 * 4)
+        # the padded copy: 32-bit columns, values, per-tile flags, 16-bit
+        # column offsets and the offsets' flag, last in the workspace
+        copy = (_align256(8 * m * 4) + _align256(8 * m * 8) + _align256((m + 511) // 512 * 4)
+                + _align256(8 * m * 2) + _align256(4))
         base = full - copy
         print(f"[gpu] workspace {p.name} {variant} panel={panel}: full {full} base {base}",
               flush=True)
@@ -480,3 +483,39 @@ def test_binding_rejects_bad_buffers_before_launch():
         amgs.qr_dense(torch.eye(m, dtype=torch.float64, device=DEV), Z, variant="hp",
                       Q=amgs.empty_colmajor(m + 1, n, torch.float64, DEV))
     torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("panel", [0, 8])
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+@pytest.mark.parametrize("variant", ["naive", "ha"])
+def test_padded_copy_wide_and_narrow_offsets(variant, precision, panel):
+    """The short-row MV reads the padded copy's 16-bit column offsets when
+    every |col - row| fits, else the 32-bit columns.  A random sparse matrix
+    with m = 70001 has offsets far beyond 32767 (32-bit path); the graded
+    Laplacian 20^3 has offsets of at most 400 (16-bit path).  Both against
+    the column algorithm of the oracle: R, Q and P within 1e-10 in binary64,
+    orthogonality within 10x the oracle's binary32 emulation in binary32."""
+    probs = (inputs.random_csr_problem(70001, 8, 5, seed=21),
+             inputs.laplacian_graded_problem(N=20, n=12, decades=2.0, seed=22))
+    for p in probs:
+        offs = np.abs(p.csr.col_idx.astype(np.int64)
+                      - np.repeat(np.arange(p.m), np.diff(p.csr.row_ptr)))
+        print(f"  {p.name}: largest |col - row| {offs.max()}")
+        Q, R, P, info, st = gpu_run(p, variant, precision=precision, panel=panel)
+        want = ref.qr_problem(p if precision == "fp64" else _as32(p), variant=variant,
+                              precision=precision)
+        assert info == 0 and want.info == 0
+        if precision == "fp64":
+            for got, ref_, what in ((R, want.R, "R"), (Q, want.Q, "Q"), (P, want.P, "P")):
+                assert _rel(got, ref_) <= 1e-10, (p.name, what, _rel(got, ref_))
+        else:
+            o_g, o_o = orth(p, Q), orth(p, want.Q)
+            print(f"  orth {o_g:.2e} (oracle {o_o:.2e})")
+            assert o_g <= max(10 * o_o, 1e-6)
+
+
+def _as32(p):
+    """The problem with its data rounded to binary32 (the binary32 form's input)."""
+    return inputs.Problem(p.name + "_f32", np.asfortranarray(p.Z.astype(np.float32).astype(np.float64)),
+                          csr=inputs.CSR(p.m, p.csr.row_ptr, p.csr.col_idx,
+                                         p.csr.vals.astype(np.float32).astype(np.float64)))
