@@ -58,6 +58,15 @@
  * 8-panel, then the column algorithm's projections inside its 4-panel.
  * With n <= 8 it is orientation 2.
  *
+ * Orientation 5 is the same regrouping on three levels: panels of 16
+ * columns, each taken apart as two panels of 8 exactly as in orientation 4
+ * but with the 8-panel blocks acting only on the columns of the same
+ * 16-panel, and each finished 16-panel acting on every later column as one
+ * block of 16.  A column receives the blocks of every earlier 16-panel, the
+ * block of the earlier 8-panel of its own 16-panel, the block of the earlier
+ * 4-panel of its own 8-panel, then the projections inside its 4-panel.  With
+ * n <= 16 it is orientation 4.
+ *
  * Orientation 3 is classical Gram-Schmidt with the same three variants
  * (Section 2: the n-MV idea applied to CGS; Section 3, analysis of CGS):
  * column j takes all its coefficients from the unmodified column,
@@ -101,6 +110,7 @@
 #define REF_PANEL 2
 #define REF_CGS 3
 #define REF_PANEL2 4
+#define REF_PANEL3 5
 #define REF_FP64 0
 #define REF_FP32 1
 #define DOT_BLOCK 1024
@@ -552,7 +562,7 @@ static int run(const ref_op *A, int64_t n, int64_t first, const double *Z, int64
 {
     int64_t m = A->m;
     if (m < 0 || n < 0 || n > m || ldz < m || ldq < m || ldr < n) return -1;
-    if (variant < 0 || variant > 2 || orientation < 0 || orientation > 4) return -1;
+    if (variant < 0 || variant > 2 || orientation < 0 || orientation > 5) return -1;
     if (prec < 0 || prec > 1) return -1;
     if (reorth < 0 || reorth > 2 || (reorth == 2 && orientation != REF_PANEL2)) return -1;
     /* successive orthogonalisation: columns before first are final in Q, P
@@ -571,7 +581,7 @@ static int run(const ref_op *A, int64_t n, int64_t first, const double *Z, int64
     double *X = NULL;
     if (variant == REF_HP) X = (double *)malloc((size_t)m * n * sizeof(double));
     int64_t calls = 0, cols = 0;
-    static const int one_level[1] = {4}, two_level[2] = {8, 4};
+    static const int one_level[1] = {4}, two_level[2] = {8, 4}, three_level[3] = {16, 8, 4};
     int info = orientation == REF_COL
         ? qr_col(A, m, n, first, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols)
         : orientation == REF_ROW
@@ -581,6 +591,9 @@ static int run(const ref_op *A, int64_t n, int64_t first, const double *Z, int64
                    &calls, &cols)
         : orientation == REF_PANEL2
         ? qr_panel(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, 2, two_level,
+                   &calls, &cols)
+        : orientation == REF_PANEL3
+        ? qr_panel(A, m, n, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, 3, three_level,
                    &calls, &cols)
         : qr_cgs(A, m, n, first, Q, ldq, R, ldr, Pw, ldpw, X, variant, reorth, prec, &calls, &cols);
     if (stats) { stats[0] = calls; stats[1] = cols; }

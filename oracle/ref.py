@@ -17,7 +17,7 @@ _SRC = os.path.join(_HERE, "amgs_ref.c")
 _LIB_PATH = os.path.join(_HERE, "libamgs_ref.so")
 
 VARIANTS = {"naive": 0, "ha": 1, "hp": 2}
-ORIENT = {"col": 0, "row": 1, "panel": 2, "cgs": 3, "panel8": 4}
+ORIENT = {"col": 0, "row": 1, "panel": 2, "cgs": 3, "panel8": 4, "panel16": 5}
 PRECISION = {"fp64": 0, "fp32": 1}
 
 CFLAGS = ["-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",

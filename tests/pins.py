@@ -46,9 +46,9 @@ def pin_hand_example(lib, golden) -> list:
     A, Z = golden["A"], golden["Z"]
     csr = inputs.csr_from_dense(A)
     for v in VARIANTS:
-        for o in ORIENTS + ("panel", "panel8", "cgs"):
+        for o in ORIENTS + ("panel", "panel8", "panel16", "cgs"):
             for prec in ("fp64", "fp32"):
-                for re_ in ((False, True) if o not in ("panel", "panel8") else (False,)):
+                for re_ in ((False, True) if o not in ("panel", "panel8", "panel16") else (False,)):
                     for kind in ("dense", "csr"):
                         kw = dict(dense=A) if kind == "dense" else dict(csr=csr)
                         r = ref.qr(Z, variant=v, orientation=o, reorth=re_, precision=prec,
@@ -557,6 +557,77 @@ def pin_panel8(lib) -> list:
     return fails
 
 
+def pin_panel16(lib) -> list:
+    """Three-level panel schedule (orientation "panel16": panels of 16
+    columns, each taken apart as two panels of 8, each of those as two of
+    4).  As for "panel8": R = chol(Z^T A Z), Q = Z R^{-1}, P = AQ on
+    well-conditioned problems spanning several 16-panels with ragged last
+    16-, 8- and 4-panels (n = 37 = 16 + 16 + 4 + 1), with and without the
+    second pass; Householder QR for A = I, the three variants equal bit for
+    bit; MV counts 2n / n / one block; with n <= 16 it is the two-level
+    orientation bit for bit (a single 16-panel is two 8-panels); with n > 16
+    it is not (the 16-panel blocks are in use) yet agrees to rounding level;
+    on the experiment-II problem of pin_panel8 the loss stays within a small
+    factor of the column algorithm's and below 10 delta_1."""
+    fails = []
+    for seed in (41, 42):
+        for p in (inputs.random_dense_problem(80, 37, seed), inputs.random_csr_problem(400, 37, 9, seed)):
+            Ad = p.dense if p.dense is not None else p.csr.to_dense()
+            Rc = _chol_R(p.Z, Ad)
+            for v in VARIANTS:
+                for re_ in (False, True):
+                    r = ref.qr(p.Z, dense=p.dense, csr=p.csr, variant=v, orientation="panel16",
+                               reorth=re_, lib=lib)
+                    e, eq, ep = (_rel(np.triu(r.R), Rc), _rel(r.Q, np.linalg.solve(Rc.T, p.Z.T).T),
+                                 _rel(r.P, Ad @ r.Q))
+                    if r.info != 0 or not (e <= 1e-13 and eq <= 1e-12 and ep <= 1e-12):
+                        fails.append(f"panel16 chol {p.name} {v} reorth={re_}: R {e} Q {eq} P {ep} "
+                                     f"info {r.info}")
+                    want_calls = {"naive": 2 * p.n, "ha": p.n, "hp": 1}[v]
+                    if r.mv_calls != want_calls:
+                        fails.append(f"panel16 MV count {p.name} {v}: {r.mv_calls} != {want_calls}")
+                r1 = ref.qr(p.Z, dense=p.dense, csr=p.csr, variant=v, orientation="panel8", lib=lib)
+                r2 = ref.qr(p.Z, dense=p.dense, csr=p.csr, variant=v, orientation="panel16", lib=lib)
+                if np.array_equal(r1.R, r2.R):
+                    fails.append(f"panel16 {p.name} {v}: identical to the two-level form at n = 37")
+                if _rel(np.triu(r2.R), np.triu(r1.R)) > 1e-13:
+                    fails.append(f"panel16 {p.name} {v}: R differs from the two-level form by "
+                                 f"{_rel(np.triu(r2.R), np.triu(r1.R))}")
+    g = inputs.rng(24)
+    m, n = 150, 35
+    Z = np.asfortranarray(g.standard_normal((m, n)))
+    eye = inputs.CSR(m, np.arange(m + 1, dtype=np.int32), np.arange(m, dtype=np.int32), np.ones(m))
+    Qh, Rh = np.linalg.qr(Z)
+    D = np.sign(np.diag(Rh))
+    Qh, Rh = Qh * D[None, :], Rh * D[:, None]
+    outs = {v: ref.qr(Z, csr=eye, variant=v, orientation="panel16", lib=lib) for v in VARIANTS}
+    for v, r in outs.items():
+        if _rel(np.triu(r.R), Rh) > 1e-14 or _rel(r.Q, Qh) > 1e-13:
+            fails.append(f"panel16 identity {v}: R {_rel(np.triu(r.R), Rh)} Q {_rel(r.Q, Qh)}")
+        if not (np.array_equal(r.R, outs["naive"].R) and np.array_equal(r.Q, outs["naive"].Q)):
+            fails.append(f"panel16 identity: {v} differs bitwise from naive")
+    for nn in (5, 12, 16):
+        p = inputs.random_dense_problem(40, nn, 6)
+        for v in VARIANTS:
+            for re_ in (False, True):
+                a = ref.qr(p.Z, dense=p.dense, variant=v, orientation="panel8", reorth=re_, lib=lib)
+                b = ref.qr(p.Z, dense=p.dense, variant=v, orientation="panel16", reorth=re_, lib=lib)
+                if not (np.array_equal(a.R, b.R) and np.array_equal(a.Q, b.Q)
+                        and np.array_equal(a.P, b.P)):
+                    fails.append(f"panel16 n={nn} {v} reorth={re_}: differs from the two-level form")
+    u = 2.0 ** -53
+    p = inputs.exp2_problem(100, 40, 1e8, 1e8, 2, 7)
+    w, V = np.linalg.eigh(p.dense)
+    d1 = u * float(w[-1] / w[0]) * _kappa((V * np.sqrt(w)[None, :]) @ V.T @ p.Z)
+    for v in ("naive", "ha"):
+        lc = ref.orth_loss(ref.qr_problem(p, variant=v, lib=lib).Q, dense=p.dense)
+        r = ref.qr_problem(p, variant=v, orientation="panel16", lib=lib)
+        lp = ref.orth_loss(r.Q, dense=p.dense)
+        if r.info != 0 or not (lp <= 30 * lc and lp <= 10 * d1):
+            fails.append(f"panel16 exp2 {v}: loss {lp} (column {lc}, 10 delta1 {10 * d1})")
+    return fails
+
+
 def pin_blocked_second_pass(lib) -> list:
     """Blocked second pass (reorth = 2, orientation "panel8"): each outer
     panel's columns get the classical pass against all earlier outer panels
@@ -714,4 +785,4 @@ ALL_PINS = [pin_hand_example, pin_cholesky, pin_identity_householder, pin_choles
             pin_col_row_bitwise, pin_mv_counts, pin_scaling, pin_first_column,
             pin_residual_and_reorth, pin_exp2_accuracy, pin_fp32_accumulation,
             pin_fp32_mv_axpy_rounding, pin_fp32_vs_fp64, pin_breakdown,
-            pin_panel, pin_panel8, pin_blocked_second_pass, pin_cgs, pin_successive]
+            pin_panel, pin_panel8, pin_panel16, pin_blocked_second_pass, pin_cgs, pin_successive]
