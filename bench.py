@@ -47,11 +47,13 @@ TRAFFIC_FILES = {
     ("sweep", "lap64_n64"): os.path.join(ROOT, "profiles", "sweep_lap64_traffic.json"),
     ("block_sweep", "lap128_n128"): os.path.join(ROOT, "profiles", "psweep_lap128_traffic.json"),
     ("block_sweep8", "lap128_n128"): os.path.join(ROOT, "profiles", "bsweep_lap128_traffic.json"),
+    ("block_sweep16", "lap128_n128"): os.path.join(ROOT, "profiles", "bsweep16_lap128_traffic.json"),
 }
 KERNEL_SOURCES = {
     "sweep": ("amgs_single.hip", "amgs_device.h", "amgs_internal.h"),
     "block_sweep": ("amgs_panel.hip", "amgs_device.h", "amgs_internal.h"),
     "block_sweep8": ("amgs_bsweep.hip", "amgs_device.h", "amgs_internal.h"),
+    "block_sweep16": ("amgs_bsweep.hip", "amgs_device.h", "amgs_internal.h"),
 }
 
 
@@ -189,8 +191,10 @@ def sweep_roofline(runner, amgs, torch, workload):
     torch.cuda.synchronize()
     amgs.amgs_profile_enable(h, 0)
     st = out.stats
-    if runner.panel == 8:
-        kind, kernel = "block_sweep8", "k_bsweep (block sweep after each panel of eight)"
+    if runner.panel in (8, 16):
+        kind = f"block_sweep{runner.panel}"
+        kernel = ("k_bsweep (block sweep after each panel of "
+                  + ("eight)" if runner.panel == 8 else "sixteen)"))
         ms, launches = amgs.amgs_profile_read(h, 3)
         nbytes, nl = st.block_sweep_bytes, st.block_sweep_launches
     elif runner.panel:
@@ -348,6 +352,9 @@ def bench_single(args, torch, amgs):
         combos += [(v, p, 2, 8, False) for p in ("fp32", "fp64") for v in ("ha", "hp")]
         combos += [(v, p, False, pan, False) for pan in (4, 8) for p in ("fp64", "fp32")
                    for v in ("naive", "ha", "hp")]
+        # the three-level schedule (naive and HA only)
+        combos += [(v, p, False, 16, False) for p in ("fp64", "fp32") for v in ("naive", "ha")]
+        combos += [("ha", p, True, 16, False) for p in ("fp32", "fp64")]
         combos += [(v, "fp64", ro, 0, True) for ro in (False, True) for v in ("naive", "ha", "hp")]
         for v, p, ro, pan, cgs in combos:
             r = Runner(data, v, p, torch, amgs, reorth=ro, panel=pan, cgs=cgs)
@@ -379,6 +386,14 @@ def bench_single(args, torch, amgs):
                     if k in variants:
                         variants[k]["speedup_vs_fp64"] = round(
                             variants[f"{v}_fp64{sfx}"]["ms"] / variants[k]["ms"], 3)
+        sfx = "_panel16"
+        for p in ("fp64", "fp32"):
+            variants[f"ha_{p}{sfx}"]["speedup_vs_naive"] = round(
+                variants[f"naive_{p}{sfx}"]["ms"] / variants[f"ha_{p}{sfx}"]["ms"], 3)
+        for k, k64 in (("naive_fp32", "naive_fp64"), ("ha_fp32", "ha_fp64"),
+                       ("ha_fp32_reorth", "ha_fp64")):
+            variants[k + sfx]["speedup_vs_fp64"] = round(
+                variants[k64 + sfx]["ms"] / variants[k + sfx]["ms"], 3)
         # fastest modified Gram-Schmidt configuration per precision (either
         # schedule, no second pass)
         best = {}
@@ -689,9 +704,10 @@ def main():
     ap.add_argument("--reorth", type=int, nargs="?", const=1, default=0, choices=[0, 1, 2],
                     help="second pass in the headline run: 1 per column, 2 blocked "
                          "(two-level schedule only)")
-    ap.add_argument("--panel", type=int, default=8, choices=[0, 4, 8],
+    ap.add_argument("--panel", type=int, default=8, choices=[0, 4, 8, 16],
                     help="schedule of the headline run: 0 column order, 4 panels of four, "
-                         "8 panels of eight taken apart as panels of four")
+                         "8 panels of eight taken apart as panels of four, 16 panels of "
+                         "sixteen taken apart as panels of eight (naive and HA)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported here "

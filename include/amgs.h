@@ -86,7 +86,7 @@ typedef struct amgs_handle *amgs_handle_t;
  *           in either schedule: it runs on column j after the column's
  *           projections and before its MV.
  *           2: blocked second pass, two-level panel schedule only (panel =
- *           8, else AMGS_ERR_UNSUPPORTED).  When an eight-panel [S, S + 8)
+ *           8; any other panel value, 16 included, AMGS_ERR_UNSUPPORTED).  When an eight-panel [S, S + 8)
  *           starts, its columns have all their first-pass projections onto
  *           the columns before S; each of them then gets the second pass
  *           against all i < S at once (s_ic = p_i^T z_c in binary64,
@@ -119,6 +119,18 @@ typedef struct amgs_handle *amgs_handle_t;
  *           four-panel of its own eight-panel, then the column steps of its
  *           four-panel.  Each later column is read and written once per
  *           eight columns; the block step runs on the matrix cores.
+ *           16: three-level panel schedule, naive and HA only (HP:
+ *           AMGS_ERR_UNSUPPORTED).  Columns are taken in panels of sixteen,
+ *           each taken apart as two eight-panels exactly as above except
+ *           that an eight-column block acts only on the columns of its own
+ *           sixteen-panel; a finished sixteen-panel acts on every later
+ *           column as one block of sixteen (W, L, (I + L) r = W as above,
+ *           with sixteen columns).  A column receives the blocks of the
+ *           earlier sixteen-panels, then that of the earlier eight-panel
+ *           of its own sixteen-panel, then the four-panel steps.  Each
+ *           later column is read and written once per sixteen columns.
+ *           reorth = 1 is supported, reorth = 2 is not
+ *           (AMGS_ERR_UNSUPPORTED).
  *           Not combined with cgs or first (AMGS_ERR_UNSUPPORTED); other
  *           values are AMGS_ERR_ARG.
  *   cgs     0: modified Gram-Schmidt (Algs. 3/5/6, default).

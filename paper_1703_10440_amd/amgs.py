@@ -281,7 +281,9 @@ def qr_csr(row_ptr, col_idx, vals, Z, variant="ha", precision="fp64", reorth=Fal
            panel=0, cgs=False, first=0, R=None) -> QRResult:
     """A-orthonormalise the columns of Z (device tensors; A in CSR).
     panel: 0 for the column schedule, 4 for the panel schedule, 8 for the
-    two-level panel schedule (panels of eight, each as two of four); reorth:
+    two-level panel schedule (panels of eight, each as two of four), 16 for
+    the three-level one (panels of sixteen, each as two of eight; naive and
+    HA only); reorth:
     False, True (second pass per column) or 2 (blocked second pass, panel=8
     only); cgs: classical
     instead of modified Gram-Schmidt; first > 0: columns before it are final
@@ -316,7 +318,9 @@ def qr_dense(A, Z, variant="ha", precision="fp64", reorth=False, return_p=False,
              R=None) -> QRResult:
     """A-orthonormalise the columns of Z (device tensors; A dense symmetric).
     panel: 0 for the column schedule, 4 for the panel schedule, 8 for the
-    two-level panel schedule (panels of eight, each as two of four); reorth:
+    two-level panel schedule (panels of eight, each as two of four), 16 for
+    the three-level one (panels of sixteen, each as two of eight; naive and
+    HA only); reorth:
     False, True (second pass per column) or 2 (blocked second pass, panel=8
     only); cgs: classical
     instead of modified Gram-Schmidt; first > 0: columns before it are final

@@ -114,15 +114,17 @@ Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_g
     L.xv = variant != VAR_HP ? take((size_t)m * w) : off;
     L.X = variant == VAR_HP ? take((size_t)m * n * w) : off;
     L.P = P_given ? off : take((size_t)m * n * w);
-    const bool two = panel == PANEL_B1;
-    const size_t pb = two ? PANEL_B1 : PANEL_B;
+    // two levels (panel 8) or three (panel 16): block sweeps of width 8, and
+    // of 16 for three levels
+    const bool two = panel == PANEL_B1 || panel == PANEL_B2;
+    const size_t pb = panel == PANEL_B2 ? PANEL_B2 : two ? PANEL_B1 : PANEL_B;
     // the outer block sweep may use more row chunks than the panel sweeps
     const int64_t g_b = two ? bsweep_chunks(m, w) : 0;
     const int64_t g_w = g_b > g_p ? g_b : g_p;
     L.wpart = panel ? take((size_t)n * pb * g_w * 8) : off;
     L.lpart = panel ? take((size_t)PANEL_B * PANEL_B * g_p * 8) : off;
-    L.lpart8 = two ? take((size_t)PANEL_B1 * PANEL_B1 * g_b * 8) : off;
-    L.lred = two ? take((size_t)PANEL_B1 * PANEL_B1 * 8) : off;
+    L.lpart8 = two ? take((size_t)pb * pb * g_b * 8) : off;
+    L.lred = two ? take((size_t)pb * pb * 8) : off;
     // blocked second pass: coefficient partials and coefficients of an outer panel
     const bool rb = two && reorth == 2;
     L.rb_part = rb ? take((size_t)n * PANEL_B1 * g_b * 8) : off;
@@ -315,7 +317,10 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
     // two levels: the later columns' first read is in the block sweep after
     // the second eight-panel, which takes them from Z (from_z below), so only
     // the first two eight-panels are copied
-    launch_init<T>(c, c.Z == c.Q ? 0 : c.panel == PANEL_B1 && c.n > 2 * PANEL_B1 ? 2 * PANEL_B1 : c.n);
+    {
+        const int64_t keep = c.panel == PANEL_B2 ? 2 * PANEL_B2 : c.panel == PANEL_B1 ? 2 * PANEL_B1 : c.n;
+        launch_init<T>(c, c.Z == c.Q ? 0 : c.n > keep ? keep : c.n);
+    }
     st.kernel_launches++;
     if (c.ell_k) {
         launch_csr_to_ell<T>(c);
@@ -334,9 +339,12 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
     }
     static_assert(HP_XB % PANEL_B == 0 && HP_XB % PANEL_B1 == 0,
                   "x-block passes fall on (outer) panel boundaries");
-    const bool two = c.panel == PANEL_B1;
+    // three levels: 16-panels taken apart as 8-panels, each as two 4-panels
+    const bool three = c.panel == PANEL_B2;
+    const bool two = c.panel == PANEL_B1 || three;
     const int64_t B = PANEL_B;
-    const int64_t B1 = two ? PANEL_B1 : PANEL_B;   // outer panel width (= B for one level)
+    const int64_t B1 = two ? PANEL_B1 : PANEL_B;   // 8-panel width (= B for one level)
+    const int64_t B2 = PANEL_B2;
     // launch with HIP events bound to the dispatch when profiling (category
     // 0, and 3 for the block sweep after an outer panel)
     auto profiled = [&](bool block, auto &&launch) {
@@ -359,6 +367,17 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
     for (int64_t S = 0; S < c.n; S += B1) {
         const int64_t E = S + B1 < c.n ? S + B1 : c.n;
         const int64_t bp0 = S > 0 ? S - B1 : S;   // the previous outer panel [bp0, S)
+        // three levels: the 16-panel [S16, E16) of this 8-panel; before its
+        // first 8-panel, the previous 16-panel's block is applied to its
+        // columns (a 16-wide block is too wide for the column-step kernels)
+        const int64_t S16 = three ? S / B2 * B2 : S;
+        const int64_t E16 = three ? (S16 + B2 < c.n ? S16 + B2 : c.n) : E;
+        if (three && S == S16 && S16 > 0) {
+            profiled(false, [&] { launch_bsweep<T>(c, S16 - B2, S16, S16, S16, S16, E16, false, PANEL_B2); });
+            st.kernel_launches++;
+            st.sweep_launches++;
+            st.sweep_bytes += ((double)(E16 - S16) * 2.0 + (double)B2) * (double)c.m * w;
+        }
         if (blk && S > 0) {
             profiled(false, [&] { launch_bsweep<T>(c, bp0, S, S, S, S, E); });
             launch_rb<T>(c, S, E, variant);
@@ -367,17 +386,20 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
             st.sweep_bytes += (double)(E - S) * 2.0 * (double)c.m * w + (double)(S - bp0) * (double)c.m * w;
         }
         c.re_lo = blk ? S : 0;
-        // the outer block still pending for this panel's columns
-        const int64_t ob0 = blk ? S : bp0;
+        // the outer block still pending for this panel's columns (three
+        // levels: the first 8-panel of its 16-panel has none left, the
+        // second has the first)
+        const int64_t ob0 = (blk || (three && S == S16)) ? S : bp0;
         for (int64_t s = S; s < E; s += B) {
             const int64_t e = s + B < E ? s + B : E;
             // the block still pending for this panel's columns: the previous
             // outer panel for the first inner panel, else the previous inner one
             const int64_t pk0 = s == S ? ob0 : s - B, pk1 = s;
             for (int64_t j = s; j < e; ++j) {
-                // (with the blocked pass the first column of an outer panel has
-                // no pending term either: it takes the same block-step path)
-                const bool first_blk = j == s && (pk1 > pk0 || (blk && j == S && S > 0));
+                // (with the blocked pass, and with three levels at the start
+                // of a 16-panel, the first column of an outer panel has no
+                // pending term either: it takes the same block-step path)
+                const bool first_blk = j == s && (pk1 > pk0 || (j == S && S > 0 && ob0 == S));
                 int64_t n_rr = 0;
                 // column kernels publish r_{j-1,c} only inside the panel
                 c.n_pub = e;
@@ -483,7 +505,38 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
                     launch_pfin<T>(c, s, e, E);
                     st.kernel_launches++;
                 }
-                if (outer_end) {
+                if (outer_end && three) {
+                    if (E < E16) {
+                        // the first 8-panel of a 16-panel: its block's dots
+                        // for the other 8-panel only
+                        profiled(false, [&] { launch_bsweep<T>(c, S, S, S, E, E, E16, false, PANEL_B1); });
+                        launch_lfin<T>(c, S, E, PANEL_B1);
+                        launch_pfin2<T>(c, S, E, E, E16, PANEL_B1);
+                        st.kernel_launches += 3;
+                        st.sweep_launches++;
+                        st.sweep_bytes += ((double)(E16 - E) + (double)(E - S)) * (double)c.m * w;
+                    } else {
+                        // a finished 16-panel: the previous 16-panel's block
+                        // on every later column and this one's dots; the
+                        // columns from E16 on are read from Z until they are
+                        // first written (the first two 16-panels)
+                        const int64_t k0b = S16 > 0 ? S16 - B2 : S16;
+                        profiled(true, [&] {
+                            launch_bsweep<T>(c, k0b, S16, S16, E16, E16, c.n, S16 < 2 * B2, PANEL_B2);
+                        });
+                        const double col = (double)c.m * (double)w;
+                        const double bb = (double)(c.n - E16) * (S16 > k0b ? 2.0 : 1.0) * col
+                                          + (double)((S16 - k0b) + (E16 - S16)) * col;
+                        st.kernel_launches++;
+                        st.sweep_launches++;
+                        st.sweep_bytes += bb;
+                        st.block_sweep_launches++;
+                        st.block_sweep_bytes += bb;
+                        launch_lfin<T>(c, S16, E16, PANEL_B2);
+                        launch_pfin2<T>(c, S16, E16, E16, c.n, PANEL_B2);
+                        st.kernel_launches += 2;
+                    }
+                } else if (outer_end) {
                     if (two) {
                         // [E, n) lacks the block [bp0, S) also with blk; after the
                         // first two eight-panels the columns from E on have never
@@ -602,7 +655,8 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
     if (reorth_mode == 2 && panel != PANEL_B1) return AMGS_ERR_UNSUPPORTED;
     const int cgs = o ? o->cgs : 0;
     const int64_t first = o ? o->first : 0;
-    if (panel != 0 && panel != PANEL_B && panel != PANEL_B1) return AMGS_ERR_ARG;
+    if (panel != 0 && panel != PANEL_B && panel != PANEL_B1 && panel != PANEL_B2) return AMGS_ERR_ARG;
+    if (panel == PANEL_B2 && v == AMGS_HP) return AMGS_ERR_UNSUPPORTED;
     if (cgs != 0 && cgs != 1) return AMGS_ERR_ARG;
     if (first < 0 || first > c.n) return AMGS_ERR_ARG;
     if (first > 0 && !P_given) return AMGS_ERR_ARG;   // p_i of the final columns are needed
@@ -772,7 +826,8 @@ size_t amgs_workspace_bytes(amgs_handle_t h, int64_t m, int64_t n, int32_t is_de
     Geo g = make_geo(m, is_dense ? 0 : m, is_dense);
     const int panel = o ? o->panel : 0;
     const int cgs = o ? o->cgs : 0;
-    if (panel != 0 && panel != PANEL_B && panel != PANEL_B1) return 0;
+    if (panel != 0 && panel != PANEL_B && panel != PANEL_B1 && panel != PANEL_B2) return 0;
+    if (panel == PANEL_B2 && v == AMGS_HP) return 0;
     if (cgs != 0 && cgs != 1) return 0;
     const int reorth_mode = o ? o->reorth : 0;
     if (reorth_mode < 0 || reorth_mode > 2) return 0;

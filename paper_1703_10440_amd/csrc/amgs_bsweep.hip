@@ -38,11 +38,10 @@ __device__ __forceinline__ int bs_act(int i)
 
 // The W partials of one 16-column tile starting at ct (nc columns): the
 // waves' entries added in wave order.
-template <typename T>
-__device__ __forceinline__ void bs_wpart(const T (*red)[16 * PANEL_B1], int64_t ct, int nc,
+template <typename T, int BB>
+__device__ __forceinline__ void bs_wpart(const T (*red)[16 * BB], int64_t ct, int nc,
                                          int nd, const BSweepArgs &a)
 {
-    constexpr int BB = PANEL_B1;
     const int tid = threadIdx.x;
     if (tid < nc * BB) {
         const int cl = tid / BB, d = tid - cl * BB;
@@ -55,14 +54,17 @@ __device__ __forceinline__ void bs_wpart(const T (*red)[16 * PANEL_B1], int64_t 
     }
 }
 
-template <typename T, bool NTS>
+// BB: the block width, 8 (two-level schedule) or 16 (three levels: all 16
+// rows of W in use, the update four 16x16x4 steps).
+template <typename T, bool NTS, int BB>
 __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
 {
     typedef typename Mfma<T>::acc_t acc_t;
     constexpr int ST = BS_ST;
     constexpr int WR = ST * 16;         // rows per wave
     constexpr int LD = WR + 4;          // padded LDS column (16-byte aligned)
-    constexpr int BB = PANEL_B1;
+    constexpr int KS = BB / 4;          // 16x16x4 steps of the update
+    static_assert(BB == 8 || BB == 16, "block widths of the panel schedules");
     static_assert(WR == WAVE, "one row per lane in the contiguous accesses");
     __shared__ T red[256 / WAVE][16 * BB];   // the waves' W of one 16-column tile
     __shared__ __attribute__((aligned(16))) T tile[256 / WAVE][16][LD];
@@ -86,31 +88,46 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
     // matrix row 4 (l/16) + v), added over the waves after the columns; its
     // strictly lower part is the L of the block solve.
     const bool own_l = blockIdx.y == 0 && nd > 1;
-    T qa[ST][2], pa[ST][4];
+    T qa[ST][KS], pa[ST][4];
     acc_t lw = {0, 0, 0, 0};
+    // P_I first, then (grid row 0) Q_I for L, then the pending Q_{I-1},
+    // each through the wave's 16-column tile.  All three are loaded at once,
+    // from clamped addresses and zeroed after the loads, so that no load
+    // waits for the one before it.
+    T vp[BB], vq[BB], vk[BB];
 #pragma unroll
     for (int c = 0; c < BB; ++c) {
-        tl[c][lane] = (rin && c < nd) ? P[myrow + (a.d0 + c) * a.ldp] : (T)0;
-        tl[BB + c][lane] = (own_l && rin && c < nd) ? Q[myrow + (a.d0 + c) * ldq] : (T)0;
+        vp[c] = ld_fix(P, myrow + (a.d0 + c) * a.ldp, 0, rin && c < nd);
+        vq[c] = ld_fix((const T *)Q, myrow + (a.d0 + c) * ldq, 0, own_l && rin && c < nd);
+        vk[c] = ld_fix((const T *)Q, myrow + (a.k0 + c) * ldq, 0, rin && c < kw);
+    }
+    pin();
+#pragma unroll
+    for (int c = 0; c < BB; ++c) tl[c][lane] = pick(vp[c], rin && c < nd);
+    __syncthreads();
+#pragma unroll
+    for (int st = 0; st < ST; ++st)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) pa[st][v] = jl < BB ? tl[jl][st * 16 + 4 * g4 + v] : (T)0;
+    if (own_l) {
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < BB; ++c) tl[c][lane] = pick(vq[c], rin && c < nd);
+        __syncthreads();
+#pragma unroll
+        for (int st = 0; st < ST; ++st)
+#pragma unroll
+            for (int v = 0; v < 4; ++v)
+                lw = Mfma<T>::op(pa[st][v], jl < BB ? tl[jl][st * 16 + 4 * g4 + v] : (T)0, lw);
     }
     __syncthreads();
 #pragma unroll
-    for (int st = 0; st < ST; ++st)
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int r = st * 16 + 4 * g4 + v;
-            pa[st][v] = jl < BB ? tl[jl][r] : (T)0;
-            if (own_l) lw = Mfma<T>::op(pa[st][v], jl < BB ? tl[BB + jl][r] : (T)0, lw);
-        }
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < BB; ++c)
-        tl[c][lane] = (rin && c < kw) ? Q[myrow + (a.k0 + c) * ldq] : (T)0;
+    for (int c = 0; c < BB; ++c) tl[c][lane] = pick(vk[c], rin && c < kw);
     __syncthreads();
 #pragma unroll
     for (int st = 0; st < ST; ++st)
 #pragma unroll
-        for (int s2 = 0; s2 < 2; ++s2) qa[st][s2] = tl[4 * s2 + g4][st * 16 + bs_act<T>(jl)];
+        for (int s2 = 0; s2 < KS; ++s2) qa[st][s2] = tl[4 * s2 + g4][st * 16 + bs_act<T>(jl)];
     const int64_t cA = a.c0 + (int64_t)blockIdx.y * a.cpw;
     const int64_t cB = (cA + a.cpw < a.c1) ? cA + a.cpw : a.c1;
     for (int64_t ct = cA; ct < cB; ct += 16) {
@@ -120,20 +137,25 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
 #pragma unroll
         for (int c = 0; c < 16; ++c)
             zl[c] = (c < nc && rin) ? ld_stream<NTS>(Zs + (ct + c) * a.ldzs + myrow) : (T)0;
+        const int64_t col = ct + jl;
+        const bool cin = jl < nc;
+        // B operand of the update, -r_{k0+4s+l/16, col}, loaded beside the
+        // block (clamped addresses: no load waits for the one before it)
+        double rd[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int kk = 4 * s + g4;
+            rd[s] = ld_fix(a.R, (a.k0 + kk) + col * a.ldr, 0, cin && kk < kw);
+        }
+        pin();
         __syncthreads();   // the previous block's LDS reads and W entries are done
-        if (ct > cA) bs_wpart<T>(red, ct - 16, 16, nd, a);
+        if (ct > cA) bs_wpart<T, BB>(red, ct - 16, 16, nd, a);
 #pragma unroll
         for (int c = 0; c < 16; ++c) tl[c][lane] = zl[c];
         __syncthreads();
-        const int64_t col = ct + jl;
-        const bool cin = jl < nc;
-        // B operand of the update: -r_{k0+4s+l/16, col}
-        T rb[2];
+        T rb[KS];
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int kk = 4 * s + g4;
-            rb[s] = (cin && kk < kw) ? -(T)a.R[(a.k0 + kk) + col * a.ldr] : (T)0;
-        }
+        for (int s = 0; s < KS; ++s) rb[s] = -(T)pick(rd[s], cin && 4 * s + g4 < kw);
         acc_t w = {0, 0, 0, 0};
 #pragma unroll
         for (int st = 0; st < ST; ++st) {
@@ -141,8 +163,9 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
 #pragma unroll
             for (int v = 0; v < 4; ++v) z[v] = tl[jl][st * 16 + 4 * g4 + v];
             if (kw > 0) {
-                z = Mfma<T>::op(qa[st][0], rb[0], z);
-                if (kw > 4) z = Mfma<T>::op(qa[st][1], rb[1], z);
+#pragma unroll
+                for (int s2 = 0; s2 < KS; ++s2)
+                    if (kw > 4 * s2) z = Mfma<T>::op(qa[st][s2], rb[s2], z);
 #pragma unroll
                 for (int v = 0; v < 4; ++v) tl[jl][st * 16 + 4 * g4 + v] = (T)z[v];
             }
@@ -155,7 +178,7 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
             for (int c = 0; c < 16; ++c)
                 if (c < nc && rin) st_stream<NTS>(Q + (ct + c) * ldq + myrow, tl[c][lane]);
         }
-        // W[i, col] for i = Mfma<T>::row(lane, v) < PANEL_B1, added over the
+        // W[i, col] for i = Mfma<T>::row(lane, v) < BB, added over the
         // waves at the next tile (or below)
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
@@ -166,7 +189,7 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
     __syncthreads();
     if (cA < cB) {
         const int64_t last = cA + (cB - 1 - cA) / 16 * 16;
-        bs_wpart<T>(red, last, (int)(cB - last), nd, a);
+        bs_wpart<T, BB>(red, last, (int)(cB - last), nd, a);
     }
     if (own_l) {
         __syncthreads();   // the W entries have been read
@@ -198,7 +221,7 @@ int64_t bsweep_chunks(int64_t m, size_t w)
 
 template <typename T>
 void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0, int64_t d1, int64_t c0,
-                   int64_t c1, bool from_z)
+                   int64_t c1, bool from_z, int bb)
 {
     BSweepArgs a{};
     a.m = c.m; a.Q = c.Q; a.ldq = c.ldq; a.P = c.P; a.ldp = c.ldp; a.R = c.R; a.ldr = c.ldr;
@@ -222,23 +245,28 @@ void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0, int64_t d1,
     a.cpw = cpw;
     const dim3 grid((unsigned)c.g_b, (unsigned)gy), block(256);
     const bool nts = (double)ncols * (double)c.m * sizeof(T) > SWEEP_NT_BYTES;
-#define AMGS_BS(NT_)                                                                              \
+#define AMGS_BS(NT_, BB_)                                                                         \
     do {                                                                                          \
         if (c.ev_start)                                                                           \
-            hipExtLaunchKernelGGL((k_bsweep<T, NT_>), grid, block, 0, c.stream, c.ev_start,       \
+            hipExtLaunchKernelGGL((k_bsweep<T, NT_, BB_>), grid, block, 0, c.stream, c.ev_start,  \
                                   c.ev_stop, 0, a);                                               \
         else                                                                                      \
-            hipLaunchKernelGGL((k_bsweep<T, NT_>), grid, block, 0, c.stream, a);                  \
+            hipLaunchKernelGGL((k_bsweep<T, NT_, BB_>), grid, block, 0, c.stream, a);             \
     } while (0)
-    if (nts) AMGS_BS(true);
-    else AMGS_BS(false);
+    if (bb == PANEL_B2) {
+        if (nts) AMGS_BS(true, PANEL_B2);
+        else AMGS_BS(false, PANEL_B2);
+    } else {
+        if (nts) AMGS_BS(true, PANEL_B1);
+        else AMGS_BS(false, PANEL_B1);
+    }
 #undef AMGS_BS
 }
 
 
 template void launch_bsweep<double>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t,
-                                    bool);
+                                    bool, int);
 template void launch_bsweep<float>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int64_t, int64_t,
-                                   bool);
+                                   bool, int);
 
 } // namespace amgs

@@ -23,6 +23,7 @@ constexpr int ELL_K = 8;       // most entries per row held in the padded copy o
 constexpr int16_t ELL_PAD = -32768;   // 16-bit column offset of a padding entry
 constexpr int PANEL_B = 4;     // columns per panel of the panel schedule (inner panels of the two-level one)
 constexpr int PANEL_B1 = 8;    // columns per outer panel of the two-level panel schedule
+constexpr int PANEL_B2 = 16;   // columns per outermost panel of the three-level schedule
 #ifndef AMGS_BS_ST
 #define AMGS_BS_ST 4
 #endif
@@ -173,8 +174,8 @@ struct BSweepArgs {
     const double *R;
     int64_t ldr;
     const int32_t *info;
-    int64_t k0, k1;   // pending block, k1 - k0 <= PANEL_B1
-    int64_t d0, nd;   // dot columns, nd <= PANEL_B1
+    int64_t k0, k1;   // pending block, k1 - k0 <= the kernel's block width
+    int64_t d0, nd;   // dot columns, nd <= the kernel's block width
     int64_t c0, c1, cpw;
     void *part;       // part[(c * PANEL_B1 + d - d0) * g + w]
     void *lpart;      // partials of P_I^T Q_I: lpart[(i * PANEL_B1 + k) * g + w]
@@ -282,9 +283,11 @@ template <typename T> void launch_psweep(const Ctx &c, int variant, int64_t j, i
                                          int64_t d0, int64_t l0, int64_t c0, int64_t c1, int64_t n_rr);
 template <typename T> void launch_pfin(const Ctx &c, int64_t s, int64_t e, int64_t c1);
 template <typename T> void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0,
-                                         int64_t d1, int64_t c0, int64_t c1, bool from_z = false);
-template <typename T> void launch_lfin(const Ctx &c, int64_t s, int64_t e);
-template <typename T> void launch_pfin2(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1);
+                                         int64_t d1, int64_t c0, int64_t c1, bool from_z = false,
+                                         int bb = PANEL_B1);
+template <typename T> void launch_lfin(const Ctx &c, int64_t s, int64_t e, int bb = PANEL_B1);
+template <typename T> void launch_pfin2(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1,
+                                        int bb = PANEL_B1);
 int64_t bsweep_chunks(int64_t m, size_t w);
 template <typename T> void launch_pcol_blk(const Ctx &c, int variant, int64_t j, int64_t k0, int64_t k1,
                                             int64_t xk0);

@@ -327,10 +327,12 @@ __global__ __launch_bounds__(256) void k_pcol_blk(RowArgs a, int64_t k0, int64_t
 
 // L = strict_lower(P_I^T Q_I) of an outer panel of b columns, each entry
 // re-reduced from the partials k_bsweep wrote (fixed order), one wave per
-// entry, into lred[i * PANEL_B1 + k] in binary64.
+// entry, into lred[i * bs + k] in binary64 (bs: the block width of the
+// block sweep that wrote the partials, which is also their stride).
 template <typename T>
 __global__ __launch_bounds__(WAVE) void k_lfin(const T *__restrict__ lpart, int64_t g, int b,
-                                               double *__restrict__ lred, const int32_t *info)
+                                               int bs, double *__restrict__ lred,
+                                               const int32_t *info)
 {
     if (*info) return;
     int q = blockIdx.x, i = 1;
@@ -339,8 +341,8 @@ __global__ __launch_bounds__(WAVE) void k_lfin(const T *__restrict__ lpart, int6
         ++i;
     }
     if (i >= b) return;
-    const T v = wave_reduce_seq(lpart + (int64_t)(i * PANEL_B1 + q) * g, g);
-    if (threadIdx.x == 0) lred[i * PANEL_B1 + q] = (double)v;
+    const T v = wave_reduce_seq(lpart + (int64_t)(i * bs + q) * g, g);
+    if (threadIdx.x == 0) lred[i * bs + q] = (double)v;
 }
 
 // r_{[s, s+b), c} for every later column c = c0 + blockIdx.x: the block dots
@@ -371,7 +373,7 @@ __global__ __launch_bounds__(B * WAVE) void k_pfin2(int64_t s, int b, int64_t c0
                 double t = wv[i];
 #pragma unroll
                 for (int k = 0; k < B; ++k)
-                    if (k < i) t = __builtin_fma(-lred[i * PANEL_B1 + k], r[k], t);
+                    if (k < i) t = __builtin_fma(-lred[i * B + k], r[k], t);
                 r[i] = t;
                 R[(s + i) + c * ldr] = t;
             }
@@ -632,22 +634,27 @@ void launch_pfin(const Ctx &c, int64_t s, int64_t e, int64_t c1)
 }
 
 template <typename T>
-void launch_lfin(const Ctx &c, int64_t s, int64_t e)
+void launch_lfin(const Ctx &c, int64_t s, int64_t e, int bb)
 {
     const int b = (int)(e - s);
     if (b < 2) return;
     hipLaunchKernelGGL(k_lfin<T>, dim3((unsigned)(b * (b - 1) / 2)), dim3(WAVE), 0, c.stream,
-                       (const T *)c.lpart8, c.g_b, b, c.lred, c.info);
+                       (const T *)c.lpart8, c.g_b, b, bb, c.lred, c.info);
 }
 
 // The outer block's coefficients for the later columns [c0, c1).
 template <typename T>
-void launch_pfin2(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1)
+void launch_pfin2(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1, int bb)
 {
     if (c1 <= c0) return;
-    hipLaunchKernelGGL((k_pfin2<T, PANEL_B1>), dim3((unsigned)(c1 - c0)), dim3(PANEL_B1 * WAVE), 0,
-                       c.stream, s, (int)(e - s), c0, (const T *)c.wpart, c.g_b,
-                       (const double *)c.lred, c.R, c.ldr, c.info);
+    if (bb == PANEL_B2)
+        hipLaunchKernelGGL((k_pfin2<T, PANEL_B2>), dim3((unsigned)(c1 - c0)), dim3(PANEL_B2 * WAVE),
+                           0, c.stream, s, (int)(e - s), c0, (const T *)c.wpart, c.g_b,
+                           (const double *)c.lred, c.R, c.ldr, c.info);
+    else
+        hipLaunchKernelGGL((k_pfin2<T, PANEL_B1>), dim3((unsigned)(c1 - c0)), dim3(PANEL_B1 * WAVE),
+                           0, c.stream, s, (int)(e - s), c0, (const T *)c.wpart, c.g_b,
+                           (const double *)c.lred, c.R, c.ldr, c.info);
 }
 
 // The blocked second pass of the outer panel [s, e) against the columns
@@ -701,10 +708,10 @@ template void launch_psweep<double>(const Ctx &, int, int64_t, int64_t, int64_t,
 template void launch_psweep<float>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t, int64_t,
                                    int64_t, int64_t, int64_t);
 template void launch_pfin<double>(const Ctx &, int64_t, int64_t, int64_t);
-template void launch_lfin<double>(const Ctx &, int64_t, int64_t);
-template void launch_lfin<float>(const Ctx &, int64_t, int64_t);
-template void launch_pfin2<double>(const Ctx &, int64_t, int64_t, int64_t, int64_t);
-template void launch_pfin2<float>(const Ctx &, int64_t, int64_t, int64_t, int64_t);
+template void launch_lfin<double>(const Ctx &, int64_t, int64_t, int);
+template void launch_lfin<float>(const Ctx &, int64_t, int64_t, int);
+template void launch_pfin2<double>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int);
+template void launch_pfin2<float>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int);
 template void launch_rb<double>(const Ctx &, int64_t, int64_t, int);
 template void launch_rb<float>(const Ctx &, int64_t, int64_t, int);
 template void launch_pfin<float>(const Ctx &, int64_t, int64_t, int64_t);

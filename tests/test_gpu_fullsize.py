@@ -22,8 +22,11 @@ orientation as an extra check.
   binary32 inputs (residual and orthogonality within 10x), and in binary64
   (residual and orthogonality within max(floor, 10x)).
 
-Every case but CGS runs in the column schedule and in both panel schedules
-(panels of four; panels of eight taken apart as panels of four).
+Every case but CGS runs in the column schedule and in the one- and two-level
+panel schedules (panels of four; panels of eight taken apart as panels of
+four); the three-level schedule (panels of sixteen taken apart as panels of
+eight) runs HA and naive on lap64 (with and without the second pass) and HA
+on lap128 in both precisions.
 """
 import numpy as np
 import pytest
@@ -73,7 +76,8 @@ def _oracles(prob, variant, precision, panel, reorth=False, cgs=False):
              ref.qr_problem(prob, orientation="cgs" if cgs else "col", **kw))]
     if panel:
         outs.append(("panel orientation",
-                     ref.qr_problem(prob, orientation={4: "panel", 8: "panel8"}[panel], **kw)))
+                     ref.qr_problem(prob, orientation={4: "panel", 8: "panel8", 16: "panel16"}[panel],
+                                    **kw)))
     return outs
 
 
@@ -233,6 +237,38 @@ def test_lap128_fp32_blocked_second_pass(lap128_fp32, variant):
     assert info == 0
     want = ref.qr_problem(p, variant=variant, orientation="panel8", precision="fp32", reorth=2)
     _at_oracle_level(p, Q, R, [("panel8 orientation, blocked pass", want)], floors=(0.0, 0.0))
+
+
+# ------------------------------------------- three-level schedule (panel 16)
+@pytest.mark.parametrize("reorth", [False, True])
+@pytest.mark.parametrize("variant", ["ha", "naive"])
+def test_lap64_three_level(lap64, variant, reorth):
+    p = lap64
+    Q, R, info = _run(p, variant, "fp64", 16, reorth=reorth)
+    assert info == 0
+    _at_oracle_level(p, Q, R, _oracles(p, variant, "fp64", 16, reorth=reorth))
+
+
+@pytest.mark.parametrize("variant", ["ha", "naive"])
+def test_lap64_three_level_fp32_second_pass(lap64_fp32, variant):
+    p = lap64_fp32
+    Q, R, info = _run(p, variant, "fp32", 16, reorth=True)
+    assert info == 0
+    _at_oracle_level(p, Q, R, _oracles(p, variant, "fp32", 16, reorth=True), floors=(0.0, 0.0))
+
+
+def test_lap128_three_level_fp64(lap128_fp64):
+    p = lap128_fp64
+    Q, R, info = _run(p, "ha", "fp64", 16)
+    assert info == 0
+    _at_oracle_level(p, Q, R, _oracles(p, "ha", "fp64", 16))
+
+
+def test_lap128_three_level_fp32(lap128_fp32):
+    p = lap128_fp32
+    Q, R, info = _run(p, "ha", "fp32", 16)
+    assert info == 0
+    _at_oracle_level(p, Q, R, _oracles(p, "ha", "fp32", 16), floors=(0.0, 0.0))
 
 
 @pytest.mark.parametrize("variant", ["hp", "ha", "naive"])

@@ -1,6 +1,8 @@
 """Panel schedules of the GPU path against the oracle: one level (opts.panel
-= 4, panels of four columns) and two levels (opts.panel = 8, panels of eight
-columns each taken apart as two panels of four).
+= 4, panels of four columns), two levels (opts.panel = 8, panels of eight
+columns each taken apart as two panels of four) and three levels
+(opts.panel = 16, panels of sixteen taken apart as two of eight; naive and
+HA only).
 
 Every GPU panel result is gated against the paper's column algorithms
 (Alg. 3/5/6, the oracle's "col" orientation), with the tolerances of the
@@ -9,9 +11,9 @@ Frobenius) for kappa(Z) <= 1e3; for kappa(Z) > 1e3 the residual and
 ||Q^T A Q - I||_2 within max(floor, 10x) the column oracle's; the binary32
 form within 64 u_32 kappa(A^{1/2} Z) sqrt(n) of the column oracle's binary32
 emulation, orthogonality within 10x.  As an extra check the same bounds are
-applied against the oracle's panel orientation of the same schedule ("panel"
-or "panel8"), which performs the same regrouped operations step by step
-(pinned in tests/pins.py, pin_panel and pin_panel8).
+applied against the oracle's panel orientation of the same schedule ("panel",
+"panel8" or "panel16"), which performs the same regrouped operations step by
+step (pinned in tests/pins.py, pin_panel, pin_panel8 and pin_panel16).
 """
 import numpy as np
 import pytest
@@ -30,8 +32,18 @@ from paper_1703_10440_amd import amgs  # noqa: E402
 DEV = torch.device("cuda:0")
 VARIANTS = ("naive", "ha", "hp")
 U32 = 2.0 ** -24
-PANELS = (4, 8)
-ORIENT = {4: "panel", 8: "panel8"}
+PANELS = (4, 8, 16)
+ORIENT = {4: "panel", 8: "panel8", 16: "panel16"}
+
+
+def variants_for(panel):
+    """The three-level schedule has no HP form (AMGS_ERR_UNSUPPORTED)."""
+    return ("naive", "ha") if panel == 16 else VARIANTS
+
+
+def need(variant, panel):
+    if variant not in variants_for(panel):
+        pytest.skip("the three-level schedule has no HP form")
 
 
 def _rel(a, b):
@@ -107,6 +119,7 @@ SMALL = small_problems()
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("pi", range(len(SMALL)), ids=[p.name for p in SMALL])
 def test_panel_fp64_parity(pi, variant, reorth, panel):
+    need(variant, panel)
     p = SMALL[pi]
     col = oracle_col(p, variant, reorth=reorth)
     want = oracle(p, variant, reorth=reorth, panel=panel)
@@ -125,6 +138,7 @@ def test_panel_fp64_parity(pi, variant, reorth, panel):
 def test_panel_graded_ill_conditioned(variant, reorth, panel):
     """kappa(Z) ~ 1e6, 6 panels of four (3 of eight): residual and
     orthogonality at the oracle's level."""
+    need(variant, panel)
     p = inputs.laplacian_graded_problem(N=16, n=24, decades=6.0, seed=11)
     col = oracle_col(p, variant, reorth=reorth)
     want = oracle(p, variant, reorth=reorth, panel=panel)
@@ -139,6 +153,7 @@ def test_panel_graded_ill_conditioned(variant, reorth, panel):
 @pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("pi", [0, 1, 3], ids=[SMALL[i].name for i in (0, 1, 3)])
 def test_panel_fp32_form(pi, variant, reorth, panel):
+    need(variant, panel)
     p = SMALL[pi]
     Z32 = np.asfortranarray(p.Z.astype(np.float32).astype(np.float64))
     if p.csr is not None:
@@ -167,6 +182,7 @@ def test_panel_fp32_form(pi, variant, reorth, panel):
 def test_panel_many_workgroups_deterministic(variant, panel):
     """m = 64000, n = 40: the sweeps after each panel run hundreds of row
     chunks and several column groups; parity and bit-identical repeats."""
+    need(variant, panel)
     p = inputs.laplacian_graded_problem(N=40, n=40, decades=2.0, seed=14)
     Q, R, P, info, _ = gpu_run(p, variant, panel=panel)
     Q2, R2, _, _, _ = gpu_run(p, variant, panel=panel)
@@ -180,16 +196,17 @@ def test_panel_many_workgroups_deterministic(variant, panel):
 @pytest.mark.parametrize("panel", PANELS)
 def test_panel_edges(panel):
     """Panel boundaries: n = 1, 4 (one full panel), 5 (a one-column last
-    panel), 8 (one outer panel), 9 (an outer panel and one column), 12, 17;
+    panel), 8 (one outer panel), 9 (an outer panel and one column), 12, 16
+    (one sixteen-panel), 17, 24 (a sixteen-panel and one eight-panel), 33;
     square and tiny m; dense and CSR."""
     g = inputs.rng(15)
-    for m, n in ((700, 1), (300, 4), (300, 5), (200, 8), (300, 9), (300, 12), (300, 17),
-                 (40, 40), (5, 3)):
+    for m, n in ((700, 1), (300, 4), (300, 5), (200, 8), (300, 9), (300, 12), (300, 16),
+                 (300, 17), (300, 24), (300, 33), (40, 40), (5, 3)):
         A = inputs.gram_spd(g, m)
         Z = np.asfortranarray(g.standard_normal((m, n)))
         for prob in (inputs.Problem(f"edge{m}x{n}", Z, dense=A),
                      inputs.Problem(f"edgecsr{m}x{n}", Z, csr=inputs.csr_from_dense(A))):
-            for v in VARIANTS:
+            for v in variants_for(panel):
                 Q, R, P, info, _ = gpu_run(prob, v, panel=panel)
                 assert info == 0
                 for what, want in (("column", oracle_col(prob, v)),
@@ -210,7 +227,7 @@ def test_panel_breakdown_reports_column(panel):
     Zc[:, 5] = 0.0
     Zn = Z.copy(order="F")
     Zn[7, 9] = np.nan
-    for v in VARIANTS:
+    for v in variants_for(panel):
         _, R, _, info, _ = gpu_run(inputs.Problem("zero", Zc, dense=A), v, panel=panel)
         want = oracle(inputs.Problem("zero", Zc, dense=A), v, panel=panel)
         col = oracle_col(inputs.Problem("zero", Zc, dense=A), v)
@@ -228,17 +245,20 @@ def test_panel_argument_errors():
     info = torch.zeros(1, dtype=torch.int32, device=DEV)
     Z = torch.zeros(10, 4, dtype=torch.float64, device=DEV)
     work = torch.empty(1 << 20, dtype=torch.uint8, device=DEV)
-    # panel values other than 4 and 8 are invalid; the panel schedules with
-    # classical Gram-Schmidt are not supported (with the second pass they are)
-    for panel, cgs, want in ((3, 0, -1), (16, 0, -1), (4, 1, -4), (8, 1, -4)):
+    # panel values other than 4, 8 and 16 are invalid; the panel schedules
+    # with classical Gram-Schmidt are not supported (with the second pass they
+    # are), nor the three-level one with HP (variant 2)
+    for panel, cgs, var, want in ((3, 0, 1, -1), (12, 0, 1, -1), (32, 0, 1, -1), (4, 1, 1, -4),
+                                  (8, 1, 1, -4), (16, 1, 1, -4), (16, 0, 2, -4)):
         opts = amgs.Opts(0, panel, cgs, 0)
         st = amgs.amgs_qr_dense(h, 10, Z.data_ptr(), 10, 4, Z.data_ptr(), 10, Z.data_ptr(), 10,
-                                Z.data_ptr(), 4, None, 0, 1, 0, C.byref(opts), work.data_ptr(),
+                                Z.data_ptr(), 4, None, 0, var, 0, C.byref(opts), work.data_ptr(),
                                 work.numel(), info.data_ptr(), None)
-        assert st == want, (panel, cgs, st)
+        assert st == want, (panel, cgs, var, st)
     assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(0, 3, 0, 0)) == 0
-    assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(0, 4, 0, 0)) > 0
-    assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(0, 8, 0, 0)) > 0
+    assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 2, 0, 0, amgs.Opts(0, 16, 0, 0)) == 0
+    for panel in (4, 8, 16):
+        assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(0, panel, 0, 0)) > 0
 
 
 # ----------------------------------------------- blocked second pass (reorth=2)
@@ -313,25 +333,35 @@ def test_blocked_second_pass_needs_two_levels():
     assert amgs.amgs_workspace_bytes(h, 10, 4, 1, 1, 0, 0, amgs.Opts(2, 4, 0, 0)) == 0
 
 
+WIDE = [inputs.random_csr_problem(3001, 45, 40, seed=17),
+        inputs.dense_gram_problem(512, 40, seed=18)]
+
+
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 @pytest.mark.parametrize("variant", VARIANTS)
-@pytest.mark.parametrize("pi", [1, 3], ids=[SMALL[i].name for i in (1, 3)])
-def test_two_level_working_copy(pi, variant, precision):
-    """Two-level schedule: only the first two eight-panels are copied from Z
-    before the call's work, and the block sweep after the second eight-panel
-    reads the later columns from Z.  Out of place, Z must come back untouched;
-    in place (Q aliases Z) the result must equal the out-of-place one bit for
-    bit.  Both problems have n > 16, so columns from 16 on take the Z path."""
-    p = SMALL[pi]
-    assert p.n > 16
+@pytest.mark.parametrize("case", [(8, 1), (8, 3), (16, 0), (16, 1)],
+                         ids=["8-" + SMALL[1].name, "8-" + SMALL[3].name, "16-" + WIDE[0].name,
+                              "16-" + WIDE[1].name])
+def test_two_level_working_copy(case, variant, precision):
+    """Two- and three-level schedules: only the first two eight-panels (two
+    sixteen-panels) are copied from Z before the call's work, and the block
+    sweep after the second one reads the later columns from Z.  Out of place,
+    Z must come back untouched; in place (Q aliases Z) the result must equal
+    the out-of-place one bit for bit.  Every problem has n > 2 x the panel
+    width, so the later columns take the Z path."""
+    panel, pi = case
+    need(variant, panel)
+    p = SMALL[pi] if panel == 8 else WIDE[pi]
+    assert p.n > 2 * panel
     dt = torch.float64 if precision == "fp64" else torch.float32
     Z0 = amgs.colmajor(torch.from_numpy(np.ascontiguousarray(p.Z)).to(DEV).to(dt))
     Zc = Z0.clone()
 
     def run(Zt, Q=None):
-        print(f"[gpu] working copy {p.name} {variant} {precision} inplace={Q is not None}",
+        print(f"[gpu] working copy panel={panel} {p.name} {variant} {precision} "
+              f"inplace={Q is not None}",
               flush=True)
-        kw = dict(variant=variant, precision=precision, return_p=True, panel=8, Q=Q)
+        kw = dict(variant=variant, precision=precision, return_p=True, panel=panel, Q=Q)
         if p.csr is not None:
             return amgs.qr_csr(torch.from_numpy(p.csr.row_ptr).to(DEV),
                                torch.from_numpy(p.csr.col_idx).to(DEV),
