@@ -704,11 +704,14 @@ def main():
     ap.add_argument("--reorth", type=int, nargs="?", const=1, default=0, choices=[0, 1, 2],
                     help="second pass in the headline run: 1 per column, 2 blocked "
                          "(two-level schedule only)")
-    ap.add_argument("--panel", type=int, default=8, choices=[0, 4, 8, 16],
+    ap.add_argument("--panel", type=int, default=None, choices=[0, 4, 8, 16],
                     help="schedule of the headline run: 0 column order, 4 panels of four, "
                          "8 panels of eight taken apart as panels of four, 16 panels of "
-                         "sixteen taken apart as panels of eight (naive and HA)")
+                         "sixteen taken apart as panels of eight (naive and HA; the "
+                         "default for them, 8 for HP)")
     args = ap.parse_args()
+    if args.panel is None:
+        args.panel = 8 if args.variant == "hp" or args.reorth == 2 else 16
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported here "
               "(the design notes describe how the path would shard).", file=sys.stderr)

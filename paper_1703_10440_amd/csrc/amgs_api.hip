@@ -119,7 +119,9 @@ Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_g
     const bool two = panel == PANEL_B1 || panel == PANEL_B2;
     const size_t pb = panel == PANEL_B2 ? PANEL_B2 : two ? PANEL_B1 : PANEL_B;
     // the outer block sweep may use more row chunks than the panel sweeps
-    const int64_t g_b = two ? bsweep_chunks(m, w) : 0;
+    // (its partials are stored in XCD order: the chunk count rounded up to
+    // a multiple of 8 entries each)
+    const int64_t g_b = two ? (bsweep_chunks(m, w) + 7) / 8 * 8 : 0;
     const int64_t g_w = g_b > g_p ? g_b : g_p;
     L.wpart = panel ? take((size_t)n * pb * g_w * 8) : off;
     L.lpart = panel ? take((size_t)PANEL_B * PANEL_B * g_p * 8) : off;

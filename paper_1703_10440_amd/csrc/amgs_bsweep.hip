@@ -37,7 +37,7 @@ __device__ __forceinline__ int bs_act(int i)
 }
 
 // The W partials of one 16-column tile starting at ct (nc columns): the
-// waves' entries added in wave order.
+// waves' entries added in wave order, stored in XCD order (xcd_pos).
 template <typename T, int BB>
 __device__ __forceinline__ void bs_wpart(const T (*red)[16 * BB], int64_t ct, int nc,
                                          int nd, const BSweepArgs &a)
@@ -49,14 +49,15 @@ __device__ __forceinline__ void bs_wpart(const T (*red)[16 * BB], int64_t ct, in
             T s = red[0][tid];
 #pragma unroll
             for (int w = 1; w < 256 / WAVE; ++w) s += red[w][tid];
-            ((T *)a.part)[((ct + cl) * BB + d) * a.g + blockIdx.x] = s;
+            ((T *)a.part)[((ct + cl) * BB + d) * xcd_span(a.g) + xcd_pos(blockIdx.x, a.g)] = s;
         }
     }
 }
 
 // BB: the block width, 8 (two-level schedule) or 16 (three levels: all 16
-// rows of W in use, the update four 16x16x4 steps).
-template <typename T, bool NTS, int BB>
+// rows of W in use, the update four 16x16x4 steps).  DOTS = false: the
+// update alone (no dot columns), without the P_I operand and the W work.
+template <typename T, bool NTS, int BB, bool DOTS>
 __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
 {
     typedef typename Mfma<T>::acc_t acc_t;
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
     // rows (entry [i, k] = p_{d0+i}^T q_{d0+k}, B operand q_{d0+l%16} at
     // matrix row 4 (l/16) + v), added over the waves after the columns; its
     // strictly lower part is the L of the block solve.
-    const bool own_l = blockIdx.y == 0 && nd > 1;
+    const bool own_l = DOTS && blockIdx.y == 0 && nd > 1;
     T qa[ST][KS], pa[ST][4];
     acc_t lw = {0, 0, 0, 0};
     // P_I first, then (grid row 0) Q_I for L, then the pending Q_{I-1},
@@ -97,18 +98,22 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
     T vp[BB], vq[BB], vk[BB];
 #pragma unroll
     for (int c = 0; c < BB; ++c) {
-        vp[c] = ld_fix(P, myrow + (a.d0 + c) * a.ldp, 0, rin && c < nd);
-        vq[c] = ld_fix((const T *)Q, myrow + (a.d0 + c) * ldq, 0, own_l && rin && c < nd);
+        if constexpr (DOTS) {
+            vp[c] = ld_fix(P, myrow + (a.d0 + c) * a.ldp, 0, rin && c < nd);
+            vq[c] = ld_fix((const T *)Q, myrow + (a.d0 + c) * ldq, 0, own_l && rin && c < nd);
+        }
         vk[c] = ld_fix((const T *)Q, myrow + (a.k0 + c) * ldq, 0, rin && c < kw);
     }
     pin();
+    if constexpr (DOTS) {
 #pragma unroll
-    for (int c = 0; c < BB; ++c) tl[c][lane] = pick(vp[c], rin && c < nd);
-    __syncthreads();
+        for (int c = 0; c < BB; ++c) tl[c][lane] = pick(vp[c], rin && c < nd);
+        __syncthreads();
 #pragma unroll
-    for (int st = 0; st < ST; ++st)
+        for (int st = 0; st < ST; ++st)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) pa[st][v] = jl < BB ? tl[jl][st * 16 + 4 * g4 + v] : (T)0;
+            for (int v = 0; v < 4; ++v) pa[st][v] = jl < BB ? tl[jl][st * 16 + 4 * g4 + v] : (T)0;
+    }
     if (own_l) {
         __syncthreads();
 #pragma unroll
@@ -120,7 +125,7 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
             for (int v = 0; v < 4; ++v)
                 lw = Mfma<T>::op(pa[st][v], jl < BB ? tl[jl][st * 16 + 4 * g4 + v] : (T)0, lw);
     }
-    __syncthreads();
+    if constexpr (DOTS) __syncthreads();
 #pragma unroll
     for (int c = 0; c < BB; ++c) tl[c][lane] = pick(vk[c], rin && c < kw);
     __syncthreads();
@@ -149,7 +154,7 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
         }
         pin();
         __syncthreads();   // the previous block's LDS reads and W entries are done
-        if (ct > cA) bs_wpart<T, BB>(red, ct - 16, 16, nd, a);
+        if (DOTS && ct > cA) bs_wpart<T, BB>(red, ct - 16, 16, nd, a);
 #pragma unroll
         for (int c = 0; c < 16; ++c) tl[c][lane] = zl[c];
         __syncthreads();
@@ -169,8 +174,10 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) tl[jl][st * 16 + 4 * g4 + v] = (T)z[v];
             }
+            if constexpr (DOTS) {
 #pragma unroll
-            for (int v = 0; v < 4; ++v) w = Mfma<T>::op(pa[st][v], (T)z[v], w);
+                for (int v = 0; v < 4; ++v) w = Mfma<T>::op(pa[st][v], (T)z[v], w);
+            }
         }
         if (kw > 0) {
             __syncthreads();
@@ -180,12 +187,15 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
         }
         // W[i, col] for i = Mfma<T>::row(lane, v) < BB, added over the
         // waves at the next tile (or below)
+        if constexpr (DOTS) {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            const int i = Mfma<T>::row(lane, v);
-            if (i < BB) red[wave][jl * BB + i] = (T)w[v];
+            for (int v = 0; v < 4; ++v) {
+                const int i = Mfma<T>::row(lane, v);
+                if (i < BB) red[wave][jl * BB + i] = (T)w[v];
+            }
         }
     }
+    if (!DOTS) return;
     __syncthreads();
     if (cA < cB) {
         const int64_t last = cA + (cB - 1 - cA) / 16 * 16;
@@ -205,7 +215,7 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
             T s = red[0][idx];
 #pragma unroll
             for (int w = 1; w < 256 / WAVE; ++w) s += red[w][idx];
-            ((T *)a.lpart)[(int64_t)idx * a.g + blockIdx.x] = s;
+            ((T *)a.lpart)[(int64_t)idx * xcd_span(a.g) + xcd_pos(blockIdx.x, a.g)] = s;
         }
     }
 }
@@ -245,13 +255,18 @@ void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0, int64_t d1,
     a.cpw = cpw;
     const dim3 grid((unsigned)c.g_b, (unsigned)gy), block(256);
     const bool nts = (double)ncols * (double)c.m * sizeof(T) > SWEEP_NT_BYTES;
-#define AMGS_BS(NT_, BB_)                                                                         \
+#define AMGS_BS1(NT_, BB_, D_)                                                                    \
     do {                                                                                          \
         if (c.ev_start)                                                                           \
-            hipExtLaunchKernelGGL((k_bsweep<T, NT_, BB_>), grid, block, 0, c.stream, c.ev_start,  \
-                                  c.ev_stop, 0, a);                                               \
+            hipExtLaunchKernelGGL((k_bsweep<T, NT_, BB_, D_>), grid, block, 0, c.stream,          \
+                                  c.ev_start, c.ev_stop, 0, a);                                   \
         else                                                                                      \
-            hipLaunchKernelGGL((k_bsweep<T, NT_, BB_>), grid, block, 0, c.stream, a);             \
+            hipLaunchKernelGGL((k_bsweep<T, NT_, BB_, D_>), grid, block, 0, c.stream, a);         \
+    } while (0)
+#define AMGS_BS(NT_, BB_)                                                                         \
+    do {                                                                                          \
+        if (a.nd > 0) AMGS_BS1(NT_, BB_, true);                                                   \
+        else AMGS_BS1(NT_, BB_, false);                                                           \
     } while (0)
     if (bb == PANEL_B2) {
         if (nts) AMGS_BS(true, PANEL_B2);
@@ -261,6 +276,7 @@ void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0, int64_t d1,
         else AMGS_BS(false, PANEL_B1);
     }
 #undef AMGS_BS
+#undef AMGS_BS1
 }
 
 

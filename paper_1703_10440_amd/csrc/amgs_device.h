@@ -113,6 +113,39 @@ __device__ __forceinline__ A wave_reduce_seq(const A *__restrict__ v, int64_t N)
     return wave_sum(s);
 }
 
+// Partials of g workgroups stored in XCD order: workgroups are dispatched
+// to the 8 XCDs in turn, so workgroup x is stored at xcd_pos(x) = (x % 8) g8
+// + x / 8 (g8 = ceil(g / 8)), and the partials that share a cache line come
+// from one XCD's L2 (written there as whole sectors, not as words from
+// eight caches).  An array of such partials spans 8 g8 entries.
+__host__ __device__ __forceinline__ int64_t xcd_span(int64_t g) { return 8 * ((g + 7) / 8); }
+__device__ __forceinline__ int64_t xcd_pos(int64_t x, int64_t g)
+{
+    return (x & 7) * ((g + 7) / 8) + (x >> 3);
+}
+
+// The reduction of g such partials: XCD segment by segment, each as in
+// wave_reduce_seq (the unused tail entries of a segment are skipped).
+template <typename A>
+__device__ __forceinline__ A wave_reduce_xcd(const A *__restrict__ v, int64_t g)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t g8 = (g + 7) / 8;
+    A s = 0;
+    for (int x = 0; x < 8; ++x) {
+        const A *__restrict__ seg = v + x * g8;
+        const int64_t n = (g - x + 7) / 8;   // workgroups x, x + 8, ... below g
+        for (int64_t i = lane; i < n; i += 8 * WAVE) {
+            A t[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) t[k] = i + k * WAVE < n ? seg[i + k * WAVE] : (A)0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) s += t[k];
+        }
+    }
+    return wave_sum(s);
+}
+
 // wave_reduce_seq computed once per workgroup (by wave 0) and broadcast
 // through one LDS slot; every thread must call it.
 template <typename A>

@@ -328,7 +328,7 @@ __global__ __launch_bounds__(256) void k_pcol_blk(RowArgs a, int64_t k0, int64_t
 // L = strict_lower(P_I^T Q_I) of an outer panel of b columns, each entry
 // re-reduced from the partials k_bsweep wrote (fixed order), one wave per
 // entry, into lred[i * bs + k] in binary64 (bs: the block width of the
-// block sweep that wrote the partials, which is also their stride).
+// block sweep that wrote the partials, stored in XCD order).
 template <typename T>
 __global__ __launch_bounds__(WAVE) void k_lfin(const T *__restrict__ lpart, int64_t g, int b,
                                                int bs, double *__restrict__ lred,
@@ -341,12 +341,12 @@ __global__ __launch_bounds__(WAVE) void k_lfin(const T *__restrict__ lpart, int6
         ++i;
     }
     if (i >= b) return;
-    const T v = wave_reduce_seq(lpart + (int64_t)(i * bs + q) * g, g);
+    const T v = wave_reduce_xcd(lpart + (int64_t)(i * bs + q) * xcd_span(g), g);
     if (threadIdx.x == 0) lred[i * bs + q] = (double)v;
 }
 
 // r_{[s, s+b), c} for every later column c = c0 + blockIdx.x: the block dots
-// W_c re-reduced from their partials (stride B per column), then
+// W_c re-reduced from their partials (stride B per column, XCD order), then
 // (I + L) r = W solved by forward substitution in binary64 with the reduced
 // L of k_lfin, and written to R.
 template <typename T, int B>
@@ -361,7 +361,7 @@ __global__ __launch_bounds__(B * WAVE) void k_pfin2(int64_t s, int b, int64_t c0
     const int64_t c = c0 + blockIdx.x;
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
     if (wave < b) {
-        const T v = wave_reduce_seq(wpart + (c * B + wave) * g, g);
+        const T v = wave_reduce_xcd(wpart + (c * B + wave) * xcd_span(g), g);
         if (lane == 0) wv[wave] = (double)v;
     }
     __syncthreads();
@@ -461,15 +461,15 @@ __global__ __launch_bounds__(256) void k_rb_dots(RbArgs a)
                     double sum = red[0][tid];
 #pragma unroll
                     for (int wv = 1; wv < 256 / WAVE; ++wv) sum += red[wv][tid];
-                    ((double *)a.part)[((ig + il) * BB + c) * a.g + blockIdx.x] = sum;
+                    ((double *)a.part)[((ig + il) * BB + c) * xcd_span(a.g) + xcd_pos(blockIdx.x, a.g)] = sum;
                 }
             }
         }
     }
 }
 
-// s_ic from its partials (one wave each, fixed order), kept for the update
-// and added into R.
+// s_ic from its partials (one wave each, fixed order; stored in XCD order),
+// kept for the update and added into R.
 __global__ __launch_bounds__(256) void k_rb_fin(RbArgs a, double *__restrict__ R, int64_t ldr)
 {
     if (*a.info) return;
@@ -477,7 +477,7 @@ __global__ __launch_bounds__(256) void k_rb_fin(RbArgs a, double *__restrict__ R
     const int nz = (int)a.nz;
     if (idx >= a.s * nz) return;
     const int64_t i = idx / nz, c = idx - i * nz;
-    const double v = wave_reduce_seq((const double *)a.part + (i * PANEL_B1 + c) * a.g, a.g);
+    const double v = wave_reduce_xcd((const double *)a.part + (i * PANEL_B1 + c) * xcd_span(a.g), a.g);
     if ((threadIdx.x & (WAVE - 1)) == 0) {
         ((double *)a.S)[i * PANEL_B1 + c] = v;
         R[i + (a.s + c) * ldr] += v;
