@@ -20,7 +20,7 @@ DEV = torch.device("cuda:0")
 
 
 @pytest.mark.parametrize("raw", [False, True], ids=["torch_stream", "raw_handle"])
-@pytest.mark.parametrize("variant,panel", [("ha", 0), ("hp", 0), ("ha", 4)])
+@pytest.mark.parametrize("variant,panel", [("ha", 0), ("hp", 0), ("ha", 4), ("ha", 16)])
 def test_side_stream_single(variant, panel, raw):
     p = inputs.laplacian_graded_problem(N=24, n=12, decades=3.0, seed=31)
     print(f"[gpu] side stream {variant} panel={panel} raw={raw}", flush=True)
