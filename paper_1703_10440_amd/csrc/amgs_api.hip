@@ -318,9 +318,12 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
     st = amgs_stats_t{};
     // two levels: the later columns' first read is in the block sweep after
     // the second eight-panel, which takes them from Z (from_z below), so only
-    // the first two eight-panels are copied
+    // the first two eight-panels are copied; three levels: the second
+    // sixteen-panel's columns are first read by the update-only sweep before
+    // it, and the later ones by the sweep after it, both from Z, so only the
+    // first sixteen-panel is copied
     {
-        const int64_t keep = c.panel == PANEL_B2 ? 2 * PANEL_B2 : c.panel == PANEL_B1 ? 2 * PANEL_B1 : c.n;
+        const int64_t keep = c.panel == PANEL_B2 ? PANEL_B2 : c.panel == PANEL_B1 ? 2 * PANEL_B1 : c.n;
         launch_init<T>(c, c.Z == c.Q ? 0 : c.n > keep ? keep : c.n);
     }
     st.kernel_launches++;
@@ -375,7 +378,9 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
         const int64_t S16 = three ? S / B2 * B2 : S;
         const int64_t E16 = three ? (S16 + B2 < c.n ? S16 + B2 : c.n) : E;
         if (three && S == S16 && S16 > 0) {
-            profiled(false, [&] { launch_bsweep<T>(c, S16 - B2, S16, S16, S16, S16, E16, false, PANEL_B2); });
+            profiled(false, [&] {
+                launch_bsweep<T>(c, S16 - B2, S16, S16, S16, S16, E16, S16 < 2 * B2, PANEL_B2);
+            });
             st.kernel_launches++;
             st.sweep_launches++;
             st.sweep_bytes += ((double)(E16 - S16) * 2.0 + (double)B2) * (double)c.m * w;

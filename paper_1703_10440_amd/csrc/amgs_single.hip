@@ -228,7 +228,7 @@ __global__ __launch_bounds__(MV_TILE) void k_csr_to_ell(int64_t m, int32_t K,
 // RPT rows per thread: the thread's rows in RPT consecutive grid-stride
 // tiles are requested together (more loads in flight per wave).  D16: the
 // columns come from the 16-bit offsets.
-template <typename T, int SRC, bool RR, int RPT, bool D16>
+template <typename T, int SRC, bool RR, int RPT, bool D16, int EK>
 __device__ __forceinline__ void csr_mv_ell_body(const CsrMvArgs &a)
 {
     __shared__ double lds[MV_TILE / WAVE];
@@ -261,8 +261,8 @@ __device__ __forceinline__ void csr_mv_ell_body(const CsrMvArgs &a)
     for (int64_t row0 = (int64_t)blockIdx.x * MV_TILE; row0 < m; row0 += RPT * stride) {
         // everything that does not depend on the coefficient is requested
         // first: the rows' entries and their own z (and q_{j-1})
-        int32_t col[RPT][ELL_K];
-        T av[RPT][ELL_K];
+        int32_t col[RPT][EK];
+        T av[RPT][EK];
         T own_s[RPT], own_q[RPT];
         int lng[RPT];
         int64_t rowc[RPT];
@@ -273,7 +273,7 @@ __device__ __forceinline__ void csr_mv_ell_body(const CsrMvArgs &a)
             rowc[u] = row < m ? row : m - 1;
             lng[u] = a.tile_long[(t0 < m ? t0 : m - 1) / MV_TILE] & -(int)(t0 < m);
 #pragma unroll
-            for (int k = 0; k < ELL_K; ++k) {
+            for (int k = 0; k < EK; ++k) {
                 const int64_t kc = k < K ? k : K - 1;
                 // (a 16-bit offset is decoded after pin() below)
                 col[u][k] = D16 ? (int32_t)ed16[kc * m + rowc[u]] : ecol[kc * m + rowc[u]];
@@ -290,7 +290,7 @@ __device__ __forceinline__ void csr_mv_ell_body(const CsrMvArgs &a)
 #pragma unroll
         for (int u = 0; u < RPT; ++u)
 #pragma unroll
-            for (int k = 0; k < ELL_K; ++k) {
+            for (int k = 0; k < EK; ++k) {
                 int32_t cv = col[u][k];
                 if (D16) cv = cv == ELL_PAD ? -1 : (int32_t)rowc[u] + cv;
                 col[u][k] = cv | -(int32_t)(k >= K);
@@ -324,11 +324,11 @@ __device__ __forceinline__ void csr_mv_ell_body(const CsrMvArgs &a)
         };
         // every gather (with q_{j-1} at the same rows) is issued before any
         // is used
-        T xv[RPT][ELL_K], xq[SRC == SRC_UPD ? RPT : 1][ELL_K];
+        T xv[RPT][EK], xq[SRC == SRC_UPD ? RPT : 1][EK];
 #pragma unroll
         for (int u = 0; u < RPT; ++u)
 #pragma unroll
-            for (int k = 0; k < ELL_K; ++k) {
+            for (int k = 0; k < EK; ++k) {
                 const int32_t c = col[u][k];
                 const int64_t l = c >= 0 ? (int64_t)c : rowc[u];
                 xv[u][k] = src[l];
@@ -338,7 +338,7 @@ __device__ __forceinline__ void csr_mv_ell_body(const CsrMvArgs &a)
 #pragma unroll
         for (int u = 0; u < RPT; ++u)
 #pragma unroll
-            for (int k = 0; k < ELL_K; ++k) {
+            for (int k = 0; k < EK; ++k) {
                 if (SRC == SRC_UPD)
                     xv[u][k] = with_upd ? upd(xv[u][k], r, xq[SRC == SRC_UPD ? u : 0][k]) : xv[u][k];
                 if (SRC == SRC_DIV) xv[u][k] = scale_div(xv[u][k], rjj);
@@ -351,7 +351,7 @@ __device__ __forceinline__ void csr_mv_ell_body(const CsrMvArgs &a)
             // multiplied by zero
             T s = 0;
 #pragma unroll
-            for (int k = 0; k < ELL_K; ++k) {
+            for (int k = 0; k < EK; ++k) {
                 const T t = s + av[u][k] * xv[u][k];
                 s = col[u][k] >= 0 ? t : s;
             }
@@ -395,12 +395,14 @@ __device__ __forceinline__ void csr_mv_ell_body(const CsrMvArgs &a)
 
 // The padded-copy MV with the column format of this call's copy: the
 // 16-bit offsets unless some offset did not fit (a wave-uniform test, once).
-template <typename T, int SRC, bool RR, int RPT>
+// EK: the slots a thread holds per row, ELL_K, or 7 when the copy has
+// exactly seven (7-point stencils), so no slot is loaded twice.
+template <typename T, int SRC, bool RR, int RPT, int EK>
 __global__ __launch_bounds__(MV_TILE) void k_csr_mv_ell(CsrMvArgs a)
 {
     if (*a.info) return;
-    if (*a.ell_wide) csr_mv_ell_body<T, SRC, RR, RPT, false>(a);
-    else csr_mv_ell_body<T, SRC, RR, RPT, true>(a);
+    if (*a.ell_wide) csr_mv_ell_body<T, SRC, RR, RPT, false, EK>(a);
+    else csr_mv_ell_body<T, SRC, RR, RPT, true, EK>(a);
 }
 
 // ----------------------------------------------------- dense MV (column kernel)
@@ -1177,10 +1179,13 @@ static void launch_csr_mv_L(const Ctx &c, CsrMvArgs &a)
     switch (c.geo.lanes == 0 && c.ell_k == 0 ? 1 : c.geo.lanes) {
     case 0:
         // two rows per thread once every workgroup has two tiles or more
-        if (c.m > 2 * (int64_t)c.geo.g_csr * MV_TILE - MV_TILE)
-            launch_k(c, k_csr_mv_ell<T, SRC, RR, 2>, grid, dim3(MV_TILE), a);
-        else
-            launch_k(c, k_csr_mv_ell<T, SRC, RR, 1>, grid, dim3(MV_TILE), a);
+        if (c.m > 2 * (int64_t)c.geo.g_csr * MV_TILE - MV_TILE) {
+            if (c.ell_k == 7) launch_k(c, k_csr_mv_ell<T, SRC, RR, 2, 7>, grid, dim3(MV_TILE), a);
+            else launch_k(c, k_csr_mv_ell<T, SRC, RR, 2, ELL_K>, grid, dim3(MV_TILE), a);
+        } else {
+            if (c.ell_k == 7) launch_k(c, k_csr_mv_ell<T, SRC, RR, 1, 7>, grid, dim3(MV_TILE), a);
+            else launch_k(c, k_csr_mv_ell<T, SRC, RR, 1, ELL_K>, grid, dim3(MV_TILE), a);
+        }
         break;
     case 1: launch_k(c, k_csr_mv<T, 1, SRC, RR>, grid, block, a); break;
     case 2: launch_k(c, k_csr_mv<T, 2, SRC, RR>, grid, block, a); break;

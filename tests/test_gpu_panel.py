@@ -343,12 +343,14 @@ WIDE = [inputs.random_csr_problem(3001, 45, 40, seed=17),
                          ids=["8-" + SMALL[1].name, "8-" + SMALL[3].name, "16-" + WIDE[0].name,
                               "16-" + WIDE[1].name])
 def test_two_level_working_copy(case, variant, precision):
-    """Two- and three-level schedules: only the first two eight-panels (two
-    sixteen-panels) are copied from Z before the call's work, and the block
-    sweep after the second one reads the later columns from Z.  Out of place,
-    Z must come back untouched; in place (Q aliases Z) the result must equal
-    the out-of-place one bit for bit.  Every problem has n > 2 x the panel
-    width, so the later columns take the Z path."""
+    """Two- and three-level schedules: only the first two eight-panels (the
+    first sixteen-panel) are copied from Z before the call's work; the block
+    sweep after the second eight-panel reads the later columns from Z (three
+    levels: the update-only sweep before the second sixteen-panel reads its
+    columns from Z, the sweep after it the later ones).  Out of place, Z must
+    come back untouched; in place (Q aliases Z) the result must equal the
+    out-of-place one bit for bit.  Every problem has n > 2 x the panel width,
+    so the later columns take the Z path."""
     panel, pi = case
     need(variant, panel)
     p = SMALL[pi] if panel == 8 else WIDE[pi]
