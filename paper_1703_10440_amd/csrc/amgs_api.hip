@@ -78,7 +78,7 @@ struct ProfScope {
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-    size_t part, s_part, rr_part, S, zt, xv, X, P, wpart, lpart, lpart8, lred, rb_part, rb_s,
+    size_t part, s_part, rr_part, S, zt, xv, X, P, wpart, lpart, lpart8, wred, rb_part, rb_s,
         ell_col, ell_val, tile_long, ell_d16, ell_wide;
     size_t base;    // bytes without the padded copy of A
     size_t total;   // bytes with it (the size the query reports)
@@ -126,7 +126,7 @@ Layout layout(int64_t m, int64_t n, const Geo &g, int variant, size_t w, int P_g
     L.wpart = panel ? take((size_t)n * pb * g_w * 8) : off;
     L.lpart = panel ? take((size_t)PANEL_B * PANEL_B * g_p * 8) : off;
     L.lpart8 = two ? take((size_t)pb * pb * g_b * 8) : off;
-    L.lred = two ? take((size_t)pb * pb * 8) : off;
+    L.wred = two ? take((size_t)(n * pb + pb * pb) * 8 * 8) : off;
     // blocked second pass: coefficient partials and coefficients of an outer panel
     const bool rb = two && reorth == 2;
     L.rb_part = rb ? take((size_t)n * PANEL_B1 * g_b * 8) : off;
@@ -306,7 +306,7 @@ double psweep_bytes(int64_t m, size_t w, int64_t ncols, int64_t kw, int64_t bd, 
 // with the inner blocks acting only on the columns of the same outer panel;
 // after an outer panel's last column, k_bsweep applies the previous outer
 // panel to every later column and forms the dots with this outer panel's p
-// vectors, and k_lfin + k_pfin2 solve for the coefficients.  A column thus
+// vectors, and k_wred + k_pfin2 solve for the coefficients.  A column thus
 // receives the blocks of the earlier outer panels, then the block of the
 // earlier inner panel of its own outer panel, then the column steps of its
 // inner panel (the order of the two-level panel reading of the method).
@@ -517,7 +517,6 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
                         // the first 8-panel of a 16-panel: its block's dots
                         // for the other 8-panel only
                         profiled(false, [&] { launch_bsweep<T>(c, S, S, S, E, E, E16, false, PANEL_B1); });
-                        launch_lfin<T>(c, S, E, PANEL_B1);
                         launch_pfin2<T>(c, S, E, E, E16, PANEL_B1);
                         st.kernel_launches += 3;
                         st.sweep_launches++;
@@ -539,7 +538,6 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
                         st.sweep_bytes += bb;
                         st.block_sweep_launches++;
                         st.block_sweep_bytes += bb;
-                        launch_lfin<T>(c, S16, E16, PANEL_B2);
                         launch_pfin2<T>(c, S16, E16, E16, c.n, PANEL_B2);
                         st.kernel_launches += 2;
                     }
@@ -557,7 +555,6 @@ amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
                         st.sweep_bytes += bb;
                         st.block_sweep_launches++;
                         st.block_sweep_bytes += bb;
-                        launch_lfin<T>(c, S, E);
                         launch_pfin2<T>(c, S, E, E, c.n);
                         st.kernel_launches += 2;
                     } else {
@@ -690,7 +687,7 @@ amgs_status_t qr_common(amgs_handle *h, Ctx &c, amgs_variant_t v, amgs_precision
         c.wpart = base + L.wpart;
         c.lpart = base + L.lpart;
         c.lpart8 = base + L.lpart8;
-        c.lred = (double *)(base + L.lred);
+        c.wred = base + L.wred;
         c.g_b = bsweep_chunks(c.m, w);
         c.reorth_blk = reorth_mode == 2;
         c.rb_part = base + L.rb_part;

@@ -237,7 +237,7 @@ struct Ctx {
     // P_I^T Q_I [PANEL_B1][PANEL_B1][g_b], and the reduced L [PANEL_B1][PANEL_B1]
     int64_t g_b;
     void *lpart8;
-    double *lred;
+    void *wred;   // first-stage sums of the block-dot and L partials (8 per row)
     int64_t x_from;   // HP column kernel: first recurrence term it applies (-1: column schedule)
     int64_t n_pub;    // column kernels publish r_{j-1,c} for c < n_pub
     int cgs;          // classical Gram-Schmidt (no pending MGS update in k_reorth_a)
@@ -285,7 +285,6 @@ template <typename T> void launch_pfin(const Ctx &c, int64_t s, int64_t e, int64
 template <typename T> void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0,
                                          int64_t d1, int64_t c0, int64_t c1, bool from_z = false,
                                          int bb = PANEL_B1);
-template <typename T> void launch_lfin(const Ctx &c, int64_t s, int64_t e, int bb = PANEL_B1);
 template <typename T> void launch_pfin2(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1,
                                         int bb = PANEL_B1);
 int64_t bsweep_chunks(int64_t m, size_t w);

@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_psweep(PSweepArgs a)
 // workgroup obtains the same L), then (I + L) r = W is solved by forward
 // substitution in binary64 and r is written to R[s.., c].
 template <typename T>
-__global__ __launch_bounds__(256) void k_pfin(int64_t s, int64_t e, const T *__restrict__ wpart,
+__global__ __launch_bounds__(16 * WAVE) void k_pfin(int64_t s, int64_t e, const T *__restrict__ wpart,
                                               const T *__restrict__ lpart, int64_t g,
                                               double *__restrict__ R, int64_t ldr,
                                               const int32_t *info)
@@ -228,8 +228,9 @@ __global__ __launch_bounds__(256) void k_pfin(int64_t s, int64_t e, const T *__r
     const int64_t c = e + blockIdx.x;
     const int b = (int)(e - s);
     const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
+    // one wave per item (at most 4 + 6), all of them at once
     const int nitems = b + b * (b - 1) / 2;
-    for (int it = wave; it < nitems; it += 256 / WAVE) {
+    for (int it = wave; it < nitems; it += 16) {
         const T *src;
         int slot;
         if (it < b) {
@@ -325,47 +326,73 @@ __global__ __launch_bounds__(256) void k_pcol_blk(RowArgs a, int64_t k0, int64_t
     }
 }
 
-// L = strict_lower(P_I^T Q_I) of an outer panel of b columns, each entry
-// re-reduced from the partials k_bsweep wrote (fixed order), one wave per
-// entry, into lred[i * bs + k] in binary64 (bs: the block width of the
-// block sweep that wrote the partials, stored in XCD order).
-template <typename T>
-__global__ __launch_bounds__(WAVE) void k_lfin(const T *__restrict__ lpart, int64_t g, int b,
-                                               int bs, double *__restrict__ lred,
-                                               const int32_t *info)
+// The coefficients of a finished block [s, s + b) for the later columns
+// [c0, c1) come from the partials k_bsweep wrote (XCD order, one entry per
+// row chunk) in two stages.  Stage one, k_wred: every partial row -- the
+// dots W_c (row (c - c0) B + d) and then the entries of
+// L = strict_lower(P_I^T Q_I) (row nW + t for the t-th entry (i, k), k < i,
+// in row-major order) -- is reduced per XCD segment x, one wave per row and
+// segment, into out[row * 8 + x]: the whole GPU takes part, not one
+// workgroup per later column.
+template <typename T, int B>
+__global__ __launch_bounds__(16 * WAVE) void k_wred(const T *__restrict__ wpart,
+                                                    const T *__restrict__ lpart, int64_t g,
+                                                    int64_t c0, int64_t nW, int64_t nL,
+                                                    T *__restrict__ out, const int32_t *info)
 {
     if (*info) return;
-    int q = blockIdx.x, i = 1;
-    while (q >= i) {
-        q -= i;
-        ++i;
+    const int64_t r = (int64_t)blockIdx.x * 16 + threadIdx.x / WAVE;
+    if (r >= nW + nL) return;
+    const int x = blockIdx.y;
+    const int64_t span = xcd_span(g), g8 = (g + 7) / 8;
+    const T *__restrict__ row;
+    if (r < nW) {
+        row = wpart + ((c0 + r / B) * B + r % B) * span;
+    } else {
+        int q = (int)(r - nW), i = 1;
+        while (q >= i) {
+            q -= i;
+            ++i;
+        }
+        row = lpart + (int64_t)(i * B + q) * span;
     }
-    if (i >= b) return;
-    const T v = wave_reduce_xcd(lpart + (int64_t)(i * bs + q) * xcd_span(g), g);
-    if (threadIdx.x == 0) lred[i * bs + q] = (double)v;
+    const T v = wave_reduce_seq(row + x * g8, (g - x + 7) / 8);
+    if ((threadIdx.x & (WAVE - 1)) == 0) out[r * 8 + x] = v;
 }
 
-// r_{[s, s+b), c} for every later column c = c0 + blockIdx.x: the block dots
-// W_c re-reduced from their partials (stride B per column, XCD order), then
-// (I + L) r = W solved by forward substitution in binary64 with the reduced
-// L of k_lfin, and written to R.
+// Stage two: r_{[s, s+b), c} for the later column c = c0 + blockIdx.x.
+// W_c and L are the eight segment sums of their rows, added in segment order
+// (every workgroup forms the same L), then (I + L) r = W is solved by
+// forward substitution in binary64 and r is written to R.
 template <typename T, int B>
-__global__ __launch_bounds__(B * WAVE) void k_pfin2(int64_t s, int b, int64_t c0,
-                                               const T *__restrict__ wpart, int64_t g,
-                                               const double *__restrict__ lred,
+__global__ __launch_bounds__(256) void k_pfin2(int64_t s, int b, int64_t c0,
+                                               const T *__restrict__ wred, int64_t nW,
                                                double *__restrict__ R, int64_t ldr,
                                                const int32_t *info)
 {
     __shared__ double wv[B];
+    __shared__ double lv[B * B];
     if (*info) return;
     const int64_t c = c0 + blockIdx.x;
-    const int wave = threadIdx.x / WAVE, lane = threadIdx.x & (WAVE - 1);
-    if (wave < b) {
-        const T v = wave_reduce_xcd(wpart + (c * B + wave) * xcd_span(g), g);
-        if (lane == 0) wv[wave] = (double)v;
+    const int tid = threadIdx.x;
+    auto seg_sum = [&](int64_t row) {
+        T v = 0;
+#pragma unroll
+        for (int x = 0; x < 8; ++x) v += wred[row * 8 + x];
+        return (double)v;
+    };
+    if (tid < b) wv[tid] = seg_sum((int64_t)blockIdx.x * B + tid);
+    const int nl = b * (b - 1) / 2;
+    for (int t = tid; t < nl; t += 256) {
+        int q = t, i = 1;
+        while (q >= i) {
+            q -= i;
+            ++i;
+        }
+        lv[i * B + q] = seg_sum(nW + t);
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         double r[B];
 #pragma unroll
         for (int i = 0; i < B; ++i) {
@@ -373,7 +400,7 @@ __global__ __launch_bounds__(B * WAVE) void k_pfin2(int64_t s, int b, int64_t c0
                 double t = wv[i];
 #pragma unroll
                 for (int k = 0; k < B; ++k)
-                    if (k < i) t = __builtin_fma(-lred[i * B + k], r[k], t);
+                    if (k < i) t = __builtin_fma(-lv[i * B + k], r[k], t);
                 r[i] = t;
                 R[(s + i) + c * ldr] = t;
             }
@@ -629,32 +656,30 @@ template <typename T>
 void launch_pfin(const Ctx &c, int64_t s, int64_t e, int64_t c1)
 {
     if (e >= c1) return;
-    hipLaunchKernelGGL(k_pfin<T>, dim3((unsigned)(c1 - e)), dim3(256), 0, c.stream, s, e,
+    hipLaunchKernelGGL(k_pfin<T>, dim3((unsigned)(c1 - e)), dim3(16 * WAVE), 0, c.stream, s, e,
                        (const T *)c.wpart, (const T *)c.lpart, c.g_p, c.R, c.ldr, c.info);
 }
 
-template <typename T>
-void launch_lfin(const Ctx &c, int64_t s, int64_t e, int bb)
+// The block's coefficients for the later columns [c0, c1): k_wred, then
+// k_pfin2 (two launches).
+template <typename T, int B>
+static void launch_pfin2_b(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1)
 {
     const int b = (int)(e - s);
-    if (b < 2) return;
-    hipLaunchKernelGGL(k_lfin<T>, dim3((unsigned)(b * (b - 1) / 2)), dim3(WAVE), 0, c.stream,
-                       (const T *)c.lpart8, c.g_b, b, bb, c.lred, c.info);
+    const int64_t nW = (c1 - c0) * B, nL = (int64_t)b * (b - 1) / 2;
+    const dim3 gw((unsigned)((nW + nL + 15) / 16), 8);
+    hipLaunchKernelGGL((k_wred<T, B>), gw, dim3(16 * WAVE), 0, c.stream, (const T *)c.wpart,
+                       (const T *)c.lpart8, c.g_b, c0, nW, nL, (T *)c.wred, c.info);
+    hipLaunchKernelGGL((k_pfin2<T, B>), dim3((unsigned)(c1 - c0)), dim3(256), 0, c.stream, s, b, c0,
+                       (const T *)c.wred, nW, c.R, c.ldr, c.info);
 }
 
-// The outer block's coefficients for the later columns [c0, c1).
 template <typename T>
 void launch_pfin2(const Ctx &c, int64_t s, int64_t e, int64_t c0, int64_t c1, int bb)
 {
     if (c1 <= c0) return;
-    if (bb == PANEL_B2)
-        hipLaunchKernelGGL((k_pfin2<T, PANEL_B2>), dim3((unsigned)(c1 - c0)), dim3(PANEL_B2 * WAVE),
-                           0, c.stream, s, (int)(e - s), c0, (const T *)c.wpart, c.g_b,
-                           (const double *)c.lred, c.R, c.ldr, c.info);
-    else
-        hipLaunchKernelGGL((k_pfin2<T, PANEL_B1>), dim3((unsigned)(c1 - c0)), dim3(PANEL_B1 * WAVE),
-                           0, c.stream, s, (int)(e - s), c0, (const T *)c.wpart, c.g_b,
-                           (const double *)c.lred, c.R, c.ldr, c.info);
+    if (bb == PANEL_B2) launch_pfin2_b<T, PANEL_B2>(c, s, e, c0, c1);
+    else launch_pfin2_b<T, PANEL_B1>(c, s, e, c0, c1);
 }
 
 // The blocked second pass of the outer panel [s, e) against the columns
@@ -708,8 +733,6 @@ template void launch_psweep<double>(const Ctx &, int, int64_t, int64_t, int64_t,
 template void launch_psweep<float>(const Ctx &, int, int64_t, int64_t, int64_t, int64_t, int64_t,
                                    int64_t, int64_t, int64_t);
 template void launch_pfin<double>(const Ctx &, int64_t, int64_t, int64_t);
-template void launch_lfin<double>(const Ctx &, int64_t, int64_t, int);
-template void launch_lfin<float>(const Ctx &, int64_t, int64_t, int);
 template void launch_pfin2<double>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int);
 template void launch_pfin2<float>(const Ctx &, int64_t, int64_t, int64_t, int64_t, int);
 template void launch_rb<double>(const Ctx &, int64_t, int64_t, int);
