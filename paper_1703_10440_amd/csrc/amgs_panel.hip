@@ -245,7 +245,7 @@ __global__ __launch_bounds__(16 * WAVE) void k_pfin(int64_t s, int64_t e, const 
             src = lpart + ((int64_t)i * B + q) * g;
             slot = B + i * B + q;
         }
-        const T v = wave_reduce_seq(src, g);
+        const T v = wave_reduce_seq_deep<16>(src, g);
         if (lane == 0) vals[slot] = v;
     }
     __syncthreads();

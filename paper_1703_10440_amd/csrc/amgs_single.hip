@@ -296,14 +296,16 @@ __device__ __forceinline__ void csr_mv_ell_body(const CsrMvArgs &a)
                 col[u][k] = cv | -(int32_t)(k >= K);
             }
         // the coefficient r_{j-1,j} (or r_jj for the naive second MV) is
-        // re-reduced by wave 0 while those loads are in flight
+        // re-reduced by wave 0 while those loads are in flight (sixteen
+        // partials in flight per lane: the same bits as the other kernels'
+        // reduction of these partials, in half the round trips)
         if (first && (with_upd || SRC == SRC_DIV)) {
             if (tid < WAVE) {
                 if (with_upd) {
-                    const T v = wave_reduce_seq((const T *)a.sp.part + a.j * a.sp.g, a.sp.g);
+                    const T v = wave_reduce_seq_deep<16>((const T *)a.sp.part + a.j * a.sp.g, a.sp.g);
                     if (tid == 0) s_r = v;
                 } else {
-                    const double v = wave_reduce_seq(a.rr_part, a.n_rr);
+                    const double v = wave_reduce_seq_deep<16>(a.rr_part, a.n_rr);
                     if (tid == 0) s_rr = v;
                 }
             }
