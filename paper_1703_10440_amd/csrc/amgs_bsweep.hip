@@ -57,7 +57,9 @@ __device__ __forceinline__ void bs_wpart(const T (*red)[16 * BB], int64_t ct, in
 // BB: the block width, 8 (two-level schedule) or 16 (three levels: all 16
 // rows of W in use, the update four 16x16x4 steps).  DOTS = false: the
 // update alone (no dot columns), without the P_I operand and the W work.
-template <typename T, bool NTS, int BB, bool DOTS>
+// ONE: every workgroup has a single 16-column tile, whose loads are issued
+// together with those of the operands (one memory round trip, not two).
+template <typename T, bool NTS, int BB, bool DOTS, bool ONE>
 __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
 {
     typedef typename Mfma<T>::acc_t acc_t;
@@ -104,6 +106,26 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
         }
         vk[c] = ld_fix((const T *)Q, myrow + (a.k0 + c) * ldq, 0, rin && c < kw);
     }
+    const int64_t cA = a.c0 + (int64_t)blockIdx.y * a.cpw;
+    const int64_t cB = (cA + a.cpw < a.c1) ? cA + a.cpw : a.c1;
+    // the wave's 64 x 16 block of the tile at ct, one contiguous column
+    // access per column, and the B operand of the update,
+    // -r_{k0+4s+l/16, col}, loaded beside it (clamped addresses: no load
+    // waits for the one before it)
+    T zl[16];
+    double rd[KS];
+    auto load_tile = [&](int64_t ct) {
+        const int nc = (int)(cB - ct < 16 ? cB - ct : 16);
+#pragma unroll
+        for (int c = 0; c < 16; ++c)
+            zl[c] = (c < nc && rin) ? ld_stream<NTS>(Zs + (ct + c) * a.ldzs + myrow) : (T)0;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+            const int kk = 4 * s + g4;
+            rd[s] = ld_fix(a.R, (a.k0 + kk) + (ct + jl) * a.ldr, 0, jl < nc && kk < kw);
+        }
+    };
+    if (ONE && cA < cB) load_tile(cA);
     pin();
     if constexpr (DOTS) {
 #pragma unroll
@@ -133,26 +155,13 @@ __global__ __launch_bounds__(256, 4) void k_bsweep(BSweepArgs a)
     for (int st = 0; st < ST; ++st)
 #pragma unroll
         for (int s2 = 0; s2 < KS; ++s2) qa[st][s2] = tl[4 * s2 + g4][st * 16 + bs_act<T>(jl)];
-    const int64_t cA = a.c0 + (int64_t)blockIdx.y * a.cpw;
-    const int64_t cB = (cA + a.cpw < a.c1) ? cA + a.cpw : a.c1;
     for (int64_t ct = cA; ct < cB; ct += 16) {
         const int nc = (int)(cB - ct < 16 ? cB - ct : 16);
-        // the wave's 64 x 16 block, one contiguous column access per column
-        T zl[16];
-#pragma unroll
-        for (int c = 0; c < 16; ++c)
-            zl[c] = (c < nc && rin) ? ld_stream<NTS>(Zs + (ct + c) * a.ldzs + myrow) : (T)0;
-        const int64_t col = ct + jl;
         const bool cin = jl < nc;
-        // B operand of the update, -r_{k0+4s+l/16, col}, loaded beside the
-        // block (clamped addresses: no load waits for the one before it)
-        double rd[KS];
-#pragma unroll
-        for (int s = 0; s < KS; ++s) {
-            const int kk = 4 * s + g4;
-            rd[s] = ld_fix(a.R, (a.k0 + kk) + col * a.ldr, 0, cin && kk < kw);
+        if constexpr (!ONE) {
+            load_tile(ct);
+            pin();
         }
-        pin();
         __syncthreads();   // the previous block's LDS reads and W entries are done
         if (DOTS && ct > cA) bs_wpart<T, BB>(red, ct - 16, 16, nd, a);
 #pragma unroll
@@ -254,19 +263,27 @@ void launch_bsweep(const Ctx &c, int64_t k0, int64_t k1, int64_t d0, int64_t d1,
     }
     a.cpw = cpw;
     const dim3 grid((unsigned)c.g_b, (unsigned)gy), block(256);
+    const bool one = ncols > 0 && cpw == 16;
     const bool nts = (double)ncols * (double)c.m * sizeof(T) > SWEEP_NT_BYTES;
-#define AMGS_BS1(NT_, BB_, D_)                                                                    \
+#define AMGS_BS1(NT_, BB_, D_, O_)                                                                \
     do {                                                                                          \
         if (c.ev_start)                                                                           \
-            hipExtLaunchKernelGGL((k_bsweep<T, NT_, BB_, D_>), grid, block, 0, c.stream,          \
+            hipExtLaunchKernelGGL((k_bsweep<T, NT_, BB_, D_, O_>), grid, block, 0, c.stream,      \
                                   c.ev_start, c.ev_stop, 0, a);                                   \
         else                                                                                      \
-            hipLaunchKernelGGL((k_bsweep<T, NT_, BB_, D_>), grid, block, 0, c.stream, a);         \
+            hipLaunchKernelGGL((k_bsweep<T, NT_, BB_, D_, O_>), grid, block, 0, c.stream, a);     \
     } while (0)
+    // the one-tile instances serve the three-level schedule's short sweeps:
+    // the update-only one (width 16) and the dots-only one (width 8)
 #define AMGS_BS(NT_, BB_)                                                                         \
     do {                                                                                          \
-        if (a.nd > 0) AMGS_BS1(NT_, BB_, true);                                                   \
-        else AMGS_BS1(NT_, BB_, false);                                                           \
+        if (a.nd > 0) {                                                                           \
+            if (BB_ == PANEL_B1 && one) AMGS_BS1(NT_, BB_, true, true);                           \
+            else AMGS_BS1(NT_, BB_, true, false);                                                 \
+        } else {                                                                                  \
+            if (BB_ == PANEL_B2 && one) AMGS_BS1(NT_, BB_, false, true);                          \
+            else AMGS_BS1(NT_, BB_, false, false);                                                \
+        }                                                                                         \
     } while (0)
     if (bb == PANEL_B2) {
         if (nts) AMGS_BS(true, PANEL_B2);
