@@ -1,9 +1,11 @@
-// amgs_bsweep.hip -- the outer block sweep of the two-level panel schedule
-// (opts->panel = 8): after each outer panel of eight columns, one pass over
-// every later column applies the previous outer panel as a block and forms
-// the dots with this outer panel's p vectors, on the matrix cores.  Kept in
-// a file of its own so that its measured HBM traffic can be tied to its
-// source.
+// amgs_bsweep.hip -- the block sweep of the two- and three-level panel
+// schedules (opts->panel = 8 and 16): after each outer panel of eight (or
+// sixteen) columns, one pass over every later column applies the previous
+// outer panel as a block and forms the dots with this outer panel's p
+// vectors, on the matrix cores.  The three-level schedule also runs it as an
+// update-only sweep over a sixteen-panel's own columns and as a dots-only
+// sweep after its first eight-panel.  Kept in a file of its own so that its
+// measured HBM traffic can be tied to its source.
 #include <hip/hip_ext.h>
 
 #include "amgs_device.h"
@@ -11,16 +13,16 @@
 
 namespace amgs {
 
-// ------------------------------------- outer block of the two-level schedule
+// ------------------------------------------------ outer block sweep
 // After an outer panel I = [d0, d0 + nd) is finished, one pass over every
 // later column c (the columns of grid row y) applies the pending outer panel
 // I-1 = [k0, k1) as a block, z_c -= Q_{I-1} r_{I-1,c} (coefficients final in
 // R), and forms the partials of W_c = P_I^T z_c.  Both are small dense
 // contractions and run on the matrix cores, on tiles of 16 rows x 16 later
-// columns: the update is D = Z + Q_{I-1} (-R_{I-1,tile}) (two 16x16x4 steps
-// over the eight pending columns, Z entering as the accumulator), and the
+// columns: the update is D = Z + Q_{I-1} (-R_{I-1,tile}) (BB/4 16x16x4 steps
+// over the BB pending columns, Z entering as the accumulator), and the
 // dots W += P_I^T D take D's registers directly as the B operand (four
-// 16x16x4 steps over the tile's rows, rows 8..15 of W unused).  For that the
+// 16x16x4 steps over the tile's rows; for BB = 8 rows 8..15 of W unused).  For that the
 // tile's rows are permuted so that register v of lane l holds matrix row
 // 4 (l/16) + v of the tile: tile row i of the update's A operand is matrix
 // row bs_act(i).  A wave owns BS_ST consecutive 16-row tiles (64 rows) and
