@@ -239,6 +239,35 @@ def test_panel_breakdown_reports_column(panel):
         assert info == 10
 
 
+@pytest.mark.parametrize("panel", PANELS)
+def test_panel_breakdown_in_a_later_panel(panel):
+    """n = 40: a zero column in the second sixteen-panel (column 21) and a NaN
+    in the third (column 35), so the block sweeps between panels (and, with
+    three levels, the update-only and dots-only sweeps) run before the
+    breakdown.  The reported column is the oracle's; the columns before it
+    agree with both oracles."""
+    g = inputs.rng(18)
+    m, n = 300, 40
+    A = inputs.gram_spd(g, m)
+    Z = np.asfortranarray(g.standard_normal((m, n)))
+    Zc = Z.copy(order="F")
+    Zc[:, 20] = 0.0
+    Zn = Z.copy(order="F")
+    Zn[7, 34] = np.nan
+    for v in variants_for(panel):
+        pz = inputs.Problem("zero40", Zc, dense=A)
+        _, R, _, info, _ = gpu_run(pz, v, panel=panel)
+        want, col = oracle(pz, v, panel=panel), oracle_col(pz, v)
+        assert info == 21 and want.info == 21 and col.info == 21, (v, info)
+        assert _rel(R[:20, :20], want.R[:20, :20]) <= 1e-10
+        assert _rel(R[:20, :20], col.R[:20, :20]) <= 1e-10
+        pn = inputs.Problem("nan40", Zn, csr=inputs.csr_from_dense(A))
+        _, R, _, info, _ = gpu_run(pn, v, panel=panel)
+        want = oracle(pn, v, panel=panel)
+        assert info == 35 and want.info == 35, (v, info, want.info)
+        assert _rel(R[:34, :34], want.R[:34, :34]) <= 1e-10
+
+
 def test_panel_argument_errors():
     h = amgs.handle(0)
     import ctypes as C
