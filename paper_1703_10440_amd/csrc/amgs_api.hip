@@ -310,6 +310,13 @@ double psweep_bytes(int64_t m, size_t w, int64_t ncols, int64_t kw, int64_t bd, 
 // receives the blocks of the earlier outer panels, then the block of the
 // earlier inner panel of its own outer panel, then the column steps of its
 // inner panel (the order of the two-level panel reading of the method).
+// Three levels (panel = 16, naive and HA): sixteen-panels taken apart as two
+// eight-panels exactly as above, the eight-column block acting only inside
+// its sixteen-panel (a dots-only k_bsweep over the other eight columns);
+// after a sixteen-panel, k_bsweep of width 16 over every later column; and
+// before one, an update-only k_bsweep applies the previous sixteen-panel to
+// its own columns, so the column kernels never hold a pending block wider
+// than eight.
 template <typename T>
 amgs_status_t run_panel(amgs_handle *h, Ctx &c, int variant, int reorth)
 {
