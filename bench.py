@@ -48,12 +48,14 @@ TRAFFIC_FILES = {
     ("block_sweep", "lap128_n128"): os.path.join(ROOT, "profiles", "psweep_lap128_traffic.json"),
     ("block_sweep8", "lap128_n128"): os.path.join(ROOT, "profiles", "bsweep_lap128_traffic.json"),
     ("block_sweep16", "lap128_n128"): os.path.join(ROOT, "profiles", "bsweep16_lap128_traffic.json"),
+    ("mv", "lap128_n128"): os.path.join(ROOT, "profiles", "mv_lap128_traffic.json"),
 }
 KERNEL_SOURCES = {
     "sweep": ("amgs_single.hip", "amgs_device.h", "amgs_internal.h"),
     "block_sweep": ("amgs_panel.hip", "amgs_device.h", "amgs_internal.h"),
     "block_sweep8": ("amgs_bsweep.hip", "amgs_device.h", "amgs_internal.h"),
     "block_sweep16": ("amgs_bsweep.hip", "amgs_device.h", "amgs_internal.h"),
+    "mv": ("amgs_single.hip", "amgs_device.h", "amgs_internal.h"),
 }
 
 
@@ -177,13 +179,40 @@ def source_sha(kind="sweep"):
     return h.hexdigest()[:16]
 
 
-def sweep_roofline(runner, amgs, torch, workload):
-    """The dominant kernel of the call: the projection sweep (column
-    schedule) or the block sweep after each panel's last column (panel
-    schedule).  Its average duration comes from HIP events that the library
-    binds to each dispatch on the call's stream (hipExtLaunchKernel
-    start/stop events); its algorithmic bytes per launch from the library's
-    counters."""
+def _traffic(kind, workload, runner):
+    """The measured HBM bytes per launch of a kernel, from its record, if the
+    record matches the kernel's sources and the run's precision, variant and
+    schedule."""
+    path = TRAFFIC_FILES.get((kind, workload))
+    if path and os.path.exists(path):
+        rec = json.load(open(path))
+        if rec.get("source_sha") == source_sha(kind) and rec.get("precision", "fp64") == \
+                runner.precision and rec.get("variant", runner.variant) == runner.variant and \
+                rec.get("panel", runner.panel) == runner.panel:
+            return rec.get("traffic_bytes_per_launch")
+    return None
+
+
+def _hbm_line(kernel, nbytes_per_launch, ms, launches, traffic):
+    avg_s = ms / 1e3 / max(launches, 1)
+    achieved = nbytes_per_launch / avg_s / 1e9
+    return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic, "avg_us": round(avg_s * 1e6, 3), "launches": int(launches),
+            "bytes_per_launch": nbytes_per_launch, "total_ms": round(ms, 4)}
+
+
+def headline_rooflines(runner, amgs, torch, workload):
+    """One profiled call of the headline configuration.  Its projection
+    sweep (the block sweep after each panel's last column in the panel
+    schedules, the column sweep in the column schedule) and, for HA, its
+    column MV (both forms, Alg. 5): each with its average duration from HIP
+    events that the library binds to each dispatch on the call's stream
+    (hipExtLaunchKernel start/stop events), its total time in the call and
+    its algorithmic bytes per launch from the library's counters.  The
+    dominant kernel is the one with the larger total time.  Returns
+    (dominant, sweep, mv); mv is None for naive (its second MV is not timed)
+    and HP (no column MV)."""
     h = amgs.handle(0)
     amgs.amgs_profile_reset(h)
     amgs.amgs_profile_enable(h, 1)
@@ -205,45 +234,16 @@ def sweep_roofline(runner, amgs, torch, workload):
         kind, kernel = "sweep", "k_sweep"
         ms, launches = amgs.amgs_profile_read(h, 0)
         nbytes, nl = st.sweep_bytes, st.sweep_launches
-    avg_s = ms / 1e3 / max(launches, 1)
-    bytes_per_launch = nbytes / max(nl, 1)
-    achieved = bytes_per_launch / avg_s / 1e9
-    traffic = None
-    path = TRAFFIC_FILES.get((kind, workload))
-    if path and os.path.exists(path):
-        rec = json.load(open(path))
-        if rec.get("source_sha") == source_sha(kind) and rec.get("precision", "fp64") == \
-                runner.precision and rec.get("variant", runner.variant) == runner.variant:
-            traffic = rec.get("traffic_bytes_per_launch")
-    return {"bound": "hbm", "kernel": kernel, "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic, "avg_us": round(avg_s * 1e6, 3), "launches": int(launches),
-            "bytes_per_launch": bytes_per_launch}
-
-
-def mv_roofline(data, precision, amgs, torch):
-    """The per-column MV of the HA form (Alg. 5; CSR SpMV or dense MV with
-    the pending projection applied on the fly): average duration from HIP
-    events bound to each MV dispatch, and its algorithmic bytes (A once, the
-    two source vectors, the two written vectors)."""
-    h = amgs.handle(0)
-    r = Runner(data, "ha", precision, torch, amgs)
-    r()
-    torch.cuda.synchronize()
-    amgs.amgs_profile_reset(h)
-    amgs.amgs_profile_enable(h, 1)
-    out = r()
-    torch.cuda.synchronize()
-    amgs.amgs_profile_enable(h, 0)
-    ms, launches = amgs.amgs_profile_read(h, 1)
-    st = out.stats
-    avg_s = ms / 1e3 / max(launches, 1)
-    bpl = st.mv_bytes / max(st.mv_calls, 1)
-    ach = bpl / avg_s / 1e9
-    return {"bound": "hbm", "kernel": "k_csr_mv_ell / k_dense_mv (HA column MV)",
-            "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(ach / HBM_PEAK_GBS, 4), "avg_us": round(avg_s * 1e6, 3),
-            "launches": int(launches), "bytes_per_launch": bpl}
+    sweep = _hbm_line(kernel, nbytes / max(nl, 1), ms, launches, _traffic(kind, workload, runner))
+    mv = None
+    if runner.variant == "ha":
+        ms1, n1 = amgs.amgs_profile_read(h, 1)
+        if n1 > 0:
+            mv = _hbm_line("k_csr_mv_ell / k_dense_mv (HA column MV, both forms)",
+                           st.mv_bytes / max(st.mv_calls, 1), ms1, n1,
+                           _traffic("mv", workload, runner))
+    dominant = mv if mv is not None and mv["total_ms"] > sweep["total_ms"] else sweep
+    return dominant, sweep, mv
 
 
 def gemm_roofline(runner, m, n, precision, amgs, torch):
@@ -333,15 +333,14 @@ def bench_single(args, torch, amgs):
                   "same_result": bool(torch.equal(gout.R, out.R))}
     del graph, gout
     log(f"[bench] {head_v}/{head_p} graph replay: {tg * 1e3:.3f} ms/step {graph_line}")
-    roof = sweep_roofline(run, amgs, torch, args.workload)
-    log(f"[bench] sweep roofline {roof}")
+    roof, sweeproof, mvroof = headline_rooflines(run, amgs, torch, args.workload)
+    log(f"[bench] sweep roofline {sweeproof}")
+    log(f"[bench] mv roofline {mvroof}")
     gemmroof = None
     if prob.csr is None and head_v == "hp":
         gemmroof = gemm_roofline(run, prob.m, prob.n, head_p, amgs, torch)
         log(f"[bench] gemm roofline {gemmroof}")
     del run
-    mvroof = mv_roofline(data, head_p, amgs, torch)
-    log(f"[bench] mv roofline {mvroof}")
 
     variants = {}
     if not args.no_variants:
@@ -422,7 +421,8 @@ def bench_single(args, torch, amgs):
             "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(t * 1e3, 4),
             "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
             "dtype": "f64" if head_p == "fp64" else "f32", "data": "synthetic", "config": cfg,
-            "roofline": roof, "mv_roofline": mvroof, "cpu_baseline": cpu, "variants": variants,
+            "roofline": roof, "sweep_roofline": sweeproof, "mv_roofline": mvroof,
+            "cpu_baseline": cpu, "variants": variants,
             "graph_replay": graph_line}
     if gemmroof is not None:
         line["gemm_roofline"] = gemmroof
