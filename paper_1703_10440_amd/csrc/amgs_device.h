@@ -131,6 +131,62 @@ __device__ __forceinline__ A wave_reduce_seq_deep(const A *__restrict__ v, int64
     return wave_sum(s);
 }
 
+// The coefficient a sweep's partials v[0..g) form, in one fixed order that
+// one wave and eight waves of a workgroup both reach bit for bit: the
+// partials are eight contiguous segments of ceil(g / 8); within a segment
+// each lane adds its entries in ascending order and the butterfly adds the
+// lanes (wave_reduce_seq); the eight segment sums are added in segment order.
+// One wave: the eight segments side by side, one load of each in flight.
+template <typename A>
+__device__ __forceinline__ A coef_reduce_wave(const A *__restrict__ v, int64_t g)
+{
+    const int lane = threadIdx.x & (WAVE - 1);
+    const int64_t g8 = (g + 7) / 8;
+    A acc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) acc[k] = 0;
+    for (int64_t i = lane; i < g8; i += WAVE) {
+        A t[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) t[k] = k * g8 + i < g ? v[k * g8 + i] : (A)0;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) acc[k] += t[k];
+    }
+    A s = wave_sum(acc[0]);
+#pragma unroll
+    for (int k = 1; k < 8; ++k) s += wave_sum(acc[k]);
+    return s;
+}
+
+// Eight waves: wave k < 8 reduces segment k (sixteen loads in flight per
+// lane) into seg[k] (LDS); the caller adds seg[0..8) in order after a
+// barrier.  Waves from 8 on do nothing.
+template <typename A>
+__device__ __forceinline__ void coef_reduce_segments(const A *__restrict__ v, int64_t g, A *seg)
+{
+    const int wave = threadIdx.x / WAVE;
+    if (wave < 8) {
+        const int64_t g8 = (g + 7) / 8;
+        const int64_t rest = g - wave * g8;
+        const int64_t len = rest < 0 ? 0 : rest < g8 ? rest : g8;
+        const A s = wave_reduce_seq_deep<16>(v + wave * g8, len);
+        if ((threadIdx.x & (WAVE - 1)) == 0) seg[wave] = s;
+    }
+}
+
+// coef_reduce_wave computed once per workgroup (by wave 0) and broadcast
+// through one LDS slot; every thread must call it.
+template <typename A>
+__device__ __forceinline__ A coef_reduce_bcast(const A *__restrict__ v, int64_t g, A *slot)
+{
+    if (threadIdx.x < WAVE) {
+        const A s = coef_reduce_wave(v, g);
+        if (threadIdx.x == 0) *slot = s;
+    }
+    __syncthreads();
+    return *slot;
+}
+
 // Partials of g workgroups stored in XCD order: workgroups are dispatched
 // to the 8 XCDs in turn, so workgroup x is stored at xcd_pos(x) = (x % 8) g8
 // + x / 8 (g8 = ceil(g / 8)), and the partials that share a cache line come

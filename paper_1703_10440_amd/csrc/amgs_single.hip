@@ -82,7 +82,7 @@ __device__ __forceinline__ void publish_row(const SweepPart &sp, int64_t jrow, i
     const int64_t nw = (int64_t)gridDim.x * (blockDim.x / WAVE);
     const int64_t w = (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
     for (int64_t c = c0 + w; c < n; c += nw) {
-        T s = wave_reduce_seq(part + c * sp.g, sp.g);
+        T s = coef_reduce_wave(part + c * sp.g, sp.g);
         if ((threadIdx.x & (WAVE - 1)) == 0) R[jrow + c * ldr] = (double)s;
     }
 }
@@ -119,7 +119,7 @@ __global__ __launch_bounds__(512) void k_csr_mv(CsrMvArgs a)
 
     T r = 0;
     double rjj = 1.0;
-    if (SRC == SRC_UPD && qprev) r = block_reduce_bcast((const T *)a.sp.part + a.j * a.sp.g, a.sp.g, &s_r);
+    if (SRC == SRC_UPD && qprev) r = coef_reduce_bcast((const T *)a.sp.part + a.j * a.sp.g, a.sp.g, &s_r);
     if (SRC == SRC_DIV) {
         double rr = block_reduce_bcast(a.rr_part, a.n_rr, &s_rr);
         if (!norm_ok(rr)) return;
@@ -231,8 +231,9 @@ __global__ __launch_bounds__(MV_TILE) void k_csr_to_ell(int64_t m, int32_t K,
 template <typename T, int SRC, bool RR, int RPT, bool D16, int EK>
 __device__ __forceinline__ void csr_mv_ell_body(const CsrMvArgs &a)
 {
+    static_assert(MV_TILE / WAVE >= 8, "eight waves reduce the coefficient's segments");
     __shared__ double lds[MV_TILE / WAVE];
-    __shared__ T s_r;
+    __shared__ T s_seg[8];
     __shared__ double s_rr;
     const T *__restrict__ vals = (const T *)a.vals;
     const int32_t *__restrict__ ecol = a.ell_col;
@@ -295,22 +296,24 @@ __device__ __forceinline__ void csr_mv_ell_body(const CsrMvArgs &a)
                 if (D16) cv = cv == ELL_PAD ? -1 : (int32_t)rowc[u] + cv;
                 col[u][k] = cv | -(int32_t)(k >= K);
             }
-        // the coefficient r_{j-1,j} (or r_jj for the naive second MV) is
-        // re-reduced by wave 0 while those loads are in flight (sixteen
-        // partials in flight per lane: the same bits as the other kernels'
-        // reduction of these partials, in half the round trips)
+        // the coefficient r_{j-1,j} is re-reduced by the workgroup's eight
+        // waves, one segment of the partials each (the same bits as the
+        // other kernels' coef_reduce_wave), or r_jj for the naive second MV
+        // by wave 0 (sixteen partials in flight per lane, the same bits as
+        // wave_reduce_seq), while those loads are in flight
         if (first && (with_upd || SRC == SRC_DIV)) {
-            if (tid < WAVE) {
-                if (with_upd) {
-                    const T v = wave_reduce_seq_deep<16>((const T *)a.sp.part + a.j * a.sp.g, a.sp.g);
-                    if (tid == 0) s_r = v;
-                } else {
-                    const double v = wave_reduce_seq_deep<16>(a.rr_part, a.n_rr);
-                    if (tid == 0) s_rr = v;
-                }
+            if (with_upd) {
+                coef_reduce_segments((const T *)a.sp.part + a.j * a.sp.g, a.sp.g, s_seg);
+            } else if (tid < WAVE) {
+                const double v = wave_reduce_seq_deep<16>(a.rr_part, a.n_rr);
+                if (tid == 0) s_rr = v;
             }
             __syncthreads();
-            if (with_upd) r = s_r;
+            if (with_upd) {
+                r = s_seg[0];
+#pragma unroll
+                for (int k = 1; k < 8; ++k) r += s_seg[k];
+            }
             if (SRC == SRC_DIV) {
                 const double rr = s_rr;
                 if (!norm_ok(rr)) return; // uniform over the workgroup
@@ -427,7 +430,7 @@ __global__ __launch_bounds__(256) void k_dense_mv(DenseMvArgs a)
     T *__restrict__ zt = (T *)a.zt;
     T r = 0;
     double rjj = 1.0;
-    if (SRC == SRC_UPD && qprev) r = block_reduce_bcast((const T *)a.sp.part + a.j * a.sp.g, a.sp.g, &s_r);
+    if (SRC == SRC_UPD && qprev) r = coef_reduce_bcast((const T *)a.sp.part + a.j * a.sp.g, a.sp.g, &s_r);
     if (SRC == SRC_DIV) {
         double rr = block_reduce_bcast(a.rr_part, a.n_rr, &s_rr);
         if (!norm_ok(rr)) return;
@@ -602,7 +605,7 @@ __global__ __launch_bounds__(256) void k_col_hp(RowArgs a)
     const bool own = blockIdx.y == 0;
     T *__restrict__ zdst = REORTH_A ? (T *)a.zt : Q + j * a.ldq;
     T r = 0;
-    if (j > 0) r = block_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
+    if (j > 0) r = coef_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
     T xr[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
@@ -689,7 +692,7 @@ __global__ __launch_bounds__(256) void k_reorth_a(RowArgs a)
         for (int t = 0; t < RE_GROUP; ++t) pv[t][u] = pick(pv[t][u], i_lo + t < j && k < a.m);
     }
     T r = 0;
-    if (pend) r = block_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
+    if (pend) r = coef_reduce_bcast((const T *)a.sp.part + j * a.sp.g, a.sp.g, &s_r);
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         const int64_t k = row0 + u * 256 + tid;
