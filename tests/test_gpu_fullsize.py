@@ -25,8 +25,9 @@ orientation as an extra check.
 Every case but CGS runs in the column schedule and in the one- and two-level
 panel schedules (panels of four; panels of eight taken apart as panels of
 four); the three-level schedule (panels of sixteen taken apart as panels of
-eight) runs HA and naive on lap64 (with and without the second pass) and HA
-on lap128 in both precisions.
+eight) runs HA and naive on lap64 (with and without the second pass), HA on
+lap128 in both precisions, and at lap128 also naive and HA with the
+per-column second pass in binary64.
 """
 import numpy as np
 import pytest
@@ -262,6 +263,17 @@ def test_lap128_three_level_fp64(lap128_fp64):
     Q, R, info = _run(p, "ha", "fp64", 16)
     assert info == 0
     _at_oracle_level(p, Q, R, _oracles(p, "ha", "fp64", 16))
+
+
+@pytest.mark.parametrize("variant,reorth", [("naive", False), ("ha", True)],
+                         ids=["naive", "ha_second_pass"])
+def test_lap128_three_level_other_forms(lap128_fp64, variant, reorth):
+    """The naive form and HA with the per-column second pass at the headline
+    size and schedule (both reported by bench.py's variants)."""
+    p = lap128_fp64
+    Q, R, info = _run(p, variant, "fp64", 16, reorth=reorth)
+    assert info == 0
+    _at_oracle_level(p, Q, R, _oracles(p, variant, "fp64", 16, reorth=reorth))
 
 
 def test_lap128_three_level_fp32(lap128_fp32):
