@@ -27,7 +27,7 @@ panel schedules (panels of four; panels of eight taken apart as panels of
 four); the three-level schedule (panels of sixteen taken apart as panels of
 eight) runs HA and naive on lap64 (with and without the second pass), HA on
 lap128 in both precisions, and at lap128 also naive and HA with the
-per-column second pass in binary64.
+per-column second pass in both precisions.
 """
 import numpy as np
 import pytest
@@ -274,6 +274,15 @@ def test_lap128_three_level_other_forms(lap128_fp64, variant, reorth):
     Q, R, info = _run(p, variant, "fp64", 16, reorth=reorth)
     assert info == 0
     _at_oracle_level(p, Q, R, _oracles(p, variant, "fp64", 16, reorth=reorth))
+
+
+@pytest.mark.parametrize("variant,reorth", [("naive", False), ("ha", True)],
+                         ids=["naive", "ha_second_pass"])
+def test_lap128_three_level_other_forms_fp32(lap128_fp32, variant, reorth):
+    p = lap128_fp32
+    Q, R, info = _run(p, variant, "fp32", 16, reorth=reorth)
+    assert info == 0
+    _at_oracle_level(p, Q, R, _oracles(p, variant, "fp32", 16, reorth=reorth), floors=(0.0, 0.0))
 
 
 def test_lap128_three_level_fp32(lap128_fp32):
